@@ -1,0 +1,423 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the paper's
+worked examples (Section 4), closed forms, finite differences, brute force on
+tiny instances, invariants (tautologies, empty clauses, permutations, polarity
+flips, the +-1 dot-product form of the unsat test), a library Adam, and the
+published SplitMix64 outputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import cnfgen
+import oracle as O
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def _cnf(clauses, n):
+    return O.OracleCNF(n, cnfgen.from_clauses(clauses))
+
+
+def _sech2(x):
+    return 1.0 / np.cosh(x) ** 2
+
+
+# ----------------------------------------------------------------------------
+# Section 4 worked example and non-injectivity example
+# ----------------------------------------------------------------------------
+
+def test_worked_example_scores_and_mask(golden):
+    g = golden("worked_example.txt")
+    c = O.OracleCNF(g["n"], np.array(g["clauses"], dtype=np.int32))
+    x = np.array(g["x"], dtype=np.float64)
+    loss, grad, unsat, f, mu = c.loss_grad(x, O.UNSAT, want_f=True)
+    tol = 0.5 * 10 ** (-g["printed_decimals"])
+    np.testing.assert_allclose(f, g["f"], atol=tol)
+    assert unsat[0] == g["unsat_count"]
+    assert list(mu) == g["unsat_mask"]
+    assert c.count((x > 0).astype(np.uint8)) == g["unsat_count"]
+
+
+def test_worked_example_optimum(golden):
+    g = golden("worked_example.txt")
+    c = O.OracleCNF(g["n"], np.array(g["clauses"], dtype=np.int32))
+    opt, nopt, arg = c.bruteforce()
+    assert c.m - opt == g["max_satisfiable"]
+    assert c.count(arg) == opt
+    assert nopt == 3  # [0,0], [1,0], [0,1] each leave one clause unsatisfied
+
+
+def test_worked_example_one_step(golden):
+    """The printed step [0.34, 1.23] is reproduced by the loss over all clauses
+    (mean over m) and plain gradient descent with lr 0.1; the masked loss gives
+    a different point, which documents the reading taken for the example."""
+    g = golden("worked_example.txt")
+    c = O.OracleCNF(g["n"], np.array(g["clauses"], dtype=np.int32))
+    x = np.array(g["x"], dtype=np.float64)
+    tol = 0.5 * 10 ** (-g["printed_decimals"])
+    _, grad, _ = c.loss_grad(x, O.ALL)
+    xs = x.copy()
+    O.sgd_step(xs, grad, g["lr"])
+    np.testing.assert_allclose(xs, g["x_after_one_step"], atol=tol)
+    _, grad_u, _ = c.loss_grad(x, O.UNSAT)
+    xu = x - g["lr"] * grad_u
+    assert np.abs(xu - np.array(g["x_after_one_step"])).max() > tol
+
+
+def test_non_injective_example(golden):
+    g = golden("non_injective.txt")
+    c = O.OracleCNF(g["n"], np.array(g["clauses"], dtype=np.int32))
+    xa = np.array(g["xa"]); xb = np.array(g["xb"])
+    _, _, ua, fa, ma = c.loss_grad(xa, O.UNSAT, want_f=True)
+    _, _, ub, fb, mb = c.loss_grad(xb, O.UNSAT, want_f=True)
+    assert fa[2] == pytest.approx(fb[2], abs=1e-15)
+    assert fa[2] < 0  # negative score although the clause is satisfied
+    assert list((xa > 0).astype(int)) == g["assign_a"]
+    assert list((xb > 0).astype(int)) == g["assign_b"]
+    assert list(ma) == [1, 0, 0] and list(mb) == [0, 1, 0]
+    assert ma[2] == 0 and mb[2] == 0
+
+
+# ----------------------------------------------------------------------------
+# Closed forms on one- and two-literal formulas
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("x", [-2.5, -0.7, -1e-3, 0.3, 4.0])
+def test_unit_clause_closed_form(x):
+    c = _cnf([[1]], 1)
+    t = math.tanh(x)
+    for mode in (O.UNSAT, O.ALL):
+        mu = 1.0 if (mode == O.ALL or x <= 0) else 0.0
+        loss, grad, unsat = c.loss_grad(np.array([x]), mode)
+        assert loss[0] == pytest.approx(mu * t * t, rel=1e-14, abs=0)
+        assert grad[0] == pytest.approx(mu * 2 * t * _sech2(x), rel=1e-13, abs=0)
+        assert unsat[0] == (1 if x <= 0 else 0)
+
+
+def test_two_literal_closed_form():
+    # (not x1 or x2), (x1): m = 2
+    c = _cnf([[-1, 2], [1]], 2)
+    x = np.array([0.8, -0.4])  # rounds to [1, 0]: first clause unsat, second sat
+    t1, t2 = math.tanh(0.8), math.tanh(-0.4)
+    f1 = -t1 + t2
+    loss, grad, unsat = c.loss_grad(x, O.UNSAT)
+    assert unsat[0] == 1
+    assert loss[0] == pytest.approx(f1 * f1 / 2, rel=1e-14)
+    a1 = 2.0 / 2 * f1
+    assert grad[0] == pytest.approx(-a1 * _sech2(0.8), rel=1e-13)
+    assert grad[1] == pytest.approx(a1 * _sech2(-0.4), rel=1e-13)
+    lossa, grada, _ = c.loss_grad(x, O.ALL)
+    f2 = t1
+    assert lossa[0] == pytest.approx((f1 * f1 + f2 * f2) / 2, rel=1e-14)
+    assert grada[0] == pytest.approx((-f1 + f2) * _sech2(0.8), rel=1e-13)
+
+
+def test_sech2_no_cancellation():
+    # At |x| = 12, 1 - tanh^2 is ~1.5e-10 in FP64 exactly as 4e^{-24}/(1+e^{-24})^2.
+    c = _cnf([[1]], 1)
+    _, g, _ = c.loss_grad(np.array([-12.0]), O.UNSAT)
+    expect = 2 * math.tanh(-12.0) * 4 * math.exp(-24) / (1 + math.exp(-24)) ** 2
+    assert g[0] == pytest.approx(expect, rel=1e-14)
+    assert g[0] != 0.0
+
+
+# ----------------------------------------------------------------------------
+# Canonicalisation rules: duplicates, tautologies, empty clauses
+# ----------------------------------------------------------------------------
+
+def test_tautology_never_counted_and_pair_cancels():
+    c = _cnf([[1, -1, 2]], 2)
+    for a in ([0, 0], [0, 1], [1, 0], [1, 1]):
+        assert c.count(np.array(a, np.uint8)) == 0
+    x = np.array([0.5, -0.9])
+    _, _, _, f, mu = c.loss_grad(x, O.ALL, want_f=True)
+    assert f[0] == pytest.approx(math.tanh(-0.9), rel=1e-15)  # x1 terms cancel
+    _, g, _ = c.loss_grad(x, O.ALL)
+    assert g[0] == 0.0
+
+
+def test_empty_clause_always_counted():
+    c = _cnf([[], [1]], 1)
+    for a in ([0], [1]):
+        assert c.count(np.array(a, np.uint8)) >= 1
+    loss, g, u = c.loss_grad(np.array([0.5]), O.UNSAT)
+    assert u[0] == 1 and loss[0] == 0.0 and g[0] == 0.0
+
+
+def test_duplicate_literals_kept_once():
+    c1 = _cnf([[1, 1, -2, 1]], 2)
+    c2 = _cnf([[1, -2]], 2)
+    x = np.array([-0.3, 0.6])
+    r1 = c1.loss_grad(x, O.ALL, want_f=True)
+    r2 = c2.loss_grad(x, O.ALL, want_f=True)
+    for a, b in zip(r1, r2):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_parse_errors():
+    with pytest.raises(O.OracleError) as e:
+        O.OracleCNF(2, np.array([1, 2], np.int32))
+    assert e.value.code == -2
+    with pytest.raises(O.OracleError) as e:
+        O.OracleCNF(2, np.array([1, 3, 0], np.int32))
+    assert e.value.code == -3
+
+
+# ----------------------------------------------------------------------------
+# Invariants
+# ----------------------------------------------------------------------------
+
+def _dense_w(clauses, n):
+    W = np.zeros((n, len(clauses)))
+    for j, cl in enumerate(clauses):
+        for l in cl:
+            W[abs(l) - 1, j] = 1 if l > 0 else -1
+    return W
+
+
+def test_pm1_dot_product_form_of_unsat():
+    """Unsat iff (2a-1) . W == -k_j on canonical non-tautological clauses
+    (the paper's x'.W = s test with x' mapped to {-1,+1})."""
+    lits = cnfgen.mixed_kcnf(30, 140, seed=11)
+    cls = cnfgen.to_clauses(lits)
+    c = O.OracleCNF(30, lits)
+    W = _dense_w(cls, 30)
+    k = np.array([len(cl) for cl in cls])
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        a = (rng.random(30) < 0.5).astype(np.uint8)
+        mask = (2.0 * a - 1.0) @ W == -k
+        np.testing.assert_array_equal(c.unsat_mask(a), mask.astype(np.uint8))
+
+
+def test_count_bounds_and_permutation_invariance():
+    n, m = 25, 110
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=5)
+    cls = cnfgen.to_clauses(lits)
+    rng = np.random.default_rng(1)
+    cperm = rng.permutation(m)
+    vperm = rng.permutation(n)  # old var i -> new var vperm[i]
+    cls2 = [[int(np.sign(l)) * (vperm[abs(l) - 1] + 1) for l in cls[j]] for j in cperm]
+    c1 = O.OracleCNF(n, lits)
+    c2 = _cnf(cls2, n)
+    x = rng.uniform(-1, 1, n)
+    x2 = np.zeros(n); x2[vperm] = x
+    for mode in (O.UNSAT, O.ALL):
+        l1, g1, u1 = c1.loss_grad(x, mode)
+        l2, g2, u2 = c2.loss_grad(x2, mode)
+        assert u1[0] == u2[0] and 0 <= u1[0] <= m
+        assert l1[0] == pytest.approx(l2[0], rel=1e-13)
+        np.testing.assert_allclose(g2[vperm], g1, rtol=1e-12, atol=1e-18)
+
+
+def test_polarity_flip_symmetry():
+    n, m = 20, 90
+    lits = cnfgen.mixed_kcnf(n, m, seed=7)
+    cls = cnfgen.to_clauses(lits)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-1.5, 1.5, n)
+    flip = 4
+    cls2 = [[-l if abs(l) == flip + 1 else l for l in cl] for cl in cls]
+    x2 = x.copy(); x2[flip] = -x2[flip]
+    c1, c2 = O.OracleCNF(n, lits), _cnf(cls2, n)
+    for mode in (O.UNSAT, O.ALL):
+        l1, g1, u1, f1, _ = c1.loss_grad(x, mode, want_f=True)
+        l2, g2, u2, f2, _ = c2.loss_grad(x2, mode, want_f=True)
+        assert u1[0] == u2[0]
+        np.testing.assert_allclose(f1, f2, rtol=1e-14, atol=1e-15)
+        assert l1[0] == pytest.approx(l2[0], rel=1e-14)
+        g2[flip] = -g2[flip]
+        np.testing.assert_allclose(g1, g2, rtol=1e-13, atol=1e-18)
+
+
+def test_zero_loss_iff_zero_count():
+    n, m = 40, 150
+    lits, plant = cnfgen.planted_kcnf(n, m, 3, seed=3)
+    c = O.OracleCNF(n, lits)
+    x = np.where(plant == 1, 0.7, -0.7)
+    l, g, u = c.loss_grad(x, O.UNSAT)
+    assert u[0] == 0 and l[0] == 0.0 and not g.any()
+    rng = np.random.default_rng(4)
+    for _ in range(10):
+        y = rng.uniform(-1, 1, n)
+        l, g, u = c.loss_grad(y, O.UNSAT)
+        assert (u[0] == 0) == (l[0] == 0.0)
+
+
+# ----------------------------------------------------------------------------
+# Gradient vs central finite differences
+# ----------------------------------------------------------------------------
+
+def _s_bound(cls, x, mu, m):
+    """S_i = sech^2(x_i) (2/m) sum_j |W_ij| mu_j F_j, F_j = sum |tanh| over c_j."""
+    t = np.tanh(x)
+    S = np.zeros_like(x)
+    for j, cl in enumerate(cls):
+        if not mu[j]:
+            continue
+        F = sum(abs(t[abs(l) - 1]) for l in cl)
+        for l in cl:
+            S[abs(l) - 1] += F
+    return _sech2(x) * 2.0 / m * S
+
+
+@pytest.mark.parametrize("mode", [O.UNSAT, O.ALL])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradient_finite_differences(mode, seed):
+    n, m = 30, 126
+    lits = cnfgen.mixed_kcnf(n, m, seed=20 + seed)
+    cls = cnfgen.to_clauses(lits)
+    c = O.OracleCNF(n, lits)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-2, 2, n)
+    x[np.abs(x) < 1e-2] = 0.5
+    h = 1e-4
+    loss, g, _, f, mu = c.loss_grad(x, mode, want_f=True)
+    S = _s_bound(cls, x, mu, m)
+    for i in range(n):
+        xp = x.copy(); xp[i] += h
+        xm = x.copy(); xm[i] -= h
+        fd = (c.loss(xp, mode) - c.loss(xm, mode)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * S[i] + 1e-12, (i, fd, g[i], S[i])
+
+
+# ----------------------------------------------------------------------------
+# Brute force
+# ----------------------------------------------------------------------------
+
+def test_bruteforce_all_sign_patterns():
+    # every one of the 2^k sign patterns over k variables: each assignment
+    # falsifies exactly one clause
+    k = 4
+    cls = [[(v + 1) if (s >> v) & 1 else -(v + 1) for v in range(k)] for s in range(2 ** k)]
+    c = _cnf(cls, k)
+    opt, nopt, arg = c.bruteforce()
+    assert (opt, nopt) == (1, 2 ** k)
+
+
+def test_bruteforce_units():
+    n = 10
+    cls = [[i + 1] for i in range(n)] + [[-(i + 1)] for i in range(n)]
+    opt, nopt, _ = _cnf(cls, n).bruteforce()
+    assert (opt, nopt) == (n, 2 ** n)
+
+
+def test_bruteforce_planted():
+    lits, plant = cnfgen.planted_kcnf(18, 75, 3, seed=9)
+    c = O.OracleCNF(18, lits)
+    opt, nopt, arg = c.bruteforce()
+    assert opt == 0 and nopt >= 1 and c.count(plant) == 0 and c.count(arg) == 0
+
+
+def test_bruteforce_matches_direct_enumeration():
+    n = 12
+    lits = cnfgen.uniform_kcnf(n, 70, 3, seed=4)
+    c = O.OracleCNF(n, lits)
+    counts = [c.count(np.array([(s >> i) & 1 for i in range(n)], np.uint8))
+              for s in range(2 ** n)]
+    opt, nopt, _ = c.bruteforce()
+    assert opt == min(counts) and nopt == counts.count(opt)
+
+
+# ----------------------------------------------------------------------------
+# Optimizer
+# ----------------------------------------------------------------------------
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(0)
+    g = rng.normal(size=50) * 10.0 ** rng.uniform(-6, 1, 50)
+    x = rng.normal(size=50)
+    x0 = x.copy()
+    m = np.zeros(50); v = np.zeros(50)
+    O.adam_step(x, m, v, g, 1, lr=1e-4)
+    np.testing.assert_allclose(x, x0 - 1e-4 * g / (np.abs(g) + 1e-8), rtol=1e-14, atol=1e-19)
+
+
+def test_adam_matches_torch_optim():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(1)
+    n = 64
+    x = rng.normal(size=n)
+    p = torch.nn.Parameter(torch.tensor(x.copy(), dtype=torch.float64))
+    opt = torch.optim.Adam([p], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(n); v = np.zeros(n)
+    for step in range(1, 8):
+        g = rng.normal(size=n) * 10.0 ** rng.uniform(-5, 0, n)
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        O.adam_step(x, m, v, g, step, lr=1e-3)
+        np.testing.assert_allclose(x, p.detach().numpy(), rtol=1e-13, atol=1e-16)
+
+
+# ----------------------------------------------------------------------------
+# SplitMix64 initial values
+# ----------------------------------------------------------------------------
+
+def test_splitmix64_published_outputs(golden):
+    g = golden("splitmix64.txt")
+    assert [O.splitmix64(g["seed0"], k) for k in (1, 2, 3)] == g["out0"]
+    assert [O.splitmix64(g["seed1"], k) for k in (1, 2, 3)] == g["out1"]
+
+
+def test_init_x_range_exactness_and_restart_streams():
+    n, R = 4000, 3
+    x = O.init_x(n, R, seed=17)
+    assert x.dtype == np.float32
+    assert x.min() >= -1.0 and x.max() <= 1.0 - 2.0 ** -23
+    assert np.all(np.float64(x) * 2.0 ** 23 == np.round(np.float64(x) * 2.0 ** 23))
+    assert abs(float(x.mean())) < 4 * (1 / math.sqrt(3)) / math.sqrt(x.size)
+    hist, _ = np.histogram(x, bins=10, range=(-1, 1))
+    assert hist.min() > 0.85 * x.size / 10
+    # restart r of seed s is restart 0 of seed s + r
+    for r in range(R):
+        np.testing.assert_array_equal(x[:, r], O.init_x(n, 1, seed=17 + r)[:, 0])
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 loop
+# ----------------------------------------------------------------------------
+
+def test_solve_invariants_small():
+    n, m = 16, 72
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=12)
+    c = O.OracleCNF(n, lits)
+    opt, _, _ = c.bruteforce()
+    res = c.solve(steps=300, restarts=4, eval_every=1, seed=3, lr=0.05)
+    assert res["best_cost"] >= opt
+    assert c.count(res["best_assignment"]) == res["best_cost"]
+    assert res["best_cost"] == res["restart_best"].min()
+    assert res["best_restart"] == int(np.argmin(res["restart_best"]))
+    assert np.all(res["restart_best"] <= m)
+
+
+def test_solve_restarts_independent_and_threads():
+    n, m = 60, 258
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=13)
+    c = O.OracleCNF(n, lits)
+    res = c.solve(steps=120, restarts=4, eval_every=10, seed=100, lr=0.02, want_x=True)
+    resp = c.solve(steps=120, restarts=4, eval_every=10, seed=100, lr=0.02, threads=4,
+                   want_x=True)
+    np.testing.assert_array_equal(res["x"], resp["x"])
+    for r in range(4):
+        one = c.solve(steps=120, restarts=1, eval_every=10, seed=100 + r, lr=0.02, want_x=True)
+        assert one["restart_best"][0] == res["restart_best"][r]
+        assert one["restart_step"][0] == res["restart_step"][r]
+        np.testing.assert_array_equal(one["x"][:, 0], res["x"][:, r])
+
+
+def test_solve_x0_and_best_monotone():
+    n, m = 30, 129
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=14)
+    c = O.OracleCNF(n, lits)
+    x0 = O.init_x(n, 1, 7)
+    a = c.solve(steps=50, restarts=1, eval_every=5, seed=7, lr=0.05)
+    b = c.solve(steps=50, restarts=1, eval_every=5, seed=999, lr=0.05, x0=x0)
+    assert a["best_cost"] == b["best_cost"] and a["restart_step"][0] == b["restart_step"][0]
+    prev = m
+    for T in (0, 10, 20, 40, 80):
+        cur = c.solve(steps=T, restarts=1, eval_every=5, seed=7, lr=0.05)["best_cost"]
+        assert cur <= prev
+        prev = cur
