@@ -1,0 +1,214 @@
+"""Benchmark of the HIP solve loop on one MI355X.
+
+Default workload: uniform random 3-CNF, n = 20000 variables, m = 86000 clauses
+(ratio 4.3), 64 restarts solved together, 2000 Adam steps (lr 1e-4), rounding
+and unsat count every 50 steps.  One benchmark step = one complete solve of
+that batch (inputs resident in HBM; loading the instance is timed apart).
+
+Printed: one JSON line with fwd+bwd literal nonzeros per second (2 L R T per
+solve), the roofline of the dominant kernel (algorithmic bytes per launch /
+average launch time from HIP events), and the FP64 CPU oracle timed on a
+bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(n, m, L, R):
+    """Algorithmic bytes per launch (index arrays once, state per restart)."""
+    fwd = 4 * L + 4 * (m + 1) + R * (4 * n + 4 * m)      # literals, offsets, x gather, a write
+    bwd = 4 * L + 4 * (n + 1) + R * (4 * m + 24 * n)     # occurrences, offsets, a gather, x/m/v r+w
+    return fwd, bwd
+
+
+def kernels_sha():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "plan.cpp", "plan.hpp"):
+        with open(os.path.join(ROOT, "paper_2402_03640_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel_key):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+    except Exception:
+        return None
+    if rec.get("kernels_sha") != kernels_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel_key)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def make_workload(name):
+    import cnfgen
+    if name == "cfg2":
+        n, m, R, T, K = 20000, 86000, 64, 2000, 50
+        lits = cnfgen.uniform_kcnf(n, m, 3, seed=2)
+        desc = ("uniform random 3-CNF n=20000 m=86000 (ratio 4.3), 64 restarts in one solve, "
+                "2000 Adam steps lr 1e-4, round+count every 50")
+    elif name == "cfg2-plain":
+        n, m, R, T, K = 20000, 86000, 1, 2000, 50
+        lits = cnfgen.uniform_kcnf(n, m, 3, seed=2)
+        desc = "uniform random 3-CNF n=20000 m=86000, one restart, 2000 Adam steps, K=50"
+    elif name == "cfg1":
+        n, m, R, T, K = 50, 215, 1, 1000, 1
+        lits = cnfgen.uniform_kcnf(n, m, 3, seed=1)
+        desc = "uniform random 3-CNF n=50 m=215, one restart, 1000 Adam steps, K=1"
+    elif name == "cfg3":
+        n, m, R, T, K = 500000, 2500000, 1, 200, 50
+        lits = cnfgen.structured_cnf(n, m, seed=3)
+        desc = ("structured CNF n=500000 m=2.5M, length 2+Geometric(0.4) capped at 12, Zipf(1.1) "
+                "occurrences, one restart, 200 Adam steps, K=50")
+    elif name == "cfg4":
+        n, m, R, T, K = 1000, 4200, 16, 1000, 1
+        lits = cnfgen.mixed_kcnf(n, m, seed=4)
+        desc = "mixed 2/3/4-CNF n=1000 m=4200, 16 restarts, 1000 Adam steps, K=1"
+    else:
+        raise SystemExit(f"unknown config {name}")
+    return dict(name=name, n=n, m=m, R=R, T=T, K=K, lits=lits, desc=desc)
+
+
+def cpu_baseline(wl, L, max_threads=16, sample_steps=None):
+    """The FP64 oracle on this host, on a bounded sample of the workload."""
+    import numpy as np
+    import oracle as O
+    oracle_lib = O.build(force=False)
+    del oracle_lib
+    oc = O.OracleCNF(wl["n"], wl["lits"])
+    threads = max(1, min(os.cpu_count() or 1, max_threads))
+    R = wl["R"]
+    if sample_steps is None:
+        sample_steps = min(wl["T"], max(1, int(2.0e9 / max(1, 2 * L * R))))
+    t0 = time.perf_counter()
+    oc.solve(steps=sample_steps, restarts=R, eval_every=wl["K"], seed=0, lr=1e-4, threads=threads)
+    dt = time.perf_counter() - t0
+    nnz = 2.0 * L * R * sample_steps
+    return {"value": nnz / dt, "unit": "nnz/s", "cores": threads, "kind": "oracle",
+            "sample": f"{R} restarts x {sample_steps} of {wl['T']} steps (eval every {wl['K']}), "
+                      f"FP64, OpenMP over restarts, {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
+    ap.add_argument("--config", default="cfg2")
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel-iters", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the solve loop is benchmarked on a single MI355X; "
+              "restarts and instances shard across GPUs without communication (see DESIGN.md), "
+              "no multi-GPU figure is produced.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2402_03640_amd as hm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = make_workload(args.config)
+    log(f"[bench] workload {wl['name']}: {wl['desc']}")
+    t0 = time.perf_counter()
+    cnf = hm.load_cnf(wl["n"], wl["lits"])
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t0
+    L = cnf.info["nnz"]
+    n, m, R, T, K = wl["n"], wl["m"], wl["R"], wl["T"], wl["K"]
+    log(f"[bench] loaded: L={L} heavy={cnf.info['n_heavy']} in {load_s:.3f} s")
+
+    kw = dict(steps=T, restarts=R, eval_every=K, seed=0, lr=1e-4, schedule=args.schedule)
+    for i in range(args.warmup):
+        r = hm.solve(cnf, **kw)
+        log(f"[bench] warmup {i}: best {r.best_cost} device {r.device_ms:.2f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev_ms = []
+    best = []
+    for i in range(args.steps):
+        r = hm.solve(cnf, **kw)
+        dev_ms.append(r.device_ms)
+        best.append(r.best_cost)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"[bench] timed {args.steps} solves: {wall:.3f} s, best {best}, schedule {r.schedule}")
+    ms_per_solve = 1e3 * wall / args.steps
+    nnz_per_solve = 2.0 * L * R * T
+    value = nnz_per_solve * args.steps / wall
+
+    fwd_ms, bwd_ms, step_ms = hm.time_kernels(cnf, restarts=R, iters=args.kernel_iters, lr=1e-4,
+                                              schedule=args.schedule)
+    fb, bb = kernel_bytes(n, m, L, R)
+    log(f"[bench] kernels: fwd {fwd_ms*1e3:.2f} us, bwd {bwd_ms*1e3:.2f} us, step {step_ms*1e3:.2f} us")
+    if bwd_ms >= fwd_ms:
+        dom, dbytes, dms, key = "backward (transposed sums + Adam)", bb, bwd_ms, "bwd"
+    else:
+        dom, dbytes, dms, key = "forward (scores + mask + adjoint)", fb, fwd_ms, "fwd"
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_record(key),
+            "kernel": dom, "algorithmic_bytes_per_launch": dbytes,
+            "avg_launch_us": round(dms * 1e3, 3),
+            "other_kernel": {"name": "forward" if key == "bwd" else "backward",
+                             "avg_launch_us": round((fwd_ms if key == "bwd" else bwd_ms) * 1e3, 3),
+                             "algorithmic_bytes_per_launch": fb if key == "bwd" else bb,
+                             "achieved_GBps": round((fb if key == "bwd" else bb) /
+                                                    ((fwd_ms if key == "bwd" else bwd_ms) * 1e-3) / 1e9, 1)}}
+    step_bytes = fb + bb
+    out = {
+        "metric": "fwd+bwd literal nnz/s",
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_solve,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": n, "m": m, "nnz": L, "restarts": R,
+                   "grad_steps_per_solve": T, "eval_every": K, "schedule": r.schedule},
+        "roofline": roof,
+        "effective_GBps_per_step": round(step_bytes / (step_ms * 1e-3) / 1e9, 1),
+        "device_ms_per_solve": round(float(np.median(dev_ms)), 3),
+        "us_per_grad_step": round(1e3 * float(np.median(dev_ms)) / max(T, 1), 3),
+        "best_cost": int(min(best)),
+        "load_s": round(load_s, 4),
+    }
+    if not args.no_cpu:
+        log("[bench] timing the FP64 oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(wl, L)
+        log(f"[bench] oracle: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * hipmsat.h -- C ABI of the MI355X (gfx950) solve loop for the gradient-based
+ * MaxSAT method of Hosny & Reda, "torchmSAT: A GPU-Accelerated Approximation To
+ * The Maximum Satisfiability Problem" (arXiv 2402.03640).
+ *
+ * The method (Section 4): each Boolean variable is relaxed to a real x_i; the
+ * clause scores are f = tanh(x) W with W[i][j] = +1 / -1 when x_i / not-x_i is
+ * a literal of clause j; a clause is unsatisfied when every literal is false
+ * under the rounding a_i = [x_i > 0]; the loss is the mean over all m clauses
+ * of f_j^2 taken over the unsatisfied clauses; its gradient is
+ * back-propagated to x and an optimizer step follows.  Algorithm 1 repeats
+ * this while tracking the assignment with the fewest unsatisfied clauses.
+ *
+ * Conventions
+ *  - Every function returns hms_status: HMS_OK (0) or a negative error code;
+ *    hms_last_error() then holds a message (thread-local, valid until the next
+ *    call on the same thread).  No C++ exception crosses this boundary.
+ *  - "HOST" pointers are ordinary CPU memory; "DEVICE" pointers are HIP device
+ *    memory on the current device.  Relaxed values are FP32, laid out [n][R]:
+ *    variable-major with the restart index innermost, in the caller's original
+ *    (0-based) variable order.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it; functions that return host results synchronise it before returning.
+ *  - An hms_cnf handle is immutable after loading; several solves may use one
+ *    handle at once (each call allocates its own state).  No call keeps a
+ *    caller pointer after it returns.
+ */
+#ifndef HIPMSAT_H
+#define HIPMSAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hms_status;
+
+#define HMS_OK 0
+#define HMS_ERR_ARG (-1)           /* invalid argument (null pointer, bad size, bad enum) */
+#define HMS_ERR_PARSE (-2)         /* malformed CNF: last clause not 0-terminated, bad DIMACS */
+#define HMS_ERR_LITERAL_RANGE (-3) /* literal |l| > n_vars */
+#define HMS_ERR_DEVICE (-4)        /* no usable gfx950 device or a HIP runtime error */
+#define HMS_ERR_NOMEM (-5)         /* host or device allocation failed */
+#define HMS_ERR_NONFINITE (-6)     /* a relaxed value or the loss became NaN/Inf */
+#define HMS_ERR_CANCELLED (-7)     /* reserved */
+#define HMS_ERR_IO (-8)            /* file could not be read */
+#define HMS_ERR_TOO_LARGE (-9)     /* instance exceeds the 31-bit index space */
+
+#define HMS_ADAM 0       /* Adam, PyTorch 1.10 semantics (Section 5 "Setup": Adam, lr 1e-4) */
+#define HMS_SGD 1        /* x <- x - lr g (the Section 4 worked example, lr 0.1) */
+
+#define HMS_LOSS_UNSAT 0 /* loss over the unsatisfied clauses (Section 4, Algorithm 1) */
+#define HMS_LOSS_ALL 1   /* loss over every clause (reproduces the worked example's step) */
+
+typedef struct hms_cnf hms_cnf; /* opaque: canonical instance, host plan and device structure */
+
+typedef struct {
+    int32_t n_vars;         /* variables as declared */
+    int32_t n_clauses;      /* clauses as given, m (the loss divides by m) */
+    int64_t n_lits;         /* nonzero literals as given */
+    int64_t nnz;            /* nonzero entries of W after canonicalisation */
+    int32_t n_empty;        /* empty clauses (always unsatisfied) */
+    int32_t n_taut;         /* clauses with a complementary pair (always satisfied) */
+    int32_t n_active;       /* variables with a nonzero W entry */
+    int32_t n_heavy;        /* variables whose transposed row is split into segments */
+    int64_t struct_bytes;   /* device bytes held by the handle */
+    int64_t state_bytes_r1; /* device bytes of solver state per restart */
+} hms_cnf_info;
+
+/*
+ * Load a CNF given DIMACS-style: `lits` (HOST, n_lits int32) holds the clauses
+ * one after the other, literals as signed 1-based variable indices, each clause
+ * ended by 0 (Section 2, CNF of equation 1; Section 4 builds W from it).
+ * Repeated literals count once; a clause holding v and not-v is always
+ * satisfied and its pair contributes 0 to the score; an empty clause is always
+ * unsatisfied.  n_vars = 0 with no clauses is valid.
+ * Errors: HMS_ERR_PARSE (last clause not terminated), HMS_ERR_LITERAL_RANGE
+ * (|l| > n_vars), HMS_ERR_ARG, HMS_ERR_DEVICE, HMS_ERR_NOMEM.
+ * On success *out owns host and device memory until hms_free_cnf.  The upload
+ * is ordered on `stream` and complete when the call returns.
+ */
+hms_status hms_load_cnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, void* stream,
+                        hms_cnf** out);
+
+/* Same, from a DIMACS .cnf file ("p cnf n m" header, "c" comments). */
+hms_status hms_load_cnf_dimacs(const char* path, void* stream, hms_cnf** out);
+
+/* Sizes of a loaded instance. */
+hms_status hms_cnf_info_get(const hms_cnf* cnf, hms_cnf_info* out);
+
+/* Release a handle (NULL is allowed).  Not while a call on it is running. */
+void hms_free_cnf(hms_cnf* cnf);
+
+typedef struct {
+    int32_t steps;       /* optimizer steps T (>= 0) */
+    int32_t restarts;    /* R independent relaxed points solved together (>= 1) */
+    int32_t eval_every;  /* K: round and count every K steps, and at x_T (>= 1) */
+    int32_t optimizer;   /* HMS_ADAM or HMS_SGD */
+    uint64_t seed;       /* restart r starts from the SplitMix64 stream seeded seed + r */
+    float lr, beta1, beta2, eps; /* Adam: PyTorch defaults 0.9 / 0.999 / 1e-8 */
+    int32_t loss_mode;   /* HMS_LOSS_UNSAT or HMS_LOSS_ALL */
+    int32_t schedule;    /* 0 = automatic; otherwise a kernel schedule id (hms_schedule_*) */
+    int32_t use_graph;   /* 1 = replay the step body as a HIP graph, 0 = direct launches */
+    int32_t reserved;
+    double time_limit_s; /* > 0: stop at a K-step boundary once exceeded (not reproducible) */
+    const float* x0;     /* DEVICE [n][R] initial values, or NULL for SplitMix64 U(-1,1) */
+    void* stream;        /* hipStream_t */
+} hms_solve_params;
+
+typedef struct {
+    int64_t best_cost;        /* fewest unsatisfied clauses seen over all restarts */
+    int32_t best_restart;     /* restart that found it (lowest index on ties) */
+    int32_t best_step;        /* step at which it was found (-1: the initial point never beaten) */
+    int32_t steps_done;       /* steps taken (< steps only with a time limit) */
+    int32_t schedule;         /* kernel schedule that ran */
+    double final_loss;        /* loss at x_T of best_restart */
+    uint8_t* best_assignment; /* caller HOST buffer of n bytes (0/1), or NULL */
+    int64_t* restart_best;    /* caller HOST [R] per-restart best cost, or NULL */
+    int32_t* restart_step;    /* caller HOST [R] per-restart best step, or NULL */
+    double* restart_loss;     /* caller HOST [R] loss at x_T, or NULL */
+    float* x_final;           /* caller DEVICE [n][R] receives x_T, or NULL */
+    double device_ms;         /* device time of the step loop (HIP events) */
+} hms_solve_result;
+
+/* Fill *p with the defaults: T = 1000, R = 1, K = 1, Adam lr 1e-4, UNSAT loss,
+ * automatic schedule, graphs on, no time limit, seed 0, null stream. */
+void hms_solve_params_default(hms_solve_params* p);
+
+/*
+ * Algorithm 1 (Section 4 "The Solving Process"), R restarts at once.
+ * Initial best cost = m (all clauses); x^0 from `x0` or SplitMix64 U(-1,1).
+ * For t = 0..T-1: when t % K == 0 the rounded iterate is counted and kept if
+ * strictly better; the loss gradient at x_t (mask from the same iterate) takes
+ * one optimizer step.  x_T is counted too.  Synchronous: returns when `result`
+ * is filled.  Results are bitwise reproducible for equal inputs and do not
+ * depend on the schedule or on R (restart r of a solve with seed s equals the
+ * single-restart solve with seed s + r), except `final_loss` rounding.
+ * Errors: HMS_ERR_ARG, HMS_ERR_DEVICE, HMS_ERR_NOMEM; HMS_ERR_NONFINITE when
+ * the final loss is not finite (the result is still filled).
+ */
+hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* params, hms_solve_result* result);
+
+/*
+ * Measurement helper for the benchmark: initialises a solve exactly as
+ * hms_solve does with `params` (steps and eval_every ignored), then times on
+ * params->stream with HIP events `iters` back-to-back launches of the forward
+ * kernel (scores, mask, adjoint), then of the backward kernels (transposed sums
+ * and fused optimizer step), then of whole steps.  Outputs are the average
+ * milliseconds per launch (any may be NULL).  The relaxed state keeps moving
+ * during the measurement; nothing is returned from it.
+ */
+hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* params, int32_t iters,
+                            double* fwd_ms, double* bwd_ms, double* step_ms);
+
+/*
+ * Count the clauses an assignment leaves unsatisfied (Section 4 "Unsatisfiable
+ * Cores", with the rounding a_i in {0,1}).  `assignment`: HOST n bytes, nonzero
+ * = true.  *unsat receives the count.  Synchronises `stream`.
+ */
+hms_status hms_evaluate(const hms_cnf* cnf, const uint8_t* assignment, int64_t* unsat, void* stream);
+
+/*
+ * One evaluation of the relaxed objective at R points (the parity entry point):
+ * x (DEVICE [n][R]) -> loss[R] (HOST, may be NULL), gradient dL/dx into grad
+ * (DEVICE [n][R], may be NULL), unsatisfied count of round(x) into unsat[R]
+ * (HOST, may be NULL).  loss_mode as in hms_solve_params.  Synchronises
+ * `stream` when a host output is requested.
+ */
+hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t restarts, int32_t loss_mode,
+                            double* loss, float* grad, int64_t* unsat, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* hms_last_error(void);
+
+/* Library version string. */
+const char* hms_version(void);
+
+/*
+ * Host-only view of an instance plan, for tests of the layouts (no device
+ * needed).  Builds the plan of the CNF as hms_load_cnf would and copies out
+ * the counters and arrays.  The arrays are owned by the view and released by
+ * hms_plan_view_free.
+ */
+typedef struct {
+    int32_t n, m, mk, c_tiles, n_act, n_heavy, seg_rows, seg_tiles, v_tiles, n_empty, n_taut;
+    int32_t tile_rows, seg_len;      /* rows per tile (64), entries per segment */
+    int64_t nnz, c_ent_len, v_ent_len;
+    const uint32_t* c_tile;          /* [c_tiles][4]: base, len, nreal, flags */
+    const uint32_t* c_ent;           /* [c_ent_len] new variable | sign << 31 */
+    const int32_t* c_row_orig;       /* [c_tiles * 64] original clause or -1 */
+    const uint32_t* v_tile;          /* [v_tiles][4] */
+    const uint32_t* v_ent;           /* [v_ent_len] clause row | sign << 31 */
+    const int32_t* seg_first;        /* [n_heavy + 1] */
+    const int32_t* seg_row;          /* [seg_rows] */
+    const int32_t* var_old;          /* [n] new -> original */
+    void* priv;
+} hms_plan_view;
+
+hms_status hms_plan_view_build(int32_t n_vars, const int32_t* lits, int64_t n_lits, hms_plan_view* out);
+void hms_plan_view_free(hms_plan_view* view);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIPMSAT_H */

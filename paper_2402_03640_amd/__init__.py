@@ -1,0 +1,13 @@
+"""hipmsat: the gradient-based MaxSAT solve loop of Hosny & Reda (arXiv 2402.03640)
+as hand-written HIP kernels for MI355X (gfx950), behind a C ABI.
+
+The Python names mirror the C entry points of ``include/hipmsat.h``:
+``load_cnf``, ``load_cnf_dimacs``, ``solve``, ``evaluate``, ``eval_relaxed``.
+"""
+from ._lib import (ADAM, LOSS_ALL, LOSS_UNSAT, SCHEDULES, SGD, Cnf, HipMsatError, Plan,
+                   SolveOutput, eval_relaxed, evaluate, lib, load_cnf, load_cnf_dimacs, solve,
+                   time_kernels, version)
+
+__all__ = ["ADAM", "SGD", "LOSS_UNSAT", "LOSS_ALL", "SCHEDULES", "Cnf", "HipMsatError", "Plan",
+           "SolveOutput", "eval_relaxed", "evaluate", "lib", "load_cnf", "load_cnf_dimacs",
+           "solve", "time_kernels", "version"]

@@ -1,0 +1,329 @@
+"""ctypes binding of ``libhipmsat.so`` (declared in ``include/hipmsat.h``).
+
+Argument marshalling only: every step of the solve loop runs in the HIP
+library.  PyTorch provides device tensors and the current stream.  Loading
+fails loudly when the built library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhipmsat.so")
+
+HMS_OK = 0
+ERRORS = {
+    -1: "HMS_ERR_ARG", -2: "HMS_ERR_PARSE", -3: "HMS_ERR_LITERAL_RANGE", -4: "HMS_ERR_DEVICE",
+    -5: "HMS_ERR_NOMEM", -6: "HMS_ERR_NONFINITE", -7: "HMS_ERR_CANCELLED", -8: "HMS_ERR_IO",
+    -9: "HMS_ERR_TOO_LARGE",
+}
+ADAM, SGD = 0, 1
+LOSS_UNSAT, LOSS_ALL = 0, 1
+
+# kernel schedules: id -> (lanes per row P, restarts per lane V)
+SCHEDULES = {1: (1, 1), 2: (2, 1), 3: (4, 1), 4: (8, 1), 5: (16, 1), 6: (32, 1), 7: (64, 1),
+             8: (16, 4), 9: (32, 2), 10: (64, 2), 11: (64, 4)}
+
+
+class HipMsatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class CnfInfo(C.Structure):
+    _fields_ = [("n_vars", C.c_int32), ("n_clauses", C.c_int32), ("n_lits", C.c_int64),
+                ("nnz", C.c_int64), ("n_empty", C.c_int32), ("n_taut", C.c_int32),
+                ("n_active", C.c_int32), ("n_heavy", C.c_int32), ("struct_bytes", C.c_int64),
+                ("state_bytes_r1", C.c_int64)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("restarts", C.c_int32), ("eval_every", C.c_int32),
+                ("optimizer", C.c_int32), ("seed", C.c_uint64), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("loss_mode", C.c_int32), ("schedule", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32), ("time_limit_s", C.c_double), ("x0", C.c_void_p),
+                ("stream", C.c_void_p)]
+
+
+class SolveResult(C.Structure):
+    _fields_ = [("best_cost", C.c_int64), ("best_restart", C.c_int32), ("best_step", C.c_int32),
+                ("steps_done", C.c_int32), ("schedule", C.c_int32), ("final_loss", C.c_double),
+                ("best_assignment", C.c_void_p), ("restart_best", C.c_void_p),
+                ("restart_step", C.c_void_p), ("restart_loss", C.c_void_p),
+                ("x_final", C.c_void_p), ("device_ms", C.c_double)]
+
+
+class PlanView(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("mk", C.c_int32), ("c_tiles", C.c_int32),
+                ("n_act", C.c_int32), ("n_heavy", C.c_int32), ("seg_rows", C.c_int32),
+                ("seg_tiles", C.c_int32), ("v_tiles", C.c_int32), ("n_empty", C.c_int32),
+                ("n_taut", C.c_int32), ("tile_rows", C.c_int32), ("seg_len", C.c_int32),
+                ("nnz", C.c_int64), ("c_ent_len", C.c_int64), ("v_ent_len", C.c_int64),
+                ("c_tile", C.c_void_p), ("c_ent", C.c_void_p), ("c_row_orig", C.c_void_p),
+                ("v_tile", C.c_void_p), ("v_ent", C.c_void_p), ("seg_first", C.c_void_p),
+                ("seg_row", C.c_void_p), ("var_old", C.c_void_p), ("priv", C.c_void_p)]
+
+
+EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_cnf",
+           "hms_solve_params_default", "hms_solve", "hms_evaluate", "hms_eval_relaxed",
+           "hms_last_error", "hms_version", "hms_plan_view_build", "hms_plan_view_free",
+           "hms_time_kernels"]
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_03640_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    L.hms_load_cnf.argtypes = [I32, P, I64, P, C.POINTER(P)]
+    L.hms_load_cnf_dimacs.argtypes = [C.c_char_p, P, C.POINTER(P)]
+    L.hms_cnf_info_get.argtypes = [P, C.POINTER(CnfInfo)]
+    L.hms_free_cnf.argtypes = [P]
+    L.hms_free_cnf.restype = None
+    L.hms_solve_params_default.argtypes = [C.POINTER(SolveParams)]
+    L.hms_solve_params_default.restype = None
+    L.hms_solve.argtypes = [P, C.POINTER(SolveParams), C.POINTER(SolveResult)]
+    L.hms_evaluate.argtypes = [P, P, P, P]
+    L.hms_time_kernels.argtypes = [P, C.POINTER(SolveParams), I32, P, P, P]
+    L.hms_eval_relaxed.argtypes = [P, P, I32, I32, P, P, P, P]
+    L.hms_last_error.argtypes = []
+    L.hms_last_error.restype = C.c_char_p
+    L.hms_version.argtypes = []
+    L.hms_version.restype = C.c_char_p
+    L.hms_plan_view_build.argtypes = [I32, P, I64, C.POINTER(PlanView)]
+    L.hms_plan_view_free.argtypes = [C.POINTER(PlanView)]
+    L.hms_plan_view_free.restype = None
+    for name in ("hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_solve",
+                 "hms_evaluate", "hms_eval_relaxed", "hms_plan_view_build", "hms_time_kernels"):
+        getattr(L, name).restype = I32
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != HMS_OK:
+        raise HipMsatError(rc, lib().hms_last_error().decode())
+
+
+def _stream_ptr(stream):
+    """hipStream_t of a torch stream (default: torch's current stream)."""
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _lits(lits) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(lits, dtype=np.int32))
+
+
+class Cnf:
+    """A loaded instance (owns its device structure)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+        info = CnfInfo()
+        _check(lib().hms_cnf_info_get(self._h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in CnfInfo._fields_}
+        self.n = info.n_vars
+        self.m = info.n_clauses
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().hms_free_cnf(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+def load_cnf(n_vars: int, lits, stream=None) -> Cnf:
+    """Load a DIMACS-style flat literal array (clauses ended by 0)."""
+    a = _lits(lits)
+    h = C.c_void_p()
+    _check(lib().hms_load_cnf(int(n_vars), a.ctypes.data_as(C.c_void_p), a.size,
+                              _stream_ptr(stream), C.byref(h)))
+    return Cnf(h)
+
+
+def load_cnf_dimacs(path: str, stream=None) -> Cnf:
+    h = C.c_void_p()
+    _check(lib().hms_load_cnf_dimacs(os.fsencode(path), _stream_ptr(stream), C.byref(h)))
+    return Cnf(h)
+
+
+@dataclass
+class SolveOutput:
+    best_cost: int
+    best_restart: int
+    best_step: int
+    steps_done: int
+    schedule: int
+    final_loss: float
+    device_ms: float
+    best_assignment: np.ndarray
+    restart_best: np.ndarray
+    restart_step: np.ndarray
+    restart_loss: np.ndarray
+    x_final: object = field(default=None)
+
+
+def _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2, eps, loss_mode,
+            schedule, use_graph, time_limit_s, x0, stream):
+    R = int(restarts)
+    p = SolveParams()
+    lib().hms_solve_params_default(C.byref(p))
+    p.steps, p.restarts, p.eval_every, p.optimizer = int(steps), R, int(eval_every), int(optimizer)
+    p.seed = int(seed) & (2 ** 64 - 1)
+    p.lr, p.beta1, p.beta2, p.eps = lr, beta1, beta2, eps
+    p.loss_mode, p.schedule, p.use_graph = int(loss_mode), int(schedule), int(bool(use_graph))
+    p.time_limit_s = float(time_limit_s)
+    if x0 is not None:
+        import torch
+        assert x0.is_cuda and x0.dtype == torch.float32 and x0.is_contiguous()
+        assert tuple(x0.shape) in ((cnf.n, R),) or (R == 1 and tuple(x0.shape) == (cnf.n,))
+        p.x0 = x0.data_ptr()
+    p.stream = _stream_ptr(stream)
+    return p
+
+
+def time_kernels(cnf: Cnf, restarts: int = 1, iters: int = 50, seed: int = 0, optimizer: int = ADAM,
+                 lr: float = 1e-4, loss_mode: int = LOSS_UNSAT, schedule: int = 0, stream=None):
+    """Average device ms per launch of the forward kernel, the backward kernels
+    and a whole step (HIP events on the launch stream)."""
+    p = _params(cnf, 1, restarts, 1, seed, optimizer, lr, 0.9, 0.999, 1e-8, loss_mode, schedule,
+                False, 0.0, None, stream)
+    f, b, st = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().hms_time_kernels(cnf.handle, C.byref(p), int(iters), C.byref(f), C.byref(b),
+                                  C.byref(st)))
+    return f.value, b.value, st.value
+
+
+def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, seed: int = 0,
+          optimizer: int = ADAM, lr: float = 1e-4, beta1: float = 0.9, beta2: float = 0.999,
+          eps: float = 1e-8, loss_mode: int = LOSS_UNSAT, schedule: int = 0, use_graph: bool = True,
+          time_limit_s: float = 0.0, x0=None, want_x: bool = False, stream=None) -> SolveOutput:
+    """Algorithm 1 over ``restarts`` relaxed points (see ``hms_solve``)."""
+    R = int(restarts)
+    p = _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2, eps, loss_mode,
+                schedule, use_graph, time_limit_s, x0, stream)
+    res = SolveResult()
+    ba = np.zeros(max(cnf.n, 1), dtype=np.uint8)
+    rb = np.zeros(R, dtype=np.int64)
+    rs = np.zeros(R, dtype=np.int32)
+    rl = np.zeros(R, dtype=np.float64)
+    res.best_assignment = ba.ctypes.data
+    res.restart_best = rb.ctypes.data
+    res.restart_step = rs.ctypes.data
+    res.restart_loss = rl.ctypes.data
+    xf = None
+    if want_x:
+        import torch
+        xf = torch.empty((cnf.n, R), dtype=torch.float32, device="cuda")
+        res.x_final = xf.data_ptr()
+    rc = lib().hms_solve(cnf.handle, C.byref(p), C.byref(res))
+    if rc != HMS_OK and rc != -6:
+        _check(rc)
+    out = SolveOutput(res.best_cost, res.best_restart, res.best_step, res.steps_done, res.schedule,
+                      res.final_loss, res.device_ms, ba[:cnf.n].copy(), rb, rs, rl, xf)
+    if rc == -6:
+        err = HipMsatError(rc, lib().hms_last_error().decode())
+        err.result = out
+        raise err
+    return out
+
+
+def evaluate(cnf: Cnf, assignment, stream=None) -> int:
+    """Unsatisfied clauses of a 0/1 assignment (host array of n entries)."""
+    a = np.ascontiguousarray(np.asarray(assignment) != 0, dtype=np.uint8)
+    assert a.shape == (cnf.n,)
+    out = C.c_int64()
+    _check(lib().hms_evaluate(cnf.handle, a.ctypes.data_as(C.c_void_p), C.byref(out),
+                              _stream_ptr(stream)))
+    return int(out.value)
+
+
+def eval_relaxed(cnf: Cnf, x, loss_mode: int = LOSS_UNSAT, want_grad: bool = True, grad_out=None,
+                 stream=None):
+    """Loss, gradient and unsat count at relaxed points x (cuda float32 [n][R]).
+
+    Returns (loss: float64[R], grad: torch [n][R] or None, unsat: int64[R])."""
+    import torch
+    assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+    X = x if x.dim() == 2 else x.view(-1, 1)
+    assert X.shape[0] == cnf.n
+    R = X.shape[1]
+    loss = np.zeros(R, dtype=np.float64)
+    unsat = np.zeros(R, dtype=np.int64)
+    g = None
+    if want_grad:
+        g = grad_out if grad_out is not None else torch.empty_like(X)
+    _check(lib().hms_eval_relaxed(cnf.handle, C.c_void_p(X.data_ptr()), R, int(loss_mode),
+                                  loss.ctypes.data_as(C.c_void_p),
+                                  C.c_void_p(g.data_ptr()) if g is not None else None,
+                                  unsat.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
+    return loss, g, unsat
+
+
+def version() -> str:
+    return lib().hms_version().decode()
+
+
+class Plan:
+    """Host-only copy of an instance plan (tests of the layouts; no device)."""
+
+    def __init__(self, n_vars: int, lits):
+        a = _lits(lits)
+        v = PlanView()
+        _check(lib().hms_plan_view_build(int(n_vars), a.ctypes.data_as(C.c_void_p), a.size,
+                                         C.byref(v)))
+        try:
+            for k, _ in PlanView._fields_:
+                if k not in ("c_tile", "c_ent", "c_row_orig", "v_tile", "v_ent", "seg_first",
+                             "seg_row", "var_old", "priv"):
+                    setattr(self, k, getattr(v, k))
+
+            def arr(ptr, count, dt):
+                if count == 0 or not ptr:
+                    return np.zeros(0, dtype=dt)
+                buf = (C.c_char * (count * np.dtype(dt).itemsize)).from_address(ptr)
+                return np.frombuffer(buf, dtype=dt).copy()
+
+            self.c_tile = arr(v.c_tile, v.c_tiles * 4, np.uint32).reshape(-1, 4)
+            self.c_ent = arr(v.c_ent, v.c_ent_len, np.uint32)
+            self.c_row_orig = arr(v.c_row_orig, v.c_tiles * v.tile_rows, np.int32)
+            self.v_tile = arr(v.v_tile, v.v_tiles * 4, np.uint32).reshape(-1, 4)
+            self.v_ent = arr(v.v_ent, v.v_ent_len, np.uint32)
+            self.seg_first = arr(v.seg_first, v.n_heavy + 1 if v.n_heavy else 0, np.int32)
+            self.seg_row = arr(v.seg_row, v.seg_rows, np.int32)
+            self.var_old = arr(v.var_old, v.n, np.int32)
+        finally:
+            lib().hms_plan_view_free(C.byref(v))

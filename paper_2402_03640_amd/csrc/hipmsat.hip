@@ -1,0 +1,782 @@
+// C ABI of the solve loop: instance loading, Algorithm 1 driver, evaluation.
+// Host code; the kernels are in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hipmsat.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+struct hms_cnf {
+    hms::HostPlan plan;
+    int device = -1;
+    void* arena = nullptr;
+    hms::TileDesc* c_tile = nullptr;
+    uint32_t* c_ent = nullptr;
+    hms::TileDesc* v_tile = nullptr;
+    uint32_t* v_ent = nullptr;
+    int32_t* seg_first = nullptr;
+    int32_t* seg_row = nullptr;
+    int32_t* var_old = nullptr;
+    int64_t struct_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+hms_status fail(hms_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPTRY(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? HMS_ERR_NOMEM : HMS_ERR_DEVICE,                \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+// Bump layout of one device allocation (256-byte aligned pieces).
+struct Layout {
+    size_t off = 0;
+    size_t add(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+hms_status current_gfx950(int& dev) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return fail(HMS_ERR_DEVICE, "no HIP device available");
+    HIPTRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPTRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(HMS_ERR_DEVICE, std::string("device is ") + prop.gcnArchName + ", this library targets gfx950");
+    return HMS_OK;
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Stream-ordered scratch arena, released on scope exit.
+struct Arena {
+    char* base = nullptr;
+    hipStream_t s = nullptr;
+    ~Arena() {
+        if (base) (void)hipFreeAsync(base, s);
+    }
+    template <typename T>
+    T* at(size_t off) const {
+        return reinterpret_cast<T*>(base + off);
+    }
+};
+
+int auto_schedule(int32_t R) {
+    if (R <= 1) return 1;
+    if (R <= 2) return 2;
+    if (R <= 4) return 3;
+    if (R <= 8) return 4;
+    if (R <= 16) return 5;
+    if (R <= 32) return 6;
+    return 7;
+}
+
+struct Shape {
+    int sched, P, V, U, chunks, RG;
+    int64_t fwd_units, bwd_units, n_tc;
+    int fwd_blocks, bwd_blocks;
+};
+
+hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, Shape& sh) {
+    if (req < 0 || req > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
+    sh.sched = req == 0 ? auto_schedule(R) : req;
+    sh.P = hms::kSchedules[sh.sched].P;
+    sh.V = hms::kSchedules[sh.sched].V;
+    if (R % sh.V != 0) return fail(HMS_ERR_ARG, "schedule vector width does not divide the restart count");
+    sh.U = hms::units_per_row_chunk(sh.P);
+    sh.chunks = hms::kTile / sh.U;
+    sh.RG = (R + sh.P * sh.V - 1) / (sh.P * sh.V);
+    sh.n_tc = (int64_t)P.c_tiles * sh.chunks;
+    sh.fwd_units = sh.n_tc * sh.RG;
+    sh.bwd_units = (int64_t)P.v_tiles * sh.chunks * sh.RG;
+    if (sh.fwd_units >= INT32_MAX / 2 || sh.bwd_units >= INT32_MAX / 2)
+        return fail(HMS_ERR_TOO_LARGE, "too many work units");
+    sh.fwd_blocks = (int)((sh.fwd_units + 3) / 4);
+    sh.bwd_blocks = (int)((sh.bwd_units + 3) / 4);
+    return HMS_OK;
+}
+
+// Device buffers of one solve / evaluation.
+struct State {
+    float *x, *m, *v, *t, *a, *g;
+    double* seg_part;
+    int32_t* cnt_part;
+    double* loss_part;
+    uint8_t* best_a;
+    int64_t *best, *cur_count;
+    int32_t *best_step, *improved;
+    double* cur_loss;
+    hms::StepState* st;
+    uint8_t* out_assign;
+};
+
+size_t layout_state(const hms::HostPlan& P, const Shape& sh, int32_t R, bool moments, bool grad, bool best,
+                    Layout& L, size_t off[16]) {
+    const size_t nR = (size_t)(P.n + 1) * R;
+    off[0] = L.add(nR * 4);                                        // x
+    off[1] = moments ? L.add(nR * 4) : 0;                          // m
+    off[2] = moments ? L.add(nR * 4) : 0;                          // v
+    off[3] = L.add(nR * 4);                                        // t
+    off[4] = L.add((size_t)P.a_rows() * R * 4);                    // a
+    off[5] = grad ? L.add(nR * 4) : 0;                             // g
+    off[6] = L.add((size_t)std::max(P.seg_rows, 1) * R * 8);       // seg_part
+    off[7] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 4); // cnt_part
+    off[8] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 8); // loss_part
+    off[9] = best ? L.add((size_t)std::max(P.n, 1) * R) : 0;       // best_a
+    off[10] = L.add((size_t)R * 8);                                // best
+    off[11] = L.add((size_t)R * 8);                                // cur_count
+    off[12] = L.add((size_t)R * 4);                                // best_step
+    off[13] = L.add((size_t)R * 4);                                // improved
+    off[14] = L.add((size_t)R * 8);                                // cur_loss
+    off[15] = L.add(256 + (size_t)std::max(P.n, 1));                  // st, then out_assign at +256
+    return L.off;
+}
+
+State bind_state(const Arena& A, const size_t off[16], bool moments, bool grad, bool best) {
+    State S{};
+    S.x = A.at<float>(off[0]);
+    S.m = moments ? A.at<float>(off[1]) : nullptr;
+    S.v = moments ? A.at<float>(off[2]) : nullptr;
+    S.t = A.at<float>(off[3]);
+    S.a = A.at<float>(off[4]);
+    S.g = grad ? A.at<float>(off[5]) : nullptr;
+    S.seg_part = A.at<double>(off[6]);
+    S.cnt_part = A.at<int32_t>(off[7]);
+    S.loss_part = A.at<double>(off[8]);
+    S.best_a = best ? A.at<uint8_t>(off[9]) : nullptr;
+    S.best = A.at<int64_t>(off[10]);
+    S.cur_count = A.at<int64_t>(off[11]);
+    S.best_step = A.at<int32_t>(off[12]);
+    S.improved = A.at<int32_t>(off[13]);
+    S.cur_loss = A.at<double>(off[14]);
+    S.st = A.at<hms::StepState>(off[15]);
+    S.out_assign = A.at<uint8_t>(off[15] + 256);
+    return S;
+}
+
+struct Launch {
+    hms::FwdArgs fa;
+    hms::BwdArgs ba;
+    hms::ReduceArgs ra;
+    Shape sh;
+    int opt;
+};
+
+Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int32_t R, int opt, int loss_mode,
+                   float lr, float b1, float b2, float eps) {
+    const hms::HostPlan& P = C->plan;
+    Launch L{};
+    L.sh = sh;
+    L.opt = opt;
+    hms::FwdArgs& f = L.fa;
+    f.tiles = C->c_tile;
+    f.ent = C->c_ent;
+    f.ntiles = P.c_tiles;
+    f.chunks = sh.chunks;
+    f.U = sh.U;
+    f.RG = sh.RG;
+    f.R = R;
+    f.all_mode = loss_mode == HMS_LOSS_ALL;
+    f.t = S.t;
+    f.a = S.a;
+    f.two_over_m = P.m > 0 ? (float)(2.0 / (double)P.m) : 0.0f;
+    f.cnt_part = S.cnt_part;
+    f.loss_part = S.loss_part;
+    f.st = S.st;
+    f.lr = lr;
+    f.b1 = b1;
+    f.b2 = b2;
+    hms::BwdArgs& b = L.ba;
+    b.tiles = C->v_tile;
+    b.ent = C->v_ent;
+    b.ntiles = P.v_tiles;
+    b.seg_tiles = P.seg_tiles;
+    b.chunks = sh.chunks;
+    b.U = sh.U;
+    b.RG = sh.RG;
+    b.R = R;
+    b.n_heavy = P.n_heavy;
+    b.n_act = P.n_act;
+    b.eval = 0;
+    b.a = S.a;
+    b.seg_part = S.seg_part;
+    b.x = S.x;
+    b.m = S.m;
+    b.v = S.v;
+    b.t = S.t;
+    b.g_out = S.g;
+    b.best_a = S.best_a;
+    b.improved = S.improved;
+    b.st = S.st;
+    b.lr = lr;
+    b.b1 = b1;
+    b.b2 = b2;
+    b.eps = eps;
+    b.omb1 = 1.0f - b1;
+    b.omb2 = 1.0f - b2;
+    b.seg_first = C->seg_first;
+    b.seg_row = C->seg_row;
+    hms::ReduceArgs& r = L.ra;
+    r.cnt_part = S.cnt_part;
+    r.loss_part = S.loss_part;
+    r.n_units = (int32_t)sh.n_tc;
+    r.R = R;
+    r.track = 1;
+    r.n_empty = P.m_empty;
+    r.inv_m = P.m > 0 ? 1.0 / (double)P.m : 0.0;
+    r.cur_count = S.cur_count;
+    r.cur_loss = S.cur_loss;
+    r.best = S.best;
+    r.best_step = S.best_step;
+    r.improved = S.improved;
+    r.st = S.st;
+    return L;
+}
+
+// One step of Algorithm 1 on stream s.
+hipError_t enqueue_step(const Launch& L, bool eval, hipStream_t s) {
+    hipError_t e = hms::launch_fwd(L.sh.sched, eval, L.fa, L.sh.fwd_blocks, s);
+    if (e != hipSuccess) return e;
+    if (eval) {
+        e = hms::launch_reduce(L.ra, s);
+        if (e != hipSuccess) return e;
+    }
+    hms::BwdArgs b = L.ba;
+    b.eval = eval ? 1 : 0;
+    e = hms::launch_bwd(L.sh.sched, L.opt, b, L.sh.bwd_blocks, s);
+    if (e != hipSuccess) return e;
+    return hms::launch_combine(L.opt, b, s);
+}
+
+hms_status check_cnf(const hms_cnf* C) {
+    if (!C) return fail(HMS_ERR_ARG, "null instance handle");
+    return HMS_OK;
+}
+
+template <typename T>
+hms_status upload(const std::vector<T>& h, T* d, hipStream_t s) {
+    if (h.empty()) return HMS_OK;
+    HIPTRY(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return HMS_OK;
+}
+
+hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
+    int dev = -1;
+    hms_status st = current_gfx950(dev);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hms_cnf* C = new (std::nothrow) hms_cnf();
+    if (!C) return fail(HMS_ERR_NOMEM, "host allocation failed");
+    C->plan = std::move(plan);
+    C->device = dev;
+    const hms::HostPlan& P = C->plan;
+    Layout L;
+    size_t o_ct = L.add(P.c_tile.size() * sizeof(hms::TileDesc));
+    size_t o_ce = L.add(P.c_ent.size() * 4);
+    size_t o_vt = L.add(P.v_tile.size() * sizeof(hms::TileDesc));
+    size_t o_ve = L.add(P.v_ent.size() * 4);
+    size_t o_sf = L.add(P.seg_first.size() * 4);
+    size_t o_sr = L.add(P.seg_row.size() * 4);
+    size_t o_vo = L.add(P.var_old.size() * 4);
+    void* base = nullptr;
+    hipError_t e = hipMalloc(&base, std::max<size_t>(L.off, 256));
+    if (e != hipSuccess) {
+        delete C;
+        return fail(e == hipErrorOutOfMemory ? HMS_ERR_NOMEM : HMS_ERR_DEVICE,
+                    std::string("hipMalloc of the instance structure: ") + hipGetErrorString(e));
+    }
+    char* b = (char*)base;
+    C->arena = base;
+    C->c_tile = (hms::TileDesc*)(b + o_ct);
+    C->c_ent = (uint32_t*)(b + o_ce);
+    C->v_tile = (hms::TileDesc*)(b + o_vt);
+    C->v_ent = (uint32_t*)(b + o_ve);
+    C->seg_first = (int32_t*)(b + o_sf);
+    C->seg_row = (int32_t*)(b + o_sr);
+    C->var_old = (int32_t*)(b + o_vo);
+    C->struct_bytes = (int64_t)L.off;
+    hms_status r = HMS_OK;
+    if (!r) r = upload(P.c_tile, C->c_tile, s);
+    if (!r) r = upload(P.c_ent, C->c_ent, s);
+    if (!r) r = upload(P.v_tile, C->v_tile, s);
+    if (!r) r = upload(P.v_ent, C->v_ent, s);
+    if (!r) r = upload(P.seg_first, C->seg_first, s);
+    if (!r) r = upload(P.seg_row, C->seg_row, s);
+    if (!r) r = upload(P.var_old, C->var_old, s);
+    if (!r) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) r = fail(HMS_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    if (r) {
+        hms_free_cnf(C);
+        return r;
+    }
+    *out = C;
+    return HMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hms_last_error(void) { return g_err.c_str(); }
+
+const char* hms_version(void) { return "hipmsat 0.1 (gfx950)"; }
+
+hms_status hms_load_cnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, void* stream, hms_cnf** out) {
+    g_err.clear();
+    if (!out) return fail(HMS_ERR_ARG, "null output pointer");
+    *out = nullptr;
+    hms::HostPlan plan;
+    std::string err;
+    int32_t rc = hms::build_plan(n_vars, lits, n_lits, plan, err);
+    if (rc) return fail(rc, err);
+    return load_plan(std::move(plan), stream, out);
+}
+
+hms_status hms_load_cnf_dimacs(const char* path, void* stream, hms_cnf** out) {
+    g_err.clear();
+    if (!out || !path) return fail(HMS_ERR_ARG, "null argument");
+    *out = nullptr;
+    int32_t n = 0;
+    std::vector<int32_t> lits;
+    std::string err;
+    int32_t rc = hms::read_dimacs(path, n, lits, err);
+    if (rc) return fail(rc, err);
+    return hms_load_cnf(n, lits.data(), (int64_t)lits.size(), stream, out);
+}
+
+void hms_free_cnf(hms_cnf* cnf) {
+    if (!cnf) return;
+    if (cnf->arena) {
+        DeviceGuard g(cnf->device);
+        (void)hipFree(cnf->arena);
+    }
+    delete cnf;
+}
+
+hms_status hms_cnf_info_get(const hms_cnf* cnf, hms_cnf_info* out) {
+    g_err.clear();
+    if (check_cnf(cnf) || !out) return fail(HMS_ERR_ARG, "null argument");
+    const hms::HostPlan& P = cnf->plan;
+    out->n_vars = P.n;
+    out->n_clauses = P.m;
+    out->n_lits = P.lits_in;
+    out->nnz = P.nnz;
+    out->n_empty = P.m_empty;
+    out->n_taut = P.m_taut;
+    out->n_active = P.n_act;
+    out->n_heavy = P.n_heavy;
+    out->struct_bytes = cnf->struct_bytes;
+    // x, m, v, t, best bytes, a, heavy partials per restart
+    out->state_bytes_r1 = (int64_t)(P.n + 1) * 16 + P.n + (int64_t)P.a_rows() * 4 + (int64_t)P.seg_rows * 8;
+    return HMS_OK;
+}
+
+void hms_solve_params_default(hms_solve_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->steps = 1000;
+    p->restarts = 1;
+    p->eval_every = 1;
+    p->optimizer = HMS_ADAM;
+    p->seed = 0;
+    p->lr = 1e-4f;
+    p->beta1 = 0.9f;
+    p->beta2 = 0.999f;
+    p->eps = 1e-8f;
+    p->loss_mode = HMS_LOSS_UNSAT;
+    p->schedule = 0;
+    p->use_graph = 1;
+    p->time_limit_s = 0.0;
+    p->x0 = nullptr;
+    p->stream = nullptr;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validated set-up shared by hms_solve and hms_time_kernels: state arena,
+// initial point, launch arguments.
+struct SolveSetup {
+    Arena A;
+    State S{};
+    Shape sh{};
+    Launch L{};
+};
+
+hms_status setup_solve(const hms_cnf* cnf, const hms_solve_params* p, SolveSetup& Z) {
+    if (check_cnf(cnf) || !p) return fail(HMS_ERR_ARG, "null argument");
+    const int32_t R = p->restarts, T = p->steps, K = p->eval_every;
+    if (R < 1 || T < 0 || K < 1) return fail(HMS_ERR_ARG, "restarts >= 1, steps >= 0 and eval_every >= 1 required");
+    if (p->optimizer != HMS_ADAM && p->optimizer != HMS_SGD) return fail(HMS_ERR_ARG, "unknown optimizer");
+    if (p->loss_mode != HMS_LOSS_UNSAT && p->loss_mode != HMS_LOSS_ALL) return fail(HMS_ERR_ARG, "unknown loss mode");
+    if (!std::isfinite(p->lr) || !std::isfinite(p->beta1) || !std::isfinite(p->beta2) || !std::isfinite(p->eps))
+        return fail(HMS_ERR_ARG, "non-finite optimizer parameter");
+    const hms::HostPlan& P = cnf->plan;
+    if ((int64_t)(P.n + 1) * R > ((int64_t)1 << 40)) return fail(HMS_ERR_TOO_LARGE, "state too large");
+    hipStream_t s = (hipStream_t)p->stream;
+    hms_status rc = make_shape(P, R, p->schedule, Z.sh);
+    if (rc) return rc;
+    const bool adam = p->optimizer == HMS_ADAM;
+    Layout lay;
+    size_t off[16];
+    layout_state(P, Z.sh, R, adam, false, true, lay, off);
+    Z.A.s = s;
+    HIPTRY(hipMallocAsync((void**)&Z.A.base, lay.off, s));
+    Z.S = bind_state(Z.A, off, adam, false, true);
+    const State& S = Z.S;
+    hms::InitArgs ia{};
+    ia.n = P.n;
+    ia.R = R;
+    ia.a_zero_row = P.a_zero_row();
+    ia.m = P.m;
+    ia.var_old = cnf->var_old;
+    ia.x0 = p->x0;
+    ia.assign0 = nullptr;
+    ia.seed = p->seed;
+    ia.x = S.x;
+    ia.t = S.t;
+    ia.mm = S.m;
+    ia.vv = S.v;
+    ia.a = S.a;
+    ia.best_a = S.best_a;
+    ia.best = S.best;
+    ia.best_step = S.best_step;
+    ia.improved = S.improved;
+    ia.st = S.st;
+    HIPTRY(hms::launch_init(ia, s));
+    Z.L = make_launch(cnf, Z.sh, S, R, adam ? hms::kAdam : hms::kSgd, p->loss_mode, p->lr, p->beta1, p->beta2,
+                      p->eps);
+    return HMS_OK;
+}
+
+struct Events {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~Events() {
+        for (auto x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_result* res) {
+    g_err.clear();
+    if (check_cnf(cnf) || !p || !res) return fail(HMS_ERR_ARG, "null argument");
+    DeviceGuard dg(cnf->device);
+    SolveSetup Z;
+    hms_status rc0 = setup_solve(cnf, p, Z);
+    if (rc0) return rc0;
+    const hms::HostPlan& P = cnf->plan;
+    const int32_t R = p->restarts, T = p->steps, K = p->eval_every;
+    hipStream_t s = (hipStream_t)p->stream;
+    const Shape& sh = Z.sh;
+    const State& S = Z.S;
+    const Launch& L = Z.L;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    HIPTRY(hipEventCreate(&ev0));
+    HIPTRY(hipEventCreate(&ev1));
+    struct EvFree {
+        hipEvent_t a, b;
+        ~EvFree() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } evf{ev0, ev1};
+    HIPTRY(hipEventRecord(ev0, s));
+
+    const auto t_host0 = std::chrono::steady_clock::now();
+    auto over_time = [&]() {
+        if (p->time_limit_s <= 0) return false;
+        double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_host0).count();
+        return el >= p->time_limit_s;
+    };
+
+    int32_t done = 0;
+    // body of B steps (a multiple of K, starting at a multiple of K)
+    const int32_t B = K * std::max(1, (32 + K - 1) / K);
+    if (p->use_graph && T >= 2 * B) {
+        hipStream_t cs = nullptr;
+        HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        struct GFree {
+            hipStream_t user;
+            hipStream_t& s;
+            hipGraph_t& g;
+            hipGraphExec_t& x;
+            ~GFree() {
+                (void)hipStreamSynchronize(user);  // replays may still be running
+                if (x) (void)hipGraphExecDestroy(x);
+                if (g) (void)hipGraphDestroy(g);
+                if (s) (void)hipStreamDestroy(s);
+            }
+        } gf{s, cs, graph, exec};
+        HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        hipError_t ce = hipSuccess;
+        for (int32_t i = 0; i < B && ce == hipSuccess; ++i) ce = enqueue_step(L, i % K == 0, cs);
+        hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (ce != hipSuccess) return fail(HMS_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(ce));
+        if (ee != hipSuccess) return fail(HMS_ERR_DEVICE, std::string("end capture: ") + hipGetErrorString(ee));
+        HIPTRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        const int32_t reps = T / B;
+        for (int32_t r = 0; r < reps; ++r) {
+            HIPTRY(hipGraphLaunch(exec, s));
+            done += B;
+            if (p->time_limit_s > 0) {
+                HIPTRY(hipStreamSynchronize(s));
+                if (over_time()) break;
+            }
+        }
+    }
+    while (done < T) {
+        HIPTRY(enqueue_step(L, done % K == 0, s));
+        ++done;
+        if (p->time_limit_s > 0 && done % K == 0) {
+            HIPTRY(hipStreamSynchronize(s));
+            if (over_time()) break;
+        }
+    }
+    // x_T is always counted
+    HIPTRY(hms::launch_fwd(sh.sched, true, L.fa, sh.fwd_blocks, s));
+    HIPTRY(hms::launch_reduce(L.ra, s));
+    HIPTRY(hms::launch_snapshot(P.n_act, R, S.x, S.improved, S.best_a, s));
+    HIPTRY(hipEventRecord(ev1, s));
+
+    std::vector<int64_t> best(R);
+    std::vector<int32_t> bstep(R);
+    std::vector<double> closs(R);
+    HIPTRY(hipMemcpyAsync(best.data(), S.best, R * 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(bstep.data(), S.best_step, R * 4, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(closs.data(), S.cur_loss, R * 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    HIPTRY(hipEventElapsedTime(&ms, ev0, ev1));
+    int32_t br = 0;
+    for (int32_t r = 1; r < R; ++r)
+        if (best[r] < best[br]) br = r;
+    if (res->best_assignment && P.n > 0) {
+        HIPTRY(hms::launch_extract(P.n, R, br, cnf->var_old, S.best_a, S.out_assign, s));
+        HIPTRY(hipMemcpyAsync(res->best_assignment, S.out_assign, P.n, hipMemcpyDeviceToHost, s));
+    }
+    if (res->x_final) HIPTRY(hms::launch_scatter(P.n, P.n, R, cnf->var_old, S.x, res->x_final, s));
+    HIPTRY(hipStreamSynchronize(s));
+    res->best_cost = best[br];
+    res->best_restart = br;
+    res->best_step = bstep[br];
+    res->steps_done = done;
+    res->schedule = sh.sched;
+    res->final_loss = closs[br];
+    res->device_ms = ms;
+    if (res->restart_best) std::memcpy(res->restart_best, best.data(), R * 8);
+    if (res->restart_step) std::memcpy(res->restart_step, bstep.data(), R * 4);
+    if (res->restart_loss) std::memcpy(res->restart_loss, closs.data(), R * 8);
+    for (int32_t r = 0; r < R; ++r)
+        if (!std::isfinite(closs[r])) return fail(HMS_ERR_NONFINITE, "the loss at the final iterate is not finite");
+    return HMS_OK;
+}
+
+hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* p, int32_t iters, double* fwd_ms,
+                            double* bwd_ms, double* step_ms) {
+    g_err.clear();
+    if (check_cnf(cnf) || !p || iters < 1) return fail(HMS_ERR_ARG, "null argument or iters < 1");
+    DeviceGuard dg(cnf->device);
+    SolveSetup Z;
+    hms_status rc0 = setup_solve(cnf, p, Z);
+    if (rc0) return rc0;
+    hipStream_t s = (hipStream_t)p->stream;
+    const Launch& L = Z.L;
+    Events E;
+    for (auto& e : E.e) HIPTRY(hipEventCreate(&e));
+    // one warm step so every code object is resident
+    HIPTRY(enqueue_step(L, false, s));
+    HIPTRY(hipEventRecord(E.e[0], s));
+    for (int32_t i = 0; i < iters; ++i) HIPTRY(hms::launch_fwd(Z.sh.sched, false, L.fa, Z.sh.fwd_blocks, s));
+    HIPTRY(hipEventRecord(E.e[1], s));
+    for (int32_t i = 0; i < iters; ++i) {
+        HIPTRY(hms::launch_bwd(Z.sh.sched, L.opt, L.ba, Z.sh.bwd_blocks, s));
+        HIPTRY(hms::launch_combine(L.opt, L.ba, s));
+    }
+    HIPTRY(hipEventRecord(E.e[2], s));
+    for (int32_t i = 0; i < iters; ++i) HIPTRY(enqueue_step(L, false, s));
+    HIPTRY(hipEventRecord(E.e[3], s));
+    HIPTRY(hipStreamSynchronize(s));
+    float a = 0, b = 0, c = 0;
+    HIPTRY(hipEventElapsedTime(&a, E.e[0], E.e[1]));
+    HIPTRY(hipEventElapsedTime(&b, E.e[1], E.e[2]));
+    HIPTRY(hipEventElapsedTime(&c, E.e[2], E.e[3]));
+    if (fwd_ms) *fwd_ms = a / iters;
+    if (bwd_ms) *bwd_ms = b / iters;
+    if (step_ms) *step_ms = c / iters;
+    return HMS_OK;
+}
+
+hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t R, int32_t loss_mode, double* loss,
+                            float* grad, int64_t* unsat, void* stream) {
+    g_err.clear();
+    if (check_cnf(cnf) || (!x && cnf->plan.n > 0)) return fail(HMS_ERR_ARG, "null argument");
+    if (R < 1) return fail(HMS_ERR_ARG, "restarts >= 1 required");
+    if (loss_mode != HMS_LOSS_UNSAT && loss_mode != HMS_LOSS_ALL) return fail(HMS_ERR_ARG, "unknown loss mode");
+    const hms::HostPlan& P = cnf->plan;
+    DeviceGuard dg(cnf->device);
+    hipStream_t s = (hipStream_t)stream;
+    Shape sh;
+    hms_status rc = make_shape(P, R, 0, sh);
+    if (rc) return rc;
+    const bool want_g = grad != nullptr;
+    Layout lay;
+    size_t off[16];
+    layout_state(P, sh, R, false, want_g, false, lay, off);
+    Arena A;
+    A.s = s;
+    HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+    State S = bind_state(A, off, false, want_g, false);
+    hms::InitArgs ia{};
+    ia.n = P.n;
+    ia.R = R;
+    ia.a_zero_row = P.a_zero_row();
+    ia.m = P.m;
+    ia.var_old = cnf->var_old;
+    ia.x0 = x;
+    ia.x = S.x;
+    ia.t = S.t;
+    ia.a = S.a;
+    ia.st = S.st;
+    HIPTRY(hms::launch_init(ia, s));
+    Launch L = make_launch(cnf, sh, S, R, hms::kGrad, loss_mode, 0.f, 0.9f, 0.999f, 1e-8f);
+    L.ra.track = 0;
+    HIPTRY(hms::launch_fwd(sh.sched, true, L.fa, sh.fwd_blocks, s));
+    HIPTRY(hms::launch_reduce(L.ra, s));
+    if (want_g) {
+        HIPTRY(hms::launch_bwd(sh.sched, hms::kGrad, L.ba, sh.bwd_blocks, s));
+        HIPTRY(hms::launch_combine(hms::kGrad, L.ba, s));
+        HIPTRY(hms::launch_scatter(P.n, P.n_act, R, cnf->var_old, S.g, grad, s));
+    }
+    if (loss) HIPTRY(hipMemcpyAsync(loss, S.cur_loss, R * 8, hipMemcpyDeviceToHost, s));
+    if (unsat) HIPTRY(hipMemcpyAsync(unsat, S.cur_count, R * 8, hipMemcpyDeviceToHost, s));
+    if (loss || unsat) HIPTRY(hipStreamSynchronize(s));
+    return HMS_OK;
+}
+
+hms_status hms_evaluate(const hms_cnf* cnf, const uint8_t* assignment, int64_t* unsat, void* stream) {
+    g_err.clear();
+    if (check_cnf(cnf) || !unsat || (!assignment && cnf->plan.n > 0)) return fail(HMS_ERR_ARG, "null argument");
+    const hms::HostPlan& P = cnf->plan;
+    DeviceGuard dg(cnf->device);
+    hipStream_t s = (hipStream_t)stream;
+    Shape sh;
+    hms_status rc = make_shape(P, 1, 1, sh);
+    if (rc) return rc;
+    Layout lay;
+    size_t off[16];
+    layout_state(P, sh, 1, false, false, false, lay, off);
+    const size_t o_in = lay.add((size_t)std::max(P.n, 1));
+    Arena A;
+    A.s = s;
+    HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+    State S = bind_state(A, off, false, false, false);
+    uint8_t* d_in = A.at<uint8_t>(o_in);
+    if (P.n > 0) HIPTRY(hipMemcpyAsync(d_in, assignment, P.n, hipMemcpyHostToDevice, s));
+    hms::InitArgs ia{};
+    ia.n = P.n;
+    ia.R = 1;
+    ia.a_zero_row = P.a_zero_row();
+    ia.m = P.m;
+    ia.var_old = cnf->var_old;
+    ia.assign0 = d_in;
+    ia.x = S.x;
+    ia.t = S.t;
+    ia.a = S.a;
+    ia.st = S.st;
+    HIPTRY(hms::launch_init(ia, s));
+    Launch L = make_launch(cnf, sh, S, 1, hms::kGrad, HMS_LOSS_UNSAT, 0.f, 0.9f, 0.999f, 1e-8f);
+    L.ra.track = 0;
+    HIPTRY(hms::launch_fwd(sh.sched, true, L.fa, sh.fwd_blocks, s));
+    HIPTRY(hms::launch_reduce(L.ra, s));
+    HIPTRY(hipMemcpyAsync(unsat, S.cur_count, 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    return HMS_OK;
+}
+
+// ---- host-only plan view --------------------------------------------------
+hms_status hms_plan_view_build(int32_t n_vars, const int32_t* lits, int64_t n_lits, hms_plan_view* out) {
+    g_err.clear();
+    if (!out) return fail(HMS_ERR_ARG, "null output");
+    std::memset(out, 0, sizeof(*out));
+    hms::HostPlan* P = new (std::nothrow) hms::HostPlan();
+    if (!P) return fail(HMS_ERR_NOMEM, "host allocation failed");
+    std::string err;
+    int32_t rc = hms::build_plan(n_vars, lits, n_lits, *P, err);
+    if (rc) {
+        delete P;
+        return fail(rc, err);
+    }
+    out->n = P->n;
+    out->m = P->m;
+    out->mk = P->mk;
+    out->c_tiles = P->c_tiles;
+    out->n_act = P->n_act;
+    out->n_heavy = P->n_heavy;
+    out->seg_rows = P->seg_rows;
+    out->seg_tiles = P->seg_tiles;
+    out->v_tiles = P->v_tiles;
+    out->n_empty = P->m_empty;
+    out->n_taut = P->m_taut;
+    out->tile_rows = hms::kTile;
+    out->seg_len = hms::kSeg;
+    out->nnz = P->nnz;
+    out->c_ent_len = (int64_t)P->c_ent.size();
+    out->v_ent_len = (int64_t)P->v_ent.size();
+    out->c_tile = reinterpret_cast<const uint32_t*>(P->c_tile.data());
+    out->c_ent = P->c_ent.data();
+    out->c_row_orig = P->c_row_orig.data();
+    out->v_tile = reinterpret_cast<const uint32_t*>(P->v_tile.data());
+    out->v_ent = P->v_ent.data();
+    out->seg_first = P->seg_first.data();
+    out->seg_row = P->seg_row.data();
+    out->var_old = P->var_old.data();
+    out->priv = P;
+    return HMS_OK;
+}
+
+void hms_plan_view_free(hms_plan_view* view) {
+    if (!view) return;
+    delete static_cast<hms::HostPlan*>(view->priv);
+    std::memset(view, 0, sizeof(*view));
+}
+
+}  // extern "C"

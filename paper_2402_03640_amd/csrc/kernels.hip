@@ -1,0 +1,535 @@
+// Solve-loop kernels for gfx950 (wave64).  See kernels.hpp for the layout.
+//
+// Summation order contract: the score of a clause is summed over its entries
+// in plan order, and the transposed sum of a variable row over its entries in
+// plan order, one lane per (row, restart), whatever the schedule.  Heavy rows
+// are summed per segment, and segment partials are combined by a fixed
+// 64-slot tree.  Hence x, m, v and every count are bitwise independent of the
+// schedule and of R; only the FP64 loss total depends on the schedule's unit
+// size.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace hms {
+
+const Schedule kSchedules[kNumSchedules + 1] = {
+    {0, 0},                                                   // 0: automatic
+    {1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {32, 1}, {64, 1},  // 1..7
+    {16, 4}, {32, 2}, {64, 2}, {64, 4},                       // 8..11
+};
+
+int units_per_row_chunk(int P) {
+    int W = 64 / P;
+    int U = W * 8;
+    return U > 64 ? 64 : U;
+}
+
+namespace {
+
+template <int V>
+struct VecF {
+    float v[V];
+};
+
+template <int V>
+__device__ __forceinline__ VecF<V> ldv(const float* p) {
+    VecF<V> r;
+    if constexpr (V == 1) {
+        r.v[0] = *p;
+    } else if constexpr (V == 2) {
+        float2 q = *reinterpret_cast<const float2*>(p);
+        r.v[0] = q.x;
+        r.v[1] = q.y;
+    } else {
+        float4 q = *reinterpret_cast<const float4*>(p);
+        r.v[0] = q.x;
+        r.v[1] = q.y;
+        r.v[2] = q.z;
+        r.v[3] = q.w;
+    }
+    return r;
+}
+
+template <int V>
+__device__ __forceinline__ void stv(float* p, const VecF<V>& r) {
+    if constexpr (V == 1) {
+        *p = r.v[0];
+    } else if constexpr (V == 2) {
+        *reinterpret_cast<float2*>(p) = make_float2(r.v[0], r.v[1]);
+    } else {
+        *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+    }
+}
+
+// tanh(x) carrying the rounding in its sign bit: set iff x does not round to
+// true (x <= 0, -0.0 or NaN).
+__device__ __forceinline__ float signed_tanh(float x) {
+    uint32_t b = __float_as_uint(tanhf(x)) & kIdx;
+    if (!(x > 0.0f)) b |= kSign;
+    return __uint_as_float(b);
+}
+
+// sech^2(x) = 4 e / (1 + e)^2 with e = exp(-2|x|): no cancellation for large |x|.
+__device__ __forceinline__ float sech2f(float x) {
+    float e = expf(-2.0f * fabsf(x));
+    float d = 1.0f + e;
+    return (4.0f * e) / (d * d);
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output k of the stream seeded `seed`.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Forward: scores, unsat mask, adjoint a_j = (2/m) mu_j f_j, unit partials.
+// ---------------------------------------------------------------------------
+template <int P, int V, bool EVAL>
+__global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
+    constexpr int W = 64 / P;
+    const int lane = threadIdx.x & 63;
+    const int s = lane / P;
+    const int q = lane % P;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && A.st != nullptr) {
+        double tt = (double)A.st->t + 1.0;
+        double bc1 = 1.0 - pow(A.b1, tt);
+        double bc2 = 1.0 - pow(A.b2, tt);
+        A.st->step_size = (float)(A.lr / bc1);
+        A.st->inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+    }
+    const int nunits = A.ntiles * A.chunks * A.RG;
+    const int passes = A.U / W;
+    for (int u = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); u < nunits;
+         u += gridDim.x * 4) {
+        const int rg = u % A.RG;
+        const int tc = u / A.RG;
+        const int tile = tc / A.chunks;
+        const int chunk = tc % A.chunks;
+        const TileDesc d = A.tiles[tile];
+        const int r0 = rg * (P * V) + q * V;
+        const bool ract = r0 < A.R;
+        const bool taut = (d.flags & 1u) != 0;
+        int cnt[V];
+        double los[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            cnt[k] = 0;
+            los[k] = 0.0;
+        }
+        for (int pass = 0; pass < passes; ++pass) {
+            const int rowin = chunk * A.U + pass * W + s;
+            const bool real = rowin < (int)d.nreal;
+            const uint32_t* e = A.ent + d.base + rowin;
+            float f[V];
+            uint32_t allf[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                f[k] = 0.0f;
+                allf[k] = ~0u;
+            }
+            if (ract) {
+                if (d.len <= 16) {
+#pragma unroll 4
+                    for (uint32_t c = 0; c < d.len; ++c) {
+                        const uint32_t en = e[(size_t)c * kTile];
+                        const VecF<V> tv = ldv<V>(A.t + (size_t)(en & kIdx) * A.R + r0);
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            const uint32_t b = __float_as_uint(tv.v[k]) ^ (en & kSign);
+                            f[k] = f[k] + __uint_as_float(b);
+                            allf[k] &= b;
+                        }
+                    }
+                } else {
+                    double fd[V];
+#pragma unroll
+                    for (int k = 0; k < V; ++k) fd[k] = 0.0;
+#pragma unroll 4
+                    for (uint32_t c = 0; c < d.len; ++c) {
+                        const uint32_t en = e[(size_t)c * kTile];
+                        const VecF<V> tv = ldv<V>(A.t + (size_t)(en & kIdx) * A.R + r0);
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            const uint32_t b = __float_as_uint(tv.v[k]) ^ (en & kSign);
+                            fd[k] = fd[k] + (double)__uint_as_float(b);
+                            allf[k] &= b;
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < V; ++k) f[k] = (float)fd[k];
+                }
+                VecF<V> av;
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const bool unsat = real && !taut && (allf[k] >> 31) != 0;
+                    const bool mu = real && (A.all_mode ? true : unsat);
+                    av.v[k] = mu ? f[k] * A.two_over_m : 0.0f;
+                    if (EVAL) {
+                        cnt[k] += unsat ? 1 : 0;
+                        los[k] += mu ? (double)f[k] * (double)f[k] : 0.0;
+                    }
+                }
+                stv<V>(A.a + (size_t)(tile * kTile + rowin) * A.R + r0, av);
+            }
+        }
+        if (EVAL) {
+#pragma unroll
+            for (int off = P; off < 64; off <<= 1) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    cnt[k] += __shfl_xor(cnt[k], off);
+                    los[k] += __shfl_xor(los[k], off);
+                }
+            }
+            if (s == 0 && ract) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    A.cnt_part[(size_t)tc * A.R + r0 + k] = cnt[k];
+                    A.loss_part[(size_t)tc * A.R + r0 + k] = los[k];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue of a variable: g = sech^2(x) G, then the optimizer step (or the
+// gradient itself), t = signed tanh of the new x.
+// ---------------------------------------------------------------------------
+template <int V, int OPT>
+__device__ __forceinline__ void var_epilogue(const BwdArgs& A, int var, int r0, const double (&G)[V]) {
+    const size_t base = (size_t)var * A.R + r0;
+    VecF<V> xv = ldv<V>(A.x + base);
+    if (A.eval) {
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if (A.improved[r0 + k]) A.best_a[base + k] = xv.v[k] > 0.0f ? 1 : 0;
+    }
+    float g[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) g[k] = (float)((double)sech2f(xv.v[k]) * G[k]);
+    if constexpr (OPT == kGrad) {
+        VecF<V> gv;
+#pragma unroll
+        for (int k = 0; k < V; ++k) gv.v[k] = g[k];
+        stv<V>(A.g_out + base, gv);
+        return;
+    } else if constexpr (OPT == kSgd) {
+        VecF<V> tv;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            xv.v[k] = xv.v[k] - A.lr * g[k];
+            tv.v[k] = signed_tanh(xv.v[k]);
+        }
+        stv<V>(A.x + base, xv);
+        stv<V>(A.t + base, tv);
+    } else {
+        const float ss = A.st->step_size;
+        const float ib2 = A.st->inv_sqrt_bc2;
+        VecF<V> mv = ldv<V>(A.m + base);
+        VecF<V> vv = ldv<V>(A.v + base);
+        VecF<V> tv;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            mv.v[k] = A.b1 * mv.v[k] + A.omb1 * g[k];
+            vv.v[k] = A.b2 * vv.v[k] + A.omb2 * (g[k] * g[k]);
+            const float denom = sqrtf(vv.v[k]) * ib2 + A.eps;
+            xv.v[k] = xv.v[k] - (ss * mv.v[k]) / denom;
+            tv.v[k] = signed_tanh(xv.v[k]);
+        }
+        stv<V>(A.m + base, mv);
+        stv<V>(A.v + base, vv);
+        stv<V>(A.x + base, xv);
+        stv<V>(A.t + base, tv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: transposed sums G = sum_j W_ij a_j over variable rows (atomic-free;
+// each (row, restart) summed by one lane in FP64), fused epilogue for whole
+// rows, partials for heavy-row segments.
+// ---------------------------------------------------------------------------
+template <int P, int V, int OPT>
+__global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
+    constexpr int W = 64 / P;
+    const int lane = threadIdx.x & 63;
+    const int s = lane / P;
+    const int q = lane % P;
+    if (OPT != kGrad && blockIdx.x == 0 && threadIdx.x == 0) A.st->t += 1;
+    const int nunits = A.ntiles * A.chunks * A.RG;
+    const int passes = A.U / W;
+    for (int u = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); u < nunits;
+         u += gridDim.x * 4) {
+        const int rg = u % A.RG;
+        const int tc = u / A.RG;
+        const int tile = tc / A.chunks;
+        const int chunk = tc % A.chunks;
+        const TileDesc d = A.tiles[tile];
+        const int r0 = rg * (P * V) + q * V;
+        const bool ract = r0 < A.R;
+        const bool segtile = tile < A.seg_tiles;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int rowin = chunk * A.U + pass * W + s;
+            if (!ract || rowin >= (int)d.nreal) continue;
+            const uint32_t* e = A.ent + d.base + rowin;
+            double G[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) G[k] = 0.0;
+#pragma unroll 4
+            for (uint32_t c = 0; c < d.len; ++c) {
+                const uint32_t en = e[(size_t)c * kTile];
+                const VecF<V> av = ldv<V>(A.a + (size_t)(en & kIdx) * A.R + r0);
+#pragma unroll
+                for (int k = 0; k < V; ++k)
+                    G[k] = G[k] + (double)__uint_as_float(__float_as_uint(av.v[k]) ^ (en & kSign));
+            }
+            const int row = tile * kTile + rowin;
+            if (segtile) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) A.seg_part[(size_t)row * A.R + r0 + k] = G[k];
+            } else {
+                const int var = A.n_heavy + (row - A.seg_tiles * kTile);
+                var_epilogue<V, OPT>(A, var, r0, G);
+            }
+        }
+    }
+}
+
+// Heavy variables: combine segment partials.  One wavefront per (variable,
+// restart); slot q sums segments q, q+64, ... in order, then a fixed tree.
+template <int OPT>
+__global__ __launch_bounds__(256) void k_combine(BwdArgs A) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= A.n_heavy * A.R) return;
+    const int h = w / A.R;
+    const int r = w % A.R;
+    double u = 0.0;
+    for (int p = A.seg_first[h] + lane; p < A.seg_first[h + 1]; p += 64)
+        u = u + A.seg_part[(size_t)A.seg_row[p] * A.R + r];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) u = u + __shfl_down(u, off);
+    if (lane == 0) {
+        double G[1] = {u};
+        var_epilogue<1, OPT>(A, h, r, G);
+    }
+}
+
+// Sum the unit partials of each restart in a fixed order; track the best.
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs A) {
+    __shared__ int64_t sc[256];
+    __shared__ double sl[256];
+    const int r = blockIdx.x;
+    const int tid = threadIdx.x;
+    int64_t c = 0;
+    double l = 0.0;
+    for (int u = tid; u < A.n_units; u += 256) {
+        c += A.cnt_part[(size_t)u * A.R + r];
+        l = l + A.loss_part[(size_t)u * A.R + r];
+    }
+    sc[tid] = c;
+    sl[tid] = l;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if (tid < s) {
+            sc[tid] += sc[tid + s];
+            sl[tid] = sl[tid] + sl[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int64_t count = sc[0] + A.n_empty;
+        A.cur_count[r] = count;
+        A.cur_loss[r] = sl[0] * A.inv_m;
+        if (A.track) {
+            if (count < A.best[r]) {
+                A.best[r] = count;
+                A.best_step[r] = A.st->t;
+                A.improved[r] = 1;
+            } else {
+                A.improved[r] = 0;
+            }
+        }
+    }
+}
+
+// State initialisation: x^0 (caller values, an assignment, or SplitMix64),
+// t = signed tanh(x), zero moments, the dummy rows, best = m.
+__global__ __launch_bounds__(256) void k_init(InitArgs A) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)A.n * A.R;
+    if (idx < total) {
+        const int32_t i = (int32_t)(idx / A.R);
+        const int32_t r = (int32_t)(idx % A.R);
+        const int32_t o = A.var_old[i];
+        float x;
+        if (A.x0 != nullptr) {
+            x = A.x0[(size_t)o * A.R + r];
+        } else if (A.assign0 != nullptr) {
+            x = A.assign0[o] ? 1.0f : -1.0f;
+        } else {
+            const uint64_t z = splitmix64(A.seed + (uint64_t)r, (uint64_t)o + 1);
+            x = 2.0f * ((float)(z >> 40) * (1.0f / 16777216.0f)) - 1.0f;
+        }
+        A.x[idx] = x;
+        A.t[idx] = signed_tanh(x);
+        if (A.mm != nullptr) {
+            A.mm[idx] = 0.0f;
+            A.vv[idx] = 0.0f;
+        }
+        if (A.best_a != nullptr) A.best_a[idx] = x > 0.0f ? 1 : 0;
+    }
+    if (idx < A.R) {
+        A.t[(size_t)A.n * A.R + idx] = -0.0f;
+        A.a[(size_t)A.a_zero_row * A.R + idx] = 0.0f;
+        if (A.best != nullptr) {
+            A.best[idx] = A.m;
+            A.best_step[idx] = -1;
+            A.improved[idx] = 0;
+        }
+    }
+    if (idx == 0 && A.st != nullptr) {
+        A.st->t = 0;
+        A.st->step_size = 0.0f;
+        A.st->inv_sqrt_bc2 = 1.0f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_snapshot(int32_t n_act, int32_t R, const float* x,
+                                                   const int32_t* improved, uint8_t* best_a) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n_act * R) return;
+    const int32_t r = (int32_t)(idx % R);
+    if (improved[r]) best_a[idx] = x[idx] > 0.0f ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_extract(int32_t n, int32_t R, int32_t r, const int32_t* var_old,
+                                                  const uint8_t* best_a, uint8_t* out) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    out[var_old[i]] = best_a[(size_t)i * R + r];
+}
+
+__global__ __launch_bounds__(256) void k_scatter(int32_t n, int32_t n_act, int32_t R, const int32_t* var_old,
+                                                  const float* src, float* dst) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n * R) return;
+    const int32_t i = (int32_t)(idx / R);
+    const int32_t r = (int32_t)(idx % R);
+    dst[(size_t)var_old[i] * R + r] = i < n_act ? src[idx] : 0.0f;
+}
+
+template <int P, int V>
+hipError_t fwd_for(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
+    if (eval)
+        hipLaunchKernelGGL((k_fwd<P, V, true>), dim3(blocks), dim3(256), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_fwd<P, V, false>), dim3(blocks), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+template <int P, int V>
+hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
+    if (opt == kAdam)
+        hipLaunchKernelGGL((k_bwd<P, V, kAdam>), dim3(blocks), dim3(256), 0, s, A);
+    else if (opt == kSgd)
+        hipLaunchKernelGGL((k_bwd<P, V, kSgd>), dim3(blocks), dim3(256), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_bwd<P, V, kGrad>), dim3(blocks), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define HMS_SCHED_SWITCH(FN, ...)                        \
+    switch (sched) {                                     \
+        case 1: return FN<1, 1>(__VA_ARGS__);            \
+        case 2: return FN<2, 1>(__VA_ARGS__);            \
+        case 3: return FN<4, 1>(__VA_ARGS__);            \
+        case 4: return FN<8, 1>(__VA_ARGS__);            \
+        case 5: return FN<16, 1>(__VA_ARGS__);           \
+        case 6: return FN<32, 1>(__VA_ARGS__);           \
+        case 7: return FN<64, 1>(__VA_ARGS__);           \
+        case 8: return FN<16, 4>(__VA_ARGS__);           \
+        case 9: return FN<32, 2>(__VA_ARGS__);           \
+        case 10: return FN<64, 2>(__VA_ARGS__);          \
+        case 11: return FN<64, 4>(__VA_ARGS__);          \
+        default: return hipErrorInvalidValue;            \
+    }
+
+hipError_t launch_fwd(int sched, bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    HMS_SCHED_SWITCH(fwd_for, eval, A, blocks, s)
+}
+
+hipError_t launch_bwd(int sched, int opt, const BwdArgs& A, int blocks, hipStream_t s) {
+    if (blocks <= 0) {
+        // still advance the step counter
+        if (opt != kGrad) {
+            hipLaunchKernelGGL((k_bwd<1, 1, kAdam>), dim3(1), dim3(256), 0, s, A);
+            return hipGetLastError();
+        }
+        return hipSuccess;
+    }
+    HMS_SCHED_SWITCH(bwd_for, opt, A, blocks, s)
+}
+
+hipError_t launch_combine(int opt, const BwdArgs& A, hipStream_t s) {
+    const int64_t waves = (int64_t)A.n_heavy * A.R;
+    if (waves == 0) return hipSuccess;
+    const int blocks = (int)((waves + 3) / 4);
+    if (opt == kAdam)
+        hipLaunchKernelGGL((k_combine<kAdam>), dim3(blocks), dim3(256), 0, s, A);
+    else if (opt == kSgd)
+        hipLaunchKernelGGL((k_combine<kSgd>), dim3(blocks), dim3(256), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_combine<kGrad>), dim3(blocks), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceArgs& A, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(A.R), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const InitArgs& A, hipStream_t s) {
+    int64_t total = (int64_t)A.n * A.R;
+    if (total < A.R) total = A.R;
+    if (total < 1) total = 1;
+    const int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(int32_t n_act, int32_t R, const float* x, const int32_t* improved,
+                           uint8_t* best_a, hipStream_t s) {
+    const int64_t total = (int64_t)n_act * R;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_snapshot, dim3((int)((total + 255) / 256)), dim3(256), 0, s, n_act, R, x, improved,
+                       best_a);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract(int32_t n, int32_t R, int32_t r, const int32_t* var_old, const uint8_t* best_a,
+                          uint8_t* out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_extract, dim3((n + 255) / 256), dim3(256), 0, s, n, R, r, var_old, best_a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(int32_t n, int32_t n_act, int32_t R, const int32_t* var_old, const float* src,
+                          float* dst, hipStream_t s) {
+    const int64_t total = (int64_t)n * R;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3((int)((total + 255) / 256)), dim3(256), 0, s, n, n_act, R, var_old,
+                       src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace hms

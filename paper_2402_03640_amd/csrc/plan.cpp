@@ -1,0 +1,328 @@
+// Instance plan builder.
+//
+// W (Section 4, network architecture) holds +1 where a variable appears in a
+// clause, -1 where its negation does.  It is never stored dense: the plan keeps
+// its nonzeros twice, clause-major for the scores f = tanh(x) W and
+// variable-major for the transposed product W a of the backward pass.
+//
+// Canonical form of a clause: repeated literals count once; a variable that
+// appears with both signs gets entry +1 - 1 = 0 and makes the clause always
+// satisfied; an empty clause is always unsatisfied with score 0.
+//
+// Layout choices (all functions of the instance only, so every kernel schedule
+// sums in the same order):
+//  * clause rows sorted by (tautology flag, length descending), cut into tiles
+//    of 64 rows stored column-major, padded to the tile's longest row;
+//  * variables renumbered by degree descending; variables with more than kSeg
+//    entries are split into segments of kSeg consecutive entries whose
+//    partial sums are combined afterwards;
+//  * variable rows (segments first, then whole light variables) tiled the same
+//    way; the entries of a row follow increasing clause-row index.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cerrno>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+
+namespace hms {
+
+namespace {
+
+struct Row {
+    int64_t off;   // into the flat entry buffer
+    int32_t len;
+    int32_t orig;  // original clause index
+    bool taut;
+};
+
+// Lay out rows (already ordered) into 64-row column-major tiles.
+template <typename LenFn, typename EntFn>
+int32_t tile_rows(int32_t nrows, LenFn len_of, EntFn ent_of,
+                  uint32_t pad, uint32_t flags, std::vector<TileDesc>& tiles,
+                  std::vector<uint32_t>& ent, std::string& err) {
+    for (int32_t t0 = 0; t0 < nrows; t0 += kTile) {
+        int32_t nreal = std::min<int32_t>(kTile, nrows - t0);
+        uint32_t len = 0;
+        for (int32_t q = 0; q < nreal; ++q) len = std::max<uint32_t>(len, (uint32_t)len_of(t0 + q));
+        uint64_t base = ent.size();
+        if (base + (uint64_t)len * kTile > 0xffffffffull) {
+            err = "instance too large: more than 2^32 padded entries";
+            return kErrTooLarge;
+        }
+        TileDesc d{(uint32_t)base, len, (uint32_t)nreal, flags};
+        tiles.push_back(d);
+        ent.resize(base + (size_t)len * kTile, pad);
+        for (int32_t q = 0; q < nreal; ++q) {
+            int32_t L = len_of(t0 + q);
+            for (int32_t c = 0; c < L; ++c) ent[base + (size_t)c * kTile + q] = ent_of(t0 + q, c);
+        }
+    }
+    return kOk;
+}
+
+}  // namespace
+
+int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, std::string& err) {
+    P = HostPlan{};
+    if (n < 0 || nlits < 0 || (nlits > 0 && lits == nullptr)) {
+        err = "bad arguments: n_vars < 0, n_lits < 0 or null literal array";
+        return kErrArg;
+    }
+    if (n >= (int32_t)kIdx) {
+        err = "too many variables";
+        return kErrTooLarge;
+    }
+    if (nlits > 0 && lits[nlits - 1] != 0) {
+        err = "last clause is not terminated by 0";
+        return kErrParse;
+    }
+    int64_t m = 0;
+    for (int64_t p = 0; p < nlits; ++p) {
+        int32_t l = lits[p];
+        if (l == 0) {
+            ++m;
+            continue;
+        }
+        if (l == INT32_MIN || std::abs(l) > n) {
+            char buf[128];
+            snprintf(buf, sizeof buf, "literal %d at position %lld is outside 1..%d", l, (long long)p, n);
+            err = buf;
+            return kErrRange;
+        }
+        P.lits_in++;
+    }
+    if (m >= (int64_t)kIdx) {
+        err = "too many clauses";
+        return kErrTooLarge;
+    }
+    P.n = n;
+    P.m = (int32_t)m;
+
+    // ---- canonical clauses: W entries in order of first appearance --------
+    std::vector<uint32_t> flat;          // original variable | sign
+    flat.reserve((size_t)P.lits_in);
+    std::vector<Row> rows;
+    rows.reserve((size_t)m);
+    std::vector<int64_t> stamp((size_t)n + 1, -1);
+    std::vector<uint8_t> seen((size_t)n + 1, 0);   // bit0 positive, bit1 negative, bit2 emitted
+    int64_t start = 0;
+    int32_t j = 0;
+    for (int64_t p = 0; p < nlits; ++p) {
+        if (lits[p] != 0) continue;
+        bool taut = false;
+        for (int64_t q = start; q < p; ++q) {
+            int32_t v = std::abs(lits[q]) - 1;
+            if (stamp[v] != j) {
+                stamp[v] = j;
+                seen[v] = 0;
+            }
+            seen[v] |= lits[q] > 0 ? 1 : 2;
+        }
+        int64_t off = (int64_t)flat.size();
+        for (int64_t q = start; q < p; ++q) {
+            int32_t v = std::abs(lits[q]) - 1;
+            if (seen[v] & 4) continue;
+            seen[v] |= 4;
+            if ((seen[v] & 3) == 3) {
+                taut = true;
+                continue;
+            }
+            flat.push_back((uint32_t)v | ((seen[v] & 2) ? kSign : 0u));
+        }
+        int32_t len = (int32_t)((int64_t)flat.size() - off);
+        if (p == start) {
+            P.m_empty++;
+        } else if (taut) {
+            P.m_taut++;
+            if (len == 0) P.m_taut_dropped++;
+        }
+        if (len > 0) rows.push_back(Row{off, len, j, taut});
+        ++j;
+        start = p + 1;
+    }
+    P.nnz = (int64_t)flat.size();
+
+    // ---- variable order: degree descending, ties by original index -------
+    std::vector<int32_t> deg_orig((size_t)n, 0);
+    for (uint32_t e : flat) deg_orig[e & kIdx]++;
+    P.var_old.resize((size_t)n);
+    std::iota(P.var_old.begin(), P.var_old.end(), 0);
+    std::stable_sort(P.var_old.begin(), P.var_old.end(), [&](int32_t a, int32_t b) {
+        return deg_orig[a] > deg_orig[b];
+    });
+    P.var_new.assign((size_t)n, 0);
+    P.degree.assign((size_t)n, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        P.var_new[P.var_old[i]] = i;
+        P.degree[i] = deg_orig[P.var_old[i]];
+        if (P.degree[i] > 0) P.n_act = i + 1;
+        if (P.degree[i] > kSeg) P.n_heavy = i + 1;
+    }
+
+    // ---- clause rows: plain rows by length desc, then tautological rows ---
+    std::stable_sort(rows.begin(), rows.end(), [](const Row& a, const Row& b) {
+        if (a.taut != b.taut) return !a.taut;
+        return a.len > b.len;
+    });
+    int32_t n_plain = 0;
+    while (n_plain < (int32_t)rows.size() && !rows[n_plain].taut) ++n_plain;
+    int32_t n_tr = (int32_t)rows.size() - n_plain;
+    const uint32_t cpad = (uint32_t)n;  // dummy variable whose relaxed value stays -0.0
+    int32_t rc;
+    rc = tile_rows(n_plain, [&](int32_t r) { return rows[r].len; },
+                   [&](int32_t r, int32_t c) {
+                       uint32_t e = flat[rows[r].off + c];
+                       return (uint32_t)P.var_new[e & kIdx] | (e & kSign);
+                   },
+                   cpad, 0u, P.c_tile, P.c_ent, err);
+    if (rc) return rc;
+    rc = tile_rows(n_tr, [&](int32_t r) { return rows[n_plain + r].len; },
+                   [&](int32_t r, int32_t c) {
+                       uint32_t e = flat[rows[n_plain + r].off + c];
+                       return (uint32_t)P.var_new[e & kIdx] | (e & kSign);
+                   },
+                   cpad, 1u, P.c_tile, P.c_ent, err);
+    if (rc) return rc;
+    P.c_tiles = (int32_t)P.c_tile.size();
+    if ((int64_t)P.c_tiles * kTile + 1 >= (int64_t)kIdx) {
+        err = "too many clause rows";
+        return kErrTooLarge;
+    }
+    P.mk = (int32_t)rows.size();
+    // kernel row index of each canonical row
+    std::vector<int32_t> krow(rows.size());
+    P.c_row_orig.assign((size_t)P.c_tiles * kTile, -1);
+    {
+        int32_t tp = (n_plain + kTile - 1) / kTile;
+        for (int32_t r = 0; r < n_plain; ++r) krow[r] = r;
+        for (int32_t r = 0; r < n_tr; ++r) krow[n_plain + r] = tp * kTile + r;
+        for (size_t r = 0; r < rows.size(); ++r) P.c_row_orig[krow[r]] = rows[r].orig;
+    }
+
+    // ---- variable-major occurrence lists (clause rows ascending) ----------
+    std::vector<int64_t> voff((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) voff[i + 1] = voff[i] + P.degree[i];
+    std::vector<uint32_t> occ((size_t)P.nnz);
+    {
+        std::vector<int64_t> fill(voff.begin(), voff.end() - 1);
+        // visit rows in increasing kernel-row order
+        std::vector<int32_t> by_krow(rows.size());
+        std::iota(by_krow.begin(), by_krow.end(), 0);
+        std::sort(by_krow.begin(), by_krow.end(), [&](int32_t a, int32_t b) { return krow[a] < krow[b]; });
+        for (int32_t r : by_krow) {
+            const Row& R = rows[r];
+            for (int32_t c = 0; c < R.len; ++c) {
+                uint32_t e = flat[R.off + c];
+                int32_t v = P.var_new[e & kIdx];
+                occ[fill[v]++] = (uint32_t)krow[r] | (e & kSign);
+            }
+        }
+    }
+
+    // ---- segments of heavy variables ---------------------------------------
+    struct Seg {
+        int32_t var, idx, len;
+        int64_t off;
+    };
+    std::vector<Seg> full, part;
+    P.seg_first.assign((size_t)P.n_heavy + 1, 0);
+    for (int32_t h = 0; h < P.n_heavy; ++h) {
+        int32_t d = P.degree[h];
+        int32_t ns = (d + kSeg - 1) / kSeg;
+        P.max_segs = std::max(P.max_segs, ns);
+        P.seg_first[h + 1] = P.seg_first[h] + ns;
+        for (int32_t s = 0; s < ns; ++s) {
+            int32_t L = std::min(kSeg, d - s * kSeg);
+            Seg g{h, s, L, voff[h] + (int64_t)s * kSeg};
+            (L == kSeg ? full : part).push_back(g);
+        }
+    }
+    std::stable_sort(part.begin(), part.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
+    std::vector<Seg> segs;
+    segs.reserve(full.size() + part.size());
+    segs.insert(segs.end(), full.begin(), full.end());
+    segs.insert(segs.end(), part.begin(), part.end());
+    P.seg_rows = (int32_t)segs.size();
+    P.seg_row.assign((size_t)P.seg_rows, 0);
+    for (int32_t r = 0; r < P.seg_rows; ++r) P.seg_row[P.seg_first[segs[r].var] + segs[r].idx] = r;
+    const uint32_t vpad = (uint32_t)P.a_zero_row();
+    rc = tile_rows(P.seg_rows, [&](int32_t r) { return segs[r].len; },
+                   [&](int32_t r, int32_t c) { return occ[segs[r].off + c]; }, vpad, 0u, P.v_tile,
+                   P.v_ent, err);
+    if (rc) return rc;
+    P.seg_tiles = (int32_t)P.v_tile.size();
+    int32_t n_light = P.n_act - P.n_heavy;
+    rc = tile_rows(n_light, [&](int32_t r) { return P.degree[P.n_heavy + r]; },
+                   [&](int32_t r, int32_t c) { return occ[voff[P.n_heavy + r] + c]; }, vpad, 0u,
+                   P.v_tile, P.v_ent, err);
+    if (rc) return rc;
+    P.v_tiles = (int32_t)P.v_tile.size();
+    return kOk;
+}
+
+int32_t read_dimacs(const char* path, int32_t& n, std::vector<int32_t>& lits, std::string& err) {
+    FILE* f = fopen(path, "rb");
+    if (!f) {
+        err = std::string("cannot open ") + path + ": " + strerror(errno);
+        return kErrIO;
+    }
+    n = -1;
+    int64_t m_decl = -1;
+    lits.clear();
+    char line[4096];
+    bool in_clause = false;
+    int32_t maxv = 0;
+    while (fgets(line, sizeof line, f)) {
+        char* s = line;
+        while (*s == ' ' || *s == '\t') ++s;
+        if (*s == 'c' || *s == '%' || *s == '\n' || *s == '\r' || *s == 0) continue;
+        if (*s == 'p') {
+            char fmt[16] = {0};
+            long long nv = -1, nc = -1;
+            if (sscanf(s, "p %15s %lld %lld", fmt, &nv, &nc) != 3 || strcmp(fmt, "cnf") != 0 || nv < 0 ||
+                nc < 0 || nv >= (long long)kIdx) {
+                fclose(f);
+                err = "bad problem line";
+                return kErrParse;
+            }
+            n = (int32_t)nv;
+            m_decl = nc;
+            continue;
+        }
+        // literals (a clause may span lines)
+        char* e = nullptr;
+        while (true) {
+            while (*s == ' ' || *s == '\t' || *s == '\n' || *s == '\r') ++s;
+            if (*s == 0) break;
+            errno = 0;
+            long v = strtol(s, &e, 10);
+            if (e == s || errno) {
+                fclose(f);
+                err = "bad literal token";
+                return kErrParse;
+            }
+            s = e;
+            if (v < -(long)kIdx || v > (long)kIdx) {
+                fclose(f);
+                err = "literal out of range";
+                return kErrRange;
+            }
+            lits.push_back((int32_t)v);
+            in_clause = v != 0;
+            if (v != 0) maxv = std::max<int32_t>(maxv, (int32_t)std::labs(v));
+        }
+    }
+    fclose(f);
+    (void)m_decl;
+    if (in_clause) {
+        err = "last clause is not terminated by 0";
+        return kErrParse;
+    }
+    if (n < 0) n = maxv;
+    return kOk;
+}
+
+}  // namespace hms

@@ -1,0 +1,81 @@
+// Host-side instance plan: canonical clauses and the two sparse layouts of W
+// (clause-major for the scores, variable-major for the adjoint) in the tiled
+// column-major form the kernels read.  No HIP in here.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hms {
+
+constexpr int kTile = 64;          // rows per tile; one wavefront lane per row at R = 1
+constexpr int kSeg = 256;          // longest variable row kept whole; longer rows are split
+constexpr uint32_t kSign = 0x80000000u;
+constexpr uint32_t kIdx = 0x7fffffffu;
+
+// Per-tile descriptor (16 bytes).  Entry (c, rowin) of the tile sits at
+// ent[base + c * kTile + rowin]; rows rowin >= nreal are padding.
+struct TileDesc {
+    uint32_t base;   // first entry of the tile
+    uint32_t len;    // entries per row (the tile's longest row; shorter rows are padded)
+    uint32_t nreal;  // real rows in the tile
+    uint32_t flags;  // clause side: 1 = rows hold a complementary pair (always satisfied)
+};
+
+struct HostPlan {
+    int32_t n = 0;              // variables as declared
+    int32_t m = 0;              // clauses as given (the loss divides by this)
+    int64_t lits_in = 0;        // nonzero literals as given
+    int32_t m_empty = 0;        // empty clauses: always unsatisfied, score 0
+    int32_t m_taut = 0;         // clauses holding v and not-v: always satisfied
+    int32_t m_taut_dropped = 0; // tautologies whose every entry cancelled
+    int64_t nnz = 0;            // nonzero entries of W over the kernel rows
+
+    // clause side (scores / mask / adjoint)
+    int32_t mk = 0;             // kernel clause rows
+    int32_t c_tiles = 0;
+    std::vector<TileDesc> c_tile;
+    std::vector<uint32_t> c_ent;     // new variable index | sign bit (negated literal)
+    std::vector<int32_t> c_row_orig; // [c_tiles * kTile] original clause of a row, -1 = padding
+
+    // variable side (transposed sums); rows are whole light variables or
+    // fixed-length segments of heavy variables
+    int32_t n_act = 0;          // variables with at least one nonzero entry
+    int32_t n_heavy = 0;        // variables with more than kSeg entries
+    int32_t seg_rows = 0;       // real segment rows
+    int32_t seg_tiles = 0;      // tiles holding segment rows (come first)
+    int32_t v_tiles = 0;        // all variable-side tiles
+    std::vector<TileDesc> v_tile;
+    std::vector<uint32_t> v_ent;     // clause row index | sign bit
+    std::vector<int32_t> seg_first;  // [n_heavy + 1] into seg_row
+    std::vector<int32_t> seg_row;    // segment rows of each heavy variable, in order
+    int32_t max_segs = 0;            // most segments of one variable
+
+    std::vector<int32_t> var_old;    // new index -> original (0-based)
+    std::vector<int32_t> var_new;    // original -> new index
+    std::vector<int32_t> degree;     // by new index
+
+    int32_t a_rows() const { return c_tiles * kTile + 1; }  // last row stays zero
+    int32_t a_zero_row() const { return c_tiles * kTile; }
+    int32_t light_row0() const { return seg_tiles * kTile; }
+};
+
+// Status codes shared with the C ABI.
+enum : int32_t {
+    kOk = 0,
+    kErrArg = -1,
+    kErrParse = -2,
+    kErrRange = -3,
+    kErrDevice = -4,
+    kErrNoMem = -5,
+    kErrNonFinite = -6,
+    kErrCancelled = -7,
+    kErrIO = -8,
+    kErrTooLarge = -9,
+};
+
+int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& plan, std::string& err);
+int32_t read_dimacs(const char* path, int32_t& n, std::vector<int32_t>& lits, std::string& err);
+
+}  // namespace hms

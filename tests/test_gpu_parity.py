@@ -1,0 +1,283 @@
+"""GPU parity: the HIP solve loop against the FP64 oracle, through the C ABI.
+
+Per evaluation (same FP32 x bits in): unsat counts bit-exact, loss within
+1e-5 of (1/m) sum mu F^2 and each gradient entry within 1e-5 S_i (see
+_helpers.tolerance_terms).  Trajectory-level checks are invariants: brute-force
+optimum, evaluate(best) == best, determinism across schedules, restarts and
+graph replay, and the SplitMix64 initial values.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import cnfgen
+import oracle as O
+
+from _helpers import assert_eval_parity, edge_case_cnf, w_abs_matrix
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hm = pytest.importorskip("paper_2402_03640_amd")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hm.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _x(n, R, seed, **kw):
+    return cnfgen.random_x(n, R, seed, **kw)
+
+
+def _eval_both(n, lits, x_np, mode, schedule_check=True):
+    oc = O.OracleCNF(n, lits)
+    W = w_abs_matrix(n, lits)
+    cnf = hm.load_cnf(n, lits)
+    xt = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
+    loss, g, u = hm.eval_relaxed(cnf, xt, loss_mode=mode)
+    torch.cuda.synchronize()
+    gn = g.cpu().numpy()
+    assert_eval_parity(oc, W, x_np, loss, gn, u, mode)
+    return cnf, loss, gn, u
+
+
+@pytest.mark.parametrize("mode", [hm.LOSS_UNSAT, hm.LOSS_ALL])
+@pytest.mark.parametrize("R", [1, 3, 16])
+def test_eval_edge_cases(mode, R):
+    n, lits = edge_case_cnf()
+    _say(f"edge cases n={n} R={R} mode={mode}")
+    x = _x(n, R, seed=R, lo=-3, hi=3, specials=True)
+    _eval_both(n, lits, x, mode)
+
+
+@pytest.mark.parametrize("mode", [hm.LOSS_UNSAT, hm.LOSS_ALL])
+def test_eval_worked_example(mode, golden):
+    g = golden("worked_example.txt")
+    lits = np.array(g["clauses"], np.int32)
+    x = np.array(g["x"], np.float32).reshape(2, 1)
+    cnf, loss, gn, u = _eval_both(2, lits, x, mode)
+    assert u[0] == g["unsat_count"]
+
+
+def test_eval_cfg1_shape():
+    n, m = 50, 215
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=1)
+    for R in (1, 8):
+        _say(f"cfg1 shape R={R}")
+        _eval_both(n, lits, _x(n, R, seed=10 + R), hm.LOSS_UNSAT)
+
+
+def test_eval_cfg4_all_schedules():
+    """Mixed 2/3/4-CNF n=1000 m=4200 R=16: parity, and every schedule gives the
+    bitwise same gradient and counts."""
+    n, m, R = 1000, 4200, 16
+    lits = cnfgen.mixed_kcnf(n, m, seed=4)
+    x = _x(n, R, seed=44, lo=-2, hi=2)
+    for mode in (hm.LOSS_UNSAT, hm.LOSS_ALL):
+        cnf, loss0, g0, u0 = _eval_both(n, lits, x, mode)
+    cnf = hm.load_cnf(n, lits)
+    xt = torch.from_numpy(x).cuda()
+    ref = None
+    for sched in range(1, 12):
+        res = hm.solve(cnf, steps=3, restarts=R, eval_every=1, x0=xt, schedule=sched, want_x=True)
+        xf = res.x_final.cpu().numpy()
+        cur = (res.restart_best.copy(), res.restart_step.copy(), xf)
+        _say(f"cfg4 schedule {sched}: best {res.restart_best[:4]}")
+        if ref is None:
+            ref = cur
+        else:
+            np.testing.assert_array_equal(cur[0], ref[0])
+            np.testing.assert_array_equal(cur[1], ref[1])
+            np.testing.assert_array_equal(cur[2].view(np.uint32), ref[2].view(np.uint32))
+
+
+def test_eval_cfg2_full_size():
+    n, m, R = 20000, 86000, 64
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=2)
+    x = _x(n, R, seed=22)
+    _say("cfg2 full size R=64")
+    _eval_both(n, lits, x, hm.LOSS_UNSAT)
+
+
+def test_eval_structured_heavy_rows():
+    n, m = 60000, 300000
+    lits = cnfgen.structured_cnf(n, m, seed=3)
+    cnf = hm.load_cnf(n, lits)
+    assert cnf.info["n_heavy"] > 0
+    for R in (1, 4):
+        _say(f"structured n={n} m={m} R={R} heavy={cnf.info['n_heavy']}")
+        _eval_both(n, lits, _x(n, R, seed=33 + R), hm.LOSS_UNSAT)
+    _eval_both(n, lits, _x(n, 1, seed=35), hm.LOSS_ALL)
+
+
+def test_eval_cfg3_full_size():
+    n, m = 500000, 2500000
+    lits = cnfgen.structured_cnf(n, m, seed=3)
+    _say("cfg3 full size")
+    _eval_both(n, lits, _x(n, 1, seed=333), hm.LOSS_UNSAT)
+
+
+def test_evaluate_counts_bit_exact():
+    n, lits = edge_case_cnf()
+    oc = O.OracleCNF(n, lits)
+    cnf = hm.load_cnf(n, lits)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        a = (rng.random(n) < 0.5).astype(np.uint8)
+        assert hm.evaluate(cnf, a) == oc.count(a)
+    n, m = 3000, 12900
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=9)
+    oc = O.OracleCNF(n, lits)
+    cnf = hm.load_cnf(n, lits)
+    for _ in range(5):
+        a = (rng.random(n) < 0.5).astype(np.uint8)
+        assert hm.evaluate(cnf, a) == oc.count(a)
+
+
+def test_init_matches_splitmix_oracle():
+    n, R, seed = 777, 5, 123456789
+    lits = cnfgen.uniform_kcnf(n, 3000, 3, seed=5)
+    cnf = hm.load_cnf(n, lits)
+    res = hm.solve(cnf, steps=0, restarts=R, seed=seed, want_x=True)
+    xg = res.x_final.cpu().numpy()
+    xo = O.init_x(n, R, seed)
+    np.testing.assert_array_equal(xg.view(np.uint32), xo.view(np.uint32))
+    oc = O.OracleCNF(n, lits)
+    for r in range(R):
+        assert res.restart_best[r] == oc.count((xo[:, r] > 0).astype(np.uint8))
+
+
+def test_step_parity_adam():
+    """Steps from the same x0 (|x| >= 0.05, no rounding flips within 3 steps of
+    lr 1e-4): x after each step within tolerance of the FP64 oracle."""
+    n, m, R = 400, 1720, 4
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=6)
+    rng = np.random.default_rng(6)
+    x0 = (rng.uniform(0.05, 1.0, (n, R)) * np.where(rng.random((n, R)) < 0.5, -1, 1)).astype(np.float32)
+    oc = O.OracleCNF(n, lits)
+    cnf = hm.load_cnf(n, lits)
+    xt = torch.from_numpy(x0).cuda()
+    for steps in (1, 2, 3):
+        res = hm.solve(cnf, steps=steps, restarts=R, eval_every=1, x0=xt, lr=1e-4, want_x=True)
+        xg = res.x_final.cpu().numpy().astype(np.float64)
+        ro = oc.solve(steps=steps, restarts=R, eval_every=1, x0=x0, lr=1e-4, want_x=True)
+        d_g = xg - x0
+        d_o = ro["x"] - x0
+        assert np.all(np.abs(d_g - d_o) <= 1e-5 * np.abs(d_o) * steps + 2e-7 * np.abs(x0) + 1e-12), steps
+        np.testing.assert_array_equal(res.restart_best, ro["restart_best"])
+
+
+def test_sgd_worked_example_step(golden):
+    g = golden("worked_example.txt")
+    lits = np.array(g["clauses"], np.int32)
+    cnf = hm.load_cnf(2, lits)
+    x0 = torch.tensor(np.array(g["x"], np.float32).reshape(2, 1)).cuda()
+    res = hm.solve(cnf, steps=1, restarts=1, optimizer=hm.SGD, lr=g["lr"], loss_mode=hm.LOSS_ALL,
+                   x0=x0, want_x=True)
+    x1 = res.x_final.cpu().numpy()[:, 0]
+    np.testing.assert_allclose(x1, g["x_after_one_step"], atol=0.005)
+    oc = O.OracleCNF(2, lits)
+    ro = oc.solve(steps=1, restarts=1, optimizer=O.SGD, lr=g["lr"], mode=O.ALL,
+                  x0=np.array(g["x"], np.float32), want_x=True)
+    np.testing.assert_allclose(x1, ro["x"][:, 0], rtol=1e-6)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_solve_never_beats_bruteforce(seed):
+    n = 18
+    lits = cnfgen.uniform_kcnf(n, 90, 3, seed=seed)
+    oc = O.OracleCNF(n, lits)
+    opt, _, _ = oc.bruteforce()
+    cnf = hm.load_cnf(n, lits)
+    res = hm.solve(cnf, steps=400, restarts=8, eval_every=1, seed=seed, lr=0.05)
+    _say(f"brute force seed {seed}: opt {opt} best {res.best_cost}")
+    assert res.best_cost >= opt
+    assert hm.evaluate(cnf, res.best_assignment) == res.best_cost
+    assert oc.count(res.best_assignment) == res.best_cost
+    assert res.best_cost == res.restart_best.min()
+    assert res.best_restart == int(np.argmin(res.restart_best))
+
+
+def test_plain_vs_batched_bitwise():
+    """Restart r of a batched solve with seed s equals the plain solve with
+    seed s + r, bitwise (state and best)."""
+    n, m, R, s = 2000, 8600, 8, 40
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=7)
+    cnf = hm.load_cnf(n, lits)
+    big = hm.solve(cnf, steps=120, restarts=R, eval_every=10, seed=s, want_x=True, lr=1e-2)
+    xb = big.x_final.cpu().numpy()
+    for r in range(R):
+        one = hm.solve(cnf, steps=120, restarts=1, eval_every=10, seed=s + r, want_x=True, lr=1e-2)
+        assert one.restart_best[0] == big.restart_best[r]
+        assert one.restart_step[0] == big.restart_step[r]
+        np.testing.assert_array_equal(one.x_final.cpu().numpy()[:, 0].view(np.uint32),
+                                      xb[:, r].view(np.uint32))
+
+
+def test_graph_and_direct_launch_identical():
+    n, m, R = 5000, 21500, 16
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=8)
+    cnf = hm.load_cnf(n, lits)
+    a = hm.solve(cnf, steps=150, restarts=R, eval_every=50, seed=3, use_graph=True, want_x=True)
+    b = hm.solve(cnf, steps=150, restarts=R, eval_every=50, seed=3, use_graph=False, want_x=True)
+    c = hm.solve(cnf, steps=150, restarts=R, eval_every=50, seed=3, use_graph=True, want_x=True)
+    for o in (b, c):
+        np.testing.assert_array_equal(a.restart_best, o.restart_best)
+        np.testing.assert_array_equal(a.restart_step, o.restart_step)
+        np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32),
+                                      o.x_final.cpu().numpy().view(np.uint32))
+
+
+def test_solve_best_monotone_and_consistent():
+    n, m = 3000, 12900
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=10)
+    cnf = hm.load_cnf(n, lits)
+    prev = m
+    for T in (0, 50, 100, 200):
+        res = hm.solve(cnf, steps=T, restarts=2, eval_every=10, seed=1, lr=1e-2)
+        assert res.best_cost <= prev
+        assert hm.evaluate(cnf, res.best_assignment) == res.best_cost
+        prev = res.best_cost
+
+
+def test_degenerate_instances():
+    cnf = hm.load_cnf(0, np.zeros(0, np.int32))
+    res = hm.solve(cnf, steps=5, restarts=2)
+    assert res.best_cost == 0
+    cnf = hm.load_cnf(3, np.array([0, 0, 0], np.int32))
+    res = hm.solve(cnf, steps=5, restarts=1)
+    assert res.best_cost == 3 and res.best_step == -1
+    assert hm.evaluate(cnf, np.zeros(3, np.uint8)) == 3
+    cnf = hm.load_cnf(2, np.array([1, -1, 0, 2, 0], np.int32))
+    res = hm.solve(cnf, steps=20, restarts=1, lr=0.1)
+    assert res.best_cost == 0
+    lo, g, u = hm.eval_relaxed(cnf, torch.tensor([[0.3], [-0.2]], device="cuda"))
+    assert u[0] == 1
+
+
+def test_nonfinite_x0_reported():
+    n, lits = 3, np.array([1, 2, 0, -3, 0], np.int32)
+    cnf = hm.load_cnf(n, lits)
+    x0 = torch.tensor([[float("nan")], [-0.5], [0.5]], device="cuda")
+    with pytest.raises(hm.HipMsatError) as e:
+        hm.solve(cnf, steps=3, restarts=1, x0=x0)
+    assert e.value.name == "HMS_ERR_NONFINITE"
+    assert e.value.result.best_cost >= 0
+
+
+def test_dimacs_file(tmp_path):
+    p = tmp_path / "f.cnf"
+    p.write_text("c comment\np cnf 3 3\n1 -2 0\n2 3\n 0\n-1 -3 0\n")
+    cnf = hm.load_cnf_dimacs(str(p))
+    assert cnf.n == 3 and cnf.m == 3
+    assert hm.evaluate(cnf, np.array([0, 0, 0], np.uint8)) == 1

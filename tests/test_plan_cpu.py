@@ -1,0 +1,159 @@
+"""Host-side tests of the C ABI library: it loads, exports every declared
+symbol, and builds instance plans whose two sparse layouts are exact
+transposes of the canonical W (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import cnfgen
+import paper_2402_03640_amd as hm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SIGN = np.uint32(0x80000000)
+IDX = np.uint32(0x7FFFFFFF)
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "hipmsat.h")).read()
+    declared = set(re.findall(r"\b(hms_[a-z_]+)\s*\(", header))
+    assert declared, "no declarations found"
+    L = hm.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), f"{name} is declared but not exported"
+    assert set(hm._lib.EXPORTS) == declared
+    assert hm.version().startswith("hipmsat")
+
+
+def _canonical(clauses):
+    """Canonical W entries per clause: (var0, sign) in first-appearance order."""
+    out, taut = [], []
+    for cl in clauses:
+        pos, neg, order = set(), set(), []
+        for l in cl:
+            v = abs(l) - 1
+            (pos if l > 0 else neg).add(v)
+            if v not in order:
+                order.append(v)
+        ents = [(v, -1 if v in neg else 1) for v in order if not (v in pos and v in neg)]
+        out.append(ents)
+        taut.append(any(v in pos and v in neg for v in order))
+    return out, taut
+
+
+def _decode_tiles(tiles, ent):
+    """Rows of a tiled layout: list of entry lists (padding kept) and nreal."""
+    rows = []
+    for base, ln, nreal, flags in tiles:
+        for q in range(64):
+            rows.append([int(ent[base + c * 64 + q]) for c in range(ln)])
+    return rows
+
+
+def _check_plan(n, lits):
+    clauses = cnfgen.to_clauses(lits)
+    P = hm.Plan(n, lits)
+    canon, taut = _canonical(clauses)
+    assert P.m == len(clauses)
+    assert P.n_empty == sum(1 for c in clauses if len(c) == 0)
+    assert P.n_taut == sum(taut)
+    assert P.nnz == sum(len(e) for e in canon)
+    var_old = P.var_old
+    assert sorted(var_old.tolist()) == list(range(n))
+    var_new = np.empty(n, np.int64)
+    var_new[var_old] = np.arange(n)
+    # ---- clause side: each kernel row is a canonical clause, padding inert
+    rows = _decode_tiles(P.c_tile, P.c_ent)
+    seen = set()
+    for r, orig in enumerate(P.c_row_orig.tolist()):
+        t, q = divmod(r, 64)
+        base, ln, nreal, flags = P.c_tile[t]
+        ents = rows[r]
+        if orig < 0:
+            assert q >= nreal
+            assert all(e == n for e in ents)  # dummy variable, positive sign
+            continue
+        assert q < nreal and orig not in seen
+        seen.add(orig)
+        want = [(int(var_new[v]), s) for v, s in canon[orig]]
+        got = [(e & 0x7FFFFFFF, -1 if e & 0x80000000 else 1) for e in ents if e != n]
+        assert got == want
+        assert all(e == n for e in ents[len(want):])
+        assert bool(flags & 1) == taut[orig]
+    assert seen == {j for j in range(len(clauses)) if canon[j]}
+    # lengths sorted descending within each flag class
+    # ---- variable side: exact transpose, clause rows ascending per variable
+    krow_of = {orig: r for r, orig in enumerate(P.c_row_orig.tolist()) if orig >= 0}
+    occ = [[] for _ in range(n)]
+    for r, orig in sorted((r, o) for o, r in krow_of.items()):
+        for e in rows[r]:
+            if e == n:
+                continue
+            occ[e & 0x7FFFFFFF].append(r | (e & 0x80000000))
+    deg = [len(o) for o in occ]
+    assert deg == sorted(deg, reverse=True)
+    assert P.n_act == sum(1 for d in deg if d > 0)
+    assert P.n_heavy == sum(1 for d in deg if d > P.seg_len)
+    vrows = _decode_tiles(P.v_tile, P.v_ent)
+    azero = P.c_tiles * 64
+    seg_rows_pad = P.seg_tiles * 64
+    for i in range(P.n_heavy):
+        segs = P.seg_row[P.seg_first[i]:P.seg_first[i + 1]]
+        got = []
+        for sr in segs.tolist():
+            assert sr < P.seg_rows
+            got.extend(e for e in vrows[sr] if e != azero)
+        assert got == occ[i]
+    assert sorted(P.seg_row.tolist()) == list(range(P.seg_rows))
+    for i in range(P.n_heavy, P.n_act):
+        r = seg_rows_pad + (i - P.n_heavy)
+        got = [e for e in vrows[r] if e != azero]
+        assert got == occ[i]
+        assert all(e == azero for e in vrows[r][len(got):])
+    return P
+
+
+def test_plan_small_edge_cases():
+    clauses = [[1, -2, 3], [2, 2, -3], [], [1, -1, 4], [-4, 4], [5], [-5, 1, 1, 2], [3, -1]]
+    P = _check_plan(6, cnfgen.from_clauses(clauses))
+    assert P.n_empty == 1 and P.n_taut == 2
+    assert P.n_act == 5  # variable 6 appears nowhere
+
+
+def test_plan_random_mixed():
+    _check_plan(200, cnfgen.mixed_kcnf(200, 900, seed=2))
+
+
+def test_plan_skewed_heavy_rows():
+    lits = cnfgen.structured_cnf(3000, 15000, seed=4)
+    P = _check_plan(3000, lits)
+    assert P.n_heavy > 0 and P.seg_rows > P.n_heavy
+
+
+def test_plan_empty_instance():
+    P = hm.Plan(0, np.zeros(0, np.int32))
+    assert P.m == 0 and P.c_tiles == 0 and P.v_tiles == 0
+    P = hm.Plan(3, np.array([0, 0], np.int32))
+    assert P.m == 2 and P.n_empty == 2 and P.n_act == 0
+
+
+def test_plan_errors():
+    with pytest.raises(hm.HipMsatError) as e:
+        hm.Plan(3, np.array([1, 2], np.int32))
+    assert e.value.name == "HMS_ERR_PARSE"
+    with pytest.raises(hm.HipMsatError) as e:
+        hm.Plan(3, np.array([1, -4, 0], np.int32))
+    assert e.value.name == "HMS_ERR_LITERAL_RANGE"
+    with pytest.raises(hm.HipMsatError) as e:
+        hm.Plan(-1, np.array([0], np.int32))
+    assert e.value.name == "HMS_ERR_ARG"
+
+
+def test_load_without_gpu_reports_device_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(hm.HipMsatError) as e:
+        hm.load_cnf(3, np.array([1, 2, 0], np.int32), stream=0)
+    assert e.value.name == "HMS_ERR_DEVICE"
