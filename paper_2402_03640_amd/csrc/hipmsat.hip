@@ -90,29 +90,42 @@ struct Arena {
     }
 };
 
+// Default kernel schedule for R restarts (table index into hms::kSchedules).
 int auto_schedule(int32_t R) {
     if (R <= 1) return 1;
     if (R <= 2) return 2;
     if (R <= 4) return 3;
-    if (R <= 8) return 4;
-    if (R <= 16) return 5;
-    if (R <= 32) return 6;
-    return 7;
+    if (R <= 8) return 5;
+    if (R <= 16) return 7;
+    if (R <= 32) return 10;
+    return 14;
 }
 
 struct Shape {
-    int sched, P, V, U, chunks, RG;
+    int sched, P, V, UR, U, chunks, RG;
     int64_t fwd_units, bwd_units, n_tc;
     int fwd_blocks, bwd_blocks;
+    int32_t code;  // schedule id as reported: table index | U << 8
 };
 
+// Schedule id: bits 0..7 = table index (0 = automatic), bits 8..15 = rows per
+// work unit U (0 = the default for that entry).
 hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, Shape& sh) {
-    if (req < 0 || req > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
-    sh.sched = req == 0 ? auto_schedule(R) : req;
-    sh.P = hms::kSchedules[sh.sched].P;
-    sh.V = hms::kSchedules[sh.sched].V;
+    const int idx = req & 0xff;
+    int U = (req >> 8) & 0xff;
+    if (req < 0 || (req >> 16) != 0 || idx > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
+    sh.sched = idx == 0 ? auto_schedule(R) : idx;
+    const hms::Schedule& c = hms::kSchedules[sh.sched];
+    sh.P = c.P;
+    sh.V = c.V;
+    sh.UR = c.UR;
     if (R % sh.V != 0) return fail(HMS_ERR_ARG, "schedule vector width does not divide the restart count");
-    sh.U = hms::units_per_row_chunk(sh.P);
+    if (U == 0) U = hms::default_rows_per_unit(sh.sched);
+    const int per_pass = (64 / sh.P) * sh.UR;
+    if (U % per_pass != 0 || hms::kTile % U != 0)
+        return fail(HMS_ERR_ARG, "rows per unit must be a multiple of the rows per pass and divide 64");
+    sh.U = U;
+    sh.code = sh.sched | (U << 8);
     sh.chunks = hms::kTile / sh.U;
     sh.RG = (R + sh.P * sh.V - 1) / (sh.P * sh.V);
     sh.n_tc = (int64_t)P.c_tiles * sh.chunks;
@@ -599,7 +612,7 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     res->best_restart = br;
     res->best_step = bstep[br];
     res->steps_done = done;
-    res->schedule = sh.sched;
+    res->schedule = sh.code;
     res->final_loss = closs[br];
     res->device_ms = ms;
     if (res->restart_best) std::memcpy(res->restart_best, best.data(), R * 8);

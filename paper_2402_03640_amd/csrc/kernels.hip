@@ -16,14 +16,18 @@
 namespace hms {
 
 const Schedule kSchedules[kNumSchedules + 1] = {
-    {0, 0},                                                   // 0: automatic
-    {1, 1}, {2, 1}, {4, 1}, {8, 1}, {16, 1}, {32, 1}, {64, 1},  // 1..7
-    {16, 4}, {32, 2}, {64, 2}, {64, 4},                       // 8..11
+    {0, 0, 0},                                                               // 0: automatic
+    {1, 1, 1},  {2, 1, 1},  {4, 1, 1},  {8, 1, 1},  {8, 1, 2},  {16, 1, 1},  // 1..6
+    {16, 1, 2}, {16, 1, 4}, {32, 1, 2}, {32, 1, 4}, {64, 1, 1}, {64, 1, 2},  // 7..12
+    {64, 1, 4}, {64, 1, 8}, {16, 4, 1}, {16, 4, 2}, {32, 2, 2}, {32, 2, 4},  // 13..18
+    {64, 2, 2}, {64, 2, 4}, {64, 4, 1}, {64, 4, 2},                          // 19..22
 };
 
-int units_per_row_chunk(int P) {
-    int W = 64 / P;
-    int U = W * 8;
+int default_rows_per_unit(int sched) {
+    const Schedule& c = kSchedules[sched];
+    const int per_pass = (64 / c.P) * c.UR;
+    int U = per_pass * 2;
+    if (U < 8) U = 8;
     return U > 64 ? 64 : U;
 }
 
@@ -87,10 +91,23 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
     return z ^ (z >> 31);
 }
 
+// Loads of plan data (read-only for the whole solve) through the constant
+// address space: a wave-uniform address becomes a scalar load.
+__device__ __forceinline__ uint32_t ldc(const uint32_t* p) {
+    return *(const __attribute__((address_space(4))) uint32_t*)p;
+}
+__device__ __forceinline__ TileDesc ldtile(const TileDesc* p) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(p);
+    return TileDesc{ldc(w), ldc(w + 1), ldc(w + 2), ldc(w + 3)};
+}
+
 // ---------------------------------------------------------------------------
 // Forward: scores, unsat mask, adjoint a_j = (2/m) mu_j f_j, unit partials.
+// A wave takes a unit of U rows of one tile for one group of P*V restarts;
+// lane (s, q) handles UR consecutive rows per pass for restarts r0..r0+V-1,
+// column by column so that UR gathers are in flight together.
 // ---------------------------------------------------------------------------
-template <int P, int V, bool EVAL>
+template <int P, int V, int UR, bool EVAL>
 __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
     constexpr int W = 64 / P;
     const int lane = threadIdx.x & 63;
@@ -104,14 +121,14 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
         A.st->inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
     }
     const int nunits = A.ntiles * A.chunks * A.RG;
-    const int passes = A.U / W;
+    const int passes = A.U / (W * UR);
     for (int u = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); u < nunits;
          u += gridDim.x * 4) {
         const int rg = u % A.RG;
         const int tc = u / A.RG;
         const int tile = tc / A.chunks;
         const int chunk = tc % A.chunks;
-        const TileDesc d = A.tiles[tile];
+        const TileDesc d = ldtile(A.tiles + tile);
         const int r0 = rg * (P * V) + q * V;
         const bool ract = r0 < A.R;
         const bool taut = (d.flags & 1u) != 0;
@@ -123,59 +140,74 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
             los[k] = 0.0;
         }
         for (int pass = 0; pass < passes; ++pass) {
-            const int rowin = chunk * A.U + pass * W + s;
-            const bool real = rowin < (int)d.nreal;
-            const uint32_t* e = A.ent + d.base + rowin;
-            float f[V];
-            uint32_t allf[V];
+            const int rowin0 = chunk * A.U + pass * (W * UR) + s * UR;
+            const uint32_t* e = A.ent + d.base + rowin0;
+            float f[UR][V];
+            uint32_t allf[UR][V];
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                f[k] = 0.0f;
-                allf[k] = ~0u;
-            }
-            if (ract) {
-                if (d.len <= 16) {
-#pragma unroll 4
-                    for (uint32_t c = 0; c < d.len; ++c) {
-                        const uint32_t en = e[(size_t)c * kTile];
-                        const VecF<V> tv = ldv<V>(A.t + (size_t)(en & kIdx) * A.R + r0);
-#pragma unroll
-                        for (int k = 0; k < V; ++k) {
-                            const uint32_t b = __float_as_uint(tv.v[k]) ^ (en & kSign);
-                            f[k] = f[k] + __uint_as_float(b);
-                            allf[k] &= b;
-                        }
-                    }
-                } else {
-                    double fd[V];
-#pragma unroll
-                    for (int k = 0; k < V; ++k) fd[k] = 0.0;
-#pragma unroll 4
-                    for (uint32_t c = 0; c < d.len; ++c) {
-                        const uint32_t en = e[(size_t)c * kTile];
-                        const VecF<V> tv = ldv<V>(A.t + (size_t)(en & kIdx) * A.R + r0);
-#pragma unroll
-                        for (int k = 0; k < V; ++k) {
-                            const uint32_t b = __float_as_uint(tv.v[k]) ^ (en & kSign);
-                            fd[k] = fd[k] + (double)__uint_as_float(b);
-                            allf[k] &= b;
-                        }
-                    }
-#pragma unroll
-                    for (int k = 0; k < V; ++k) f[k] = (float)fd[k];
-                }
-                VecF<V> av;
+            for (int j = 0; j < UR; ++j)
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
-                    const bool unsat = real && !taut && (allf[k] >> 31) != 0;
-                    const bool mu = real && (A.all_mode ? true : unsat);
-                    av.v[k] = mu ? f[k] * A.two_over_m : 0.0f;
-                    if (EVAL) {
-                        cnt[k] += unsat ? 1 : 0;
-                        los[k] += mu ? (double)f[k] * (double)f[k] : 0.0;
+                    f[j][k] = 0.0f;
+                    allf[j][k] = ~0u;
+                }
+            if (ract) {
+                if (d.len <= 16) {
+#pragma unroll 2
+                    for (uint32_t c = 0; c < d.len; ++c) {
+                        uint32_t en[UR];
+#pragma unroll
+                        for (int j = 0; j < UR; ++j) en[j] = ldc(e + (size_t)c * kTile + j);
+                        VecF<V> tv[UR];
+#pragma unroll
+                        for (int j = 0; j < UR; ++j) tv[j] = ldv<V>(A.t + (size_t)(en[j] & kIdx) * A.R + r0);
+#pragma unroll
+                        for (int j = 0; j < UR; ++j)
+#pragma unroll
+                            for (int k = 0; k < V; ++k) {
+                                const uint32_t b = __float_as_uint(tv[j].v[k]) ^ (en[j] & kSign);
+                                f[j][k] = f[j][k] + __uint_as_float(b);
+                                allf[j][k] &= b;
+                            }
+                    }
+                } else {
+                    // long clauses: FP64 accumulation, one row at a time
+#pragma unroll
+                    for (int j = 0; j < UR; ++j) {
+                        double fd[V];
+#pragma unroll
+                        for (int k = 0; k < V; ++k) fd[k] = 0.0;
+#pragma unroll 4
+                        for (uint32_t c = 0; c < d.len; ++c) {
+                            const uint32_t en = ldc(e + (size_t)c * kTile + j);
+                            const VecF<V> tv = ldv<V>(A.t + (size_t)(en & kIdx) * A.R + r0);
+#pragma unroll
+                            for (int k = 0; k < V; ++k) {
+                                const uint32_t b = __float_as_uint(tv.v[k]) ^ (en & kSign);
+                                fd[k] = fd[k] + (double)__uint_as_float(b);
+                                allf[j][k] &= b;
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < V; ++k) f[j][k] = (float)fd[k];
                     }
                 }
-                stv<V>(A.a + (size_t)(tile * kTile + rowin) * A.R + r0, av);
+#pragma unroll
+                for (int j = 0; j < UR; ++j) {
+                    const bool real = rowin0 + j < (int)d.nreal;
+                    VecF<V> av;
+#pragma unroll
+                    for (int k = 0; k < V; ++k) {
+                        const bool unsat = real && !taut && (allf[j][k] >> 31) != 0;
+                        const bool mu = real && (A.all_mode ? true : unsat);
+                        av.v[k] = mu ? f[j][k] * A.two_over_m : 0.0f;
+                        if (EVAL) {
+                            cnt[k] += unsat ? 1 : 0;
+                            los[k] += mu ? (double)f[j][k] * (double)f[j][k] : 0.0;
+                        }
+                    }
+                    stv<V>(A.a + (size_t)(tile * kTile + rowin0 + j) * A.R + r0, av);
+                }
             }
         }
         if (EVAL) {
@@ -252,10 +284,10 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, int var, int r0, 
 
 // ---------------------------------------------------------------------------
 // Backward: transposed sums G = sum_j W_ij a_j over variable rows (atomic-free;
-// each (row, restart) summed by one lane in FP64), fused epilogue for whole
-// rows, partials for heavy-row segments.
+// each (row, restart) summed by one lane in FP64 in entry order), fused
+// epilogue for whole rows, partials for heavy-row segments.
 // ---------------------------------------------------------------------------
-template <int P, int V, int OPT>
+template <int P, int V, int UR, int OPT>
 __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
     constexpr int W = 64 / P;
     const int lane = threadIdx.x & 63;
@@ -263,39 +295,51 @@ __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
     const int q = lane % P;
     if (OPT != kGrad && blockIdx.x == 0 && threadIdx.x == 0) A.st->t += 1;
     const int nunits = A.ntiles * A.chunks * A.RG;
-    const int passes = A.U / W;
+    const int passes = A.U / (W * UR);
     for (int u = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); u < nunits;
          u += gridDim.x * 4) {
         const int rg = u % A.RG;
         const int tc = u / A.RG;
         const int tile = tc / A.chunks;
         const int chunk = tc % A.chunks;
-        const TileDesc d = A.tiles[tile];
+        const TileDesc d = ldtile(A.tiles + tile);
         const int r0 = rg * (P * V) + q * V;
-        const bool ract = r0 < A.R;
+        if (r0 >= A.R) continue;
         const bool segtile = tile < A.seg_tiles;
         for (int pass = 0; pass < passes; ++pass) {
-            const int rowin = chunk * A.U + pass * W + s;
-            if (!ract || rowin >= (int)d.nreal) continue;
-            const uint32_t* e = A.ent + d.base + rowin;
-            double G[V];
+            const int rowin0 = chunk * A.U + pass * (W * UR) + s * UR;
+            if (rowin0 >= (int)d.nreal) break;
+            const uint32_t* e = A.ent + d.base + rowin0;
+            double G[UR][V];
 #pragma unroll
-            for (int k = 0; k < V; ++k) G[k] = 0.0;
-#pragma unroll 4
+            for (int j = 0; j < UR; ++j)
+#pragma unroll
+                for (int k = 0; k < V; ++k) G[j][k] = 0.0;
+#pragma unroll 2
             for (uint32_t c = 0; c < d.len; ++c) {
-                const uint32_t en = e[(size_t)c * kTile];
-                const VecF<V> av = ldv<V>(A.a + (size_t)(en & kIdx) * A.R + r0);
+                uint32_t en[UR];
 #pragma unroll
-                for (int k = 0; k < V; ++k)
-                    G[k] = G[k] + (double)__uint_as_float(__float_as_uint(av.v[k]) ^ (en & kSign));
+                for (int j = 0; j < UR; ++j) en[j] = ldc(e + (size_t)c * kTile + j);
+                VecF<V> av[UR];
+#pragma unroll
+                for (int j = 0; j < UR; ++j) av[j] = ldv<V>(A.a + (size_t)(en[j] & kIdx) * A.R + r0);
+#pragma unroll
+                for (int j = 0; j < UR; ++j)
+#pragma unroll
+                    for (int k = 0; k < V; ++k)
+                        G[j][k] = G[j][k] + (double)__uint_as_float(__float_as_uint(av[j].v[k]) ^ (en[j] & kSign));
             }
-            const int row = tile * kTile + rowin;
-            if (segtile) {
 #pragma unroll
-                for (int k = 0; k < V; ++k) A.seg_part[(size_t)row * A.R + r0 + k] = G[k];
-            } else {
-                const int var = A.n_heavy + (row - A.seg_tiles * kTile);
-                var_epilogue<V, OPT>(A, var, r0, G);
+            for (int j = 0; j < UR; ++j) {
+                if (rowin0 + j >= (int)d.nreal) break;
+                const int row = tile * kTile + rowin0 + j;
+                if (segtile) {
+#pragma unroll
+                    for (int k = 0; k < V; ++k) A.seg_part[(size_t)row * A.R + r0 + k] = G[j][k];
+                } else {
+                    const int var = A.n_heavy + (row - A.seg_tiles * kTile);
+                    var_epilogue<V, OPT>(A, var, r0, G[j]);
+                }
             }
         }
     }
@@ -322,31 +366,41 @@ __global__ __launch_bounds__(256) void k_combine(BwdArgs A) {
 }
 
 // Sum the unit partials of each restart in a fixed order; track the best.
-__global__ __launch_bounds__(256) void k_reduce(ReduceArgs A) {
-    __shared__ int64_t sc[256];
-    __shared__ double sl[256];
-    const int r = blockIdx.x;
+// Block b covers restarts [64 b, 64 b + 64); lane l of wave w holds restart
+// 64 b + (l % RP) and slot (w * 64 + l) / RP; slot k sums units k, k + NS, ...
+// in order, then a fixed tree over the NS slots.
+__global__ __launch_bounds__(1024) void k_reduce(ReduceArgs A) {
+    __shared__ int64_t sc[1024];
+    __shared__ double sl[1024];
     const int tid = threadIdx.x;
+    int RP = 1;  // restarts side by side: the next power of two >= R, at most 64
+    while (RP < 64 && RP < A.R) RP <<= 1;
+    const int NS = 1024 / RP;
+    const int rloc = tid % RP;
+    const int slot = tid / RP;
+    const int r = blockIdx.x * 64 + rloc;
     int64_t c = 0;
     double l = 0.0;
-    for (int u = tid; u < A.n_units; u += 256) {
-        c += A.cnt_part[(size_t)u * A.R + r];
-        l = l + A.loss_part[(size_t)u * A.R + r];
+    if (r < A.R) {
+        for (int u = slot; u < A.n_units; u += NS) {
+            c += A.cnt_part[(size_t)u * A.R + r];
+            l = l + A.loss_part[(size_t)u * A.R + r];
+        }
     }
     sc[tid] = c;
     sl[tid] = l;
     __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if (tid < s) {
-            sc[tid] += sc[tid + s];
-            sl[tid] = sl[tid] + sl[tid + s];
+    for (int h = NS / 2; h >= 1; h >>= 1) {
+        if (slot < h) {
+            sc[tid] += sc[tid + h * RP];
+            sl[tid] = sl[tid] + sl[tid + h * RP];
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        const int64_t count = sc[0] + A.n_empty;
+    if (slot == 0 && r < A.R) {
+        const int64_t count = sc[tid] + A.n_empty;
         A.cur_count[r] = count;
-        A.cur_loss[r] = sl[0] * A.inv_m;
+        A.cur_loss[r] = sl[tid] * A.inv_m;
         if (A.track) {
             if (count < A.best[r]) {
                 A.best[r] = count;
@@ -425,42 +479,53 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t n, int32_t n_act, int32
     dst[(size_t)var_old[i] * R + r] = i < n_act ? src[idx] : 0.0f;
 }
 
-template <int P, int V>
+template <int P, int V, int UR>
 hipError_t fwd_for(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
     if (eval)
-        hipLaunchKernelGGL((k_fwd<P, V, true>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_fwd<P, V, UR, true>), dim3(blocks), dim3(256), 0, s, A);
     else
-        hipLaunchKernelGGL((k_fwd<P, V, false>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_fwd<P, V, UR, false>), dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
-template <int P, int V>
+template <int P, int V, int UR>
 hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
     if (opt == kAdam)
-        hipLaunchKernelGGL((k_bwd<P, V, kAdam>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kAdam>), dim3(blocks), dim3(256), 0, s, A);
     else if (opt == kSgd)
-        hipLaunchKernelGGL((k_bwd<P, V, kSgd>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kSgd>), dim3(blocks), dim3(256), 0, s, A);
     else
-        hipLaunchKernelGGL((k_bwd<P, V, kGrad>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kGrad>), dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
 }  // namespace
 
-#define HMS_SCHED_SWITCH(FN, ...)                        \
-    switch (sched) {                                     \
-        case 1: return FN<1, 1>(__VA_ARGS__);            \
-        case 2: return FN<2, 1>(__VA_ARGS__);            \
-        case 3: return FN<4, 1>(__VA_ARGS__);            \
-        case 4: return FN<8, 1>(__VA_ARGS__);            \
-        case 5: return FN<16, 1>(__VA_ARGS__);           \
-        case 6: return FN<32, 1>(__VA_ARGS__);           \
-        case 7: return FN<64, 1>(__VA_ARGS__);           \
-        case 8: return FN<16, 4>(__VA_ARGS__);           \
-        case 9: return FN<32, 2>(__VA_ARGS__);           \
-        case 10: return FN<64, 2>(__VA_ARGS__);          \
-        case 11: return FN<64, 4>(__VA_ARGS__);          \
-        default: return hipErrorInvalidValue;            \
+#define HMS_SCHED_SWITCH(FN, ...)                          \
+    switch (sched) {                                       \
+        case 1: return FN<1, 1, 1>(__VA_ARGS__);           \
+        case 2: return FN<2, 1, 1>(__VA_ARGS__);           \
+        case 3: return FN<4, 1, 1>(__VA_ARGS__);           \
+        case 4: return FN<8, 1, 1>(__VA_ARGS__);           \
+        case 5: return FN<8, 1, 2>(__VA_ARGS__);           \
+        case 6: return FN<16, 1, 1>(__VA_ARGS__);          \
+        case 7: return FN<16, 1, 2>(__VA_ARGS__);          \
+        case 8: return FN<16, 1, 4>(__VA_ARGS__);          \
+        case 9: return FN<32, 1, 2>(__VA_ARGS__);          \
+        case 10: return FN<32, 1, 4>(__VA_ARGS__);         \
+        case 11: return FN<64, 1, 1>(__VA_ARGS__);         \
+        case 12: return FN<64, 1, 2>(__VA_ARGS__);         \
+        case 13: return FN<64, 1, 4>(__VA_ARGS__);         \
+        case 14: return FN<64, 1, 8>(__VA_ARGS__);         \
+        case 15: return FN<16, 4, 1>(__VA_ARGS__);         \
+        case 16: return FN<16, 4, 2>(__VA_ARGS__);         \
+        case 17: return FN<32, 2, 2>(__VA_ARGS__);         \
+        case 18: return FN<32, 2, 4>(__VA_ARGS__);         \
+        case 19: return FN<64, 2, 2>(__VA_ARGS__);         \
+        case 20: return FN<64, 2, 4>(__VA_ARGS__);         \
+        case 21: return FN<64, 4, 1>(__VA_ARGS__);         \
+        case 22: return FN<64, 4, 2>(__VA_ARGS__);         \
+        default: return hipErrorInvalidValue;              \
     }
 
 hipError_t launch_fwd(int sched, bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
@@ -472,7 +537,7 @@ hipError_t launch_bwd(int sched, int opt, const BwdArgs& A, int blocks, hipStrea
     if (blocks <= 0) {
         // still advance the step counter
         if (opt != kGrad) {
-            hipLaunchKernelGGL((k_bwd<1, 1, kAdam>), dim3(1), dim3(256), 0, s, A);
+            hipLaunchKernelGGL((k_bwd<1, 1, 1, kAdam>), dim3(1), dim3(256), 0, s, A);
             return hipGetLastError();
         }
         return hipSuccess;
@@ -494,7 +559,7 @@ hipError_t launch_combine(int opt, const BwdArgs& A, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const ReduceArgs& A, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(A.R), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_reduce, dim3((A.R + 63) / 64), dim3(1024), 0, s, A);
     return hipGetLastError();
 }
 

@@ -98,14 +98,16 @@ struct InitArgs {
     StepState* st;
 };
 
-// Kernel schedules: P lanes per row, V restarts per lane (vector width).
+// Kernel schedules: P lanes per restart group (64 / P rows side by side),
+// V restarts per lane (vector width), UR rows per lane handled together.
+// A work unit is U rows of one tile (U a multiple of (64 / P) * UR dividing 64).
 struct Schedule {
-    int P, V;
+    int P, V, UR;
 };
-constexpr int kNumSchedules = 11;
+constexpr int kNumSchedules = 22;
 extern const Schedule kSchedules[kNumSchedules + 1];
 
-int units_per_row_chunk(int P);  // rows per work unit U for a schedule
+int default_rows_per_unit(int sched);
 
 hipError_t launch_fwd(int sched, bool eval, const FwdArgs& A, int blocks, hipStream_t s);
 hipError_t launch_bwd(int sched, int opt, const BwdArgs& A, int blocks, hipStream_t s);

@@ -88,7 +88,9 @@ def test_eval_cfg4_all_schedules():
     cnf = hm.load_cnf(n, lits)
     xt = torch.from_numpy(x).cuda()
     ref = None
-    for sched in range(1, 12):
+    codes = list(range(1, 23)) + [14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
+                                  7 | (64 << 8), 1 | (64 << 8)]
+    for sched in codes:
         res = hm.solve(cnf, steps=3, restarts=R, eval_every=1, x0=xt, schedule=sched, want_x=True)
         xf = res.x_final.cpu().numpy()
         cur = (res.restart_best.copy(), res.restart_step.copy(), xf)
