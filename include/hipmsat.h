@@ -100,9 +100,10 @@ typedef struct {
     uint64_t seed;       /* restart r starts from the SplitMix64 stream seeded seed + r */
     float lr, beta1, beta2, eps; /* Adam: PyTorch defaults 0.9 / 0.999 / 1e-8 */
     int32_t loss_mode;   /* HMS_LOSS_UNSAT or HMS_LOSS_ALL */
-    int32_t schedule;    /* 0 = automatic; otherwise a kernel schedule id (hms_schedule_*) */
+    int32_t schedule;    /* 0 = automatic; else table index | rows-per-unit << 8 (see hms_tune) */
     int32_t use_graph;   /* 1 = replay the step body as a HIP graph, 0 = direct launches */
-    int32_t reserved;
+    int32_t autotune;    /* 1 = with schedule 0, time the candidate schedules once per handle,
+                            restart count, optimizer and loss mode, and keep the fastest */
     double time_limit_s; /* > 0: stop at a K-step boundary once exceeded (not reproducible) */
     const float* x0;     /* DEVICE [n][R] initial values, or NULL for SplitMix64 U(-1,1) */
     void* stream;        /* hipStream_t */
@@ -124,7 +125,8 @@ typedef struct {
 } hms_solve_result;
 
 /* Fill *p with the defaults: T = 1000, R = 1, K = 1, Adam lr 1e-4, UNSAT loss,
- * automatic schedule, graphs on, no time limit, seed 0, null stream. */
+ * automatic schedule with autotuning, graphs on, no time limit, seed 0, null
+ * stream. */
 void hms_solve_params_default(hms_solve_params* p);
 
 /*
@@ -152,6 +154,16 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* params, hms_sol
  */
 hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* params, int32_t iters,
                             double* fwd_ms, double* bwd_ms, double* step_ms);
+
+/*
+ * Schedule autotuner: times every kernel schedule that can run
+ * params->restarts restarts (`iters` steps each, HIP events on params->stream)
+ * and records the fastest for this handle; later solves with schedule 0 use
+ * it.  The choice changes speed only: results are bitwise the same under
+ * every schedule.  Outputs the chosen schedule id and its time per step.
+ */
+hms_status hms_tune(const hms_cnf* cnf, const hms_solve_params* params, int32_t iters, int32_t* schedule,
+                    double* step_ms);
 
 /*
  * Count the clauses an assignment leaves unsatisfied (Section 4 "Unsatisfiable

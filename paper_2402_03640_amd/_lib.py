@@ -48,7 +48,7 @@ class SolveParams(C.Structure):
                 ("optimizer", C.c_int32), ("seed", C.c_uint64), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("loss_mode", C.c_int32), ("schedule", C.c_int32), ("use_graph", C.c_int32),
-                ("reserved", C.c_int32), ("time_limit_s", C.c_double), ("x0", C.c_void_p),
+                ("autotune", C.c_int32), ("time_limit_s", C.c_double), ("x0", C.c_void_p),
                 ("stream", C.c_void_p)]
 
 
@@ -74,7 +74,7 @@ class PlanView(C.Structure):
 EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_cnf",
            "hms_solve_params_default", "hms_solve", "hms_evaluate", "hms_eval_relaxed",
            "hms_last_error", "hms_version", "hms_plan_view_build", "hms_plan_view_free",
-           "hms_time_kernels"]
+           "hms_time_kernels", "hms_tune"]
 
 _lib = None
 
@@ -98,6 +98,7 @@ def lib():
     L.hms_solve.argtypes = [P, C.POINTER(SolveParams), C.POINTER(SolveResult)]
     L.hms_evaluate.argtypes = [P, P, P, P]
     L.hms_time_kernels.argtypes = [P, C.POINTER(SolveParams), I32, P, P, P]
+    L.hms_tune.argtypes = [P, C.POINTER(SolveParams), I32, P, P]
     L.hms_eval_relaxed.argtypes = [P, P, I32, I32, P, P, P, P]
     L.hms_last_error.argtypes = []
     L.hms_last_error.restype = C.c_char_p
@@ -107,7 +108,7 @@ def lib():
     L.hms_plan_view_free.argtypes = [C.POINTER(PlanView)]
     L.hms_plan_view_free.restype = None
     for name in ("hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_solve",
-                 "hms_evaluate", "hms_eval_relaxed", "hms_plan_view_build", "hms_time_kernels"):
+                 "hms_evaluate", "hms_eval_relaxed", "hms_plan_view_build", "hms_time_kernels", "hms_tune"):
         getattr(L, name).restype = I32
     _lib = L
     return L
@@ -197,7 +198,7 @@ class SolveOutput:
 
 
 def _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2, eps, loss_mode,
-            schedule, use_graph, time_limit_s, x0, stream):
+            schedule, use_graph, time_limit_s, x0, stream, autotune=True):
     R = int(restarts)
     p = SolveParams()
     lib().hms_solve_params_default(C.byref(p))
@@ -206,6 +207,7 @@ def _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2,
     p.lr, p.beta1, p.beta2, p.eps = lr, beta1, beta2, eps
     p.loss_mode, p.schedule, p.use_graph = int(loss_mode), int(schedule), int(bool(use_graph))
     p.time_limit_s = float(time_limit_s)
+    p.autotune = int(bool(autotune))
     if x0 is not None:
         import torch
         assert x0.is_cuda and x0.dtype == torch.float32 and x0.is_contiguous()
@@ -227,14 +229,25 @@ def time_kernels(cnf: Cnf, restarts: int = 1, iters: int = 50, seed: int = 0, op
     return f.value, b.value, st.value
 
 
+def tune(cnf: Cnf, restarts: int = 1, iters: int = 6, optimizer: int = ADAM, lr: float = 1e-4,
+         loss_mode: int = LOSS_UNSAT, stream=None):
+    """Time every schedule for this restart count; returns (schedule id, ms per step)."""
+    p = _params(cnf, 1, restarts, 1, 0, optimizer, lr, 0.9, 0.999, 1e-8, loss_mode, 0, False, 0.0,
+                None, stream)
+    code, ms = C.c_int32(), C.c_double()
+    _check(lib().hms_tune(cnf.handle, C.byref(p), int(iters), C.byref(code), C.byref(ms)))
+    return code.value, ms.value
+
+
 def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, seed: int = 0,
           optimizer: int = ADAM, lr: float = 1e-4, beta1: float = 0.9, beta2: float = 0.999,
           eps: float = 1e-8, loss_mode: int = LOSS_UNSAT, schedule: int = 0, use_graph: bool = True,
-          time_limit_s: float = 0.0, x0=None, want_x: bool = False, stream=None) -> SolveOutput:
+          time_limit_s: float = 0.0, x0=None, want_x: bool = False, stream=None,
+          autotune: bool = True) -> SolveOutput:
     """Algorithm 1 over ``restarts`` relaxed points (see ``hms_solve``)."""
     R = int(restarts)
     p = _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2, eps, loss_mode,
-                schedule, use_graph, time_limit_s, x0, stream)
+                schedule, use_graph, time_limit_s, x0, stream, autotune)
     res = SolveResult()
     ba = np.zeros(max(cnf.n, 1), dtype=np.uint8)
     rb = np.zeros(R, dtype=np.int64)

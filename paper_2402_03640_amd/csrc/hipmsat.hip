@@ -6,6 +6,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,6 +27,10 @@ struct hms_cnf {
     int32_t* seg_row = nullptr;
     int32_t* var_old = nullptr;
     int64_t struct_bytes = 0;
+    // autotuned schedule per (restarts, optimizer, loss mode); results do not
+    // depend on the schedule, only the speed does
+    mutable std::mutex tune_mu;
+    mutable std::map<uint64_t, int32_t> tuned;
 };
 
 namespace {
@@ -91,50 +97,65 @@ struct Arena {
 };
 
 // Default kernel schedule for R restarts (table index into hms::kSchedules).
-int auto_schedule(int32_t R) {
-    if (R <= 1) return 1;
+int auto_schedule(int32_t R, int loss_mode) {
+    if (R <= 1) return loss_mode == HMS_LOSS_UNSAT ? 24 : 2;
     if (R <= 2) return 2;
     if (R <= 4) return 3;
     if (R <= 8) return 5;
-    if (R <= 16) return 7;
+    if (R <= 16) return 4;
     if (R <= 32) return 10;
+    if (R % 4 == 0) return 15;
     return 14;
 }
 
 struct Shape {
-    int sched, P, V, UR, U, chunks, RG;
-    int64_t fwd_units, bwd_units, n_tc;
+    int sched, P, V, UR, U, chunks, mask;
+    hms::Blocking B;
+    int64_t n_tc, fwd_blocks64, bwd_blocks64;
     int fwd_blocks, bwd_blocks;
     int32_t code;  // schedule id as reported: table index | U << 8
 };
 
 // Schedule id: bits 0..7 = table index (0 = automatic), bits 8..15 = rows per
-// work unit U (0 = the default for that entry).
-hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, Shape& sh) {
+// work unit U (0 = the default for that entry).  The bitset variants apply to
+// one restart with the unsat-masked loss; elsewhere they fall back to their
+// unmasked twin (same arithmetic).
+hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_mode, Shape& sh) {
     const int idx = req & 0xff;
     int U = (req >> 8) & 0xff;
     if (req < 0 || (req >> 16) != 0 || idx > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
-    sh.sched = idx == 0 ? auto_schedule(R) : idx;
+    sh.sched = idx == 0 ? auto_schedule(R, loss_mode) : idx;
+    if (hms::kSchedules[sh.sched].mask && (R != 1 || loss_mode != HMS_LOSS_UNSAT)) sh.sched -= 22;  // 23..25 -> 1..3
     const hms::Schedule& c = hms::kSchedules[sh.sched];
     sh.P = c.P;
     sh.V = c.V;
     sh.UR = c.UR;
+    sh.mask = c.mask;
     if (R % sh.V != 0) return fail(HMS_ERR_ARG, "schedule vector width does not divide the restart count");
     if (U == 0) U = hms::default_rows_per_unit(sh.sched);
     const int per_pass = (64 / sh.P) * sh.UR;
-    if (U % per_pass != 0 || hms::kTile % U != 0)
+    if (U % per_pass != 0 || hms::kTile % U != 0 || (sh.mask && U < 32))
         return fail(HMS_ERR_ARG, "rows per unit must be a multiple of the rows per pass and divide 64");
     sh.U = U;
     sh.code = sh.sched | (U << 8);
     sh.chunks = hms::kTile / sh.U;
-    sh.RG = (R + sh.P * sh.V - 1) / (sh.P * sh.V);
+    int G = sh.P * sh.V;
+    int Rp = 1;
+    while (Rp < R && Rp < G) Rp <<= 1;
+    G = std::min(G, Rp);
+    sh.B.R = R;
+    sh.B.G = G;
+    sh.B.RG = (R + G - 1) / G;
+    sh.B.rows_x = P.n + 1;
+    sh.B.rows_a = P.a_rows();
+    sh.B.rows_seg = std::max(P.seg_rows, 1);
     sh.n_tc = (int64_t)P.c_tiles * sh.chunks;
-    sh.fwd_units = sh.n_tc * sh.RG;
-    sh.bwd_units = (int64_t)P.v_tiles * sh.chunks * sh.RG;
-    if (sh.fwd_units >= INT32_MAX / 2 || sh.bwd_units >= INT32_MAX / 2)
+    sh.fwd_blocks64 = (int64_t)sh.B.RG * ((sh.n_tc + 3) / 4);
+    sh.bwd_blocks64 = (int64_t)sh.B.RG * (((int64_t)P.v_tiles * sh.chunks + 3) / 4);
+    if (sh.fwd_blocks64 >= INT32_MAX / 2 || sh.bwd_blocks64 >= INT32_MAX / 2)
         return fail(HMS_ERR_TOO_LARGE, "too many work units");
-    sh.fwd_blocks = (int)((sh.fwd_units + 3) / 4);
-    sh.bwd_blocks = (int)((sh.bwd_units + 3) / 4);
+    sh.fwd_blocks = (int)sh.fwd_blocks64;
+    sh.bwd_blocks = (int)sh.bwd_blocks64;
     return HMS_OK;
 }
 
@@ -145,55 +166,99 @@ struct State {
     int32_t* cnt_part;
     double* loss_part;
     uint8_t* best_a;
+    uint32_t* umask;
     int64_t *best, *cur_count;
     int32_t *best_step, *improved;
     double* cur_loss;
+    int32_t* cnt_mid;
+    double* loss_mid;
     hms::StepState* st;
     uint8_t* out_assign;
 };
 
-size_t layout_state(const hms::HostPlan& P, const Shape& sh, int32_t R, bool moments, bool grad, bool best,
-                    Layout& L, size_t off[16]) {
-    const size_t nR = (size_t)(P.n + 1) * R;
-    off[0] = L.add(nR * 4);                                        // x
-    off[1] = moments ? L.add(nR * 4) : 0;                          // m
-    off[2] = moments ? L.add(nR * 4) : 0;                          // v
-    off[3] = L.add(nR * 4);                                        // t
-    off[4] = L.add((size_t)P.a_rows() * R * 4);                    // a
-    off[5] = grad ? L.add(nR * 4) : 0;                             // g
-    off[6] = L.add((size_t)std::max(P.seg_rows, 1) * R * 8);       // seg_part
-    off[7] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 4); // cnt_part
-    off[8] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 8); // loss_part
-    off[9] = best ? L.add((size_t)std::max(P.n, 1) * R) : 0;       // best_a
-    off[10] = L.add((size_t)R * 8);                                // best
-    off[11] = L.add((size_t)R * 8);                                // cur_count
-    off[12] = L.add((size_t)R * 4);                                // best_step
-    off[13] = L.add((size_t)R * 4);                                // improved
-    off[14] = L.add((size_t)R * 8);                                // cur_loss
-    off[15] = L.add(256 + (size_t)std::max(P.n, 1));                  // st, then out_assign at +256
-    return L.off;
+enum { kOffX, kOffM, kOffV, kOffT, kOffA, kOffG, kOffSeg, kOffCnt, kOffLoss, kOffBest, kOffMask, kOffBestC,
+       kOffCurC, kOffBestS, kOffImp, kOffCurL, kOffCntMid, kOffLossMid, kOffSt, kOffN };
+
+// Units per stage-1 reduce chunk: a fixed function of the unit count.
+int32_t reduce_chunk(int64_t n_units) { return (int32_t)std::max<int64_t>(64, (n_units + 1023) / 1024); }
+int32_t reduce_chunks(int64_t n_units) { return (int32_t)((n_units + reduce_chunk(n_units) - 1) / reduce_chunk(n_units)); }
+
+int32_t umask_words(const hms::HostPlan& P) { return P.c_tiles * 2 + 1; }
+
+void layout_state(const hms::HostPlan& P, const Shape& sh, bool moments, bool grad, bool best, Layout& L,
+                  size_t off[kOffN]) {
+    const int32_t R = sh.B.R;
+    const size_t Rp = (size_t)sh.B.RG * sh.B.G;  // padded restart count of the blocked layout
+    const size_t nR = (size_t)sh.B.rows_x * Rp;
+    off[kOffX] = L.add(nR * 4);
+    off[kOffM] = moments ? L.add(nR * 4) : 0;
+    off[kOffV] = moments ? L.add(nR * 4) : 0;
+    off[kOffT] = L.add(nR * 4);
+    off[kOffA] = L.add((size_t)sh.B.rows_a * Rp * 4);
+    off[kOffG] = grad ? L.add(nR * 4) : 0;
+    off[kOffSeg] = L.add((size_t)sh.B.rows_seg * Rp * 8);
+    off[kOffCnt] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 4);
+    off[kOffLoss] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 8);
+    off[kOffBest] = best ? L.add(nR) : 0;
+    off[kOffMask] = L.add((size_t)umask_words(P) * 4);
+    off[kOffBestC] = L.add((size_t)R * 8);
+    off[kOffCurC] = L.add((size_t)R * 8);
+    off[kOffBestS] = L.add((size_t)R * 4);
+    off[kOffImp] = L.add((size_t)R * 4);
+    off[kOffCurL] = L.add((size_t)R * 8);
+    off[kOffCntMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc), 1) * R * 4);
+    off[kOffLossMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc), 1) * R * 8);
+    off[kOffSt] = L.add(256 + (size_t)std::max(P.n, 1));  // step state, then out_assign at +256
 }
 
-State bind_state(const Arena& A, const size_t off[16], bool moments, bool grad, bool best) {
+State bind_state(const Arena& A, const size_t off[kOffN], bool moments, bool grad, bool best) {
     State S{};
-    S.x = A.at<float>(off[0]);
-    S.m = moments ? A.at<float>(off[1]) : nullptr;
-    S.v = moments ? A.at<float>(off[2]) : nullptr;
-    S.t = A.at<float>(off[3]);
-    S.a = A.at<float>(off[4]);
-    S.g = grad ? A.at<float>(off[5]) : nullptr;
-    S.seg_part = A.at<double>(off[6]);
-    S.cnt_part = A.at<int32_t>(off[7]);
-    S.loss_part = A.at<double>(off[8]);
-    S.best_a = best ? A.at<uint8_t>(off[9]) : nullptr;
-    S.best = A.at<int64_t>(off[10]);
-    S.cur_count = A.at<int64_t>(off[11]);
-    S.best_step = A.at<int32_t>(off[12]);
-    S.improved = A.at<int32_t>(off[13]);
-    S.cur_loss = A.at<double>(off[14]);
-    S.st = A.at<hms::StepState>(off[15]);
-    S.out_assign = A.at<uint8_t>(off[15] + 256);
+    S.x = A.at<float>(off[kOffX]);
+    S.m = moments ? A.at<float>(off[kOffM]) : nullptr;
+    S.v = moments ? A.at<float>(off[kOffV]) : nullptr;
+    S.t = A.at<float>(off[kOffT]);
+    S.a = A.at<float>(off[kOffA]);
+    S.g = grad ? A.at<float>(off[kOffG]) : nullptr;
+    S.seg_part = A.at<double>(off[kOffSeg]);
+    S.cnt_part = A.at<int32_t>(off[kOffCnt]);
+    S.loss_part = A.at<double>(off[kOffLoss]);
+    S.best_a = best ? A.at<uint8_t>(off[kOffBest]) : nullptr;
+    S.umask = A.at<uint32_t>(off[kOffMask]);
+    S.best = A.at<int64_t>(off[kOffBestC]);
+    S.cur_count = A.at<int64_t>(off[kOffCurC]);
+    S.best_step = A.at<int32_t>(off[kOffBestS]);
+    S.improved = A.at<int32_t>(off[kOffImp]);
+    S.cur_loss = A.at<double>(off[kOffCurL]);
+    S.cnt_mid = A.at<int32_t>(off[kOffCntMid]);
+    S.loss_mid = A.at<double>(off[kOffLossMid]);
+    S.st = A.at<hms::StepState>(off[kOffSt]);
+    S.out_assign = A.at<uint8_t>(off[kOffSt] + 256);
     return S;
+}
+
+hms::InitArgs make_init(const hms_cnf* C, const Shape& sh, const State& S) {
+    const hms::HostPlan& P = C->plan;
+    hms::InitArgs ia{};
+    ia.n = P.n;
+    ia.m = P.m;
+    ia.a_zero_row = P.a_zero_row();
+    ia.umask_words = umask_words(P);
+    ia.B = sh.B;
+    ia.var_old = C->var_old;
+    ia.x = S.x;
+    ia.t = S.t;
+    ia.mm = S.m;
+    ia.vv = S.v;
+    ia.a = S.a;
+    ia.umask = S.umask;
+    ia.best_a = S.best_a;
+    ia.st = S.st;
+    if (S.best_a) {
+        ia.best = S.best;
+        ia.best_step = S.best_step;
+        ia.improved = S.improved;
+    }
+    return ia;
 }
 
 struct Launch {
@@ -204,8 +269,8 @@ struct Launch {
     int opt;
 };
 
-Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int32_t R, int opt, int loss_mode,
-                   float lr, float b1, float b2, float eps) {
+Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, int loss_mode, float lr, float b1,
+                   float b2, float eps) {
     const hms::HostPlan& P = C->plan;
     Launch L{};
     L.sh = sh;
@@ -216,11 +281,11 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int32_t R,
     f.ntiles = P.c_tiles;
     f.chunks = sh.chunks;
     f.U = sh.U;
-    f.RG = sh.RG;
-    f.R = R;
     f.all_mode = loss_mode == HMS_LOSS_ALL;
+    f.B = sh.B;
     f.t = S.t;
     f.a = S.a;
+    f.umask = S.umask;
     f.two_over_m = P.m > 0 ? (float)(2.0 / (double)P.m) : 0.0f;
     f.cnt_part = S.cnt_part;
     f.loss_part = S.loss_part;
@@ -235,12 +300,13 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int32_t R,
     b.seg_tiles = P.seg_tiles;
     b.chunks = sh.chunks;
     b.U = sh.U;
-    b.RG = sh.RG;
-    b.R = R;
+    b.B = sh.B;
     b.n_heavy = P.n_heavy;
+    b.n_heavy_wide = P.n_heavy_wide;
     b.n_act = P.n_act;
     b.eval = 0;
     b.a = S.a;
+    b.umask = S.umask;
     b.seg_part = S.seg_part;
     b.x = S.x;
     b.m = S.m;
@@ -262,7 +328,11 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int32_t R,
     r.cnt_part = S.cnt_part;
     r.loss_part = S.loss_part;
     r.n_units = (int32_t)sh.n_tc;
-    r.R = R;
+    r.chunk = reduce_chunk(sh.n_tc);
+    r.n_chunks = reduce_chunks(sh.n_tc);
+    r.cnt_mid = S.cnt_mid;
+    r.loss_mid = S.loss_mid;
+    r.R = sh.B.R;
     r.track = 1;
     r.n_empty = P.m_empty;
     r.inv_m = P.m > 0 ? 1.0 / (double)P.m : 0.0;
@@ -430,6 +500,7 @@ void hms_solve_params_default(hms_solve_params* p) {
     p->loss_mode = HMS_LOSS_UNSAT;
     p->schedule = 0;
     p->use_graph = 1;
+    p->autotune = 1;
     p->time_limit_s = 0.0;
     p->x0 = nullptr;
     p->stream = nullptr;
@@ -459,37 +530,20 @@ hms_status setup_solve(const hms_cnf* cnf, const hms_solve_params* p, SolveSetup
     const hms::HostPlan& P = cnf->plan;
     if ((int64_t)(P.n + 1) * R > ((int64_t)1 << 40)) return fail(HMS_ERR_TOO_LARGE, "state too large");
     hipStream_t s = (hipStream_t)p->stream;
-    hms_status rc = make_shape(P, R, p->schedule, Z.sh);
+    hms_status rc = make_shape(P, R, p->schedule, p->loss_mode, Z.sh);
     if (rc) return rc;
     const bool adam = p->optimizer == HMS_ADAM;
     Layout lay;
-    size_t off[16];
-    layout_state(P, Z.sh, R, adam, false, true, lay, off);
+    size_t off[kOffN];
+    layout_state(P, Z.sh, adam, false, true, lay, off);
     Z.A.s = s;
     HIPTRY(hipMallocAsync((void**)&Z.A.base, lay.off, s));
     Z.S = bind_state(Z.A, off, adam, false, true);
-    const State& S = Z.S;
-    hms::InitArgs ia{};
-    ia.n = P.n;
-    ia.R = R;
-    ia.a_zero_row = P.a_zero_row();
-    ia.m = P.m;
-    ia.var_old = cnf->var_old;
+    hms::InitArgs ia = make_init(cnf, Z.sh, Z.S);
     ia.x0 = p->x0;
-    ia.assign0 = nullptr;
     ia.seed = p->seed;
-    ia.x = S.x;
-    ia.t = S.t;
-    ia.mm = S.m;
-    ia.vv = S.v;
-    ia.a = S.a;
-    ia.best_a = S.best_a;
-    ia.best = S.best;
-    ia.best_step = S.best_step;
-    ia.improved = S.improved;
-    ia.st = S.st;
     HIPTRY(hms::launch_init(ia, s));
-    Z.L = make_launch(cnf, Z.sh, S, R, adam ? hms::kAdam : hms::kSgd, p->loss_mode, p->lr, p->beta1, p->beta2,
+    Z.L = make_launch(cnf, Z.sh, Z.S, adam ? hms::kAdam : hms::kSgd, p->loss_mode, p->lr, p->beta1, p->beta2,
                       p->eps);
     return HMS_OK;
 }
@@ -502,6 +556,85 @@ struct Events {
     }
 };
 
+
+uint64_t tune_key(const hms_solve_params* p) {
+    return (uint64_t)(uint32_t)p->restarts | ((uint64_t)(uint32_t)p->optimizer << 32) |
+           ((uint64_t)(uint32_t)p->loss_mode << 40);
+}
+
+// Every (schedule, rows per unit) pair that can run R restarts.
+std::vector<int32_t> tune_candidates(int32_t R, int loss_mode) {
+    std::vector<int32_t> out;
+    for (int idx = 1; idx <= hms::kNumSchedules; ++idx) {
+        const hms::Schedule& c = hms::kSchedules[idx];
+        if (R % c.V) continue;
+        if (c.mask && (R != 1 || loss_mode != HMS_LOSS_UNSAT)) continue;
+        if (c.P * c.V > 2 * std::max(R, 1) && c.P * c.V > 2) continue;  // mostly idle lanes
+        const int per = (64 / c.P) * c.UR;
+        for (int U = per; U <= 64; U *= 2) {
+            if (64 % U || (c.mask && U < 32)) continue;
+            out.push_back(idx | (U << 8));
+        }
+    }
+    return out;
+}
+
+// Average device time of one (non-evaluation) step under schedule `code`.
+hms_status time_steps(const hms_cnf* cnf, const hms_solve_params* p0, int32_t code, int32_t iters, double& ms) {
+    hms_solve_params p = *p0;
+    p.schedule = code;
+    p.x0 = nullptr;
+    SolveSetup Z;
+    hms_status rc = setup_solve(cnf, &p, Z);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)p.stream;
+    Events E;
+    for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
+    HIPTRY(enqueue_step(Z.L, false, s));
+    HIPTRY(hipEventRecord(E.e[0], s));
+    for (int32_t i = 0; i < iters; ++i) HIPTRY(enqueue_step(Z.L, false, s));
+    HIPTRY(hipEventRecord(E.e[1], s));
+    HIPTRY(hipStreamSynchronize(s));
+    float t = 0;
+    HIPTRY(hipEventElapsedTime(&t, E.e[0], E.e[1]));
+    ms = t / iters;
+    return HMS_OK;
+}
+
+hms_status tune(const hms_cnf* cnf, const hms_solve_params* p, int32_t iters, int32_t& best, double& best_ms) {
+    best = 0;
+    best_ms = 1e300;
+    for (int32_t code : tune_candidates(p->restarts, p->loss_mode)) {
+        double ms = 0;
+        hms_status rc = time_steps(cnf, p, code, iters, ms);
+        if (rc) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = code;
+        }
+    }
+    std::lock_guard<std::mutex> lk(cnf->tune_mu);
+    cnf->tuned[tune_key(p)] = best;
+    return HMS_OK;
+}
+
+// Schedule to run when the caller asked for the automatic choice.
+hms_status resolve_schedule(const hms_cnf* cnf, const hms_solve_params* p, int32_t& code) {
+    code = p->schedule;
+    if (code != 0) return HMS_OK;
+    {
+        std::lock_guard<std::mutex> lk(cnf->tune_mu);
+        auto it = cnf->tuned.find(tune_key(p));
+        if (it != cnf->tuned.end()) {
+            code = it->second;
+            return HMS_OK;
+        }
+    }
+    if (!p->autotune || (double)cnf->plan.nnz * p->restarts < (double)(1 << 18)) return HMS_OK;
+    double ms = 0;
+    return tune(cnf, p, 6, code, ms);
+}
+
 }  // namespace
 
 extern "C" {
@@ -510,8 +643,12 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     g_err.clear();
     if (check_cnf(cnf) || !p || !res) return fail(HMS_ERR_ARG, "null argument");
     DeviceGuard dg(cnf->device);
+    hms_solve_params pr = *p;
+    hms_status rc0 = resolve_schedule(cnf, p, pr.schedule);
+    if (rc0) return rc0;
+    p = &pr;
     SolveSetup Z;
-    hms_status rc0 = setup_solve(cnf, p, Z);
+    rc0 = setup_solve(cnf, p, Z);
     if (rc0) return rc0;
     const hms::HostPlan& P = cnf->plan;
     const int32_t R = p->restarts, T = p->steps, K = p->eval_every;
@@ -587,7 +724,7 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     // x_T is always counted
     HIPTRY(hms::launch_fwd(sh.sched, true, L.fa, sh.fwd_blocks, s));
     HIPTRY(hms::launch_reduce(L.ra, s));
-    HIPTRY(hms::launch_snapshot(P.n_act, R, S.x, S.improved, S.best_a, s));
+    HIPTRY(hms::launch_snapshot(P.n_act, sh.B, S.x, S.improved, S.best_a, s));
     HIPTRY(hipEventRecord(ev1, s));
 
     std::vector<int64_t> best(R);
@@ -603,10 +740,10 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     for (int32_t r = 1; r < R; ++r)
         if (best[r] < best[br]) br = r;
     if (res->best_assignment && P.n > 0) {
-        HIPTRY(hms::launch_extract(P.n, R, br, cnf->var_old, S.best_a, S.out_assign, s));
+        HIPTRY(hms::launch_extract(P.n, sh.B, br, cnf->var_old, S.best_a, S.out_assign, s));
         HIPTRY(hipMemcpyAsync(res->best_assignment, S.out_assign, P.n, hipMemcpyDeviceToHost, s));
     }
-    if (res->x_final) HIPTRY(hms::launch_scatter(P.n, P.n, R, cnf->var_old, S.x, res->x_final, s));
+    if (res->x_final) HIPTRY(hms::launch_scatter(P.n, P.n, sh.B, cnf->var_old, S.x, res->x_final, s));
     HIPTRY(hipStreamSynchronize(s));
     res->best_cost = best[br];
     res->best_restart = br;
@@ -628,8 +765,12 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* p, int32
     g_err.clear();
     if (check_cnf(cnf) || !p || iters < 1) return fail(HMS_ERR_ARG, "null argument or iters < 1");
     DeviceGuard dg(cnf->device);
+    hms_solve_params pr = *p;
+    hms_status rc0 = resolve_schedule(cnf, p, pr.schedule);
+    if (rc0) return rc0;
+    p = &pr;
     SolveSetup Z;
-    hms_status rc0 = setup_solve(cnf, p, Z);
+    rc0 = setup_solve(cnf, p, Z);
     if (rc0) return rc0;
     hipStream_t s = (hipStream_t)p->stream;
     const Launch& L = Z.L;
@@ -658,6 +799,20 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* p, int32
     return HMS_OK;
 }
 
+hms_status hms_tune(const hms_cnf* cnf, const hms_solve_params* params, int32_t iters, int32_t* schedule,
+                    double* step_ms) {
+    g_err.clear();
+    if (check_cnf(cnf) || !params || iters < 1) return fail(HMS_ERR_ARG, "null argument or iters < 1");
+    DeviceGuard dg(cnf->device);
+    int32_t best = 0;
+    double ms = 0;
+    hms_status rc = tune(cnf, params, iters, best, ms);
+    if (rc) return rc;
+    if (schedule) *schedule = best;
+    if (step_ms) *step_ms = ms;
+    return HMS_OK;
+}
+
 hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t R, int32_t loss_mode, double* loss,
                             float* grad, int64_t* unsat, void* stream) {
     g_err.clear();
@@ -668,36 +823,27 @@ hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t R, int32
     DeviceGuard dg(cnf->device);
     hipStream_t s = (hipStream_t)stream;
     Shape sh;
-    hms_status rc = make_shape(P, R, 0, sh);
+    hms_status rc = make_shape(P, R, 0, loss_mode, sh);
     if (rc) return rc;
     const bool want_g = grad != nullptr;
     Layout lay;
-    size_t off[16];
-    layout_state(P, sh, R, false, want_g, false, lay, off);
+    size_t off[kOffN];
+    layout_state(P, sh, false, want_g, false, lay, off);
     Arena A;
     A.s = s;
     HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
     State S = bind_state(A, off, false, want_g, false);
-    hms::InitArgs ia{};
-    ia.n = P.n;
-    ia.R = R;
-    ia.a_zero_row = P.a_zero_row();
-    ia.m = P.m;
-    ia.var_old = cnf->var_old;
+    hms::InitArgs ia = make_init(cnf, sh, S);
     ia.x0 = x;
-    ia.x = S.x;
-    ia.t = S.t;
-    ia.a = S.a;
-    ia.st = S.st;
     HIPTRY(hms::launch_init(ia, s));
-    Launch L = make_launch(cnf, sh, S, R, hms::kGrad, loss_mode, 0.f, 0.9f, 0.999f, 1e-8f);
+    Launch L = make_launch(cnf, sh, S, hms::kGrad, loss_mode, 0.f, 0.9f, 0.999f, 1e-8f);
     L.ra.track = 0;
     HIPTRY(hms::launch_fwd(sh.sched, true, L.fa, sh.fwd_blocks, s));
     HIPTRY(hms::launch_reduce(L.ra, s));
     if (want_g) {
         HIPTRY(hms::launch_bwd(sh.sched, hms::kGrad, L.ba, sh.bwd_blocks, s));
         HIPTRY(hms::launch_combine(hms::kGrad, L.ba, s));
-        HIPTRY(hms::launch_scatter(P.n, P.n_act, R, cnf->var_old, S.g, grad, s));
+        HIPTRY(hms::launch_scatter(P.n, P.n_act, sh.B, cnf->var_old, S.g, grad, s));
     }
     if (loss) HIPTRY(hipMemcpyAsync(loss, S.cur_loss, R * 8, hipMemcpyDeviceToHost, s));
     if (unsat) HIPTRY(hipMemcpyAsync(unsat, S.cur_count, R * 8, hipMemcpyDeviceToHost, s));
@@ -712,11 +858,11 @@ hms_status hms_evaluate(const hms_cnf* cnf, const uint8_t* assignment, int64_t* 
     DeviceGuard dg(cnf->device);
     hipStream_t s = (hipStream_t)stream;
     Shape sh;
-    hms_status rc = make_shape(P, 1, 1, sh);
+    hms_status rc = make_shape(P, 1, 1, HMS_LOSS_UNSAT, sh);
     if (rc) return rc;
     Layout lay;
-    size_t off[16];
-    layout_state(P, sh, 1, false, false, false, lay, off);
+    size_t off[kOffN];
+    layout_state(P, sh, false, false, false, lay, off);
     const size_t o_in = lay.add((size_t)std::max(P.n, 1));
     Arena A;
     A.s = s;
@@ -724,19 +870,10 @@ hms_status hms_evaluate(const hms_cnf* cnf, const uint8_t* assignment, int64_t* 
     State S = bind_state(A, off, false, false, false);
     uint8_t* d_in = A.at<uint8_t>(o_in);
     if (P.n > 0) HIPTRY(hipMemcpyAsync(d_in, assignment, P.n, hipMemcpyHostToDevice, s));
-    hms::InitArgs ia{};
-    ia.n = P.n;
-    ia.R = 1;
-    ia.a_zero_row = P.a_zero_row();
-    ia.m = P.m;
-    ia.var_old = cnf->var_old;
+    hms::InitArgs ia = make_init(cnf, sh, S);
     ia.assign0 = d_in;
-    ia.x = S.x;
-    ia.t = S.t;
-    ia.a = S.a;
-    ia.st = S.st;
     HIPTRY(hms::launch_init(ia, s));
-    Launch L = make_launch(cnf, sh, S, 1, hms::kGrad, HMS_LOSS_UNSAT, 0.f, 0.9f, 0.999f, 1e-8f);
+    Launch L = make_launch(cnf, sh, S, hms::kGrad, HMS_LOSS_UNSAT, 0.f, 0.9f, 0.999f, 1e-8f);
     L.ra.track = 0;
     HIPTRY(hms::launch_fwd(sh.sched, true, L.fa, sh.fwd_blocks, s));
     HIPTRY(hms::launch_reduce(L.ra, s));

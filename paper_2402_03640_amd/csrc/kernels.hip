@@ -3,8 +3,8 @@
 // Summation order contract: the score of a clause is summed over its entries
 // in plan order, and the transposed sum of a variable row over its entries in
 // plan order, one lane per (row, restart), whatever the schedule.  Heavy rows
-// are summed per segment, and segment partials are combined by a fixed
-// 64-slot tree.  Hence x, m, v and every count are bitwise independent of the
+// are summed per segment, and segment partials are combined by a fixed tree
+// (64 or 1024 slots, chosen by the instance).  Hence x, m, v and every count are bitwise independent of the
 // schedule and of R; only the FP64 loss total depends on the schedule's unit
 // size.
 #include "kernels.hpp"
@@ -16,11 +16,12 @@
 namespace hms {
 
 const Schedule kSchedules[kNumSchedules + 1] = {
-    {0, 0, 0},                                                               // 0: automatic
-    {1, 1, 1},  {2, 1, 1},  {4, 1, 1},  {8, 1, 1},  {8, 1, 2},  {16, 1, 1},  // 1..6
-    {16, 1, 2}, {16, 1, 4}, {32, 1, 2}, {32, 1, 4}, {64, 1, 1}, {64, 1, 2},  // 7..12
-    {64, 1, 4}, {64, 1, 8}, {16, 4, 1}, {16, 4, 2}, {32, 2, 2}, {32, 2, 4},  // 13..18
-    {64, 2, 2}, {64, 2, 4}, {64, 4, 1}, {64, 4, 2},                          // 19..22
+    {0, 0, 0, 0},                                                                          // 0: automatic
+    {1, 1, 1, 0},  {2, 1, 1, 0},  {4, 1, 1, 0},  {8, 1, 1, 0},  {8, 1, 2, 0},  {16, 1, 1, 0},  // 1..6
+    {16, 1, 2, 0}, {16, 1, 4, 0}, {32, 1, 2, 0}, {32, 1, 4, 0}, {64, 1, 1, 0}, {64, 1, 2, 0},  // 7..12
+    {64, 1, 4, 0}, {64, 1, 8, 0}, {16, 4, 1, 0}, {16, 4, 2, 0}, {32, 2, 2, 0}, {32, 2, 4, 0},  // 13..18
+    {64, 2, 2, 0}, {64, 2, 4, 0}, {64, 4, 1, 0}, {64, 4, 2, 0}, {1, 1, 1, 1},  {2, 1, 1, 1},   // 19..24
+    {4, 1, 1, 1},  {2, 4, 1, 0},  {4, 2, 1, 0},  {8, 1, 4, 0},                                // 25..28
 };
 
 int default_rows_per_unit(int sched) {
@@ -28,6 +29,7 @@ int default_rows_per_unit(int sched) {
     const int per_pass = (64 / c.P) * c.UR;
     int U = per_pass * 2;
     if (U < 8) U = 8;
+    if (c.mask && U < 32) U = 32;
     return U > 64 ? 64 : U;
 }
 
@@ -101,13 +103,39 @@ __device__ __forceinline__ TileDesc ldtile(const TileDesc* p) {
     return TileDesc{ldc(w), ldc(w + 1), ldc(w + 2), ldc(w + 3)};
 }
 
+// Compact the ballot bits of lanes 0, P, 2P, ... into consecutive bits.
+template <int P>
+__device__ __forceinline__ uint64_t compact_bits(uint64_t x) {
+    if constexpr (P == 1) {
+        return x;
+    } else if constexpr (P == 2) {
+        x &= 0x5555555555555555ull;
+        x = (x | (x >> 1)) & 0x3333333333333333ull;
+        x = (x | (x >> 2)) & 0x0f0f0f0f0f0f0f0full;
+        x = (x | (x >> 4)) & 0x00ff00ff00ff00ffull;
+        x = (x | (x >> 8)) & 0x0000ffff0000ffffull;
+        x = (x | (x >> 16)) & 0x00000000ffffffffull;
+        return x;
+    } else {
+        static_assert(P == 4, "bitset schedules use 1, 2 or 4 lanes per row");
+        x &= 0x1111111111111111ull;
+        x = (x | (x >> 3)) & 0x0303030303030303ull;
+        x = (x | (x >> 6)) & 0x000f000f000f000full;
+        x = (x | (x >> 12)) & 0x000000ff000000ffull;
+        x = (x | (x >> 24)) & 0x000000000000ffffull;
+        return x;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Forward: scores, unsat mask, adjoint a_j = (2/m) mu_j f_j, unit partials.
-// A wave takes a unit of U rows of one tile for one group of P*V restarts;
-// lane (s, q) handles UR consecutive rows per pass for restarts r0..r0+V-1,
-// column by column so that UR gathers are in flight together.
+// Workgroup b works on restart group b % RG; each wave takes a unit of U rows
+// of one tile; lane (s, q) handles UR consecutive rows per pass for restarts
+// rl..rl+V-1 of the group, column by column so that UR gathers are in flight
+// together.  With MASK the unsat bits of the unit's rows are written to the
+// bitset and the adjoint only for unsatisfied rows.
 // ---------------------------------------------------------------------------
-template <int P, int V, int UR, bool EVAL>
+template <int P, int V, int UR, bool EVAL, bool MASK>
 __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
     constexpr int W = 64 / P;
     const int lane = threadIdx.x & 63;
@@ -120,111 +148,127 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
         A.st->step_size = (float)(A.lr / bc1);
         A.st->inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
     }
-    const int nunits = A.ntiles * A.chunks * A.RG;
+    const Blocking B = A.B;
+    const int rg = blockIdx.x % B.RG;
+    const int tc = __builtin_amdgcn_readfirstlane((blockIdx.x / B.RG) * 4 + (threadIdx.x >> 6));
+    if (tc >= A.ntiles * A.chunks) return;
+    const int tile = tc / A.chunks;
+    const int chunk = tc % A.chunks;
+    const TileDesc d = ldtile(A.tiles + tile);
+    const int rl = q * V;
+    const int r0 = rg * B.G + rl;
+    const bool ract = rl < B.G && r0 < B.R;
+    const bool taut = (d.flags & 1u) != 0;
+    const float* tg = A.t + (size_t)rg * B.rows_x * B.G;
+    float* ag = A.a + (size_t)rg * B.rows_a * B.G;
     const int passes = A.U / (W * UR);
-    for (int u = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); u < nunits;
-         u += gridDim.x * 4) {
-        const int rg = u % A.RG;
-        const int tc = u / A.RG;
-        const int tile = tc / A.chunks;
-        const int chunk = tc % A.chunks;
-        const TileDesc d = ldtile(A.tiles + tile);
-        const int r0 = rg * (P * V) + q * V;
-        const bool ract = r0 < A.R;
-        const bool taut = (d.flags & 1u) != 0;
-        int cnt[V];
-        double los[V];
+    int cnt[V];
+    double los[V];
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            cnt[k] = 0;
-            los[k] = 0.0;
-        }
-        for (int pass = 0; pass < passes; ++pass) {
-            const int rowin0 = chunk * A.U + pass * (W * UR) + s * UR;
-            const uint32_t* e = A.ent + d.base + rowin0;
-            float f[UR][V];
-            uint32_t allf[UR][V];
+    for (int k = 0; k < V; ++k) {
+        cnt[k] = 0;
+        los[k] = 0.0;
+    }
+    uint64_t mbits = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int rowin0 = chunk * A.U + pass * (W * UR) + s * UR;
+        const uint32_t* e = A.ent + d.base + rowin0;
+        float f[UR][V];
+        uint32_t allf[UR][V];
 #pragma unroll
-            for (int j = 0; j < UR; ++j)
+        for (int j = 0; j < UR; ++j)
 #pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    f[j][k] = 0.0f;
-                    allf[j][k] = ~0u;
-                }
-            if (ract) {
-                if (d.len <= 16) {
+            for (int k = 0; k < V; ++k) {
+                f[j][k] = 0.0f;
+                allf[j][k] = ~0u;
+            }
+        if (ract) {
+            if (d.len <= 16) {
 #pragma unroll 2
-                    for (uint32_t c = 0; c < d.len; ++c) {
-                        uint32_t en[UR];
+                for (uint32_t c = 0; c < d.len; ++c) {
+                    uint32_t en[UR];
 #pragma unroll
-                        for (int j = 0; j < UR; ++j) en[j] = ldc(e + (size_t)c * kTile + j);
-                        VecF<V> tv[UR];
+                    for (int j = 0; j < UR; ++j) en[j] = ldc(e + (size_t)c * kTile + j);
+                    VecF<V> tv[UR];
 #pragma unroll
-                        for (int j = 0; j < UR; ++j) tv[j] = ldv<V>(A.t + (size_t)(en[j] & kIdx) * A.R + r0);
+                    for (int j = 0; j < UR; ++j) tv[j] = ldv<V>(tg + (size_t)(en[j] & kIdx) * B.G + rl);
 #pragma unroll
-                        for (int j = 0; j < UR; ++j)
+                    for (int j = 0; j < UR; ++j)
 #pragma unroll
-                            for (int k = 0; k < V; ++k) {
-                                const uint32_t b = __float_as_uint(tv[j].v[k]) ^ (en[j] & kSign);
-                                f[j][k] = f[j][k] + __uint_as_float(b);
-                                allf[j][k] &= b;
-                            }
-                    }
-                } else {
-                    // long clauses: FP64 accumulation, one row at a time
-#pragma unroll
-                    for (int j = 0; j < UR; ++j) {
-                        double fd[V];
-#pragma unroll
-                        for (int k = 0; k < V; ++k) fd[k] = 0.0;
-#pragma unroll 4
-                        for (uint32_t c = 0; c < d.len; ++c) {
-                            const uint32_t en = ldc(e + (size_t)c * kTile + j);
-                            const VecF<V> tv = ldv<V>(A.t + (size_t)(en & kIdx) * A.R + r0);
-#pragma unroll
-                            for (int k = 0; k < V; ++k) {
-                                const uint32_t b = __float_as_uint(tv.v[k]) ^ (en & kSign);
-                                fd[k] = fd[k] + (double)__uint_as_float(b);
-                                allf[j][k] &= b;
-                            }
+                        for (int k = 0; k < V; ++k) {
+                            const uint32_t b = __float_as_uint(tv[j].v[k]) ^ (en[j] & kSign);
+                            f[j][k] = f[j][k] + __uint_as_float(b);
+                            allf[j][k] &= b;
                         }
-#pragma unroll
-                        for (int k = 0; k < V; ++k) f[j][k] = (float)fd[k];
-                    }
                 }
+            } else {
+                // long clauses: FP64 accumulation, one row at a time
 #pragma unroll
                 for (int j = 0; j < UR; ++j) {
-                    const bool real = rowin0 + j < (int)d.nreal;
-                    VecF<V> av;
+                    double fd[V];
 #pragma unroll
-                    for (int k = 0; k < V; ++k) {
-                        const bool unsat = real && !taut && (allf[j][k] >> 31) != 0;
-                        const bool mu = real && (A.all_mode ? true : unsat);
-                        av.v[k] = mu ? f[j][k] * A.two_over_m : 0.0f;
-                        if (EVAL) {
-                            cnt[k] += unsat ? 1 : 0;
-                            los[k] += mu ? (double)f[j][k] * (double)f[j][k] : 0.0;
+                    for (int k = 0; k < V; ++k) fd[k] = 0.0;
+#pragma unroll 4
+                    for (uint32_t c = 0; c < d.len; ++c) {
+                        const uint32_t en = ldc(e + (size_t)c * kTile + j);
+                        const VecF<V> tv = ldv<V>(tg + (size_t)(en & kIdx) * B.G + rl);
+#pragma unroll
+                        for (int k = 0; k < V; ++k) {
+                            const uint32_t b = __float_as_uint(tv.v[k]) ^ (en & kSign);
+                            fd[k] = fd[k] + (double)__uint_as_float(b);
+                            allf[j][k] &= b;
                         }
                     }
-                    stv<V>(A.a + (size_t)(tile * kTile + rowin0 + j) * A.R + r0, av);
+#pragma unroll
+                    for (int k = 0; k < V; ++k) f[j][k] = (float)fd[k];
                 }
             }
         }
-        if (EVAL) {
 #pragma unroll
-            for (int off = P; off < 64; off <<= 1) {
+        for (int j = 0; j < UR; ++j) {
+            const bool real = ract && rowin0 + j < (int)d.nreal;
+            VecF<V> av;
+            bool any_mu = false;
 #pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    cnt[k] += __shfl_xor(cnt[k], off);
-                    los[k] += __shfl_xor(los[k], off);
+            for (int k = 0; k < V; ++k) {
+                const bool unsat = real && !taut && (allf[j][k] >> 31) != 0;
+                const bool mu = real && (A.all_mode ? true : unsat);
+                av.v[k] = mu ? f[j][k] * A.two_over_m : 0.0f;
+                any_mu = any_mu || mu;
+                if (EVAL) {
+                    cnt[k] += unsat ? 1 : 0;
+                    los[k] += mu ? (double)f[j][k] * (double)f[j][k] : 0.0;
                 }
             }
-            if (s == 0 && ract) {
+            if constexpr (MASK) {
+                mbits |= compact_bits<P>(__ballot(any_mu ? 1 : 0)) << (pass * W);
+                if (any_mu) stv<V>(ag + (size_t)(tile * kTile + rowin0 + j) * B.G + rl, av);
+            } else if (ract) {
+                stv<V>(ag + (size_t)(tile * kTile + rowin0 + j) * B.G + rl, av);
+            }
+        }
+    }
+    if constexpr (MASK) {
+        if (lane == 0) {
+            uint32_t* w = A.umask + ((size_t)tile * kTile + chunk * A.U) / 32;
+            w[0] = (uint32_t)mbits;
+            if (A.U == 64) w[1] = (uint32_t)(mbits >> 32);
+        }
+    }
+    if (EVAL) {
 #pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    A.cnt_part[(size_t)tc * A.R + r0 + k] = cnt[k];
-                    A.loss_part[(size_t)tc * A.R + r0 + k] = los[k];
-                }
+        for (int off = P; off < 64; off <<= 1) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                cnt[k] += __shfl_xor(cnt[k], off);
+                los[k] += __shfl_xor(los[k], off);
+            }
+        }
+        if (s == 0 && ract) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                A.cnt_part[(size_t)tc * B.R + r0 + k] = cnt[k];
+                A.loss_part[(size_t)tc * B.R + r0 + k] = los[k];
             }
         }
     }
@@ -232,11 +276,12 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
 
 // ---------------------------------------------------------------------------
 // Epilogue of a variable: g = sech^2(x) G, then the optimizer step (or the
-// gradient itself), t = signed tanh of the new x.
+// gradient itself), t = signed tanh of the new x.  `base` is the element
+// offset of (variable, first restart) in the blocked state arrays; r0 is the
+// first restart's index.
 // ---------------------------------------------------------------------------
 template <int V, int OPT>
-__device__ __forceinline__ void var_epilogue(const BwdArgs& A, int var, int r0, const double (&G)[V]) {
-    const size_t base = (size_t)var * A.R + r0;
+__device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int r0, const double (&G)[V]) {
     VecF<V> xv = ldv<V>(A.x + base);
     if (A.eval) {
 #pragma unroll
@@ -285,96 +330,181 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, int var, int r0, 
 // ---------------------------------------------------------------------------
 // Backward: transposed sums G = sum_j W_ij a_j over variable rows (atomic-free;
 // each (row, restart) summed by one lane in FP64 in entry order), fused
-// epilogue for whole rows, partials for heavy-row segments.
+// epilogue for whole rows, partials for heavy-row segments.  With MASK the
+// adjoint of a clause is read only when its unsat bit is set (it is 0
+// otherwise).
 // ---------------------------------------------------------------------------
-template <int P, int V, int UR, int OPT>
+template <int P, int V, int UR, int OPT, bool MASK>
 __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
     constexpr int W = 64 / P;
     const int lane = threadIdx.x & 63;
     const int s = lane / P;
     const int q = lane % P;
     if (OPT != kGrad && blockIdx.x == 0 && threadIdx.x == 0) A.st->t += 1;
-    const int nunits = A.ntiles * A.chunks * A.RG;
+    const Blocking B = A.B;
+    const int rg = blockIdx.x % B.RG;
+    const int tc = __builtin_amdgcn_readfirstlane((blockIdx.x / B.RG) * 4 + (threadIdx.x >> 6));
+    if (tc >= A.ntiles * A.chunks) return;
+    const int tile = tc / A.chunks;
+    const int chunk = tc % A.chunks;
+    const TileDesc d = ldtile(A.tiles + tile);
+    const int rl = q * V;
+    const int r0 = rg * B.G + rl;
+    if (rl >= B.G || r0 >= B.R) return;
+    const bool segtile = tile < A.seg_tiles;
+    const float* ag = A.a + (size_t)rg * B.rows_a * B.G;
+    const size_t xbase = (size_t)rg * B.rows_x * B.G;
+    double* sg = A.seg_part + (size_t)rg * B.rows_seg * B.G;
     const int passes = A.U / (W * UR);
-    for (int u = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); u < nunits;
-         u += gridDim.x * 4) {
-        const int rg = u % A.RG;
-        const int tc = u / A.RG;
-        const int tile = tc / A.chunks;
-        const int chunk = tc % A.chunks;
-        const TileDesc d = ldtile(A.tiles + tile);
-        const int r0 = rg * (P * V) + q * V;
-        if (r0 >= A.R) continue;
-        const bool segtile = tile < A.seg_tiles;
-        for (int pass = 0; pass < passes; ++pass) {
-            const int rowin0 = chunk * A.U + pass * (W * UR) + s * UR;
-            if (rowin0 >= (int)d.nreal) break;
-            const uint32_t* e = A.ent + d.base + rowin0;
-            double G[UR][V];
+    for (int pass = 0; pass < passes; ++pass) {
+        const int rowin0 = chunk * A.U + pass * (W * UR) + s * UR;
+        if (rowin0 >= (int)d.nreal) break;
+        const uint32_t* e = A.ent + d.base + rowin0;
+        double G[UR][V];
+#pragma unroll
+        for (int j = 0; j < UR; ++j)
+#pragma unroll
+            for (int k = 0; k < V; ++k) G[j][k] = 0.0;
+#pragma unroll((P * 4 <= 8 && UR == 1 && V == 1) ? 8 : 2)
+        for (uint32_t c = 0; c < d.len; ++c) {
+            uint32_t en[UR];
+#pragma unroll
+            for (int j = 0; j < UR; ++j) en[j] = ldc(e + (size_t)c * kTile + j);
+            VecF<V> av[UR];
+            if constexpr (MASK) {
+#pragma unroll
+                for (int j = 0; j < UR; ++j) {
+                    const uint32_t row = en[j] & kIdx;
+                    const uint32_t w = A.umask[row >> 5];
+#pragma unroll
+                    for (int k = 0; k < V; ++k) av[j].v[k] = 0.0f;
+                    if ((w >> (row & 31)) & 1u) av[j] = ldv<V>(ag + (size_t)row * B.G + rl);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < UR; ++j) av[j] = ldv<V>(ag + (size_t)(en[j] & kIdx) * B.G + rl);
+            }
 #pragma unroll
             for (int j = 0; j < UR; ++j)
 #pragma unroll
-                for (int k = 0; k < V; ++k) G[j][k] = 0.0;
-#pragma unroll 2
-            for (uint32_t c = 0; c < d.len; ++c) {
-                uint32_t en[UR];
+                for (int k = 0; k < V; ++k)
+                    G[j][k] = G[j][k] + (double)__uint_as_float(__float_as_uint(av[j].v[k]) ^ (en[j] & kSign));
+        }
 #pragma unroll
-                for (int j = 0; j < UR; ++j) en[j] = ldc(e + (size_t)c * kTile + j);
-                VecF<V> av[UR];
+        for (int j = 0; j < UR; ++j) {
+            if (rowin0 + j >= (int)d.nreal) break;
+            const int row = tile * kTile + rowin0 + j;
+            if (segtile) {
 #pragma unroll
-                for (int j = 0; j < UR; ++j) av[j] = ldv<V>(A.a + (size_t)(en[j] & kIdx) * A.R + r0);
-#pragma unroll
-                for (int j = 0; j < UR; ++j)
-#pragma unroll
-                    for (int k = 0; k < V; ++k)
-                        G[j][k] = G[j][k] + (double)__uint_as_float(__float_as_uint(av[j].v[k]) ^ (en[j] & kSign));
-            }
-#pragma unroll
-            for (int j = 0; j < UR; ++j) {
-                if (rowin0 + j >= (int)d.nreal) break;
-                const int row = tile * kTile + rowin0 + j;
-                if (segtile) {
-#pragma unroll
-                    for (int k = 0; k < V; ++k) A.seg_part[(size_t)row * A.R + r0 + k] = G[j][k];
-                } else {
-                    const int var = A.n_heavy + (row - A.seg_tiles * kTile);
-                    var_epilogue<V, OPT>(A, var, r0, G[j]);
-                }
+                for (int k = 0; k < V; ++k) sg[(size_t)row * B.G + rl + k] = G[j][k];
+            } else {
+                const int var = A.n_heavy + (row - A.seg_tiles * kTile);
+                var_epilogue<V, OPT>(A, xbase + (size_t)var * B.G + rl, r0, G[j]);
             }
         }
     }
 }
 
-// Heavy variables: combine segment partials.  One wavefront per (variable,
-// restart); slot q sums segments q, q+64, ... in order, then a fixed tree.
+// Heavy variables: combine segment partials in a fixed order that depends on
+// the instance only.  A variable with at most kWideSegs segments uses 64
+// slots (one wavefront): slot q sums segments q, q+64, ... in order, then a
+// fixed halving tree.  Wider variables use 1024 slots (one workgroup) the same
+// way.  One launch of 1024-thread workgroups: the first n_heavy_wide * R
+// workgroups take one wide (variable, restart) each, the rest take sixteen
+// narrow ones (one per wavefront).
 template <int OPT>
-__global__ __launch_bounds__(256) void k_combine(BwdArgs A) {
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (w >= A.n_heavy * A.R) return;
-    const int h = w / A.R;
-    const int r = w % A.R;
+__global__ __launch_bounds__(1024) void k_combine(BwdArgs A) {
+    __shared__ double su[1024];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const Blocking B = A.B;
+    const int nwide = A.n_heavy_wide * B.R;
+    int h, r;
     double u = 0.0;
-    for (int p = A.seg_first[h] + lane; p < A.seg_first[h + 1]; p += 64)
-        u = u + A.seg_part[(size_t)A.seg_row[p] * A.R + r];
+    if ((int)blockIdx.x < nwide) {
+        h = blockIdx.x / B.R;
+        r = blockIdx.x % B.R;
+        const double* sg = A.seg_part + (size_t)(r / B.G) * B.rows_seg * B.G + r % B.G;
+        const int p1 = A.seg_first[h + 1];
+#pragma unroll 8
+        for (int p = A.seg_first[h] + tid; p < p1; p += 1024) u = u + sg[(size_t)A.seg_row[p] * B.G];
+        su[tid] = u;
+        __syncthreads();
+        for (int s = 512; s >= 1; s >>= 1) {
+            if (tid < s) su[tid] = su[tid] + su[tid + s];
+            __syncthreads();
+        }
+        if (tid != 0) return;
+        u = su[0];
+    } else {
+        const int w = (blockIdx.x - nwide) * 16 + (tid >> 6);
+        if (w >= (A.n_heavy - A.n_heavy_wide) * B.R) return;
+        h = A.n_heavy_wide + w / B.R;
+        r = w % B.R;
+        const double* sg = A.seg_part + (size_t)(r / B.G) * B.rows_seg * B.G + r % B.G;
+        const int p1 = A.seg_first[h + 1];
+#pragma unroll 8
+        for (int p = A.seg_first[h] + lane; p < p1; p += 64) u = u + sg[(size_t)A.seg_row[p] * B.G];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) u = u + __shfl_down(u, off);
-    if (lane == 0) {
-        double G[1] = {u};
-        var_epilogue<1, OPT>(A, h, r, G);
+        for (int off = 32; off >= 1; off >>= 1) u = u + __shfl_down(u, off);
+        if (lane != 0) return;
+    }
+    double G[1] = {u};
+    var_epilogue<1, OPT>(A, ((size_t)(r / B.G) * B.rows_x + h) * B.G + r % B.G, r, G);
+}
+
+// Count/loss partials are summed in two fixed stages.  Stage 1: block
+// (restart block rb, chunk c) sums units [c * CH, (c + 1) * CH) for 64
+// restarts: lane l of the 256 threads holds restart 64 rb + (l % RP) and slot
+// l / RP; a slot sums its units with stride NS = 256 / RP in order, then a
+// fixed tree over the slots.  Stage 2 sums the chunk partials the same way
+// with one 1024-thread block per restart block, and tracks the best.
+__device__ __forceinline__ int restart_lanes(int R) {
+    int RP = 1;  // restarts side by side: the next power of two >= R, at most 64
+    while (RP < 64 && RP < R) RP <<= 1;
+    return RP;
+}
+
+__global__ __launch_bounds__(256) void k_reduce1(ReduceArgs A) {
+    __shared__ int32_t sc[256];
+    __shared__ double sl[256];
+    const int tid = threadIdx.x;
+    const int RP = restart_lanes(A.R);
+    const int NS = 256 / RP;
+    const int rloc = tid % RP;
+    const int slot = tid / RP;
+    const int r = blockIdx.x * 64 + rloc;
+    const int u0 = blockIdx.y * A.chunk;
+    const int u1 = min(u0 + A.chunk, A.n_units);
+    int32_t c = 0;
+    double l = 0.0;
+    if (r < A.R) {
+        for (int u = u0 + slot; u < u1; u += NS) {
+            c += A.cnt_part[(size_t)u * A.R + r];
+            l = l + A.loss_part[(size_t)u * A.R + r];
+        }
+    }
+    sc[tid] = c;
+    sl[tid] = l;
+    __syncthreads();
+    for (int h = NS / 2; h >= 1; h >>= 1) {
+        if (slot < h) {
+            sc[tid] += sc[tid + h * RP];
+            sl[tid] = sl[tid] + sl[tid + h * RP];
+        }
+        __syncthreads();
+    }
+    if (slot == 0 && r < A.R) {
+        A.cnt_mid[(size_t)blockIdx.y * A.R + r] = sc[tid];
+        A.loss_mid[(size_t)blockIdx.y * A.R + r] = sl[tid];
     }
 }
 
-// Sum the unit partials of each restart in a fixed order; track the best.
-// Block b covers restarts [64 b, 64 b + 64); lane l of wave w holds restart
-// 64 b + (l % RP) and slot (w * 64 + l) / RP; slot k sums units k, k + NS, ...
-// in order, then a fixed tree over the NS slots.
 __global__ __launch_bounds__(1024) void k_reduce(ReduceArgs A) {
     __shared__ int64_t sc[1024];
     __shared__ double sl[1024];
     const int tid = threadIdx.x;
-    int RP = 1;  // restarts side by side: the next power of two >= R, at most 64
-    while (RP < 64 && RP < A.R) RP <<= 1;
+    const int RP = restart_lanes(A.R);
     const int NS = 1024 / RP;
     const int rloc = tid % RP;
     const int slot = tid / RP;
@@ -382,9 +512,9 @@ __global__ __launch_bounds__(1024) void k_reduce(ReduceArgs A) {
     int64_t c = 0;
     double l = 0.0;
     if (r < A.R) {
-        for (int u = slot; u < A.n_units; u += NS) {
-            c += A.cnt_part[(size_t)u * A.R + r];
-            l = l + A.loss_part[(size_t)u * A.R + r];
+        for (int u = slot; u < A.n_chunks; u += NS) {
+            c += A.cnt_mid[(size_t)u * A.R + r];
+            l = l + A.loss_mid[(size_t)u * A.R + r];
         }
     }
     sc[tid] = c;
@@ -413,41 +543,50 @@ __global__ __launch_bounds__(1024) void k_reduce(ReduceArgs A) {
     }
 }
 
+// Element offset of (row, restart r) in a blocked array with `rows` rows.
+__device__ __forceinline__ size_t boff(const Blocking& B, int rows, int row, int r) {
+    return ((size_t)(r / B.G) * rows + row) * B.G + (r % B.G);
+}
+
 // State initialisation: x^0 (caller values, an assignment, or SplitMix64),
 // t = signed tanh(x), zero moments, the dummy rows, best = m.
 __global__ __launch_bounds__(256) void k_init(InitArgs A) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t total = (int64_t)A.n * A.R;
+    const Blocking B = A.B;
+    const int64_t total = (int64_t)A.n * B.R;
     if (idx < total) {
-        const int32_t i = (int32_t)(idx / A.R);
-        const int32_t r = (int32_t)(idx % A.R);
+        const int32_t i = (int32_t)(idx / B.R);
+        const int32_t r = (int32_t)(idx % B.R);
         const int32_t o = A.var_old[i];
         float x;
         if (A.x0 != nullptr) {
-            x = A.x0[(size_t)o * A.R + r];
+            x = A.x0[(size_t)o * B.R + r];
         } else if (A.assign0 != nullptr) {
             x = A.assign0[o] ? 1.0f : -1.0f;
         } else {
             const uint64_t z = splitmix64(A.seed + (uint64_t)r, (uint64_t)o + 1);
             x = 2.0f * ((float)(z >> 40) * (1.0f / 16777216.0f)) - 1.0f;
         }
-        A.x[idx] = x;
-        A.t[idx] = signed_tanh(x);
+        const size_t e = boff(B, B.rows_x, i, r);
+        A.x[e] = x;
+        A.t[e] = signed_tanh(x);
         if (A.mm != nullptr) {
-            A.mm[idx] = 0.0f;
-            A.vv[idx] = 0.0f;
+            A.mm[e] = 0.0f;
+            A.vv[e] = 0.0f;
         }
-        if (A.best_a != nullptr) A.best_a[idx] = x > 0.0f ? 1 : 0;
+        if (A.best_a != nullptr) A.best_a[e] = x > 0.0f ? 1 : 0;
     }
-    if (idx < A.R) {
-        A.t[(size_t)A.n * A.R + idx] = -0.0f;
-        A.a[(size_t)A.a_zero_row * A.R + idx] = 0.0f;
+    if (idx < B.R) {
+        const int r = (int)idx;
+        A.t[boff(B, B.rows_x, A.n, r)] = -0.0f;
+        A.a[boff(B, B.rows_a, A.a_zero_row, r)] = 0.0f;
         if (A.best != nullptr) {
-            A.best[idx] = A.m;
-            A.best_step[idx] = -1;
-            A.improved[idx] = 0;
+            A.best[r] = A.m;
+            A.best_step[r] = -1;
+            A.improved[r] = 0;
         }
     }
+    if (A.umask != nullptr && idx < A.umask_words) A.umask[idx] = 0u;
     if (idx == 0 && A.st != nullptr) {
         A.st->t = 0;
         A.st->step_size = 0.0f;
@@ -455,47 +594,51 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_snapshot(int32_t n_act, int32_t R, const float* x,
+__global__ __launch_bounds__(256) void k_snapshot(int32_t n_act, Blocking B, const float* x,
                                                    const int32_t* improved, uint8_t* best_a) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int64_t)n_act * R) return;
-    const int32_t r = (int32_t)(idx % R);
-    if (improved[r]) best_a[idx] = x[idx] > 0.0f ? 1 : 0;
+    if (idx >= (int64_t)n_act * B.R) return;
+    const int32_t i = (int32_t)(idx / B.R);
+    const int32_t r = (int32_t)(idx % B.R);
+    if (improved[r]) {
+        const size_t e = boff(B, B.rows_x, i, r);
+        best_a[e] = x[e] > 0.0f ? 1 : 0;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_extract(int32_t n, int32_t R, int32_t r, const int32_t* var_old,
+__global__ __launch_bounds__(256) void k_extract(int32_t n, Blocking B, int32_t r, const int32_t* var_old,
                                                   const uint8_t* best_a, uint8_t* out) {
     const int32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    out[var_old[i]] = best_a[(size_t)i * R + r];
+    out[var_old[i]] = best_a[boff(B, B.rows_x, i, r)];
 }
 
-__global__ __launch_bounds__(256) void k_scatter(int32_t n, int32_t n_act, int32_t R, const int32_t* var_old,
+__global__ __launch_bounds__(256) void k_scatter(int32_t n, int32_t n_act, Blocking B, const int32_t* var_old,
                                                   const float* src, float* dst) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int64_t)n * R) return;
-    const int32_t i = (int32_t)(idx / R);
-    const int32_t r = (int32_t)(idx % R);
-    dst[(size_t)var_old[i] * R + r] = i < n_act ? src[idx] : 0.0f;
+    if (idx >= (int64_t)n * B.R) return;
+    const int32_t i = (int32_t)(idx / B.R);
+    const int32_t r = (int32_t)(idx % B.R);
+    dst[(size_t)var_old[i] * B.R + r] = i < n_act ? src[boff(B, B.rows_x, i, r)] : 0.0f;
 }
 
-template <int P, int V, int UR>
+template <int P, int V, int UR, int MASK>
 hipError_t fwd_for(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
     if (eval)
-        hipLaunchKernelGGL((k_fwd<P, V, UR, true>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_fwd<P, V, UR, true, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
     else
-        hipLaunchKernelGGL((k_fwd<P, V, UR, false>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_fwd<P, V, UR, false, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
-template <int P, int V, int UR>
+template <int P, int V, int UR, int MASK>
 hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
     if (opt == kAdam)
-        hipLaunchKernelGGL((k_bwd<P, V, UR, kAdam>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kAdam, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
     else if (opt == kSgd)
-        hipLaunchKernelGGL((k_bwd<P, V, UR, kSgd>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kSgd, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
     else
-        hipLaunchKernelGGL((k_bwd<P, V, UR, kGrad>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kGrad, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
@@ -503,28 +646,34 @@ hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
 
 #define HMS_SCHED_SWITCH(FN, ...)                          \
     switch (sched) {                                       \
-        case 1: return FN<1, 1, 1>(__VA_ARGS__);           \
-        case 2: return FN<2, 1, 1>(__VA_ARGS__);           \
-        case 3: return FN<4, 1, 1>(__VA_ARGS__);           \
-        case 4: return FN<8, 1, 1>(__VA_ARGS__);           \
-        case 5: return FN<8, 1, 2>(__VA_ARGS__);           \
-        case 6: return FN<16, 1, 1>(__VA_ARGS__);          \
-        case 7: return FN<16, 1, 2>(__VA_ARGS__);          \
-        case 8: return FN<16, 1, 4>(__VA_ARGS__);          \
-        case 9: return FN<32, 1, 2>(__VA_ARGS__);          \
-        case 10: return FN<32, 1, 4>(__VA_ARGS__);         \
-        case 11: return FN<64, 1, 1>(__VA_ARGS__);         \
-        case 12: return FN<64, 1, 2>(__VA_ARGS__);         \
-        case 13: return FN<64, 1, 4>(__VA_ARGS__);         \
-        case 14: return FN<64, 1, 8>(__VA_ARGS__);         \
-        case 15: return FN<16, 4, 1>(__VA_ARGS__);         \
-        case 16: return FN<16, 4, 2>(__VA_ARGS__);         \
-        case 17: return FN<32, 2, 2>(__VA_ARGS__);         \
-        case 18: return FN<32, 2, 4>(__VA_ARGS__);         \
-        case 19: return FN<64, 2, 2>(__VA_ARGS__);         \
-        case 20: return FN<64, 2, 4>(__VA_ARGS__);         \
-        case 21: return FN<64, 4, 1>(__VA_ARGS__);         \
-        case 22: return FN<64, 4, 2>(__VA_ARGS__);         \
+        case 1: return FN<1, 1, 1, 0>(__VA_ARGS__);        \
+        case 2: return FN<2, 1, 1, 0>(__VA_ARGS__);        \
+        case 3: return FN<4, 1, 1, 0>(__VA_ARGS__);        \
+        case 4: return FN<8, 1, 1, 0>(__VA_ARGS__);        \
+        case 5: return FN<8, 1, 2, 0>(__VA_ARGS__);        \
+        case 6: return FN<16, 1, 1, 0>(__VA_ARGS__);       \
+        case 7: return FN<16, 1, 2, 0>(__VA_ARGS__);       \
+        case 8: return FN<16, 1, 4, 0>(__VA_ARGS__);       \
+        case 9: return FN<32, 1, 2, 0>(__VA_ARGS__);       \
+        case 10: return FN<32, 1, 4, 0>(__VA_ARGS__);      \
+        case 11: return FN<64, 1, 1, 0>(__VA_ARGS__);      \
+        case 12: return FN<64, 1, 2, 0>(__VA_ARGS__);      \
+        case 13: return FN<64, 1, 4, 0>(__VA_ARGS__);      \
+        case 14: return FN<64, 1, 8, 0>(__VA_ARGS__);      \
+        case 15: return FN<16, 4, 1, 0>(__VA_ARGS__);      \
+        case 16: return FN<16, 4, 2, 0>(__VA_ARGS__);      \
+        case 17: return FN<32, 2, 2, 0>(__VA_ARGS__);      \
+        case 18: return FN<32, 2, 4, 0>(__VA_ARGS__);      \
+        case 19: return FN<64, 2, 2, 0>(__VA_ARGS__);      \
+        case 20: return FN<64, 2, 4, 0>(__VA_ARGS__);      \
+        case 21: return FN<64, 4, 1, 0>(__VA_ARGS__);      \
+        case 22: return FN<64, 4, 2, 0>(__VA_ARGS__);      \
+        case 23: return FN<1, 1, 1, 1>(__VA_ARGS__);       \
+        case 24: return FN<2, 1, 1, 1>(__VA_ARGS__);       \
+        case 25: return FN<4, 1, 1, 1>(__VA_ARGS__);       \
+        case 26: return FN<2, 4, 1, 0>(__VA_ARGS__);       \
+        case 27: return FN<4, 2, 1, 0>(__VA_ARGS__);       \
+        case 28: return FN<8, 1, 4, 0>(__VA_ARGS__);       \
         default: return hipErrorInvalidValue;              \
     }
 
@@ -537,7 +686,7 @@ hipError_t launch_bwd(int sched, int opt, const BwdArgs& A, int blocks, hipStrea
     if (blocks <= 0) {
         // still advance the step counter
         if (opt != kGrad) {
-            hipLaunchKernelGGL((k_bwd<1, 1, 1, kAdam>), dim3(1), dim3(256), 0, s, A);
+            hipLaunchKernelGGL((k_bwd<1, 1, 1, kAdam, false>), dim3(1), dim3(256), 0, s, A);
             return hipGetLastError();
         }
         return hipSuccess;
@@ -546,54 +695,62 @@ hipError_t launch_bwd(int sched, int opt, const BwdArgs& A, int blocks, hipStrea
 }
 
 hipError_t launch_combine(int opt, const BwdArgs& A, hipStream_t s) {
-    const int64_t waves = (int64_t)A.n_heavy * A.R;
-    if (waves == 0) return hipSuccess;
-    const int blocks = (int)((waves + 3) / 4);
+    const int64_t wide = (int64_t)A.n_heavy_wide * A.B.R;
+    const int64_t narrow = (int64_t)(A.n_heavy - A.n_heavy_wide) * A.B.R;
+    const int64_t blocks = wide + (narrow + 15) / 16;
+    if (blocks == 0) return hipSuccess;
     if (opt == kAdam)
-        hipLaunchKernelGGL((k_combine<kAdam>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_combine<kAdam>), dim3((int)blocks), dim3(1024), 0, s, A);
     else if (opt == kSgd)
-        hipLaunchKernelGGL((k_combine<kSgd>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_combine<kSgd>), dim3((int)blocks), dim3(1024), 0, s, A);
     else
-        hipLaunchKernelGGL((k_combine<kGrad>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_combine<kGrad>), dim3((int)blocks), dim3(1024), 0, s, A);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce(const ReduceArgs& A, hipStream_t s) {
+    if (A.n_chunks > 0) {
+        hipLaunchKernelGGL(k_reduce1, dim3((A.R + 63) / 64, A.n_chunks), dim3(256), 0, s, A);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_reduce, dim3((A.R + 63) / 64), dim3(1024), 0, s, A);
     return hipGetLastError();
 }
 
+
 hipError_t launch_init(const InitArgs& A, hipStream_t s) {
-    int64_t total = (int64_t)A.n * A.R;
-    if (total < A.R) total = A.R;
+    int64_t total = (int64_t)A.n * A.B.R;
+    if (total < A.B.R) total = A.B.R;
+    if (total < A.umask_words) total = A.umask_words;
     if (total < 1) total = 1;
     const int blocks = (int)((total + 255) / 256);
     hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
-hipError_t launch_snapshot(int32_t n_act, int32_t R, const float* x, const int32_t* improved,
+hipError_t launch_snapshot(int32_t n_act, const Blocking& B, const float* x, const int32_t* improved,
                            uint8_t* best_a, hipStream_t s) {
-    const int64_t total = (int64_t)n_act * R;
+    const int64_t total = (int64_t)n_act * B.R;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_snapshot, dim3((int)((total + 255) / 256)), dim3(256), 0, s, n_act, R, x, improved,
+    hipLaunchKernelGGL(k_snapshot, dim3((int)((total + 255) / 256)), dim3(256), 0, s, n_act, B, x, improved,
                        best_a);
     return hipGetLastError();
 }
 
-hipError_t launch_extract(int32_t n, int32_t R, int32_t r, const int32_t* var_old, const uint8_t* best_a,
+hipError_t launch_extract(int32_t n, const Blocking& B, int32_t r, const int32_t* var_old, const uint8_t* best_a,
                           uint8_t* out, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_extract, dim3((n + 255) / 256), dim3(256), 0, s, n, R, r, var_old, best_a, out);
+    hipLaunchKernelGGL(k_extract, dim3((n + 255) / 256), dim3(256), 0, s, n, B, r, var_old, best_a, out);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(int32_t n, int32_t n_act, int32_t R, const int32_t* var_old, const float* src,
+hipError_t launch_scatter(int32_t n, int32_t n_act, const Blocking& B, const int32_t* var_old, const float* src,
                           float* dst, hipStream_t s) {
-    const int64_t total = (int64_t)n * R;
+    const int64_t total = (int64_t)n * B.R;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3((int)((total + 255) / 256)), dim3(256), 0, s, n, n_act, R, var_old,
-                       src, dst);
+    hipLaunchKernelGGL(k_scatter, dim3((int)((total + 255) / 256)), dim3(256), 0, s, n, n_act, B, var_old, src,
+                       dst);
     return hipGetLastError();
 }
 

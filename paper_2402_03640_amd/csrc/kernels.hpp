@@ -1,12 +1,20 @@
 // Device kernels of the solve loop (gfx950, wave64).
 //
-// Data layout in HBM (n' = n + 1 rows, the last one a dummy variable whose
-// relaxed value is -0.0; restart index innermost):
-//   x, m, v, t : [n'][R] FP32   relaxed values, Adam moments, signed tanh(x)
-//   a          : [c_tiles * 64 + 1][R] FP32   adjoint of the scores, last row 0
-//   seg_part   : [seg_rows][R] FP64   partial transposed sums of heavy rows
-//   cnt_part, loss_part : [units][R]   per-unit count / loss partials
-//   best_a     : [n][R] bytes   rounded iterate of each restart's best step
+// Data layout in HBM.  Restarts are stored in groups of G (blocked layout):
+// element (row, r) of an array with `rows` rows sits at
+//     ((r / G) * rows + row) * G + (r % G).
+// G is the number of restarts one wavefront group covers (P lanes x V), so a
+// gather of one row for one group is one contiguous run of G floats, and a
+// workgroup works on a single restart group chosen as blockIdx % RG.  Since
+// workgroups are dispatched round-robin over the 8 XCDs, with RG = 8 each XCD
+// only touches its own restart slice, which stays in that XCD's L2.
+//   x, m, v, t : [RG][n + 1][G] FP32   relaxed values, Adam moments, signed tanh(x)
+//                (row n is a dummy variable whose t is -0.0: the padding literal)
+//   a          : [RG][c_tiles * 64 + 1][G] FP32   adjoint of the scores (last row 0)
+//   seg_part   : [RG][seg_rows][G] FP64   partial transposed sums of heavy rows
+//   best_a     : [RG][n + 1][G] bytes     rounded iterate at each restart's best step
+//   cnt_part, loss_part : [units][R]     per-unit count / loss partials
+//   umask      : bitset over clause rows (G = 1 only): bit j = clause j unsatisfied
 //
 // t stores tanh(x) with its sign bit forced to "x does not round to true":
 // sign(t) = 1 iff !(x > 0).  A literal entry holds the variable index and the
@@ -33,12 +41,22 @@ struct StepState {
     float inv_sqrt_bc2;  // 1 / sqrt(1 - beta2^(t+1))
 };
 
+// Restart blocking shared by all kernels of one solve.
+struct Blocking {
+    int32_t R, G, RG;   // restarts, group width, groups
+    int32_t rows_x;     // n + 1
+    int32_t rows_a;     // c_tiles * 64 + 1
+    int32_t rows_seg;   // max(seg_rows, 1)
+};
+
 struct FwdArgs {
     const TileDesc* tiles;
     const uint32_t* ent;
-    int32_t ntiles, chunks, U, RG, R, all_mode;
+    int32_t ntiles, chunks, U, all_mode;
+    Blocking B;
     const float* t;
     float* a;
+    uint32_t* umask;     // written when the schedule keeps the unsat bitset
     float two_over_m;
     int32_t* cnt_part;
     double* loss_part;
@@ -49,9 +67,11 @@ struct FwdArgs {
 struct BwdArgs {
     const TileDesc* tiles;
     const uint32_t* ent;
-    int32_t ntiles, seg_tiles, chunks, U, RG, R;
-    int32_t n_heavy, n_act, eval;
+    int32_t ntiles, seg_tiles, chunks, U;
+    Blocking B;
+    int32_t n_heavy, n_heavy_wide, n_act, eval;
     const float* a;
+    const uint32_t* umask;
     double* seg_part;
     float* x;
     float* m;
@@ -69,7 +89,9 @@ struct BwdArgs {
 struct ReduceArgs {
     const int32_t* cnt_part;
     const double* loss_part;
-    int32_t n_units, R, track;
+    int32_t* cnt_mid;        // [n_chunks][R] stage-1 partials
+    double* loss_mid;
+    int32_t n_units, chunk, n_chunks, R, track;
     int64_t n_empty;
     double inv_m;
     int64_t* cur_count;
@@ -81,7 +103,8 @@ struct ReduceArgs {
 };
 
 struct InitArgs {
-    int32_t n, R, a_zero_row, m;
+    int32_t n, m, a_zero_row, umask_words;
+    Blocking B;
     const int32_t* var_old;
     const float* x0;          // caller order [n][R] or null
     const uint8_t* assign0;   // caller order [n] (evaluate) or null
@@ -91,6 +114,7 @@ struct InitArgs {
     float* mm;
     float* vv;
     float* a;
+    uint32_t* umask;
     uint8_t* best_a;
     int64_t* best;
     int32_t* best_step;
@@ -101,10 +125,12 @@ struct InitArgs {
 // Kernel schedules: P lanes per restart group (64 / P rows side by side),
 // V restarts per lane (vector width), UR rows per lane handled together.
 // A work unit is U rows of one tile (U a multiple of (64 / P) * UR dividing 64).
+// MASK schedules (G = 1 only) keep the unsat bitset and skip the adjoint
+// gathers of satisfied clauses; they need U >= 32.
 struct Schedule {
-    int P, V, UR;
+    int P, V, UR, mask;
 };
-constexpr int kNumSchedules = 22;
+constexpr int kNumSchedules = 28;
 extern const Schedule kSchedules[kNumSchedules + 1];
 
 int default_rows_per_unit(int sched);
@@ -114,11 +140,11 @@ hipError_t launch_bwd(int sched, int opt, const BwdArgs& A, int blocks, hipStrea
 hipError_t launch_combine(int opt, const BwdArgs& A, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& A, hipStream_t s);
 hipError_t launch_init(const InitArgs& A, hipStream_t s);
-hipError_t launch_snapshot(int32_t n_act, int32_t R, const float* x, const int32_t* improved,
+hipError_t launch_snapshot(int32_t n_act, const Blocking& B, const float* x, const int32_t* improved,
                            uint8_t* best_a, hipStream_t s);
-hipError_t launch_extract(int32_t n, int32_t R, int32_t r, const int32_t* var_old, const uint8_t* best_a,
+hipError_t launch_extract(int32_t n, const Blocking& B, int32_t r, const int32_t* var_old, const uint8_t* best_a,
                           uint8_t* out, hipStream_t s);
-hipError_t launch_scatter(int32_t n, int32_t n_act, int32_t R, const int32_t* var_old, const float* src,
+hipError_t launch_scatter(int32_t n, int32_t n_act, const Blocking& B, const int32_t* var_old, const float* src,
                           float* dst, hipStream_t s);
 
 }  // namespace hms

@@ -11,8 +11,9 @@
 //
 // Layout choices (all functions of the instance only, so every kernel schedule
 // sums in the same order):
-//  * clause rows sorted by (tautology flag, length descending), cut into tiles
-//    of 64 rows stored column-major, padded to the tile's longest row;
+//  * clause rows sorted by (tautology flag, length descending, smallest
+//    variable), cut into tiles of 64 rows stored column-major, padded to the
+//    tile's longest row;
 //  * variables renumbered by degree descending; variables with more than kSeg
 //    entries are split into segments of kSeg consecutive entries whose
 //    partial sums are combined afterwards;
@@ -32,9 +33,10 @@ namespace hms {
 namespace {
 
 struct Row {
-    int64_t off;   // into the flat entry buffer
+    int64_t off;     // into the flat entry buffer
     int32_t len;
-    int32_t orig;  // original clause index
+    int32_t orig;    // original clause index
+    int32_t minvar;  // smallest new variable index of the row
     bool taut;
 };
 
@@ -139,7 +141,7 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
             P.m_taut++;
             if (len == 0) P.m_taut_dropped++;
         }
-        if (len > 0) rows.push_back(Row{off, len, j, taut});
+        if (len > 0) rows.push_back(Row{off, len, j, 0, taut});
         ++j;
         start = p + 1;
     }
@@ -162,10 +164,19 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
         if (P.degree[i] > kSeg) P.n_heavy = i + 1;
     }
 
-    // ---- clause rows: plain rows by length desc, then tautological rows ---
+    // ---- clause rows: plain rows by length desc, then tautological rows; ---
+    // within a length, by the smallest (hottest) new variable index, so that
+    // the clauses of a frequent variable sit together and its transposed row
+    // reads neighbouring adjoint entries.
+    for (Row& r : rows) {
+        int32_t mv = INT32_MAX;
+        for (int32_t c = 0; c < r.len; ++c) mv = std::min(mv, P.var_new[flat[r.off + c] & kIdx]);
+        r.minvar = mv;
+    }
     std::stable_sort(rows.begin(), rows.end(), [](const Row& a, const Row& b) {
         if (a.taut != b.taut) return !a.taut;
-        return a.len > b.len;
+        if (a.len != b.len) return a.len > b.len;
+        return a.minvar < b.minvar;
     });
     int32_t n_plain = 0;
     while (n_plain < (int32_t)rows.size() && !rows[n_plain].taut) ++n_plain;
@@ -233,6 +244,7 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
         int32_t d = P.degree[h];
         int32_t ns = (d + kSeg - 1) / kSeg;
         P.max_segs = std::max(P.max_segs, ns);
+        if (ns > kWideSegs) P.n_heavy_wide = h + 1;
         P.seg_first[h + 1] = P.seg_first[h] + ns;
         for (int32_t s = 0; s < ns; ++s) {
             int32_t L = std::min(kSeg, d - s * kSeg);

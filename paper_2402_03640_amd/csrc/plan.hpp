@@ -10,7 +10,8 @@
 namespace hms {
 
 constexpr int kTile = 64;          // rows per tile; one wavefront lane per row at R = 1
-constexpr int kSeg = 256;          // longest variable row kept whole; longer rows are split
+constexpr int kSeg = 64;           // longest variable row kept whole; longer rows are split
+constexpr int kWideSegs = 1024;    // variables with more segments combine over 1024 slots (else 64)
 constexpr uint32_t kSign = 0x80000000u;
 constexpr uint32_t kIdx = 0x7fffffffu;
 
@@ -51,6 +52,7 @@ struct HostPlan {
     std::vector<int32_t> seg_first;  // [n_heavy + 1] into seg_row
     std::vector<int32_t> seg_row;    // segment rows of each heavy variable, in order
     int32_t max_segs = 0;            // most segments of one variable
+    int32_t n_heavy_wide = 0;        // heavy variables with more than kWideSegs segments (come first)
 
     std::vector<int32_t> var_old;    // new index -> original (0-based)
     std::vector<int32_t> var_new;    // original -> new index

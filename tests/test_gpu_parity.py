@@ -88,7 +88,7 @@ def test_eval_cfg4_all_schedules():
     cnf = hm.load_cnf(n, lits)
     xt = torch.from_numpy(x).cuda()
     ref = None
-    codes = list(range(1, 23)) + [14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
+    codes = list(range(1, 29)) + [14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
                                   7 | (64 << 8), 1 | (64 << 8)]
     for sched in codes:
         res = hm.solve(cnf, steps=3, restarts=R, eval_every=1, x0=xt, schedule=sched, want_x=True)
@@ -101,6 +101,27 @@ def test_eval_cfg4_all_schedules():
             np.testing.assert_array_equal(cur[0], ref[0])
             np.testing.assert_array_equal(cur[1], ref[1])
             np.testing.assert_array_equal(cur[2].view(np.uint32), ref[2].view(np.uint32))
+
+
+def test_single_restart_schedules_bitwise():
+    """R = 1 on a skewed instance (heavy rows): every schedule, with and
+    without the unsat bitset, gives the same trajectory bit for bit."""
+    n, m = 20000, 100000
+    lits = cnfgen.structured_cnf(n, m, seed=12)
+    cnf = hm.load_cnf(n, lits)
+    assert cnf.info["n_heavy"] > 0
+    ref = None
+    for sched in [1, 2, 3, 4, 11, 23, 24, 25, 24 | (32 << 8), 25 | (64 << 8), 2 | (32 << 8)]:
+        res = hm.solve(cnf, steps=60, restarts=1, eval_every=7, seed=5, lr=1e-2, schedule=sched,
+                       want_x=True)
+        cur = (res.restart_best.copy(), res.restart_step.copy(),
+               res.x_final.cpu().numpy().view(np.uint32).copy(), res.best_assignment.copy())
+        _say(f"R=1 schedule {sched}: best {res.best_cost} at {res.best_step}")
+        if ref is None:
+            ref = cur
+        else:
+            for a, b in zip(cur, ref):
+                np.testing.assert_array_equal(a, b)
 
 
 def test_eval_cfg2_full_size():
