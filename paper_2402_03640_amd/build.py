@@ -44,13 +44,15 @@ def build(verbose: bool = False) -> str:
                                os.path.join(BUILD, "kernels.o")],
         [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "hipmsat.hip"), "-o",
                                os.path.join(BUILD, "hipmsat.o")],
+        [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "small.hip"), "-o",
+                               os.path.join(BUILD, "small.o")],
     ]
-    with ThreadPoolExecutor(3) as ex:
+    with ThreadPoolExecutor(4) as ex:
         outs = list(ex.map(_run, jobs))
     tmp = OUT + ".tmp"
     outs.append(_run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
                       os.path.join(BUILD, "plan.o"), os.path.join(BUILD, "kernels.o"),
-                      os.path.join(BUILD, "hipmsat.o")]))
+                      os.path.join(BUILD, "hipmsat.o"), os.path.join(BUILD, "small.o")]))
     os.replace(tmp, OUT)
     if verbose:
         for o in outs:

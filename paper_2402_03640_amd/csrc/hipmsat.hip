@@ -14,6 +14,7 @@
 #include "hipmsat.h"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "small.hpp"
 
 struct hms_cnf {
     hms::HostPlan plan;
@@ -557,6 +558,10 @@ struct Events {
 };
 
 
+bool resident_ok(const hms_cnf* cnf, const hms_solve_params* p);
+hms_status time_resident(const hms_cnf* cnf, const hms_solve_params* p0, int32_t iters, double& ms);
+constexpr int32_t kResidentId = 0xff;
+
 uint64_t tune_key(const hms_solve_params* p) {
     return (uint64_t)(uint32_t)p->restarts | ((uint64_t)(uint32_t)p->optimizer << 32) |
            ((uint64_t)(uint32_t)p->loss_mode << 40);
@@ -604,9 +609,11 @@ hms_status time_steps(const hms_cnf* cnf, const hms_solve_params* p0, int32_t co
 hms_status tune(const hms_cnf* cnf, const hms_solve_params* p, int32_t iters, int32_t& best, double& best_ms) {
     best = 0;
     best_ms = 1e300;
-    for (int32_t code : tune_candidates(p->restarts, p->loss_mode)) {
+    std::vector<int32_t> cands = tune_candidates(p->restarts, p->loss_mode);
+    if (resident_ok(cnf, p)) cands.push_back(kResidentId);
+    for (int32_t code : cands) {
         double ms = 0;
-        hms_status rc = time_steps(cnf, p, code, iters, ms);
+        hms_status rc = code == kResidentId ? time_resident(cnf, p, iters, ms) : time_steps(cnf, p, code, iters, ms);
         if (rc) return rc;
         if (ms < best_ms) {
             best_ms = ms;
@@ -630,9 +637,151 @@ hms_status resolve_schedule(const hms_cnf* cnf, const hms_solve_params* p, int32
             return HMS_OK;
         }
     }
-    if (!p->autotune || (double)cnf->plan.nnz * p->restarts < (double)(1 << 18)) return HMS_OK;
+    if (!p->autotune || (double)cnf->plan.nnz * p->restarts < (double)(1 << 18)) {
+        if (resident_ok(cnf, p)) code = kResidentId;  // small: launch latency dominates
+        return HMS_OK;
+    }
     double ms = 0;
     return tune(cnf, p, 6, code, ms);
+}
+
+// ---- resident path (one workgroup per restart, state in LDS) ---------------
+constexpr int32_t kResident = kResidentId;  // schedule id of the resident solver
+
+size_t lds_limit(int dev) {
+    static size_t cached[64] = {0};
+    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+    const size_t lim = (size_t)v > 4096 ? (size_t)v - 4096 : 0;  // keep room for the static LDS
+    if (dev >= 0 && dev < 64) cached[dev] = lim;
+    return lim;
+}
+
+bool resident_ok(const hms_cnf* cnf, const hms_solve_params* p) {
+    const hms::HostPlan& P = cnf->plan;
+    return P.n_heavy_wide == 0 && p->time_limit_s <= 0 && hms::small_lds_bytes(P) <= lds_limit(cnf->device);
+}
+
+hms::SmallDesc make_desc(const hms_cnf* cnf, const hms_solve_params* p) {
+    const hms::HostPlan& P = cnf->plan;
+    hms::SmallDesc D{};
+    D.c_tile = cnf->c_tile;
+    D.c_ent = cnf->c_ent;
+    D.v_tile = cnf->v_tile;
+    D.v_ent = cnf->v_ent;
+    D.seg_first = cnf->seg_first;
+    D.seg_row = cnf->seg_row;
+    D.var_old = cnf->var_old;
+    D.n = P.n;
+    D.m = P.m;
+    D.n_act = P.n_act;
+    D.n_heavy = P.n_heavy;
+    D.c_tiles = P.c_tiles;
+    D.v_tiles = P.v_tiles;
+    D.seg_tiles = P.seg_tiles;
+    D.seg_rows = P.seg_rows;
+    D.n_empty = P.m_empty;
+    D.R = p->restarts;
+    D.T = p->steps;
+    D.K = p->eval_every;
+    D.opt = p->optimizer == HMS_SGD ? hms::kSgd : hms::kAdam;
+    D.all_mode = p->loss_mode == HMS_LOSS_ALL;
+    D.two_over_m = P.m > 0 ? (float)(2.0 / (double)P.m) : 0.0f;
+    D.inv_m = P.m > 0 ? 1.0 / (double)P.m : 0.0;
+    D.lr = p->lr;
+    D.b1 = p->beta1;
+    D.b2 = p->beta2;
+    D.eps = p->eps;
+    D.omb1 = 1.0f - p->beta1;
+    D.omb2 = 1.0f - p->beta2;
+    D.lr_d = (double)p->lr;
+    D.b1_d = (double)p->beta1;
+    D.b2_d = (double)p->beta2;
+    D.seed = p->seed;
+    D.x0 = p->x0;
+    return D;
+}
+
+// Device outputs of one resident instance, carved from an arena.
+struct SmallOut {
+    size_t o_best_a, o_best, o_step, o_loss;
+};
+
+SmallOut layout_small_out(const hms::HostPlan& P, int32_t R, Layout& L) {
+    SmallOut o;
+    o.o_best_a = L.add((size_t)std::max(P.n, 1) * R);
+    o.o_best = L.add((size_t)R * 8);
+    o.o_step = L.add((size_t)R * 4);
+    o.o_loss = L.add((size_t)R * 8);
+    return o;
+}
+
+hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_result* res) {
+    const hms::HostPlan& P = cnf->plan;
+    const int32_t R = p->restarts;
+    hipStream_t s = (hipStream_t)p->stream;
+    Layout lay;
+    const size_t o_desc = lay.add(sizeof(hms::SmallDesc));
+    SmallOut so = layout_small_out(P, R, lay);
+    Arena A;
+    A.s = s;
+    HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+    hms::SmallDesc D = make_desc(cnf, p);
+    D.block0 = 0;
+    D.best_a = A.at<uint8_t>(so.o_best_a);
+    D.best = A.at<int64_t>(so.o_best);
+    D.best_step = A.at<int32_t>(so.o_step);
+    D.final_loss = A.at<double>(so.o_loss);
+    D.x_final = res->x_final;
+    Events E;
+    for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
+    HIPTRY(hipMemcpyAsync(A.base + o_desc, &D, sizeof(D), hipMemcpyHostToDevice, s));
+    HIPTRY(hipEventRecord(E.e[0], s));
+    HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc), 1, R, hms::small_lds_bytes(P), s));
+    HIPTRY(hipEventRecord(E.e[1], s));
+    std::vector<int64_t> best(R);
+    std::vector<int32_t> bstep(R);
+    std::vector<double> closs(R);
+    HIPTRY(hipMemcpyAsync(best.data(), D.best, R * 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(bstep.data(), D.best_step, R * 4, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(closs.data(), D.final_loss, R * 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    int32_t br = 0;
+    for (int32_t r = 1; r < R; ++r)
+        if (best[r] < best[br]) br = r;
+    if (res->best_assignment && P.n > 0) {
+        HIPTRY(hipMemcpyAsync(res->best_assignment, D.best_a + (size_t)br * P.n, P.n, hipMemcpyDeviceToHost, s));
+        HIPTRY(hipStreamSynchronize(s));
+    }
+    float ms = 0;
+    HIPTRY(hipEventElapsedTime(&ms, E.e[0], E.e[1]));
+    res->best_cost = best[br];
+    res->best_restart = br;
+    res->best_step = bstep[br];
+    res->steps_done = p->steps;
+    res->schedule = kResident;
+    res->final_loss = closs[br];
+    res->device_ms = ms;
+    if (res->restart_best) std::memcpy(res->restart_best, best.data(), R * 8);
+    if (res->restart_step) std::memcpy(res->restart_step, bstep.data(), R * 4);
+    if (res->restart_loss) std::memcpy(res->restart_loss, closs.data(), R * 8);
+    for (int32_t r = 0; r < R; ++r)
+        if (!std::isfinite(closs[r])) return fail(HMS_ERR_NONFINITE, "the loss at the final iterate is not finite");
+    return HMS_OK;
+}
+
+// Device time per step of a short resident solve.
+hms_status time_resident(const hms_cnf* cnf, const hms_solve_params* p0, int32_t iters, double& ms) {
+    hms_solve_params p = *p0;
+    p.steps = std::max(iters, 8) * 4;
+    p.eval_every = std::max(p0->eval_every, 1);
+    p.x0 = nullptr;
+    hms_solve_result r{};
+    hms_status rc = solve_resident(cnf, &p, &r);
+    if (rc) return rc;
+    ms = r.device_ms / p.steps;
+    return HMS_OK;
 }
 
 }  // namespace
@@ -647,6 +796,12 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     hms_status rc0 = resolve_schedule(cnf, p, pr.schedule);
     if (rc0) return rc0;
     p = &pr;
+    if (p->schedule == kResidentId) {
+        if (!resident_ok(cnf, p)) return fail(HMS_ERR_ARG, "the resident schedule does not fit this instance");
+        if (p->restarts < 1 || p->steps < 0 || p->eval_every < 1)
+            return fail(HMS_ERR_ARG, "restarts >= 1, steps >= 0 and eval_every >= 1 required");
+        return solve_resident(cnf, p, res);
+    }
     SolveSetup Z;
     rc0 = setup_solve(cnf, p, Z);
     if (rc0) return rc0;
@@ -769,6 +924,15 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* p, int32
     hms_status rc0 = resolve_schedule(cnf, p, pr.schedule);
     if (rc0) return rc0;
     p = &pr;
+    if (p->schedule == kResidentId) {
+        double ms = 0;
+        hms_status rc = time_resident(cnf, p, iters, ms);
+        if (rc) return rc;
+        if (fwd_ms) *fwd_ms = 0.0;
+        if (bwd_ms) *bwd_ms = 0.0;
+        if (step_ms) *step_ms = ms;
+        return HMS_OK;
+    }
     SolveSetup Z;
     rc0 = setup_solve(cnf, p, Z);
     if (rc0) return rc0;

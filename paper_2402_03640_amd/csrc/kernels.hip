@@ -13,6 +13,8 @@
 
 #include <cmath>
 
+#include "device_common.hpp"
+
 namespace hms {
 
 const Schedule kSchedules[kNumSchedules + 1] = {
@@ -70,39 +72,6 @@ __device__ __forceinline__ void stv(float* p, const VecF<V>& r) {
     }
 }
 
-// tanh(x) carrying the rounding in its sign bit: set iff x does not round to
-// true (x <= 0, -0.0 or NaN).
-__device__ __forceinline__ float signed_tanh(float x) {
-    uint32_t b = __float_as_uint(tanhf(x)) & kIdx;
-    if (!(x > 0.0f)) b |= kSign;
-    return __uint_as_float(b);
-}
-
-// sech^2(x) = 4 e / (1 + e)^2 with e = exp(-2|x|): no cancellation for large |x|.
-__device__ __forceinline__ float sech2f(float x) {
-    float e = expf(-2.0f * fabsf(x));
-    float d = 1.0f + e;
-    return (4.0f * e) / (d * d);
-}
-
-// SplitMix64 (Steele, Lea, Flood 2014): output k of the stream seeded `seed`.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
-    uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-// Loads of plan data (read-only for the whole solve) through the constant
-// address space: a wave-uniform address becomes a scalar load.
-__device__ __forceinline__ uint32_t ldc(const uint32_t* p) {
-    return *(const __attribute__((address_space(4))) uint32_t*)p;
-}
-__device__ __forceinline__ TileDesc ldtile(const TileDesc* p) {
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(p);
-    return TileDesc{ldc(w), ldc(w + 1), ldc(w + 2), ldc(w + 3)};
-}
-
 // Compact the ballot bits of lanes 0, P, 2P, ... into consecutive bits.
 template <int P>
 __device__ __forceinline__ uint64_t compact_bits(uint64_t x) {
@@ -141,13 +110,8 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
     const int lane = threadIdx.x & 63;
     const int s = lane / P;
     const int q = lane % P;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && A.st != nullptr) {
-        double tt = (double)A.st->t + 1.0;
-        double bc1 = 1.0 - pow(A.b1, tt);
-        double bc2 = 1.0 - pow(A.b2, tt);
-        A.st->step_size = (float)(A.lr / bc1);
-        A.st->inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && A.st != nullptr)
+        adam_scalars((double)A.st->t + 1.0, A.lr, A.b1, A.b2, A.st->step_size, A.st->inv_sqrt_bc2);
     const Blocking B = A.B;
     const int rg = blockIdx.x % B.RG;
     const int tc = __builtin_amdgcn_readfirstlane((blockIdx.x / B.RG) * 4 + (threadIdx.x >> 6));
@@ -290,7 +254,7 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int 
     }
     float g[V];
 #pragma unroll
-    for (int k = 0; k < V; ++k) g[k] = (float)((double)sech2f(xv.v[k]) * G[k]);
+    for (int k = 0; k < V; ++k) g[k] = grad_of(xv.v[k], G[k]);
     if constexpr (OPT == kGrad) {
         VecF<V> gv;
 #pragma unroll
@@ -309,15 +273,13 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int 
     } else {
         const float ss = A.st->step_size;
         const float ib2 = A.st->inv_sqrt_bc2;
+        const AdamCoef co{A.b1, A.b2, A.eps, A.omb1, A.omb2};
         VecF<V> mv = ldv<V>(A.m + base);
         VecF<V> vv = ldv<V>(A.v + base);
         VecF<V> tv;
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            mv.v[k] = A.b1 * mv.v[k] + A.omb1 * g[k];
-            vv.v[k] = A.b2 * vv.v[k] + A.omb2 * (g[k] * g[k]);
-            const float denom = sqrtf(vv.v[k]) * ib2 + A.eps;
-            xv.v[k] = xv.v[k] - (ss * mv.v[k]) / denom;
+            adam_update(xv.v[k], mv.v[k], vv.v[k], g[k], ss, ib2, co);
             tv.v[k] = signed_tanh(xv.v[k]);
         }
         stv<V>(A.m + base, mv);

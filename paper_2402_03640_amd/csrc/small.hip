@@ -1,0 +1,257 @@
+// Resident solver (see small.hpp).  The arithmetic is the same as the tiled
+// kernels', operation for operation: clause scores summed over the tile's
+// entries in plan order (FP64 for rows longer than 16), transposed sums over
+// the variable rows in plan order in FP64, heavy rows by segment with the
+// 64-slot combine tree, the same gradient and optimizer expressions.  So a
+// resident solve is bitwise equal to the tiled one.
+#include "small.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace hms {
+
+namespace {
+
+constexpr int kThreads = 1024;
+constexpr int kWaves = kThreads / 64;
+
+struct SmallLds {
+    float* t;      // [n + 1]
+    float* a;      // [c_tiles * 64 + 1]
+    float* x;      // [n]
+    float* m;      // [n]
+    float* v;      // [n]
+    double* seg;   // [seg_rows]
+};
+
+__device__ __forceinline__ size_t align8(size_t b) { return (b + 7) & ~size_t(7); }
+
+__global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict__ descs, int32_t n_desc) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t red_c[kWaves];
+    __shared__ double red_l[kWaves];
+    __shared__ float s_ss, s_ib2;
+    __shared__ int s_improved;
+    __shared__ int64_t s_best;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    // instance of this workgroup: the last descriptor with block0 <= blockIdx.x
+    int lo = 0, hi = n_desc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].block0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const SmallDesc& D = descs[lo];
+    const int r = blockIdx.x - D.block0;
+    const int n = D.n;
+    const int crows = D.c_tiles * kTile;
+    const int vrows = D.v_tiles * kTile;
+
+    SmallLds L;
+    size_t off = 0;
+    L.t = reinterpret_cast<float*>(smem + off);
+    off += (size_t)(n + 1) * 4;
+    L.a = reinterpret_cast<float*>(smem + off);
+    off += (size_t)(crows + 1) * 4;
+    L.x = reinterpret_cast<float*>(smem + off);
+    off += (size_t)n * 4;
+    L.m = reinterpret_cast<float*>(smem + off);
+    off += (size_t)n * 4;
+    L.v = reinterpret_cast<float*>(smem + off);
+    off += (size_t)n * 4;
+    L.seg = reinterpret_cast<double*>(smem + align8(off));
+
+    const AdamCoef co{D.b1, D.b2, D.eps, D.omb1, D.omb2};
+    uint8_t* best_a = D.best_a + (size_t)r * n;
+
+    // ---- initial point -------------------------------------------------------
+    for (int i = tid; i < n; i += kThreads) {
+        const int o = D.var_old[i];
+        float x;
+        if (D.x0 != nullptr) {
+            x = D.x0[(size_t)o * D.R + r];
+        } else {
+            const uint64_t z = splitmix64(D.seed + (uint64_t)r, (uint64_t)o + 1);
+            x = 2.0f * ((float)(z >> 40) * (1.0f / 16777216.0f)) - 1.0f;
+        }
+        L.x[i] = x;
+        L.t[i] = signed_tanh(x);
+        L.m[i] = 0.0f;
+        L.v[i] = 0.0f;
+        best_a[o] = x > 0.0f ? 1 : 0;
+    }
+    if (tid == 0) {
+        L.t[n] = -0.0f;
+        L.a[crows] = 0.0f;
+        s_best = D.m;
+    }
+    int best_step = -1;
+    __syncthreads();
+
+    for (int step = 0; step <= D.T; ++step) {
+        const bool eval = (step % D.K == 0) || step == D.T;
+        // ---- clause scores, mask, adjoint ------------------------------------
+        int cnt = 0;
+        double los = 0.0;
+        for (int row = tid; row < crows; row += kThreads) {
+            const int tile = row >> 6;
+            const int rowin = row & 63;
+            const TileDesc d = D.c_tile[tile];
+            const uint32_t* e = D.c_ent + d.base + rowin;
+            float f = 0.0f;
+            uint32_t allf = ~0u;
+            if (d.len <= 16) {
+#pragma unroll 4
+                for (uint32_t c = 0; c < d.len; ++c) {
+                    const uint32_t en = e[(size_t)c * kTile];
+                    const uint32_t b = __float_as_uint(L.t[en & kIdx]) ^ (en & kSign);
+                    f = f + __uint_as_float(b);
+                    allf &= b;
+                }
+            } else {
+                double fd = 0.0;
+#pragma unroll 4
+                for (uint32_t c = 0; c < d.len; ++c) {
+                    const uint32_t en = e[(size_t)c * kTile];
+                    const uint32_t b = __float_as_uint(L.t[en & kIdx]) ^ (en & kSign);
+                    fd = fd + (double)__uint_as_float(b);
+                    allf &= b;
+                }
+                f = (float)fd;
+            }
+            const bool real = rowin < (int)d.nreal;
+            const bool unsat = real && !(d.flags & 1u) && (allf >> 31) != 0;
+            const bool mu = real && (D.all_mode ? true : unsat);
+            L.a[row] = mu ? f * D.two_over_m : 0.0f;
+            if (eval) {
+                cnt += unsat ? 1 : 0;
+                los += mu ? (double)f * (double)f : 0.0;
+            }
+        }
+        if (eval) {
+            for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+                cnt += __shfl_xor(cnt, o2);
+                los += __shfl_xor(los, o2);
+            }
+            if (lane == 0) {
+                red_c[wave] = cnt;
+                red_l[wave] = los;
+            }
+        }
+        if (tid == 0 && step < D.T)
+            adam_scalars((double)step + 1.0, D.lr_d, D.b1_d, D.b2_d, s_ss, s_ib2);
+        __syncthreads();
+        if (eval) {
+            if (tid == 0) {
+                int64_t c = 0;
+                double l = 0.0;
+                for (int w = 0; w < kWaves; ++w) {
+                    c += red_c[w];
+                    l = l + red_l[w];
+                }
+                c += D.n_empty;
+                s_improved = c < s_best ? 1 : 0;
+                if (s_improved) s_best = c;
+                if (step == D.T) D.final_loss[r] = l * D.inv_m;
+            }
+            __syncthreads();
+            if (s_improved) {
+                best_step = step;
+                for (int i = tid; i < D.n_act; i += kThreads) best_a[D.var_old[i]] = L.x[i] > 0.0f ? 1 : 0;
+                __syncthreads();  // x is read above and rewritten below
+            }
+        }
+        if (step == D.T) break;
+        // ---- transposed sums, fused optimizer step ---------------------------
+        const float ss = s_ss, ib2 = s_ib2;
+        for (int row = tid; row < vrows; row += kThreads) {
+            const int tile = row >> 6;
+            const int rowin = row & 63;
+            const TileDesc d = D.v_tile[tile];
+            if (rowin >= (int)d.nreal) continue;
+            const uint32_t* e = D.v_ent + d.base + rowin;
+            double G = 0.0;
+#pragma unroll 4
+            for (uint32_t c = 0; c < d.len; ++c) {
+                const uint32_t en = e[(size_t)c * kTile];
+                G = G + (double)__uint_as_float(__float_as_uint(L.a[en & kIdx]) ^ (en & kSign));
+            }
+            if (tile < D.seg_tiles) {
+                L.seg[row] = G;
+            } else {
+                const int var = D.n_heavy + (row - D.seg_tiles * kTile);
+                float x = L.x[var];
+                const float g = grad_of(x, G);
+                if (D.opt == kSgd) {
+                    x = x - D.lr * g;
+                } else {
+                    float mm = L.m[var], vv = L.v[var];
+                    adam_update(x, mm, vv, g, ss, ib2, co);
+                    L.m[var] = mm;
+                    L.v[var] = vv;
+                }
+                L.x[var] = x;
+                L.t[var] = signed_tanh(x);
+            }
+        }
+        if (D.n_heavy > 0) {
+            __syncthreads();
+            for (int h = wave; h < D.n_heavy; h += kWaves) {
+                double u = 0.0;
+                const int p1 = D.seg_first[h + 1];
+                for (int p = D.seg_first[h] + lane; p < p1; p += 64) u = u + L.seg[D.seg_row[p]];
+#pragma unroll
+                for (int o2 = 32; o2 >= 1; o2 >>= 1) u = u + __shfl_down(u, o2);
+                if (lane == 0) {
+                    float x = L.x[h];
+                    const float g = grad_of(x, u);
+                    if (D.opt == kSgd) {
+                        x = x - D.lr * g;
+                    } else {
+                        float mm = L.m[h], vv = L.v[h];
+                        adam_update(x, mm, vv, g, ss, ib2, co);
+                        L.m[h] = mm;
+                        L.v[h] = vv;
+                    }
+                    L.x[h] = x;
+                    L.t[h] = signed_tanh(x);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        D.best[r] = s_best;
+        D.best_step[r] = best_step;
+    }
+    if (D.x_final != nullptr)
+        for (int i = tid; i < n; i += kThreads) D.x_final[(size_t)D.var_old[i] * D.R + r] = L.x[i];
+}
+
+}  // namespace
+
+size_t small_lds_bytes(const HostPlan& P) {
+    size_t b = (size_t)(P.n + 1) * 4 + (size_t)(P.c_tiles * kTile + 1) * 4 + (size_t)P.n * 12;
+    b = (b + 7) & ~size_t(7);
+    b += (size_t)P.seg_rows * 8;
+    return b;
+}
+
+hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_small, dim3(blocks), dim3(kThreads), lds_bytes, s, d_descs, n_desc);
+    return hipGetLastError();
+}
+
+}  // namespace hms

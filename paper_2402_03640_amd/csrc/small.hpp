@@ -1,0 +1,48 @@
+// Resident solver: one workgroup runs the whole Algorithm 1 loop for one
+// (instance, restart) with the relaxed state in LDS.  Used for instances whose
+// state fits in LDS, where the tiled kernels would be bound by launch latency,
+// and for batches of many such instances in one launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace hms {
+
+// One instance of a resident launch (device-visible, 256-byte aligned array).
+struct SmallDesc {
+    // plan (device)
+    const TileDesc* c_tile;
+    const uint32_t* c_ent;
+    const TileDesc* v_tile;
+    const uint32_t* v_ent;
+    const int32_t* seg_first;
+    const int32_t* seg_row;
+    const int32_t* var_old;
+    int32_t n, m, n_act, n_heavy, c_tiles, v_tiles, seg_tiles, seg_rows, n_empty;
+    // solve parameters
+    int32_t R, T, K, opt, all_mode, block0;
+    float two_over_m;
+    float lr, b1, b2, eps, omb1, omb2;
+    double inv_m, lr_d, b1_d, b2_d;
+    uint64_t seed;
+    const float* x0;      // caller order [n][R] or null
+    // outputs (device)
+    uint8_t* best_a;      // [R][n] caller order: rounded iterate at each restart's best step
+    int64_t* best;        // [R]
+    int32_t* best_step;   // [R]
+    double* final_loss;   // [R] loss at x_T
+    float* x_final;       // caller order [n][R] or null
+};
+
+// LDS bytes the resident solver needs for an instance (per workgroup).
+size_t small_lds_bytes(const HostPlan& P);
+
+// Launch one workgroup per (instance, restart): descs[i].block0 must be the
+// running sum of the restart counts, `blocks` the total.
+hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s);
+
+}  // namespace hms

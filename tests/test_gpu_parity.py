@@ -89,7 +89,7 @@ def test_eval_cfg4_all_schedules():
     xt = torch.from_numpy(x).cuda()
     ref = None
     codes = list(range(1, 29)) + [14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
-                                  7 | (64 << 8), 1 | (64 << 8)]
+                                  7 | (64 << 8), 1 | (64 << 8), 255]
     for sched in codes:
         res = hm.solve(cnf, steps=3, restarts=R, eval_every=1, x0=xt, schedule=sched, want_x=True)
         xf = res.x_final.cpu().numpy()
@@ -122,6 +122,42 @@ def test_single_restart_schedules_bitwise():
         else:
             for a, b in zip(cur, ref):
                 np.testing.assert_array_equal(a, b)
+
+
+RESIDENT = 255
+
+
+@pytest.mark.parametrize("kind,R,opt,mode", [
+    ("uniform", 1, hm.ADAM, hm.LOSS_UNSAT), ("uniform", 4, hm.SGD, hm.LOSS_ALL),
+    ("mixed", 16, hm.ADAM, hm.LOSS_UNSAT), ("skewed", 1, hm.ADAM, hm.LOSS_UNSAT),
+    ("skewed", 3, hm.SGD, hm.LOSS_UNSAT), ("edge", 2, hm.ADAM, hm.LOSS_ALL)])
+def test_resident_matches_tiled(kind, R, opt, mode):
+    """The resident solver (whole loop in one workgroup, state in LDS) is
+    bitwise equal to the tiled kernels: per-restart bests, steps, final x and
+    best assignment."""
+    if kind == "uniform":
+        n, lits = 50, cnfgen.uniform_kcnf(50, 215, 3, seed=1)
+    elif kind == "mixed":
+        n, lits = 1000, cnfgen.mixed_kcnf(1000, 4200, seed=4)
+    elif kind == "skewed":
+        n, lits = 3000, cnfgen.structured_cnf(3000, 15000, seed=4)
+    else:
+        n, lits = edge_case_cnf()
+    cnf = hm.load_cnf(n, lits)
+    lr = 0.05 if opt == hm.SGD else 1e-2
+    kw = dict(steps=150, restarts=R, eval_every=5, seed=9, optimizer=opt, lr=lr, loss_mode=mode,
+              want_x=True)
+    a = hm.solve(cnf, schedule=RESIDENT, **kw)
+    b = hm.solve(cnf, schedule={1: 1, 2: 2, 3: 3, 4: 3, 16: 4}[R], **kw)
+    _say(f"resident {kind} R={R}: best {a.best_cost} vs tiled {b.best_cost} (sched {b.schedule})")
+    assert a.schedule == RESIDENT and b.schedule != RESIDENT
+    np.testing.assert_array_equal(a.restart_best, b.restart_best)
+    np.testing.assert_array_equal(a.restart_step, b.restart_step)
+    np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32),
+                                  b.x_final.cpu().numpy().view(np.uint32))
+    np.testing.assert_array_equal(a.best_assignment, b.best_assignment)
+    assert hm.evaluate(cnf, a.best_assignment) == a.best_cost
+    np.testing.assert_allclose(a.restart_loss, b.restart_loss, rtol=1e-12)
 
 
 def test_eval_cfg2_full_size():
