@@ -182,6 +182,25 @@ hms_status hms_evaluate(const hms_cnf* cnf, const uint8_t* assignment, int64_t* 
 hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t restarts, int32_t loss_mode,
                             double* loss, float* grad, int64_t* unsat, void* stream);
 
+/*
+ * Differentiable pieces of the loss, for autograd frameworks (Section 4: the
+ * loss is differentiated through the network by backpropagation).
+ * hms_forward: loss[R] (DEVICE doubles) at x (DEVICE [n][R]) and optionally the
+ * unsat counts (DEVICE int64 [R]); when `adjoint` is non-NULL it receives the
+ * score adjoint dL/df (DEVICE workspace of hms_adjoint_bytes bytes, opaque
+ * layout) for a later hms_backward.  The unsat mask is held constant under
+ * differentiation (it depends on the rounding only).
+ * hms_backward: grad_x (DEVICE [n][R]) = grad_loss[r] * dL_r/dx (grad_loss DEVICE
+ * floats [R], or NULL for 1).  With `adjoint` NULL the scores are recomputed
+ * from x (checkpoint mode); the gradient is bitwise the same either way.
+ * Both are asynchronous on `stream`.
+ */
+hms_status hms_adjoint_bytes(const hms_cnf* cnf, int32_t restarts, int64_t* bytes);
+hms_status hms_forward(const hms_cnf* cnf, const float* x, int32_t restarts, int32_t loss_mode, double* loss,
+                       int64_t* unsat, void* adjoint, void* stream);
+hms_status hms_backward(const hms_cnf* cnf, const float* x, int32_t restarts, int32_t loss_mode,
+                        const void* adjoint, const float* grad_loss, float* grad_x, void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* hms_last_error(void);
 

@@ -74,7 +74,7 @@ class PlanView(C.Structure):
 EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_cnf",
            "hms_solve_params_default", "hms_solve", "hms_evaluate", "hms_eval_relaxed",
            "hms_last_error", "hms_version", "hms_plan_view_build", "hms_plan_view_free",
-           "hms_time_kernels", "hms_tune"]
+           "hms_time_kernels", "hms_tune", "hms_adjoint_bytes", "hms_forward", "hms_backward"]
 
 _lib = None
 
@@ -99,6 +99,9 @@ def lib():
     L.hms_evaluate.argtypes = [P, P, P, P]
     L.hms_time_kernels.argtypes = [P, C.POINTER(SolveParams), I32, P, P, P]
     L.hms_tune.argtypes = [P, C.POINTER(SolveParams), I32, P, P]
+    L.hms_adjoint_bytes.argtypes = [P, I32, P]
+    L.hms_forward.argtypes = [P, P, I32, I32, P, P, P, P]
+    L.hms_backward.argtypes = [P, P, I32, I32, P, P, P, P]
     L.hms_eval_relaxed.argtypes = [P, P, I32, I32, P, P, P, P]
     L.hms_last_error.argtypes = []
     L.hms_last_error.restype = C.c_char_p
@@ -108,7 +111,8 @@ def lib():
     L.hms_plan_view_free.argtypes = [C.POINTER(PlanView)]
     L.hms_plan_view_free.restype = None
     for name in ("hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_solve",
-                 "hms_evaluate", "hms_eval_relaxed", "hms_plan_view_build", "hms_time_kernels", "hms_tune"):
+                 "hms_evaluate", "hms_eval_relaxed", "hms_plan_view_build", "hms_time_kernels", "hms_tune", "hms_adjoint_bytes",
+                 "hms_forward", "hms_backward"):
         getattr(L, name).restype = I32
     _lib = L
     return L

@@ -121,12 +121,14 @@ struct Shape {
 // work unit U (0 = the default for that entry).  The bitset variants apply to
 // one restart with the unsat-masked loss; elsewhere they fall back to their
 // unmasked twin (same arithmetic).
-hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_mode, Shape& sh) {
+hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_mode, Shape& sh,
+                      bool allow_mask = true) {
     const int idx = req & 0xff;
     int U = (req >> 8) & 0xff;
     if (req < 0 || (req >> 16) != 0 || idx > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
     sh.sched = idx == 0 ? auto_schedule(R, loss_mode) : idx;
-    if (hms::kSchedules[sh.sched].mask && (R != 1 || loss_mode != HMS_LOSS_UNSAT)) sh.sched -= 22;  // 23..25 -> 1..3
+    if (hms::kSchedules[sh.sched].mask && (R != 1 || loss_mode != HMS_LOSS_UNSAT || !allow_mask))
+        sh.sched -= 22;  // 23..25 -> 1..3
     const hms::Schedule& c = hms::kSchedules[sh.sched];
     sh.P = c.P;
     sh.V = c.V;
@@ -1012,6 +1014,86 @@ hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t R, int32
     if (loss) HIPTRY(hipMemcpyAsync(loss, S.cur_loss, R * 8, hipMemcpyDeviceToHost, s));
     if (unsat) HIPTRY(hipMemcpyAsync(unsat, S.cur_count, R * 8, hipMemcpyDeviceToHost, s));
     if (loss || unsat) HIPTRY(hipStreamSynchronize(s));
+    return HMS_OK;
+}
+
+// ---- differentiable forward / backward ---------------------------------------
+// Both use the automatic schedule for R without the bitset, so the adjoint a
+// forward saves is the array the backward reads.
+hms_status adjoint_shape(const hms_cnf* cnf, int32_t R, int32_t loss_mode, Shape& sh) {
+    if (R < 1) return fail(HMS_ERR_ARG, "restarts >= 1 required");
+    if (loss_mode != HMS_LOSS_UNSAT && loss_mode != HMS_LOSS_ALL) return fail(HMS_ERR_ARG, "unknown loss mode");
+    return make_shape(cnf->plan, R, 0, loss_mode, sh, false);
+}
+
+hms_status hms_adjoint_bytes(const hms_cnf* cnf, int32_t R, int64_t* bytes) {
+    g_err.clear();
+    if (check_cnf(cnf) || !bytes) return fail(HMS_ERR_ARG, "null argument");
+    Shape sh;
+    hms_status rc = adjoint_shape(cnf, R, HMS_LOSS_UNSAT, sh);
+    if (rc) return rc;
+    *bytes = (int64_t)sh.B.rows_a * sh.B.RG * sh.B.G * 4;
+    return HMS_OK;
+}
+
+hms_status hms_forward(const hms_cnf* cnf, const float* x, int32_t R, int32_t loss_mode, double* loss,
+                       int64_t* unsat, void* adjoint, void* stream) {
+    g_err.clear();
+    if (check_cnf(cnf) || (!x && cnf->plan.n > 0) || !loss) return fail(HMS_ERR_ARG, "null argument");
+    const hms::HostPlan& P = cnf->plan;
+    DeviceGuard dg(cnf->device);
+    hipStream_t s = (hipStream_t)stream;
+    Shape sh;
+    hms_status rc = adjoint_shape(cnf, R, loss_mode, sh);
+    if (rc) return rc;
+    Layout lay;
+    size_t off[kOffN];
+    layout_state(P, sh, false, false, false, lay, off);
+    Arena A;
+    A.s = s;
+    HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+    State S = bind_state(A, off, false, false, false);
+    if (adjoint) S.a = static_cast<float*>(adjoint);
+    hms::InitArgs ia = make_init(cnf, sh, S);
+    ia.x0 = x;
+    HIPTRY(hms::launch_init(ia, s));
+    Launch L = make_launch(cnf, sh, S, hms::kGrad, loss_mode, 0.f, 0.9f, 0.999f, 1e-8f);
+    L.ra.track = 0;
+    HIPTRY(hms::launch_fwd(sh.sched, true, L.fa, sh.fwd_blocks, s));
+    HIPTRY(hms::launch_reduce(L.ra, s));
+    HIPTRY(hipMemcpyAsync(loss, S.cur_loss, (size_t)R * 8, hipMemcpyDeviceToDevice, s));
+    if (unsat) HIPTRY(hipMemcpyAsync(unsat, S.cur_count, (size_t)R * 8, hipMemcpyDeviceToDevice, s));
+    return HMS_OK;
+}
+
+hms_status hms_backward(const hms_cnf* cnf, const float* x, int32_t R, int32_t loss_mode, const void* adjoint,
+                        const float* grad_loss, float* grad_x, void* stream) {
+    g_err.clear();
+    if (check_cnf(cnf) || (!x && cnf->plan.n > 0) || (!grad_x && cnf->plan.n > 0))
+        return fail(HMS_ERR_ARG, "null argument");
+    const hms::HostPlan& P = cnf->plan;
+    DeviceGuard dg(cnf->device);
+    hipStream_t s = (hipStream_t)stream;
+    Shape sh;
+    hms_status rc = adjoint_shape(cnf, R, loss_mode, sh);
+    if (rc) return rc;
+    Layout lay;
+    size_t off[kOffN];
+    layout_state(P, sh, false, true, false, lay, off);
+    Arena A;
+    A.s = s;
+    HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+    State S = bind_state(A, off, false, true, false);
+    if (adjoint) S.a = const_cast<float*>(static_cast<const float*>(adjoint));
+    hms::InitArgs ia = make_init(cnf, sh, S);
+    ia.x0 = x;
+    if (adjoint) ia.a = nullptr;  // the saved adjoint is read-only here
+    HIPTRY(hms::launch_init(ia, s));
+    Launch L = make_launch(cnf, sh, S, hms::kGrad, loss_mode, 0.f, 0.9f, 0.999f, 1e-8f);
+    if (!adjoint) HIPTRY(hms::launch_fwd(sh.sched, false, L.fa, sh.fwd_blocks, s));  // recompute the scores
+    HIPTRY(hms::launch_bwd(sh.sched, hms::kGrad, L.ba, sh.bwd_blocks, s));
+    HIPTRY(hms::launch_combine(hms::kGrad, L.ba, s));
+    HIPTRY(hms::launch_scatter(P.n, P.n_act, sh.B, cnf->var_old, S.g, grad_x, s, grad_loss));
     return HMS_OK;
 }
 

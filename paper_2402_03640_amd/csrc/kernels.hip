@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
     if (idx < B.R) {
         const int r = (int)idx;
         A.t[boff(B, B.rows_x, A.n, r)] = -0.0f;
-        A.a[boff(B, B.rows_a, A.a_zero_row, r)] = 0.0f;
+        if (A.a != nullptr) A.a[boff(B, B.rows_a, A.a_zero_row, r)] = 0.0f;
         if (A.best != nullptr) {
             A.best[r] = A.m;
             A.best_step[r] = -1;
@@ -576,12 +576,14 @@ __global__ __launch_bounds__(256) void k_extract(int32_t n, Blocking B, int32_t 
 }
 
 __global__ __launch_bounds__(256) void k_scatter(int32_t n, int32_t n_act, Blocking B, const int32_t* var_old,
-                                                  const float* src, float* dst) {
+                                                  const float* src, float* dst, const float* scale) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= (int64_t)n * B.R) return;
     const int32_t i = (int32_t)(idx / B.R);
     const int32_t r = (int32_t)(idx % B.R);
-    dst[(size_t)var_old[i] * B.R + r] = i < n_act ? src[boff(B, B.rows_x, i, r)] : 0.0f;
+    float v = i < n_act ? src[boff(B, B.rows_x, i, r)] : 0.0f;
+    if (scale != nullptr) v = scale[r] * v;
+    dst[(size_t)var_old[i] * B.R + r] = v;
 }
 
 template <int P, int V, int UR, int MASK>
@@ -708,11 +710,11 @@ hipError_t launch_extract(int32_t n, const Blocking& B, int32_t r, const int32_t
 }
 
 hipError_t launch_scatter(int32_t n, int32_t n_act, const Blocking& B, const int32_t* var_old, const float* src,
-                          float* dst, hipStream_t s) {
+                          float* dst, hipStream_t s, const float* scale) {
     const int64_t total = (int64_t)n * B.R;
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter, dim3((int)((total + 255) / 256)), dim3(256), 0, s, n, n_act, B, var_old, src,
-                       dst);
+                       dst, scale);
     return hipGetLastError();
 }
 

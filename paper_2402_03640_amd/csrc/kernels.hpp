@@ -144,7 +144,8 @@ hipError_t launch_snapshot(int32_t n_act, const Blocking& B, const float* x, con
                            uint8_t* best_a, hipStream_t s);
 hipError_t launch_extract(int32_t n, const Blocking& B, int32_t r, const int32_t* var_old, const uint8_t* best_a,
                           uint8_t* out, hipStream_t s);
+// dst[var_old[i]][r] = scale[r] * src(i, r) (scale may be null: 1), 0 for inactive variables.
 hipError_t launch_scatter(int32_t n, int32_t n_act, const Blocking& B, const int32_t* var_old, const float* src,
-                          float* dst, hipStream_t s);
+                          float* dst, hipStream_t s, const float* scale = nullptr);
 
 }  // namespace hms
