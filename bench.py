@@ -111,6 +111,87 @@ def cpu_baseline(wl, L, max_threads=16, sample_steps=None):
                       f"FP64, OpenMP over restarts, {dt:.2f} s wall"}
 
 
+def serve_bench(args):
+    """Serving workload: Poisson arrivals replayed in real time into the
+    continuous-batching server, then the same instances one at a time."""
+    import numpy as np
+    import torch
+
+    import cnfgen
+    import paper_2402_03640_amd as hm
+    from paper_2402_03640_amd.serve import Server, percentile
+
+    reqs = cnfgen.serving_stream(args.serve_requests, seed=5)
+    log(f"[serve] generating {len(reqs)} instances ...")
+    data = []
+    for i, r in enumerate(reqs):
+        data.append(r.cnf())
+        if i % 64 == 63:
+            log(f"[serve] generated {i + 1}")
+    L_tot = int(sum(int(np.count_nonzero(d)) for d in data))
+    T = args.serve_steps
+    params = [dict(steps=T, restarts=1, eval_every=50, seed=r.index, lr=1e-4, autotune=False)
+              for r in reqs]
+    # warm the code objects on a small instance
+    c = hm.load_cnf(reqs[0].n, data[0])
+    hm.solve(c, **params[0])
+    c.free()
+    torch.cuda.synchronize()
+    log("[serve] served run ...")
+    srv = Server(workers=args.serve_workers)
+    t0 = time.perf_counter()
+    futs = []
+    for r, lits, p in zip(reqs, data, params):
+        target = t0 + r.arrival_s
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            time.sleep(min(target - now, 0.002))
+        futs.append(srv.submit(r.n, lits, arrival=target, **p))
+    res = [f.result() for f in futs]
+    srv.close()
+    first = t0 + reqs[0].arrival_s
+    span = max(x.done for x in res) - first
+    lat = [x.latency for x in res]
+    served_ips = len(res) / span
+    log(f"[serve] served {len(res)} in {span:.3f} s, p50 {percentile(lat, 50)*1e3:.1f} ms, "
+        f"p99 {percentile(lat, 99)*1e3:.1f} ms")
+    log("[serve] plain run (one at a time, arrival order) ...")
+    t1 = time.perf_counter()
+    plain = []
+    plain_lat = []
+    for r, lits, p in zip(reqs, data, params):
+        a = time.perf_counter()
+        c = hm.load_cnf(r.n, lits)
+        plain.append(hm.solve(c, **p))
+        c.free()
+        plain_lat.append(time.perf_counter() - a)
+    plain_span = time.perf_counter() - t1
+    plain_ips = len(plain) / plain_span
+    same = all(int(a.best_cost) == int(b.output.best_cost) and
+               np.array_equal(a.best_assignment, b.output.best_assignment) for a, b in zip(plain, res))
+    log(f"[serve] plain {plain_span:.3f} s ({plain_ips:.1f} inst/s); results identical: {same}")
+    out = {
+        "metric": "instances/s (served, continuous batching)",
+        "value": served_ips, "unit": "instances/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * span, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} random k-CNF requests (k in 3..5, n log-uniform "
+                               f"100..200000, m = n U(3.5,5) 2^k/8), Poisson 200/s, {T} Adam steps, "
+                               f"eval every 50", "total_literals": L_tot,
+                   "workers": args.serve_workers},
+        "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99),
+                       "max": 1e3 * max(lat)},
+        "plain": {"instances_per_s": plain_ips, "p50_solve_ms": 1e3 * percentile(plain_lat, 50),
+                  "total_s": plain_span},
+        "speedup_vs_plain": served_ips / plain_ips,
+        "equal_cost": bool(same),
+        "fwd_bwd_nnz_per_s_served": 2.0 * L_tot * T / span,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +201,12 @@ def main():
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only time the forward/backward kernels (for counter runs), after a "
+                         "256 MiB device copy used to calibrate the byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solve loop is benchmarked on a single MI355X; "
@@ -133,6 +220,9 @@ def main():
     import paper_2402_03640_amd as hm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.config == "serve":
+        serve_bench(args)
+        return
     wl = make_workload(args.config)
     log(f"[bench] workload {wl['name']}: {wl['desc']}")
     t0 = time.perf_counter()
@@ -144,6 +234,21 @@ def main():
     log(f"[bench] loaded: L={L} heavy={cnf.info['n_heavy']} in {load_s:.3f} s")
 
     kw = dict(steps=T, restarts=R, eval_every=K, seed=0, lr=1e-4, schedule=args.schedule)
+    if args.kernels_only:
+        src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # calibration: 256 MiB read, 256 MiB written
+        torch.cuda.synchronize()
+        code = args.schedule or hm.tune(cnf, restarts=R)[0]
+        f, b, st = hm.time_kernels(cnf, restarts=R, iters=args.kernel_iters, lr=1e-4, schedule=code)
+        fb, bb = kernel_bytes(n, m, L, R)
+        print(json.dumps({"config": wl["name"], "schedule": code, "fwd_us": f * 1e3, "bwd_us": b * 1e3,
+                          "step_us": st * 1e3, "fwd_bytes": fb, "bwd_bytes": bb,
+                          "kernel_iters": args.kernel_iters, "calibration_copy_bytes": 2 * 4 * src.numel()}),
+              flush=True)
+        return
     for i in range(args.warmup):
         r = hm.solve(cnf, **kw)
         log(f"[bench] warmup {i}: best {r.best_cost} device {r.device_ms:.2f} ms")

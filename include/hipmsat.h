@@ -156,6 +156,17 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* params, 
                             double* fwd_ms, double* bwd_ms, double* step_ms);
 
 /*
+ * Batched solve of `count` instances (Algorithm 1 for each, as hms_solve):
+ * cnfs[i] with params[i] into results[i] (statuses[i], may be NULL, receives each
+ * instance's status).  Instances that fit the resident solver share launches,
+ * one workgroup per (instance, restart); the rest run one after the other on
+ * the tiled kernels.  All work goes on params[0].stream.  Each result is bitwise
+ * the one hms_solve gives for that instance alone.  Returns the first error.
+ */
+hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* params, int32_t count,
+                           hms_solve_result* results, hms_status* statuses);
+
+/*
  * Schedule autotuner: times every kernel schedule that can run
  * params->restarts restarts (`iters` steps each, HIP events on params->stream)
  * and records the fastest for this handle; later solves with schedule 0 use

@@ -74,7 +74,8 @@ class PlanView(C.Structure):
 EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_cnf",
            "hms_solve_params_default", "hms_solve", "hms_evaluate", "hms_eval_relaxed",
            "hms_last_error", "hms_version", "hms_plan_view_build", "hms_plan_view_free",
-           "hms_time_kernels", "hms_tune", "hms_adjoint_bytes", "hms_forward", "hms_backward"]
+           "hms_time_kernels", "hms_tune", "hms_adjoint_bytes", "hms_forward", "hms_backward",
+           "hms_solve_batch"]
 
 _lib = None
 
@@ -100,6 +101,7 @@ def lib():
     L.hms_time_kernels.argtypes = [P, C.POINTER(SolveParams), I32, P, P, P]
     L.hms_tune.argtypes = [P, C.POINTER(SolveParams), I32, P, P]
     L.hms_adjoint_bytes.argtypes = [P, I32, P]
+    L.hms_solve_batch.argtypes = [P, P, I32, P, P]
     L.hms_forward.argtypes = [P, P, I32, I32, P, P, P, P]
     L.hms_backward.argtypes = [P, P, I32, I32, P, P, P, P]
     L.hms_eval_relaxed.argtypes = [P, P, I32, I32, P, P, P, P]
@@ -112,7 +114,7 @@ def lib():
     L.hms_plan_view_free.restype = None
     for name in ("hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_solve",
                  "hms_evaluate", "hms_eval_relaxed", "hms_plan_view_build", "hms_time_kernels", "hms_tune", "hms_adjoint_bytes",
-                 "hms_forward", "hms_backward"):
+                 "hms_forward", "hms_backward", "hms_solve_batch"):
         getattr(L, name).restype = I32
     _lib = L
     return L
@@ -276,6 +278,53 @@ def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, s
         err.result = out
         raise err
     return out
+
+
+def solve_batch(cnfs, steps=1000, restarts=1, eval_every=1, seeds=0, optimizer: int = ADAM,
+                lr: float = 1e-4, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                loss_mode: int = LOSS_UNSAT, schedule: int = 0, stream=None):
+    """Solve many instances in one call (see ``hms_solve_batch``).  Scalar
+    arguments apply to every instance; lists give one value per instance.
+    Returns one SolveOutput per instance (``status`` set on each)."""
+    cnfs = list(cnfs)
+    N = len(cnfs)
+
+    def per(v):
+        return list(v) if isinstance(v, (list, tuple)) else [v] * N
+
+    steps, restarts, eval_every, seeds = per(steps), per(restarts), per(eval_every), per(seeds)
+    optimizer, lr, loss_mode, schedule = per(optimizer), per(lr), per(loss_mode), per(schedule)
+    params = (SolveParams * N)()
+    results = (SolveResult * N)()
+    statuses = (C.c_int32 * N)()
+    bufs = []
+    for i, cnf in enumerate(cnfs):
+        p = _params(cnf, steps[i], restarts[i], eval_every[i], seeds[i], optimizer[i], lr[i], beta1,
+                    beta2, eps, loss_mode[i], schedule[i], True, 0.0, None, stream, False)
+        params[i] = p
+        R = int(restarts[i])
+        ba = np.zeros(max(cnf.n, 1), dtype=np.uint8)
+        rb = np.zeros(R, dtype=np.int64)
+        rs = np.zeros(R, dtype=np.int32)
+        rl = np.zeros(R, dtype=np.float64)
+        results[i].best_assignment = ba.ctypes.data
+        results[i].restart_best = rb.ctypes.data
+        results[i].restart_step = rs.ctypes.data
+        results[i].restart_loss = rl.ctypes.data
+        bufs.append((ba, rb, rs, rl))
+    handles = (C.c_void_p * N)(*[c.handle.value for c in cnfs])
+    rc = lib().hms_solve_batch(handles, params, N, results, statuses)
+    outs = []
+    for i, cnf in enumerate(cnfs):
+        ba, rb, rs, rl = bufs[i]
+        r = results[i]
+        o = SolveOutput(r.best_cost, r.best_restart, r.best_step, r.steps_done, r.schedule,
+                        r.final_loss, r.device_ms, ba[:cnf.n].copy(), rb, rs, rl, None)
+        o.status = int(statuses[i])
+        outs.append(o)
+    if rc != HMS_OK and rc != -6:
+        _check(rc)
+    return outs
 
 
 def evaluate(cnf: Cnf, assignment, stream=None) -> int:

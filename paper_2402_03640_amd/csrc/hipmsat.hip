@@ -98,8 +98,8 @@ struct Arena {
 };
 
 // Default kernel schedule for R restarts (table index into hms::kSchedules).
-int auto_schedule(int32_t R, int loss_mode) {
-    if (R <= 1) return loss_mode == HMS_LOSS_UNSAT ? 24 : 2;
+int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0) {
+    if (R <= 1) return loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 21) ? 23 : 2;
     if (R <= 2) return 2;
     if (R <= 4) return 3;
     if (R <= 8) return 5;
@@ -126,7 +126,7 @@ hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_m
     const int idx = req & 0xff;
     int U = (req >> 8) & 0xff;
     if (req < 0 || (req >> 16) != 0 || idx > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
-    sh.sched = idx == 0 ? auto_schedule(R, loss_mode) : idx;
+    sh.sched = idx == 0 ? auto_schedule(R, loss_mode, P.nnz) : idx;
     if (hms::kSchedules[sh.sched].mask && (R != 1 || loss_mode != HMS_LOSS_UNSAT || !allow_mask))
         sh.sched -= 22;  // 23..25 -> 1..3
     const hms::Schedule& c = hms::kSchedules[sh.sched];
@@ -569,6 +569,24 @@ uint64_t tune_key(const hms_solve_params* p) {
            ((uint64_t)(uint32_t)p->loss_mode << 40);
 }
 
+int ilog2(int64_t v) {
+    int k = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++k;
+    }
+    return k;
+}
+
+// Process-wide cache by size class (restarts, optimizer, loss mode, log2 nnz,
+// log2 n): a new instance of a size already tuned reuses that choice.
+std::mutex g_tune_mu;
+std::map<uint64_t, int32_t> g_tuned;
+
+uint64_t class_key(const hms_cnf* cnf, const hms_solve_params* p) {
+    return tune_key(p) ^ ((uint64_t)ilog2(cnf->plan.nnz + 1) << 48) ^ ((uint64_t)ilog2(cnf->plan.n + 1) << 56);
+}
+
 // Every (schedule, rows per unit) pair that can run R restarts.
 std::vector<int32_t> tune_candidates(int32_t R, int loss_mode) {
     std::vector<int32_t> out;
@@ -622,8 +640,12 @@ hms_status tune(const hms_cnf* cnf, const hms_solve_params* p, int32_t iters, in
             best = code;
         }
     }
-    std::lock_guard<std::mutex> lk(cnf->tune_mu);
-    cnf->tuned[tune_key(p)] = best;
+    {
+        std::lock_guard<std::mutex> lk(cnf->tune_mu);
+        cnf->tuned[tune_key(p)] = best;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[class_key(cnf, p)] = best;
     return HMS_OK;
 }
 
@@ -635,6 +657,14 @@ hms_status resolve_schedule(const hms_cnf* cnf, const hms_solve_params* p, int32
         std::lock_guard<std::mutex> lk(cnf->tune_mu);
         auto it = cnf->tuned.find(tune_key(p));
         if (it != cnf->tuned.end()) {
+            code = it->second;
+            return HMS_OK;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(class_key(cnf, p));
+        if (it != g_tuned.end() && (it->second != kResidentId || resident_ok(cnf, p))) {
             code = it->second;
             return HMS_OK;
         }
@@ -962,6 +992,150 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* p, int32
     if (fwd_ms) *fwd_ms = a / iters;
     if (bwd_ms) *bwd_ms = b / iters;
     if (step_ms) *step_ms = c / iters;
+    return HMS_OK;
+}
+
+// Batched solve: every instance that fits the resident solver runs in shared
+// launches (one workgroup per (instance, restart), grouped by LDS size so
+// each launch wastes at most half its LDS), the others one after the other on
+// the tiled path.  Each result is bitwise what hms_solve gives alone.
+hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* params, int32_t count,
+                           hms_solve_result* results, hms_status* statuses) {
+    g_err.clear();
+    if (count < 0 || (count > 0 && (!cnfs || !params || !results))) return fail(HMS_ERR_ARG, "null argument");
+    if (count == 0) return HMS_OK;
+    hipStream_t s = (hipStream_t)params[0].stream;
+    int dev = cnfs[0] ? cnfs[0]->device : -1;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!cnfs[i]) return fail(HMS_ERR_ARG, "null instance handle");
+        if (cnfs[i]->device != dev) return fail(HMS_ERR_ARG, "all instances of a batch must be on one device");
+        const hms_solve_params& p = params[i];
+        if (p.restarts < 1 || p.steps < 0 || p.eval_every < 1 || (p.optimizer != HMS_ADAM && p.optimizer != HMS_SGD) ||
+            (p.loss_mode != HMS_LOSS_UNSAT && p.loss_mode != HMS_LOSS_ALL))
+            return fail(HMS_ERR_ARG, "invalid parameters for instance " + std::to_string(i));
+    }
+    DeviceGuard dg(dev);
+    std::vector<int32_t> res_idx, tiled_idx;
+    for (int32_t i = 0; i < count; ++i) {
+        const bool want_res = params[i].schedule == kResidentId ||
+                              (params[i].schedule == 0 && resident_ok(cnfs[i], &params[i]));
+        if (want_res && resident_ok(cnfs[i], &params[i])) res_idx.push_back(i);
+        else tiled_idx.push_back(i);
+    }
+    hms_status worst = HMS_OK;
+    std::string worst_msg;
+    if (!res_idx.empty()) {
+        std::sort(res_idx.begin(), res_idx.end(), [&](int32_t a, int32_t b) {
+            return hms::small_lds_bytes(cnfs[a]->plan) > hms::small_lds_bytes(cnfs[b]->plan);
+        });
+        // device arena: descriptors, then each instance's outputs
+        Layout lay;
+        const size_t o_desc = lay.add(sizeof(hms::SmallDesc) * res_idx.size());
+        std::vector<SmallOut> outs(res_idx.size());
+        for (size_t k = 0; k < res_idx.size(); ++k)
+            outs[k] = layout_small_out(cnfs[res_idx[k]]->plan, params[res_idx[k]].restarts, lay);
+        Arena A;
+        A.s = s;
+        HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+        std::vector<hms::SmallDesc> D(res_idx.size());
+        for (size_t k = 0; k < res_idx.size(); ++k) {
+            const int32_t i = res_idx[k];
+            D[k] = make_desc(cnfs[i], &params[i]);
+            D[k].best_a = A.at<uint8_t>(outs[k].o_best_a);
+            D[k].best = A.at<int64_t>(outs[k].o_best);
+            D[k].best_step = A.at<int32_t>(outs[k].o_step);
+            D[k].final_loss = A.at<double>(outs[k].o_loss);
+            D[k].x_final = results[i].x_final;
+        }
+        // launches: consecutive instances whose LDS need is within 2x of the first
+        size_t k0 = 0;
+        std::vector<std::pair<size_t, size_t>> groups;
+        while (k0 < res_idx.size()) {
+            const size_t big = hms::small_lds_bytes(cnfs[res_idx[k0]]->plan);
+            size_t k1 = k0 + 1;
+            while (k1 < res_idx.size() && 2 * hms::small_lds_bytes(cnfs[res_idx[k1]]->plan) >= big) ++k1;
+            groups.emplace_back(k0, k1);
+            k0 = k1;
+        }
+        for (auto& g : groups) {
+            int32_t blocks = 0;
+            for (size_t k = g.first; k < g.second; ++k) {
+                D[k].block0 = blocks;
+                blocks += params[res_idx[k]].restarts;
+            }
+        }
+        HIPTRY(hipMemcpyAsync(A.base + o_desc, D.data(), sizeof(hms::SmallDesc) * D.size(), hipMemcpyHostToDevice, s));
+        Events E;
+        for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
+        HIPTRY(hipEventRecord(E.e[0], s));
+        for (auto& g : groups) {
+            int32_t blocks = 0;
+            for (size_t k = g.first; k < g.second; ++k) blocks += params[res_idx[k]].restarts;
+            HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc) + g.first, (int32_t)(g.second - g.first), blocks,
+                                     hms::small_lds_bytes(cnfs[res_idx[g.first]]->plan), s));
+        }
+        HIPTRY(hipEventRecord(E.e[1], s));
+        // read back every resident result
+        std::vector<std::vector<int64_t>> best(res_idx.size());
+        std::vector<std::vector<int32_t>> step(res_idx.size());
+        std::vector<std::vector<double>> loss(res_idx.size());
+        for (size_t k = 0; k < res_idx.size(); ++k) {
+            const int32_t R = params[res_idx[k]].restarts;
+            best[k].resize(R);
+            step[k].resize(R);
+            loss[k].resize(R);
+            HIPTRY(hipMemcpyAsync(best[k].data(), D[k].best, R * 8, hipMemcpyDeviceToHost, s));
+            HIPTRY(hipMemcpyAsync(step[k].data(), D[k].best_step, R * 4, hipMemcpyDeviceToHost, s));
+            HIPTRY(hipMemcpyAsync(loss[k].data(), D[k].final_loss, R * 8, hipMemcpyDeviceToHost, s));
+        }
+        HIPTRY(hipStreamSynchronize(s));
+        float ms = 0;
+        HIPTRY(hipEventElapsedTime(&ms, E.e[0], E.e[1]));
+        for (size_t k = 0; k < res_idx.size(); ++k) {
+            const int32_t i = res_idx[k];
+            const int32_t R = params[i].restarts;
+            const hms::HostPlan& P = cnfs[i]->plan;
+            hms_solve_result& res = results[i];
+            int32_t br = 0;
+            for (int32_t r = 1; r < R; ++r)
+                if (best[k][r] < best[k][br]) br = r;
+            if (res.best_assignment && P.n > 0)
+                HIPTRY(hipMemcpyAsync(res.best_assignment, D[k].best_a + (size_t)br * P.n, P.n, hipMemcpyDeviceToHost,
+                                      s));
+            res.best_cost = best[k][br];
+            res.best_restart = br;
+            res.best_step = step[k][br];
+            res.steps_done = params[i].steps;
+            res.schedule = kResidentId;
+            res.final_loss = loss[k][br];
+            res.device_ms = ms;
+            if (res.restart_best) std::memcpy(res.restart_best, best[k].data(), R * 8);
+            if (res.restart_step) std::memcpy(res.restart_step, step[k].data(), R * 4);
+            if (res.restart_loss) std::memcpy(res.restart_loss, loss[k].data(), R * 8);
+            hms_status st = HMS_OK;
+            for (int32_t r = 0; r < R; ++r)
+                if (!std::isfinite(loss[k][r])) st = HMS_ERR_NONFINITE;
+            if (statuses) statuses[i] = st;
+            if (st && !worst) {
+                worst = st;
+                worst_msg = "instance " + std::to_string(i) + ": the loss at the final iterate is not finite";
+            }
+        }
+        HIPTRY(hipStreamSynchronize(s));
+    }
+    for (int32_t i : tiled_idx) {
+        hms_solve_params p = params[i];
+        p.stream = params[0].stream;
+        if (p.schedule == kResidentId) p.schedule = 0;
+        hms_status st = hms_solve(cnfs[i], &p, &results[i]);
+        if (statuses) statuses[i] = st;
+        if (st && !worst) {
+            worst = st;
+            worst_msg = "instance " + std::to_string(i) + ": " + g_err;
+        }
+    }
+    if (worst) return fail(worst, worst_msg);
+    g_err.clear();
     return HMS_OK;
 }
 

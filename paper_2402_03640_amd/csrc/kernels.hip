@@ -27,10 +27,9 @@ const Schedule kSchedules[kNumSchedules + 1] = {
 };
 
 int default_rows_per_unit(int sched) {
+    // one pass per unit: the most wavefronts, which the schedule sweeps favour
     const Schedule& c = kSchedules[sched];
-    const int per_pass = (64 / c.P) * c.UR;
-    int U = per_pass * 2;
-    if (U < 8) U = 8;
+    int U = (64 / c.P) * c.UR;
     if (c.mask && U < 32) U = 32;
     return U > 64 ? 64 : U;
 }

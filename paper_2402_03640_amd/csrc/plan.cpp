@@ -150,11 +150,16 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
     // ---- variable order: degree descending, ties by original index -------
     std::vector<int32_t> deg_orig((size_t)n, 0);
     for (uint32_t e : flat) deg_orig[e & kIdx]++;
-    P.var_old.resize((size_t)n);
-    std::iota(P.var_old.begin(), P.var_old.end(), 0);
-    std::stable_sort(P.var_old.begin(), P.var_old.end(), [&](int32_t a, int32_t b) {
-        return deg_orig[a] > deg_orig[b];
-    });
+    // counting sort: degree descending, ties by original index (stable)
+    {
+        int32_t maxd = 0;
+        for (int32_t i = 0; i < n; ++i) maxd = std::max(maxd, deg_orig[i]);
+        std::vector<int64_t> start((size_t)maxd + 2, 0);
+        for (int32_t i = 0; i < n; ++i) start[(size_t)(maxd - deg_orig[i]) + 1]++;
+        for (int32_t d = 0; d <= maxd; ++d) start[d + 1] += start[d];
+        P.var_old.resize((size_t)n);
+        for (int32_t i = 0; i < n; ++i) P.var_old[start[(size_t)(maxd - deg_orig[i])]++] = i;
+    }
     P.var_new.assign((size_t)n, 0);
     P.degree.assign((size_t)n, 0);
     for (int32_t i = 0; i < n; ++i) {
@@ -173,11 +178,24 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
         for (int32_t c = 0; c < r.len; ++c) mv = std::min(mv, P.var_new[flat[r.off + c] & kIdx]);
         r.minvar = mv;
     }
-    std::stable_sort(rows.begin(), rows.end(), [](const Row& a, const Row& b) {
-        if (a.taut != b.taut) return !a.taut;
-        if (a.len != b.len) return a.len > b.len;
-        return a.minvar < b.minvar;
-    });
+    // stable two-pass counting sort: by smallest variable, then by (tautology
+    // flag, length descending)
+    {
+        std::vector<Row> tmp(rows.size());
+        std::vector<int64_t> cnt((size_t)n + 2, 0);
+        for (const Row& r : rows) cnt[(size_t)r.minvar + 1]++;
+        for (int32_t v = 0; v <= n; ++v) cnt[v + 1] += cnt[v];
+        for (const Row& r : rows) tmp[cnt[r.minvar]++] = r;
+        int32_t maxl = 0;
+        for (const Row& r : tmp) maxl = std::max(maxl, r.len);
+        // bucket b: plain rows of length maxl - b for b <= maxl, then tautologies likewise
+        const size_t nb = 2 * ((size_t)maxl + 1);
+        std::vector<int64_t> c2(nb + 1, 0);
+        auto bucket = [&](const Row& r) { return (size_t)(r.taut ? maxl + 1 : 0) + (size_t)(maxl - r.len); };
+        for (const Row& r : tmp) c2[bucket(r) + 1]++;
+        for (size_t b = 0; b < nb; ++b) c2[b + 1] += c2[b];
+        for (const Row& r : tmp) rows[c2[bucket(r)]++] = r;
+    }
     int32_t n_plain = 0;
     while (n_plain < (int32_t)rows.size() && !rows[n_plain].taut) ++n_plain;
     int32_t n_tr = (int32_t)rows.size() - n_plain;
@@ -219,11 +237,8 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
     std::vector<uint32_t> occ((size_t)P.nnz);
     {
         std::vector<int64_t> fill(voff.begin(), voff.end() - 1);
-        // visit rows in increasing kernel-row order
-        std::vector<int32_t> by_krow(rows.size());
-        std::iota(by_krow.begin(), by_krow.end(), 0);
-        std::sort(by_krow.begin(), by_krow.end(), [&](int32_t a, int32_t b) { return krow[a] < krow[b]; });
-        for (int32_t r : by_krow) {
+        // rows are already in increasing kernel-row order
+        for (size_t r = 0; r < rows.size(); ++r) {
             const Row& R = rows[r];
             for (int32_t c = 0; c < R.len; ++c) {
                 uint32_t e = flat[R.off + c];

@@ -1,0 +1,212 @@
+"""Continuous-batching solve server.
+
+Requests (a CNF plus solve parameters) arrive at any time.  A dispatcher admits
+them in arrival order while their estimated device footprint fits the budget;
+worker threads, each with its own HIP stream, build and upload the instance plan
+and solve it, so requests admitted while others are running overlap on the
+device.  Queued requests small enough for the resident solver are taken
+together and solved in one launch (one workgroup per instance and restart).
+Every instance's result is bitwise what a solo ``solve`` gives: the kernels'
+summation order depends on the instance only, never on the batch.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+
+# instances at most this large (n + m) are grouped for the resident solver
+SMALL_ROWS = 12000
+
+
+def footprint_bytes(n: int, m: int, n_lits: int, restarts: int = 1) -> int:
+    """Device bytes of one solve: plan (both sparse layouts, tiles, offsets)
+    plus per-restart state (x, m, v, t, adjoint, best bytes, heavy partials)."""
+    L = max(n_lits, 0)
+    struct = 4 * (2 * L + m + n + 2) + 16 * (m + n) // 64 + 4 * n + 8 * L // 64
+    state = restarts * (16 * (n + 1) + 4 * (m + 64) + (n + 1) + 8 * L // 64) + 4096
+    return int(1.25 * (struct + state)) + (1 << 16)
+
+
+@dataclass
+class Request:
+    n: int
+    lits: np.ndarray
+    params: dict
+    arrival: float = 0.0
+    future: Future = field(default_factory=Future)
+    footprint: int = 0
+    small: bool = False
+    rid: int = 0
+
+
+@dataclass
+class ServeResult:
+    rid: int
+    output: object          # SolveOutput
+    arrival: float
+    admitted: float
+    done: float
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Server:
+    """Admit by footprint, overlap on device, batch the small ones."""
+
+    def __init__(self, workers: int = 8, hbm_budget: int | None = None, small_batch: int = 64,
+                 device: int = 0):
+        import torch
+        self._torch = torch
+        torch.cuda.set_device(device)
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(device)
+            hbm_budget = int(0.5 * free)
+        self.budget = int(hbm_budget)
+        self.in_use = 0
+        self.small_batch = int(small_batch)
+        self._queue: collections.deque[Request] = collections.deque()
+        self._cv = threading.Condition()
+        self._closed = False
+        self._ids = 0
+        self._jobs: collections.deque[list[Request]] = collections.deque()
+        self._workers = []
+        for w in range(workers):
+            t = threading.Thread(target=self._work, args=(w, device), daemon=True)
+            t.start()
+            self._workers.append(t)
+        self._disp = threading.Thread(target=self._dispatch, daemon=True)
+        self._disp.start()
+
+    # -- client side -------------------------------------------------------------
+    def submit(self, n: int, lits, arrival: float | None = None, **params) -> Future:
+        lits = np.ascontiguousarray(lits, dtype=np.int32)
+        m = int(np.count_nonzero(lits == 0))
+        R = int(params.get("restarts", 1))
+        req = Request(n=int(n), lits=lits, params=params,
+                      arrival=time.perf_counter() if arrival is None else arrival)
+        req.footprint = footprint_bytes(n, m, lits.size - m, R)
+        req.small = (n + m) <= SMALL_ROWS
+        with self._cv:
+            if self._closed:
+                raise RuntimeError("server is closed")
+            req.rid = self._ids
+            self._ids += 1
+            self._queue.append(req)
+            self._cv.notify_all()
+        return req.future
+
+    def close(self, wait: bool = True):
+        with self._cv:
+            self._closed = True
+            self._cv.notify_all()
+        if wait:
+            self._disp.join()
+            for t in self._workers:
+                t.join()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- dispatcher: admission control and grouping -----------------------------
+    def _dispatch(self):
+        while True:
+            with self._cv:
+                while True:
+                    if self._queue:
+                        head = self._queue[0]
+                        if self.in_use + head.footprint <= self.budget or self.in_use == 0:
+                            break
+                    elif self._closed:
+                        self._jobs.append(None)
+                        self._cv.notify_all()
+                        return
+                    self._cv.wait()
+                job = [self._queue.popleft()]
+                self.in_use += job[0].footprint
+                if job[0].small:
+                    # take the other queued small requests that fit as well
+                    keep = collections.deque()
+                    while self._queue and len(job) < self.small_batch:
+                        r = self._queue.popleft()
+                        if r.small and self.in_use + r.footprint <= self.budget:
+                            job.append(r)
+                            self.in_use += r.footprint
+                        else:
+                            keep.append(r)
+                    keep.extend(self._queue)
+                    self._queue = keep
+                now = time.perf_counter()
+                for r in job:
+                    r.params["_admitted"] = now
+                self._jobs.append(job)
+                self._cv.notify_all()
+
+    # -- workers ------------------------------------------------------------------
+    def _work(self, w: int, device: int):
+        torch = self._torch
+        torch.cuda.set_device(device)
+        stream = torch.cuda.Stream(device=device)
+        while True:
+            with self._cv:
+                while not self._jobs:
+                    self._cv.wait()
+                job = self._jobs.popleft()
+                if job is None:
+                    self._jobs.append(None)  # let the other workers see it
+                    self._cv.notify_all()
+                    return
+            try:
+                self._run(job, stream)
+            except Exception as e:  # deliver the failure to every request of the job
+                for r in job:
+                    if not r.future.done():
+                        r.future.set_exception(e)
+            finally:
+                with self._cv:
+                    for r in job:
+                        self.in_use -= r.footprint
+                    self._cv.notify_all()
+
+    def _run(self, job, stream):
+        cnfs = [_lib.load_cnf(r.n, r.lits, stream=stream) for r in job]
+        try:
+            clean = []
+            for r in job:
+                p = {k: v for k, v in r.params.items() if not k.startswith("_")}
+                clean.append(p)
+            if len(job) == 1:
+                outs = [_lib.solve(cnfs[0], stream=stream, **clean[0])]
+            else:
+                keys = ("steps", "restarts", "eval_every", "optimizer", "lr", "loss_mode")
+                kw = {k: [p.get(k, d) for p in clean] for k, d in
+                      zip(keys, (1000, 1, 1, _lib.ADAM, 1e-4, _lib.LOSS_UNSAT))}
+                outs = _lib.solve_batch(cnfs, seeds=[p.get("seed", 0) for p in clean], stream=stream,
+                                        **kw)
+        finally:
+            for c in cnfs:
+                c.free()
+        done = time.perf_counter()
+        for r, o in zip(job, outs):
+            r.future.set_result(ServeResult(r.rid, o, r.arrival, r.params["_admitted"], done))
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    f = int(np.floor(k))
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)

@@ -1,0 +1,96 @@
+"""Batching and serving: each instance's result is the same alone, in a
+batched launch, and served in a mix with others (bitwise)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import cnfgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hm = pytest.importorskip("paper_2402_03640_amd")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+def _requests(count, seed, n_hi=6000):
+    reqs = cnfgen.serving_stream(count, seed=seed, rate=400.0, n_lo=50, n_hi=n_hi)
+    return [(r.n, r.cnf(), dict(steps=120, restarts=1 + (r.index % 3), eval_every=10, seed=r.index,
+                                lr=1e-2)) for r in reqs]
+
+
+def _same(a, b):
+    np.testing.assert_array_equal(a.restart_best, b.restart_best)
+    np.testing.assert_array_equal(a.restart_step, b.restart_step)
+    np.testing.assert_array_equal(a.best_assignment, b.best_assignment)
+    # the FP64 loss total may differ in the last bits between schedules
+    np.testing.assert_allclose(a.restart_loss, b.restart_loss, rtol=1e-12, atol=0)
+
+
+def test_solve_batch_equals_solo():
+    reqs = _requests(24, seed=1)
+    cnfs = [hm.load_cnf(n, lits) for n, lits, _ in reqs]
+    solo = [hm.solve(c, **p) for c, (_, _, p) in zip(cnfs, reqs)]
+    batch = hm.solve_batch(cnfs, steps=[p["steps"] for *_, p in reqs],
+                           restarts=[p["restarts"] for *_, p in reqs],
+                           eval_every=[p["eval_every"] for *_, p in reqs],
+                           seeds=[p["seed"] for *_, p in reqs], lr=[p["lr"] for *_, p in reqs])
+    kinds = {}
+    for c, a, b in zip(cnfs, solo, batch):
+        assert b.status == 0
+        _same(a, b)
+        kinds[b.schedule == 255] = kinds.get(b.schedule == 255, 0) + 1
+        assert hm.evaluate(c, b.best_assignment) == b.best_cost
+    _say(f"batch: resident {kinds.get(True, 0)}, tiled {kinds.get(False, 0)}")
+    assert kinds.get(True, 0) > 0 and kinds.get(False, 0) > 0
+
+
+def test_served_equals_solo_and_overlaps():
+    from paper_2402_03640_amd.serve import Server
+    reqs = _requests(40, seed=2)
+    solo = []
+    for n, lits, p in reqs:
+        c = hm.load_cnf(n, lits)
+        solo.append(hm.solve(c, **p))
+        c.free()
+    t0 = time.perf_counter()
+    with Server(workers=4) as srv:
+        futs = []
+        for i, (n, lits, p) in enumerate(reqs):
+            futs.append(srv.submit(n, lits, **p))
+            time.sleep(0.001 * (i % 3))
+        res = [f.result(timeout=120) for f in futs]
+    wall = time.perf_counter() - t0
+    for a, r in zip(solo, res):
+        _same(a, r.output)
+        assert r.latency > 0 and r.done >= r.admitted >= r.arrival
+    # requests were in flight together: latencies overlap in time
+    spans = sorted((r.admitted, r.done) for r in res)
+    overlap = sum(1 for (a0, a1), (b0, b1) in zip(spans, spans[1:]) if b0 < a1)
+    _say(f"served {len(res)} in {wall:.3f} s, overlapping pairs {overlap}")
+    assert overlap > 0
+
+
+def test_admission_respects_budget():
+    from paper_2402_03640_amd.serve import Server, footprint_bytes
+    reqs = _requests(10, seed=3, n_hi=3000)
+    budget = max(footprint_bytes(n, int(np.count_nonzero(l == 0)), l.size, p["restarts"])
+                 for n, l, p in reqs) + 1
+    with Server(workers=4, hbm_budget=budget) as srv:
+        futs = [srv.submit(n, lits, **p) for n, lits, p in reqs]
+        res = [f.result(timeout=120) for f in futs]
+    # with room for about one request at a time the admissions do not overlap much
+    assert all(r.output.best_cost >= 0 for r in res)
+    assert srv.in_use == 0
