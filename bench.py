@@ -44,9 +44,10 @@ def kernels_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_record(kernel_key):
-    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+def traffic_record(config, schedule, kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/traffic.json), if it was taken on the current kernel sources
+    with the same schedule; None otherwise."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -56,10 +57,11 @@ def traffic_record(kernel_key):
         return None
     if rec.get("kernels_sha") != kernels_sha():
         return None
-    k = rec.get("kernels", {}).get(kernel_key)
-    if not k:
+    c = rec.get("configs", {}).get(config)
+    if not c or c.get("schedule") != schedule:
         return None
-    return k.get("hbm_bytes_per_launch")
+    k = c.get("kernels", {}).get(kernel_key)
+    return None if not k else round(k["hbm_bytes_per_launch"])
 
 
 def make_workload(name):
@@ -284,7 +286,8 @@ def main():
             oname, obytes, oms = "backward", bb, bwd_ms
         achieved = dbytes / (dms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_record(key),
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": traffic_record(wl["name"], r.schedule, key),
                 "kernel": dom, "algorithmic_bytes_per_launch": dbytes,
                 "avg_launch_us": round(dms * 1e3, 3),
                 "other_kernel": {"name": oname, "avg_launch_us": round(oms * 1e3, 3),
