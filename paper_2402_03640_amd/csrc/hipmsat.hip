@@ -281,6 +281,7 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     hms::FwdArgs& f = L.fa;
     f.tiles = C->c_tile;
     f.ent = C->c_ent;
+    f.pad_entry = (uint32_t)P.n;
     f.ntiles = P.c_tiles;
     f.chunks = sh.chunks;
     f.U = sh.U;
@@ -299,6 +300,7 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     hms::BwdArgs& b = L.ba;
     b.tiles = C->v_tile;
     b.ent = C->v_ent;
+    b.pad_entry = (uint32_t)P.a_zero_row();
     b.ntiles = P.v_tiles;
     b.seg_tiles = P.seg_tiles;
     b.chunks = sh.chunks;
@@ -387,9 +389,9 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     const hms::HostPlan& P = C->plan;
     Layout L;
     size_t o_ct = L.add(P.c_tile.size() * sizeof(hms::TileDesc));
-    size_t o_ce = L.add(P.c_ent.size() * 4);
+    size_t o_ce = L.add((P.c_ent.size() + hms::kEntrySlack) * 4);
     size_t o_vt = L.add(P.v_tile.size() * sizeof(hms::TileDesc));
-    size_t o_ve = L.add(P.v_ent.size() * 4);
+    size_t o_ve = L.add((P.v_ent.size() + hms::kEntrySlack) * 4);
     size_t o_sf = L.add(P.seg_first.size() * 4);
     size_t o_sr = L.add(P.seg_row.size() * 4);
     size_t o_vo = L.add(P.var_old.size() * 4);

@@ -36,6 +36,12 @@ int default_rows_per_unit(int sched) {
 
 namespace {
 
+// Columns per load batch in the tiled kernels: clauses are short, variable
+// rows longer (the entry arrays carry kEntrySlack entries of slack at their
+// end, so a batch may read past a row's end).
+constexpr int kChunkF = 4;
+constexpr int kChunkB = 8;
+
 template <int V>
 struct VecF {
     float v[V];
@@ -147,22 +153,34 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
             }
         if (ract) {
             if (d.len <= 16) {
-#pragma unroll 2
-                for (uint32_t c = 0; c < d.len; ++c) {
-                    uint32_t en[UR];
+                // chunks of kChunkF columns: all entry loads, then all gathers,
+                // then the sums in column order; columns past the row's end
+                // read the padding entry (inert: adds -0.0, stays "false")
+                for (uint32_t c0 = 0; c0 < d.len; c0 += kChunkF) {
+                    uint32_t en[kChunkF][UR];
 #pragma unroll
-                    for (int j = 0; j < UR; ++j) en[j] = ldc(e + (size_t)c * kTile + j);
-                    VecF<V> tv[UR];
+                    for (int cc = 0; cc < kChunkF; ++cc)
 #pragma unroll
-                    for (int j = 0; j < UR; ++j) tv[j] = ldv<V>(tg + (size_t)(en[j] & kIdx) * B.G + rl);
-#pragma unroll
-                    for (int j = 0; j < UR; ++j)
-#pragma unroll
-                        for (int k = 0; k < V; ++k) {
-                            const uint32_t b = __float_as_uint(tv[j].v[k]) ^ (en[j] & kSign);
-                            f[j][k] = f[j][k] + __uint_as_float(b);
-                            allf[j][k] &= b;
+                        for (int j = 0; j < UR; ++j) {
+                            const uint32_t v = ldc(e + (size_t)(c0 + cc) * kTile + j);
+                            en[cc][j] = c0 + cc < d.len ? v : A.pad_entry;
                         }
+                    VecF<V> tv[kChunkF][UR];
+#pragma unroll
+                    for (int cc = 0; cc < kChunkF; ++cc)
+#pragma unroll
+                        for (int j = 0; j < UR; ++j)
+                            tv[cc][j] = ldv<V>(tg + (size_t)(en[cc][j] & kIdx) * B.G + rl);
+#pragma unroll
+                    for (int cc = 0; cc < kChunkF; ++cc)
+#pragma unroll
+                        for (int j = 0; j < UR; ++j)
+#pragma unroll
+                            for (int k = 0; k < V; ++k) {
+                                const uint32_t b = __float_as_uint(tv[cc][j].v[k]) ^ (en[cc][j] & kSign);
+                                f[j][k] = f[j][k] + __uint_as_float(b);
+                                allf[j][k] &= b;
+                            }
                 }
             } else {
                 // long clauses: FP64 accumulation, one row at a time
@@ -244,8 +262,27 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
 // first restart's index.
 // ---------------------------------------------------------------------------
 template <int V, int OPT>
-__device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int r0, const double (&G)[V]) {
-    VecF<V> xv = ldv<V>(A.x + base);
+struct VarState {
+    VecF<V> x, m, v;
+};
+
+// Loads of the epilogue's inputs, issued before the transposed sum so they
+// overlap its gathers.
+template <int V, int OPT>
+__device__ __forceinline__ VarState<V, OPT> var_load(const BwdArgs& A, size_t base) {
+    VarState<V, OPT> st;
+    st.x = ldv<V>(A.x + base);
+    if constexpr (OPT == kAdam) {
+        st.m = ldv<V>(A.m + base);
+        st.v = ldv<V>(A.v + base);
+    }
+    return st;
+}
+
+template <int V, int OPT>
+__device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int r0, const double (&G)[V],
+                                             VarState<V, OPT> st) {
+    VecF<V>& xv = st.x;
     if (A.eval) {
 #pragma unroll
         for (int k = 0; k < V; ++k)
@@ -273,8 +310,8 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int 
         const float ss = A.st->step_size;
         const float ib2 = A.st->inv_sqrt_bc2;
         const AdamCoef co{A.b1, A.b2, A.eps, A.omb1, A.omb2};
-        VecF<V> mv = ldv<V>(A.m + base);
-        VecF<V> vv = ldv<V>(A.v + base);
+        VecF<V>& mv = st.m;
+        VecF<V>& vv = st.v;
         VecF<V> tv;
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -288,6 +325,11 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int 
     }
 }
 
+template <int V, int OPT>
+__device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int r0, const double (&G)[V]) {
+    var_epilogue<V, OPT>(A, base, r0, G, var_load<V, OPT>(A, base));
+}
+
 // ---------------------------------------------------------------------------
 // Backward: transposed sums G = sum_j W_ij a_j over variable rows (atomic-free;
 // each (row, restart) summed by one lane in FP64 in entry order), fused
@@ -298,6 +340,7 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int 
 template <int P, int V, int UR, int OPT, bool MASK>
 __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
     constexpr int W = 64 / P;
+    constexpr int CB = kChunkB;
     const int lane = threadIdx.x & 63;
     const int s = lane / P;
     const int q = lane % P;
@@ -326,30 +369,49 @@ __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
         for (int j = 0; j < UR; ++j)
 #pragma unroll
             for (int k = 0; k < V; ++k) G[j][k] = 0.0;
-#pragma unroll((P * 4 <= 8 && UR == 1 && V == 1) ? 8 : 2)
-        for (uint32_t c = 0; c < d.len; ++c) {
-            uint32_t en[UR];
+        for (uint32_t c0 = 0; c0 < d.len; c0 += CB) {
+            // all entry loads of the chunk, then all gathers, then the sums in
+            // column order; columns past the row's end read the padding entry
+            // (the always-zero adjoint row)
+            uint32_t en[CB][UR];
 #pragma unroll
-            for (int j = 0; j < UR; ++j) en[j] = ldc(e + (size_t)c * kTile + j);
-            VecF<V> av[UR];
-            if constexpr (MASK) {
+            for (int cc = 0; cc < CB; ++cc)
 #pragma unroll
                 for (int j = 0; j < UR; ++j) {
-                    const uint32_t row = en[j] & kIdx;
-                    const uint32_t w = A.umask[row >> 5];
-#pragma unroll
-                    for (int k = 0; k < V; ++k) av[j].v[k] = 0.0f;
-                    if ((w >> (row & 31)) & 1u) av[j] = ldv<V>(ag + (size_t)row * B.G + rl);
+                    const uint32_t v = ldc(e + (size_t)(c0 + cc) * kTile + j);
+                    en[cc][j] = c0 + cc < d.len ? v : A.pad_entry;
                 }
+            VecF<V> av[CB][UR];
+            if constexpr (MASK) {
+                uint32_t w[CB][UR];
+#pragma unroll
+                for (int cc = 0; cc < CB; ++cc)
+#pragma unroll
+                    for (int j = 0; j < UR; ++j) w[cc][j] = A.umask[(en[cc][j] & kIdx) >> 5];
+                // a satisfied clause's adjoint is 0: read the always-zero row
+                // instead (one cached line), so every gather issues at once
+#pragma unroll
+                for (int cc = 0; cc < CB; ++cc)
+#pragma unroll
+                    for (int j = 0; j < UR; ++j) {
+                        const uint32_t row = en[cc][j] & kIdx;
+                        const uint32_t src = ((w[cc][j] >> (row & 31)) & 1u) ? row : (A.pad_entry & kIdx);
+                        av[cc][j] = ldv<V>(ag + (size_t)src * B.G + rl);
+                    }
             } else {
 #pragma unroll
-                for (int j = 0; j < UR; ++j) av[j] = ldv<V>(ag + (size_t)(en[j] & kIdx) * B.G + rl);
+                for (int cc = 0; cc < CB; ++cc)
+#pragma unroll
+                    for (int j = 0; j < UR; ++j)
+                        av[cc][j] = ldv<V>(ag + (size_t)(en[cc][j] & kIdx) * B.G + rl);
             }
 #pragma unroll
-            for (int j = 0; j < UR; ++j)
+            for (int cc = 0; cc < CB; ++cc)
 #pragma unroll
-                for (int k = 0; k < V; ++k)
-                    G[j][k] = G[j][k] + (double)__uint_as_float(__float_as_uint(av[j].v[k]) ^ (en[j] & kSign));
+                for (int j = 0; j < UR; ++j)
+#pragma unroll
+                    for (int k = 0; k < V; ++k)
+                        G[j][k] = G[j][k] + (double)__uint_as_float(__float_as_uint(av[cc][j].v[k]) ^ (en[cc][j] & kSign));
         }
 #pragma unroll
         for (int j = 0; j < UR; ++j) {

@@ -52,6 +52,7 @@ struct Blocking {
 struct FwdArgs {
     const TileDesc* tiles;
     const uint32_t* ent;
+    uint32_t pad_entry;  // entry standing for "no literal" (the dummy variable)
     int32_t ntiles, chunks, U, all_mode;
     Blocking B;
     const float* t;
@@ -67,6 +68,7 @@ struct FwdArgs {
 struct BwdArgs {
     const TileDesc* tiles;
     const uint32_t* ent;
+    uint32_t pad_entry;  // entry standing for "no occurrence" (the zero adjoint row)
     int32_t ntiles, seg_tiles, chunks, U;
     Blocking B;
     int32_t n_heavy, n_heavy_wide, n_act, eval;
@@ -121,6 +123,10 @@ struct InitArgs {
     int32_t* improved;
     StepState* st;
 };
+
+// Slack at the end of the entry arrays, in entries (tile columns read past a
+// row's end by the batched loads of the tiled kernels).
+constexpr int kEntrySlack = 16 * kTile;
 
 // Kernel schedules: P lanes per restart group (64 / P rows side by side),
 // V restarts per lane (vector width), UR rows per lane handled together.
