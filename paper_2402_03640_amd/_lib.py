@@ -24,9 +24,9 @@ ERRORS = {
 ADAM, SGD = 0, 1
 LOSS_UNSAT, LOSS_ALL = 0, 1
 
-# kernel schedules: id -> (lanes per row P, restarts per lane V)
-SCHEDULES = {1: (1, 1), 2: (2, 1), 3: (4, 1), 4: (8, 1), 5: (16, 1), 6: (32, 1), 7: (64, 1),
-             8: (16, 4), 9: (32, 2), 10: (64, 2), 11: (64, 4)}
+# schedule id of the resident solver (whole loop in one workgroup per restart);
+# other ids are a kernel table index | rows per work unit << 8
+RESIDENT = 255
 
 
 class HipMsatError(RuntimeError):
