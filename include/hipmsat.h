@@ -177,6 +177,14 @@ hms_status hms_tune(const hms_cnf* cnf, const hms_solve_params* params, int32_t 
                     double* step_ms);
 
 /*
+ * The schedule ids hms_tune times for `restarts` restarts and `loss_mode`
+ * (host only, no device needed): up to `cap` ids into `codes` (HOST), the
+ * number of candidates into *count (also when it exceeds cap).  The resident
+ * schedule (255), tried as well when an instance fits it, is not listed.
+ */
+hms_status hms_tune_candidates(int32_t restarts, int32_t loss_mode, int32_t* codes, int32_t cap, int32_t* count);
+
+/*
  * Count the clauses an assignment leaves unsatisfied (Section 4 "Unsatisfiable
  * Cores", with the rounding a_i in {0,1}).  `assignment`: HOST n bytes, nonzero
  * = true.  *unsat receives the count.  Synchronises `stream`.

@@ -75,7 +75,7 @@ EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_
            "hms_solve_params_default", "hms_solve", "hms_evaluate", "hms_eval_relaxed",
            "hms_last_error", "hms_version", "hms_plan_view_build", "hms_plan_view_free",
            "hms_time_kernels", "hms_tune", "hms_adjoint_bytes", "hms_forward", "hms_backward",
-           "hms_solve_batch"]
+           "hms_solve_batch", "hms_tune_candidates"]
 
 _lib = None
 
@@ -112,9 +112,10 @@ def lib():
     L.hms_plan_view_build.argtypes = [I32, P, I64, C.POINTER(PlanView)]
     L.hms_plan_view_free.argtypes = [C.POINTER(PlanView)]
     L.hms_plan_view_free.restype = None
+    L.hms_tune_candidates.argtypes = [I32, I32, P, I32, P]
     for name in ("hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_solve",
                  "hms_evaluate", "hms_eval_relaxed", "hms_plan_view_build", "hms_time_kernels", "hms_tune", "hms_adjoint_bytes",
-                 "hms_forward", "hms_backward", "hms_solve_batch"):
+                 "hms_forward", "hms_backward", "hms_solve_batch", "hms_tune_candidates"):
         getattr(L, name).restype = I32
     _lib = L
     return L
@@ -243,6 +244,16 @@ def tune(cnf: Cnf, restarts: int = 1, iters: int = 6, optimizer: int = ADAM, lr:
     code, ms = C.c_int32(), C.c_double()
     _check(lib().hms_tune(cnf.handle, C.byref(p), int(iters), C.byref(code), C.byref(ms)))
     return code.value, ms.value
+
+
+def tune_candidates(restarts: int = 1, loss_mode: int = LOSS_UNSAT) -> list[int]:
+    """Schedule ids the autotuner times for this restart count (host only)."""
+    cnt = C.c_int32()
+    _check(lib().hms_tune_candidates(int(restarts), int(loss_mode), None, 0, C.byref(cnt)))
+    buf = (C.c_int32 * max(cnt.value, 1))()
+    _check(lib().hms_tune_candidates(int(restarts), int(loss_mode), C.cast(buf, C.c_void_p), cnt.value,
+                                     C.byref(cnt)))
+    return [int(buf[i]) for i in range(cnt.value)]
 
 
 def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, seed: int = 0,

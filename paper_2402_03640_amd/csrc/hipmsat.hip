@@ -959,6 +959,7 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* p, int32
     if (rc0) return rc0;
     p = &pr;
     if (p->schedule == kResidentId) {
+        if (!resident_ok(cnf, p)) return fail(HMS_ERR_ARG, "the resident schedule does not fit this instance");
         double ms = 0;
         hms_status rc = time_resident(cnf, p, iters, ms);
         if (rc) return rc;
@@ -1138,6 +1139,17 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
     }
     if (worst) return fail(worst, worst_msg);
     g_err.clear();
+    return HMS_OK;
+}
+
+hms_status hms_tune_candidates(int32_t restarts, int32_t loss_mode, int32_t* codes, int32_t cap, int32_t* count) {
+    g_err.clear();
+    if (!count || cap < 0 || (cap > 0 && !codes)) return fail(HMS_ERR_ARG, "null argument or negative capacity");
+    if (restarts < 1) return fail(HMS_ERR_ARG, "restarts >= 1 required");
+    if (loss_mode != HMS_LOSS_UNSAT && loss_mode != HMS_LOSS_ALL) return fail(HMS_ERR_ARG, "unknown loss mode");
+    const std::vector<int32_t> c = tune_candidates(restarts, loss_mode);
+    *count = (int32_t)c.size();
+    for (size_t i = 0; i < c.size() && (int32_t)i < cap; ++i) codes[i] = c[i];
     return HMS_OK;
 }
 
