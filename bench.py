@@ -57,11 +57,107 @@ def traffic_record(config, schedule, kernel_key):
         return None
     if rec.get("kernels_sha") != kernels_sha():
         return None
-    c = rec.get("configs", {}).get(config)
-    if not c or c.get("schedule") != schedule:
+    c = rec.get("configs", {}).get(config, {}).get(str(schedule))
+    if not c:
         return None
     k = c.get("kernels", {}).get(kernel_key)
     return None if not k else round(k["hbm_bytes_per_launch"])
+
+
+def counters_summary(dirs):
+    """Summarise rocprofv3 counter runs of ``--kernels-only``.
+
+    Each directory is the ``-d`` of one ``rocprofv3 --pmc <COUNTER>
+    --kernel-trace -f csv -o pmc`` run, named pmc_<config>_<schedule>_<COUNTER>.
+    The counter of the 256 MiB calibration copy in the same run gives the
+    scale factor (bytes the copy must move / bytes the counter reports); the
+    forward and backward kernels' per-dispatch averages are scaled by it.
+    Writes profiles/traffic.json and prints the text summary."""
+    import csv
+    import glob
+    copy_bytes = 256 * 2 ** 20
+    runs = {}
+    for d in dirs:
+        base = os.path.basename(os.path.normpath(d))
+        parts = base.split("_")
+        if len(parts) < 4 or parts[0] != "pmc":
+            continue
+        counter = "_".join(parts[-2:])
+        config, sched = "_".join(parts[1:-3]), parts[-3]
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            continue
+        rows = list(csv.DictReader(open(files[0])))
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        per = {}
+        for r in rows:
+            name = r["Kernel_Name"]
+            key = "fwd" if "k_fwd<" in name else ("bwd" if "k_bwd<" in name else None)
+            if key:
+                per.setdefault(key, [name, []])[1].append(float(r["Counter_Value"]))
+        runs.setdefault((config, sched), {})[counter] = (max(copies) if copies else None, per)
+    out = {"kernels_sha": kernels_sha(),
+           "method": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --kernel-trace, KiB per dispatch averaged "
+                     "over launches, each scaled by (256 MiB / the counter's reading for the 256 MiB device "
+                     "copy made in the same run)",
+           "configs": {}}
+    lines = ["# HBM traffic per launch from rocprofv3 counters (calibrated)",
+             "# commands (one run per counter, config and schedule):",
+             "#   rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d gpurun_out/pmc_<cfg>_<sched>_FETCH_SIZE -o pmc "
+             "-- python -u bench.py --config <cfg> --kernels-only --kernel-iters 20 --schedule <sched>",
+             "#   (the same with WRITE_SIZE)",
+             "#   python bench.py --counters-summary gpurun_out/pmc_*",
+             "# columns: config, schedule, kernel, launches, FETCH KiB avg, WRITE KiB avg, FETCH factor, "
+             "WRITE factor, calibrated MB per launch, algorithmic MB per launch"]
+    for (config, sched), ctr in sorted(runs.items()):
+        if "FETCH_SIZE" not in ctr or "WRITE_SIZE" not in ctr:
+            continue
+        import paper_2402_03640_amd as hm
+        wl = make_workload(config)
+        L = int(hm.Plan(wl["n"], wl["lits"]).nnz)  # canonical literal count (host-only plan)
+        fb, bb = kernel_bytes(wl["n"], wl["m"], L, wl["R"])
+        fcopy, fper = ctr["FETCH_SIZE"]
+        wcopy, wper = ctr["WRITE_SIZE"]
+        ff = copy_bytes / (fcopy * 1024) if fcopy else None
+        wf = copy_bytes / (wcopy * 1024) if wcopy else None
+        rec = {"fetch_factor": ff, "write_factor": wf, "kernels": {}}
+        for key, alg in (("fwd", fb), ("bwd", bb)):
+            if key not in fper or key not in wper or ff is None or wf is None:
+                continue
+            name, fv = fper[key]
+            wv = wper[key][1]
+            fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
+            hbm = (fk * ff + wk * wf) * 1024
+            rec["kernels"][key] = {"name": name, "launches": len(fv), "fetch_kib": fk, "write_kib": wk,
+                                   "hbm_bytes_per_launch": hbm, "algorithmic_bytes": alg}
+            lines.append(f"{config} {sched} {name[:60]} {len(fv)} {fk:.1f} {wk:.1f} {ff:.3f} {wf:.3f} "
+                         f"{hbm / 1e6:.2f} {alg / 1e6:.2f}")
+        out["configs"].setdefault(config, {})[sched] = rec
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("\n".join(lines))
+
+
+def sweep(cnf, wl, iters):
+    """Time every schedule the autotuner considers (hms_time_kernels, HIP events)."""
+    import paper_2402_03640_amd as hm
+    R = wl["R"]
+    codes = hm.tune_candidates(R, hm.LOSS_UNSAT) + [hm.RESIDENT]
+    res = []
+    print(f"# schedule sweep of {wl['name']} ({wl['desc']}): hms_time_kernels, {iters} launches each\n"
+          f"# command: python -u bench.py --config {wl['name']} --sweep --kernel-iters {iters}\n"
+          f"# columns: schedule id, table index, rows per unit, fwd us, bwd us, step us", flush=True)
+    for code in codes:
+        try:
+            f, b, st = hm.time_kernels(cnf, restarts=R, iters=iters, lr=1e-4, schedule=code)
+        except hm.HipMsatError as e:
+            print(f"{code:6d} {code & 0xff:3d} {code >> 8:3d}  skipped: {e}", flush=True)
+            continue
+        res.append((st, code))
+        print(f"{code:6d} {code & 0xff:3d} {code >> 8:3d} {f * 1e3:8.2f} {b * 1e3:8.2f} {st * 1e3:8.2f}",
+              flush=True)
+    res.sort()
+    print("# fastest: " + ", ".join(f"{c} ({t * 1e3:.2f} us)" for t, c in res[:5]), flush=True)
 
 
 def make_workload(name):
@@ -103,7 +199,8 @@ def cpu_baseline(wl, L, max_threads=16, sample_steps=None):
     threads = max(1, min(os.cpu_count() or 1, max_threads))
     R = wl["R"]
     if sample_steps is None:
-        sample_steps = min(wl["T"], max(1, int(2.0e9 / max(1, 2 * L * R))))
+        # about 6e10 literal visits: 10-30 s of the oracle on 8-16 host cores
+        sample_steps = min(wl["T"], max(1, int(6.0e10 / max(1, 2 * L * R))))
     t0 = time.perf_counter()
     oc.solve(steps=sample_steps, restarts=R, eval_every=wl["K"], seed=0, lr=1e-4, threads=threads)
     dt = time.perf_counter() - t0
@@ -206,10 +303,17 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-steps", type=int, default=1000)
     ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--sweep", action="store_true", help="time every candidate schedule and exit")
+    ap.add_argument("--tune-iters", type=int, default=20)
+    ap.add_argument("--counters-summary", nargs="*", default=None, metavar="DIR",
+                    help="summarise rocprofv3 counter runs of --kernels-only into profiles/traffic.json")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only time the forward/backward kernels (for counter runs), after a "
                          "256 MiB device copy used to calibrate the byte counters")
     args = ap.parse_args()
+    if args.counters_summary is not None:
+        counters_summary(args.counters_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solve loop is benchmarked on a single MI355X; "
               "restarts and instances shard across GPUs without communication (see DESIGN.md), "
@@ -235,7 +339,15 @@ def main():
     n, m, R, T, K = wl["n"], wl["m"], wl["R"], wl["T"], wl["K"]
     log(f"[bench] loaded: L={L} heavy={cnf.info['n_heavy']} in {load_s:.3f} s")
 
-    kw = dict(steps=T, restarts=R, eval_every=K, seed=0, lr=1e-4, schedule=args.schedule)
+    if args.sweep:
+        sweep(cnf, wl, args.kernel_iters)
+        return
+    code = args.schedule
+    if code == 0:
+        # one tuning pass (outside the timed region); the solves use its choice
+        code, tms = hm.tune(cnf, restarts=R, iters=args.tune_iters, eval_every=K)
+        log(f"[bench] tuned schedule {code} ({tms * 1e3:.2f} us per step)")
+    kw = dict(steps=T, restarts=R, eval_every=K, seed=0, lr=1e-4, schedule=code)
     if args.kernels_only:
         src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -243,7 +355,6 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)  # calibration: 256 MiB read, 256 MiB written
         torch.cuda.synchronize()
-        code = args.schedule or hm.tune(cnf, restarts=R)[0]
         f, b, st = hm.time_kernels(cnf, restarts=R, iters=args.kernel_iters, lr=1e-4, schedule=code)
         fb, bb = kernel_bytes(n, m, L, R)
         print(json.dumps({"config": wl["name"], "schedule": code, "fwd_us": f * 1e3, "bwd_us": b * 1e3,
@@ -270,7 +381,7 @@ def main():
     value = nnz_per_solve * args.steps / wall
 
     fwd_ms, bwd_ms, step_ms = hm.time_kernels(cnf, restarts=R, iters=args.kernel_iters, lr=1e-4,
-                                              schedule=args.schedule)
+                                              schedule=code)
     fb, bb = kernel_bytes(n, m, L, R)
     log(f"[bench] kernels: fwd {fwd_ms*1e3:.2f} us, bwd {bwd_ms*1e3:.2f} us, step {step_ms*1e3:.2f} us")
     if fwd_ms <= 0 or bwd_ms <= 0:

@@ -237,9 +237,10 @@ def time_kernels(cnf: Cnf, restarts: int = 1, iters: int = 50, seed: int = 0, op
 
 
 def tune(cnf: Cnf, restarts: int = 1, iters: int = 6, optimizer: int = ADAM, lr: float = 1e-4,
-         loss_mode: int = LOSS_UNSAT, stream=None):
-    """Time every schedule for this restart count; returns (schedule id, ms per step)."""
-    p = _params(cnf, 1, restarts, 1, 0, optimizer, lr, 0.9, 0.999, 1e-8, loss_mode, 0, False, 0.0,
+         loss_mode: int = LOSS_UNSAT, stream=None, eval_every: int = 1):
+    """Time every schedule for this restart count; returns (schedule id, ms per step).
+    ``eval_every`` is the counting period the resident solver is timed with."""
+    p = _params(cnf, 1, restarts, int(eval_every), 0, optimizer, lr, 0.9, 0.999, 1e-8, loss_mode, 0, False, 0.0,
                 None, stream)
     code, ms = C.c_int32(), C.c_double()
     _check(lib().hms_tune(cnf.handle, C.byref(p), int(iters), C.byref(code), C.byref(ms)))
