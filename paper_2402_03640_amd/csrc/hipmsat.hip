@@ -119,16 +119,16 @@ struct Shape {
 
 // Schedule id: bits 0..7 = table index (0 = automatic), bits 8..15 = rows per
 // work unit U (0 = the default for that entry).  The bitset variants apply to
-// one restart with the unsat-masked loss; elsewhere they fall back to their
-// unmasked twin (same arithmetic).
+// the unsat-masked loss; elsewhere they fall back to their unmasked twin (same
+// arithmetic).
 hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_mode, Shape& sh,
                       bool allow_mask = true) {
     const int idx = req & 0xff;
     int U = (req >> 8) & 0xff;
     if (req < 0 || (req >> 16) != 0 || idx > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
     sh.sched = idx == 0 ? auto_schedule(R, loss_mode, P.nnz) : idx;
-    if (hms::kSchedules[sh.sched].mask && (R != 1 || loss_mode != HMS_LOSS_UNSAT || !allow_mask))
-        sh.sched -= 22;  // 23..25 -> 1..3
+    if (hms::kSchedules[sh.sched].mask && (loss_mode != HMS_LOSS_UNSAT || !allow_mask))
+        sh.sched = hms::kSchedules[sh.sched].twin;
     const hms::Schedule& c = hms::kSchedules[sh.sched];
     sh.P = c.P;
     sh.V = c.V;
@@ -203,7 +203,7 @@ void layout_state(const hms::HostPlan& P, const Shape& sh, bool moments, bool gr
     off[kOffCnt] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 4);
     off[kOffLoss] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 8);
     off[kOffBest] = best ? L.add(nR) : 0;
-    off[kOffMask] = L.add((size_t)umask_words(P) * 4);
+    off[kOffMask] = L.add((size_t)umask_words(P) * sh.B.RG * 4);
     off[kOffBestC] = L.add((size_t)R * 8);
     off[kOffCurC] = L.add((size_t)R * 8);
     off[kOffBestS] = L.add((size_t)R * 4);
@@ -245,7 +245,7 @@ hms::InitArgs make_init(const hms_cnf* C, const Shape& sh, const State& S) {
     ia.n = P.n;
     ia.m = P.m;
     ia.a_zero_row = P.a_zero_row();
-    ia.umask_words = umask_words(P);
+    ia.umask_words = umask_words(P) * sh.B.RG;
     ia.B = sh.B;
     ia.var_old = C->var_old;
     ia.x = S.x;
@@ -290,6 +290,7 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     f.t = S.t;
     f.a = S.a;
     f.umask = S.umask;
+    f.umask_words = umask_words(P);
     f.two_over_m = P.m > 0 ? (float)(2.0 / (double)P.m) : 0.0f;
     f.cnt_part = S.cnt_part;
     f.loss_part = S.loss_part;
@@ -312,6 +313,7 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     b.eval = 0;
     b.a = S.a;
     b.umask = S.umask;
+    b.umask_words = umask_words(P);
     b.seg_part = S.seg_part;
     b.x = S.x;
     b.m = S.m;
@@ -595,7 +597,7 @@ std::vector<int32_t> tune_candidates(int32_t R, int loss_mode) {
     for (int idx = 1; idx <= hms::kNumSchedules; ++idx) {
         const hms::Schedule& c = hms::kSchedules[idx];
         if (R % c.V) continue;
-        if (c.mask && (R != 1 || loss_mode != HMS_LOSS_UNSAT)) continue;
+        if (c.mask && loss_mode != HMS_LOSS_UNSAT) continue;
         if (c.P * c.V > 2 * std::max(R, 1) && c.P * c.V > 2) continue;  // mostly idle lanes
         const int per = (64 / c.P) * c.UR;
         for (int U = per; U <= 64; U *= 2) {

@@ -18,12 +18,14 @@
 namespace hms {
 
 const Schedule kSchedules[kNumSchedules + 1] = {
-    {0, 0, 0, 0},                                                                          // 0: automatic
-    {1, 1, 1, 0},  {2, 1, 1, 0},  {4, 1, 1, 0},  {8, 1, 1, 0},  {8, 1, 2, 0},  {16, 1, 1, 0},  // 1..6
-    {16, 1, 2, 0}, {16, 1, 4, 0}, {32, 1, 2, 0}, {32, 1, 4, 0}, {64, 1, 1, 0}, {64, 1, 2, 0},  // 7..12
-    {64, 1, 4, 0}, {64, 1, 8, 0}, {16, 4, 1, 0}, {16, 4, 2, 0}, {32, 2, 2, 0}, {32, 2, 4, 0},  // 13..18
-    {64, 2, 2, 0}, {64, 2, 4, 0}, {64, 4, 1, 0}, {64, 4, 2, 0}, {1, 1, 1, 1},  {2, 1, 1, 1},   // 19..24
-    {4, 1, 1, 1},  {2, 4, 1, 0},  {4, 2, 1, 0},  {8, 1, 4, 0},                                // 25..28
+    {0, 0, 0, 0, 0},                                                                         // 0: automatic
+    {1, 1, 1, 0, 0},  {2, 1, 1, 0, 0},  {4, 1, 1, 0, 0},  {8, 1, 1, 0, 0},  {8, 1, 2, 0, 0},   // 1..5
+    {16, 1, 1, 0, 0}, {16, 1, 2, 0, 0}, {16, 1, 4, 0, 0}, {32, 1, 2, 0, 0}, {32, 1, 4, 0, 0},  // 6..10
+    {64, 1, 1, 0, 0}, {64, 1, 2, 0, 0}, {64, 1, 4, 0, 0}, {64, 1, 8, 0, 0}, {16, 4, 1, 0, 0},  // 11..15
+    {16, 4, 2, 0, 0}, {32, 2, 2, 0, 0}, {32, 2, 4, 0, 0}, {64, 2, 2, 0, 0}, {64, 2, 4, 0, 0},  // 16..20
+    {64, 4, 1, 0, 0}, {64, 4, 2, 0, 0}, {1, 1, 1, 1, 1},  {2, 1, 1, 1, 2},  {4, 1, 1, 1, 3},   // 21..25
+    {2, 4, 1, 0, 0},  {4, 2, 1, 0, 0},  {8, 1, 4, 0, 0},                                      // 26..28
+    {1, 2, 1, 1, 27}, {1, 4, 1, 1, 26}, {2, 4, 1, 1, 26}, {4, 2, 1, 1, 27},                  // 29..32
 };
 
 int default_rows_per_unit(int sched) {
@@ -77,6 +79,15 @@ __device__ __forceinline__ void stv(float* p, const VecF<V>& r) {
     }
 }
 
+// OR each aligned group of P ballot bits into its first bit (the row's
+// bit is set when any of its P lanes has an unsatisfied restart).
+template <int P>
+__device__ __forceinline__ uint64_t fold_bits(uint64_t x) {
+    if constexpr (P >= 2) x |= x >> 1;
+    if constexpr (P >= 4) x |= x >> 2;
+    return x;
+}
+
 // Compact the ballot bits of lanes 0, P, 2P, ... into consecutive bits.
 template <int P>
 __device__ __forceinline__ uint64_t compact_bits(uint64_t x) {
@@ -106,8 +117,9 @@ __device__ __forceinline__ uint64_t compact_bits(uint64_t x) {
 // Workgroup b works on restart group b % RG; each wave takes a unit of U rows
 // of one tile; lane (s, q) handles UR consecutive rows per pass for restarts
 // rl..rl+V-1 of the group, column by column so that UR gathers are in flight
-// together.  With MASK the unsat bits of the unit's rows are written to the
-// bitset and the adjoint only for unsatisfied rows.
+// together.  With MASK a row's bit in its restart group's bitset is set when
+// the clause is unsatisfied in some restart of the group, and the adjoint is
+// written only for rows whose bit is set.
 // ---------------------------------------------------------------------------
 template <int P, int V, int UR, bool EVAL, bool MASK>
 __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
@@ -222,8 +234,13 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
                 }
             }
             if constexpr (MASK) {
-                mbits |= compact_bits<P>(__ballot(any_mu ? 1 : 0)) << (pass * W);
-                if (any_mu) stv<V>(ag + (size_t)(tile * kTile + rowin0 + j) * B.G + rl, av);
+                static_assert(UR == 1, "bitset schedules take one row per lane");
+                const uint64_t folded = fold_bits<P>(__ballot(any_mu ? 1 : 0));
+                mbits |= compact_bits<P>(folded) << (pass * W);
+                // every lane of a row whose bit is set writes its restarts
+                // (zeros included): the backward pass reads the whole row
+                if (ract && ((folded >> (s * P)) & 1u))
+                    stv<V>(ag + (size_t)(tile * kTile + rowin0 + j) * B.G + rl, av);
             } else if (ract) {
                 stv<V>(ag + (size_t)(tile * kTile + rowin0 + j) * B.G + rl, av);
             }
@@ -231,7 +248,7 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
     }
     if constexpr (MASK) {
         if (lane == 0) {
-            uint32_t* w = A.umask + ((size_t)tile * kTile + chunk * A.U) / 32;
+            uint32_t* w = A.umask + (size_t)rg * A.umask_words + ((size_t)tile * kTile + chunk * A.U) / 32;
             w[0] = (uint32_t)mbits;
             if (A.U == 64) w[1] = (uint32_t)(mbits >> 32);
         }
@@ -357,6 +374,7 @@ __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
     if (rl >= B.G || r0 >= B.R) return;
     const bool segtile = tile < A.seg_tiles;
     const float* ag = A.a + (size_t)rg * B.rows_a * B.G;
+    const uint32_t* um = A.umask + (size_t)rg * A.umask_words;
     const size_t xbase = (size_t)rg * B.rows_x * B.G;
     double* sg = A.seg_part + (size_t)rg * B.rows_seg * B.G;
     const int passes = A.U / (W * UR);
@@ -387,7 +405,7 @@ __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
 #pragma unroll
                 for (int cc = 0; cc < CB; ++cc)
 #pragma unroll
-                    for (int j = 0; j < UR; ++j) w[cc][j] = A.umask[(en[cc][j] & kIdx) >> 5];
+                    for (int j = 0; j < UR; ++j) w[cc][j] = um[(en[cc][j] & kIdx) >> 5];
                 // a satisfied clause's adjoint is 0: read the always-zero row
                 // instead (one cached line), so every gather issues at once
 #pragma unroll
@@ -699,6 +717,10 @@ hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
         case 26: return FN<2, 4, 1, 0>(__VA_ARGS__);       \
         case 27: return FN<4, 2, 1, 0>(__VA_ARGS__);       \
         case 28: return FN<8, 1, 4, 0>(__VA_ARGS__);       \
+        case 29: return FN<1, 2, 1, 1>(__VA_ARGS__);       \
+        case 30: return FN<1, 4, 1, 1>(__VA_ARGS__);       \
+        case 31: return FN<2, 4, 1, 1>(__VA_ARGS__);       \
+        case 32: return FN<4, 2, 1, 1>(__VA_ARGS__);       \
         default: return hipErrorInvalidValue;              \
     }
 

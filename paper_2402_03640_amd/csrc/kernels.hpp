@@ -14,7 +14,8 @@
 //   seg_part   : [RG][seg_rows][G] FP64   partial transposed sums of heavy rows
 //   best_a     : [RG][n + 1][G] bytes     rounded iterate at each restart's best step
 //   cnt_part, loss_part : [units][R]     per-unit count / loss partials
-//   umask      : bitset over clause rows (G = 1 only): bit j = clause j unsatisfied
+//   umask      : [RG][c_tiles * 2 + 1] bitset words over clause rows: bit j of group g =
+//                clause j unsatisfied for some restart of group g (unsat-masked loss)
 //
 // t stores tanh(x) with its sign bit forced to "x does not round to true":
 // sign(t) = 1 iff !(x > 0).  A literal entry holds the variable index and the
@@ -54,6 +55,7 @@ struct FwdArgs {
     const uint32_t* ent;
     uint32_t pad_entry;  // entry standing for "no literal" (the dummy variable)
     int32_t ntiles, chunks, U, all_mode;
+    int32_t umask_words; // bitset words per restart group
     Blocking B;
     const float* t;
     float* a;
@@ -72,6 +74,7 @@ struct BwdArgs {
     int32_t ntiles, seg_tiles, chunks, U;
     Blocking B;
     int32_t n_heavy, n_heavy_wide, n_act, eval;
+    int32_t umask_words; // bitset words per restart group
     const float* a;
     const uint32_t* umask;
     double* seg_part;
@@ -131,12 +134,14 @@ constexpr int kEntrySlack = 16 * kTile;
 // Kernel schedules: P lanes per restart group (64 / P rows side by side),
 // V restarts per lane (vector width), UR rows per lane handled together.
 // A work unit is U rows of one tile (U a multiple of (64 / P) * UR dividing 64).
-// MASK schedules (G = 1 only) keep the unsat bitset and skip the adjoint
-// gathers of satisfied clauses; they need U >= 32.
+// MASK schedules (unsat-masked loss only) keep the unsat bitset and skip the
+// adjoint gathers of clauses satisfied in every restart of the group; they
+// need U >= 32 and UR = 1.  `twin` is the schedule with the same arithmetic
+// and no bitset that runs in their place when the loss is not masked.
 struct Schedule {
-    int P, V, UR, mask;
+    int P, V, UR, mask, twin;
 };
-constexpr int kNumSchedules = 28;
+constexpr int kNumSchedules = 32;
 extern const Schedule kSchedules[kNumSchedules + 1];
 
 int default_rows_per_unit(int sched);

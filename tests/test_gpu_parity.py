@@ -88,7 +88,7 @@ def test_eval_cfg4_all_schedules():
     cnf = hm.load_cnf(n, lits)
     xt = torch.from_numpy(x).cuda()
     ref = None
-    codes = list(range(1, 29)) + [14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
+    codes = list(range(1, 33)) + [14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
                                   7 | (64 << 8), 1 | (64 << 8), 255]
     for sched in codes:
         res = hm.solve(cnf, steps=3, restarts=R, eval_every=1, x0=xt, schedule=sched, want_x=True)
@@ -117,6 +117,30 @@ def test_single_restart_schedules_bitwise():
         cur = (res.restart_best.copy(), res.restart_step.copy(),
                res.x_final.cpu().numpy().view(np.uint32).copy(), res.best_assignment.copy())
         _say(f"R=1 schedule {sched}: best {res.best_cost} at {res.best_step}")
+        if ref is None:
+            ref = cur
+        else:
+            for a, b in zip(cur, ref):
+                np.testing.assert_array_equal(a, b)
+
+
+def test_restart_group_bitset_bitwise():
+    """Several restarts on a skewed instance (heavy rows): the bitset
+    schedules, one bit per clause and restart group, give the trajectory of
+    the plain schedules bit for bit."""
+    n, m, R = 20000, 100000, 8
+    lits = cnfgen.structured_cnf(n, m, seed=12)
+    cnf = hm.load_cnf(n, lits)
+    assert cnf.info["n_heavy"] > 0
+    ref = None
+    for sched in [4, 26, 23 | (64 << 8), 24 | (32 << 8), 25 | (32 << 8), 25 | (64 << 8), 29 | (64 << 8),
+                  30 | (64 << 8), 31 | (32 << 8), 32 | (64 << 8)]:
+        res = hm.solve(cnf, steps=60, restarts=R, eval_every=7, seed=5, lr=1e-2, schedule=sched,
+                       want_x=True)
+        cur = (res.restart_best.copy(), res.restart_step.copy(),
+               res.x_final.cpu().numpy().view(np.uint32).copy(), res.best_assignment.copy())
+        _say(f"R={R} schedule {sched}: best {res.best_cost} at {res.best_step} (ran {res.schedule})")
+        assert res.schedule & 0xFF == sched & 0xFF
         if ref is None:
             ref = cur
         else:

@@ -133,15 +133,15 @@ def test_plan_skewed_heavy_rows():
 
 def test_tune_candidates():
     """The autotuner's candidate list (host only): valid table entries and
-    rows per unit, bitset variants only for one restart with the unsat loss."""
+    rows per unit, bitset variants only with the unsat-masked loss."""
     for R, mode in ((1, hm.LOSS_UNSAT), (1, hm.LOSS_ALL), (3, hm.LOSS_UNSAT), (64, hm.LOSS_UNSAT)):
         codes = hm.tune_candidates(R, mode)
         assert codes and len(set(codes)) == len(codes)
         for c in codes:
             idx, U = c & 0xFF, c >> 8
-            assert 1 <= idx <= 28 and U >= 1 and 64 % U == 0
-        has_mask = any(23 <= (c & 0xFF) <= 25 for c in codes)
-        assert has_mask == (R == 1 and mode == hm.LOSS_UNSAT)
+            assert 1 <= idx <= 32 and U >= 1 and 64 % U == 0
+        has_mask = any((c & 0xFF) in (23, 24, 25, 29, 30, 31, 32) for c in codes)
+        assert has_mask == (mode == hm.LOSS_UNSAT)
     assert (26 | (32 << 8)) in hm.tune_candidates(64)
     with pytest.raises(hm.HipMsatError):
         hm.tune_candidates(0)
