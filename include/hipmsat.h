@@ -100,7 +100,8 @@ typedef struct {
     uint64_t seed;       /* restart r starts from the SplitMix64 stream seeded seed + r */
     float lr, beta1, beta2, eps; /* Adam: PyTorch defaults 0.9 / 0.999 / 1e-8 */
     int32_t loss_mode;   /* HMS_LOSS_UNSAT or HMS_LOSS_ALL */
-    int32_t schedule;    /* 0 = automatic; else table index | rows-per-unit << 8 (see hms_tune) */
+    int32_t schedule;    /* 0 = automatic; else table index | rows-per-unit << 8
+                            | backward rows-per-unit << 16 (0 = the same; see hms_tune) */
     int32_t use_graph;   /* 1 = replay the step body as a HIP graph, 0 = direct launches */
     int32_t autotune;    /* 1 = with schedule 0, time the candidate schedules once per handle,
                             restart count, optimizer and loss mode, and keep the fastest */
@@ -167,10 +168,12 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
                            hms_solve_result* results, hms_status* statuses);
 
 /*
- * Schedule autotuner: times every kernel schedule that can run
- * params->restarts restarts (`iters` steps each, HIP events on params->stream)
- * and records the fastest for this handle; later solves with schedule 0 use
- * it.  The choice changes speed only: results are bitwise the same under
+ * Schedule autotuner: for every kernel schedule that can run
+ * params->restarts restarts, times the forward and the backward pass at each
+ * rows-per-unit value (`iters` launches each, HIP events on params->stream)
+ * and pairs the fastest of each; then times whole steps of those pairs and
+ * of the resident solver, and records the fastest for this handle (and its
+ * size class); later solves with schedule 0 use it.  The choice changes speed only: results are bitwise the same under
  * every schedule.  Outputs the chosen schedule id and its time per step.
  */
 hms_status hms_tune(const hms_cnf* cnf, const hms_solve_params* params, int32_t iters, int32_t* schedule,

@@ -111,6 +111,7 @@ int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0) {
 
 struct Shape {
     int sched, P, V, UR, U, chunks, mask;
+    int Ub, chunks_b;  // rows per work unit and units per tile of the backward pass
     hms::Blocking B;
     int64_t n_tc, fwd_blocks64, bwd_blocks64;
     int fwd_blocks, bwd_blocks;
@@ -118,14 +119,16 @@ struct Shape {
 };
 
 // Schedule id: bits 0..7 = table index (0 = automatic), bits 8..15 = rows per
-// work unit U (0 = the default for that entry).  The bitset variants apply to
+// work unit U (0 = the default for that entry), bits 16..23 = rows per work
+// unit of the backward pass (0 = U).  The bitset variants apply to
 // the unsat-masked loss; elsewhere they fall back to their unmasked twin (same
 // arithmetic).
 hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_mode, Shape& sh,
                       bool allow_mask = true) {
     const int idx = req & 0xff;
     int U = (req >> 8) & 0xff;
-    if (req < 0 || (req >> 16) != 0 || idx > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
+    int Ub = (req >> 16) & 0xff;
+    if (req < 0 || (req >> 24) != 0 || idx > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
     sh.sched = idx == 0 ? auto_schedule(R, loss_mode, P.nnz) : idx;
     if (hms::kSchedules[sh.sched].mask && (loss_mode != HMS_LOSS_UNSAT || !allow_mask))
         sh.sched = hms::kSchedules[sh.sched].twin;
@@ -136,12 +139,15 @@ hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_m
     sh.mask = c.mask;
     if (R % sh.V != 0) return fail(HMS_ERR_ARG, "schedule vector width does not divide the restart count");
     if (U == 0) U = hms::default_rows_per_unit(sh.sched);
+    if (Ub == 0) Ub = U;
     const int per_pass = (64 / sh.P) * sh.UR;
-    if (U % per_pass != 0 || hms::kTile % U != 0 || (sh.mask && U < 32))
+    if (U % per_pass != 0 || hms::kTile % U != 0 || (sh.mask && U < 32) || Ub % per_pass != 0 || hms::kTile % Ub != 0)
         return fail(HMS_ERR_ARG, "rows per unit must be a multiple of the rows per pass and divide 64");
     sh.U = U;
-    sh.code = sh.sched | (U << 8);
+    sh.Ub = Ub;
+    sh.code = sh.sched | (U << 8) | (Ub != U ? Ub << 16 : 0);
     sh.chunks = hms::kTile / sh.U;
+    sh.chunks_b = hms::kTile / sh.Ub;
     int G = sh.P * sh.V;
     int Rp = 1;
     while (Rp < R && Rp < G) Rp <<= 1;
@@ -154,7 +160,7 @@ hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_m
     sh.B.rows_seg = std::max(P.seg_rows, 1);
     sh.n_tc = (int64_t)P.c_tiles * sh.chunks;
     sh.fwd_blocks64 = (int64_t)sh.B.RG * ((sh.n_tc + 3) / 4);
-    sh.bwd_blocks64 = (int64_t)sh.B.RG * (((int64_t)P.v_tiles * sh.chunks + 3) / 4);
+    sh.bwd_blocks64 = (int64_t)sh.B.RG * (((int64_t)P.v_tiles * sh.chunks_b + 3) / 4);
     if (sh.fwd_blocks64 >= INT32_MAX / 2 || sh.bwd_blocks64 >= INT32_MAX / 2)
         return fail(HMS_ERR_TOO_LARGE, "too many work units");
     sh.fwd_blocks = (int)sh.fwd_blocks64;
@@ -304,8 +310,8 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     b.pad_entry = (uint32_t)P.a_zero_row();
     b.ntiles = P.v_tiles;
     b.seg_tiles = P.seg_tiles;
-    b.chunks = sh.chunks;
-    b.U = sh.U;
+    b.chunks = sh.chunks_b;
+    b.U = sh.Ub;
     b.B = sh.B;
     b.n_heavy = P.n_heavy;
     b.n_heavy_wide = P.n_heavy_wide;
@@ -630,10 +636,66 @@ hms_status time_steps(const hms_cnf* cnf, const hms_solve_params* p0, int32_t co
     return HMS_OK;
 }
 
+// Average device time of the forward pass alone and of the backward pass
+// (with the heavy-row combine) alone under schedule `code`.
+hms_status time_split(const hms_cnf* cnf, const hms_solve_params* p0, int32_t code, int32_t iters, double& fwd_ms,
+                      double& bwd_ms) {
+    hms_solve_params p = *p0;
+    p.schedule = code;
+    p.x0 = nullptr;
+    SolveSetup Z;
+    hms_status rc = setup_solve(cnf, &p, Z);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)p.stream;
+    const Launch& L = Z.L;
+    Events E;
+    for (int i = 0; i < 3; ++i) HIPTRY(hipEventCreate(&E.e[i]));
+    HIPTRY(enqueue_step(L, false, s));
+    HIPTRY(hipEventRecord(E.e[0], s));
+    for (int32_t i = 0; i < iters; ++i) HIPTRY(hms::launch_fwd(Z.sh.sched, false, L.fa, Z.sh.fwd_blocks, s));
+    HIPTRY(hipEventRecord(E.e[1], s));
+    for (int32_t i = 0; i < iters; ++i) {
+        HIPTRY(hms::launch_bwd(Z.sh.sched, L.opt, L.ba, Z.sh.bwd_blocks, s));
+        HIPTRY(hms::launch_combine(L.opt, L.ba, s));
+    }
+    HIPTRY(hipEventRecord(E.e[2], s));
+    HIPTRY(hipStreamSynchronize(s));
+    float a = 0, b = 0;
+    HIPTRY(hipEventElapsedTime(&a, E.e[0], E.e[1]));
+    HIPTRY(hipEventElapsedTime(&b, E.e[1], E.e[2]));
+    fwd_ms = a / iters;
+    bwd_ms = b / iters;
+    return HMS_OK;
+}
+
+// Autotuner: for every table entry, the forward and the backward pass each
+// take their fastest rows per unit (timed apart), then whole steps of each
+// entry's pair are timed against each other (and the resident solver).
 hms_status tune(const hms_cnf* cnf, const hms_solve_params* p, int32_t iters, int32_t& best, double& best_ms) {
     best = 0;
     best_ms = 1e300;
-    std::vector<int32_t> cands = tune_candidates(p->restarts, p->loss_mode);
+    struct Pick {
+        double f = 1e300, b = 1e300;
+        int Uf = 0, Ub = 0;
+    };
+    std::map<int, Pick> picks;
+    for (int32_t code : tune_candidates(p->restarts, p->loss_mode)) {
+        double f = 0, b = 0;
+        hms_status rc = time_split(cnf, p, code, iters, f, b);
+        if (rc) return rc;
+        Pick& k = picks[code & 0xff];
+        const int U = (code >> 8) & 0xff;
+        if (f < k.f) {
+            k.f = f;
+            k.Uf = U;
+        }
+        if (b < k.b) {
+            k.b = b;
+            k.Ub = U;
+        }
+    }
+    std::vector<int32_t> cands;
+    for (auto& kv : picks) cands.push_back(kv.first | (kv.second.Uf << 8) | (kv.second.Ub << 16));
     if (resident_ok(cnf, p)) cands.push_back(kResidentId);
     for (int32_t code : cands) {
         double ms = 0;
@@ -644,6 +706,7 @@ hms_status tune(const hms_cnf* cnf, const hms_solve_params* p, int32_t iters, in
             best = code;
         }
     }
+    if (best != kResidentId && ((best >> 16) & 0xff) == ((best >> 8) & 0xff)) best &= 0xffff;  // canonical id
     {
         std::lock_guard<std::mutex> lk(cnf->tune_mu);
         cnf->tuned[tune_key(p)] = best;

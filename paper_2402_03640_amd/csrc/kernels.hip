@@ -26,6 +26,7 @@ const Schedule kSchedules[kNumSchedules + 1] = {
     {64, 4, 1, 0, 0}, {64, 4, 2, 0, 0}, {1, 1, 1, 1, 1},  {2, 1, 1, 1, 2},  {4, 1, 1, 1, 3},   // 21..25
     {2, 4, 1, 0, 0},  {4, 2, 1, 0, 0},  {8, 1, 4, 0, 0},                                      // 26..28
     {1, 2, 1, 1, 27}, {1, 4, 1, 1, 26}, {2, 4, 1, 1, 26}, {4, 2, 1, 1, 27},                  // 29..32
+    {4, 4, 1, 0, 0},  {8, 4, 1, 0, 0},  {8, 2, 1, 0, 0},                                      // 33..35
 };
 
 int default_rows_per_unit(int sched) {
@@ -721,6 +722,9 @@ hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
         case 30: return FN<1, 4, 1, 1>(__VA_ARGS__);       \
         case 31: return FN<2, 4, 1, 1>(__VA_ARGS__);       \
         case 32: return FN<4, 2, 1, 1>(__VA_ARGS__);       \
+        case 33: return FN<4, 4, 1, 0>(__VA_ARGS__);       \
+        case 34: return FN<8, 4, 1, 0>(__VA_ARGS__);       \
+        case 35: return FN<8, 2, 1, 0>(__VA_ARGS__);       \
         default: return hipErrorInvalidValue;              \
     }
 

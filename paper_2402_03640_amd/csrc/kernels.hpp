@@ -141,7 +141,7 @@ constexpr int kEntrySlack = 16 * kTile;
 struct Schedule {
     int P, V, UR, mask, twin;
 };
-constexpr int kNumSchedules = 32;
+constexpr int kNumSchedules = 35;
 extern const Schedule kSchedules[kNumSchedules + 1];
 
 int default_rows_per_unit(int sched);

@@ -88,7 +88,8 @@ def test_eval_cfg4_all_schedules():
     cnf = hm.load_cnf(n, lits)
     xt = torch.from_numpy(x).cuda()
     ref = None
-    codes = list(range(1, 33)) + [14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
+    codes = list(range(1, 36)) + [34 | (32 << 8) | (8 << 16), 26 | (32 << 8) | (64 << 16),
+                                  25 | (32 << 8) | (16 << 16), 14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
                                   7 | (64 << 8), 1 | (64 << 8), 255]
     for sched in codes:
         res = hm.solve(cnf, steps=3, restarts=R, eval_every=1, x0=xt, schedule=sched, want_x=True)
@@ -122,6 +123,17 @@ def test_single_restart_schedules_bitwise():
         else:
             for a, b in zip(cur, ref):
                 np.testing.assert_array_equal(a, b)
+
+
+def test_schedule_id_errors():
+    n, lits = 200, cnfgen.uniform_kcnf(200, 860, 3, seed=1)
+    cnf = hm.load_cnf(n, lits)
+    for bad in (26 | (32 << 8) | (3 << 16), 26 | (3 << 8), 1 << 24, 36, 26 | (128 << 8)):
+        with pytest.raises(hm.HipMsatError):
+            hm.solve(cnf, steps=2, restarts=8, schedule=bad)
+    code, ms = hm.tune(cnf, restarts=8, iters=3)
+    res = hm.solve(cnf, steps=2, restarts=8)
+    assert res.schedule == code and ms > 0
 
 
 def test_restart_group_bitset_bitwise():

@@ -139,7 +139,7 @@ def test_tune_candidates():
         assert codes and len(set(codes)) == len(codes)
         for c in codes:
             idx, U = c & 0xFF, c >> 8
-            assert 1 <= idx <= 32 and U >= 1 and 64 % U == 0
+            assert 1 <= idx <= 35 and U >= 1 and 64 % U == 0
         has_mask = any((c & 0xFF) in (23, 24, 25, 29, 30, 31, 32) for c in codes)
         assert has_mask == (mode == hm.LOSS_UNSAT)
     assert (26 | (32 << 8)) in hm.tune_candidates(64)
