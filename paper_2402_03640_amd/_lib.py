@@ -87,6 +87,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_03640_amd.build`")
+    # torch first: it brings its own HIP runtime (same soname), which the
+    # library then binds to, so the process holds one runtime whatever the
+    # import order of the caller (a runtime loaded ahead of torch's bundled
+    # libraries can leave the device unusable)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
     L.hms_load_cnf.argtypes = [I32, P, I64, P, C.POINTER(P)]

@@ -64,7 +64,8 @@ struct Layout {
 hms_status current_gfx950(int& dev) {
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
-    if (e != hipSuccess || count == 0) return fail(HMS_ERR_DEVICE, "no HIP device available");
+    if (e != hipSuccess) return fail(HMS_ERR_DEVICE, std::string("no HIP device available: ") + hipGetErrorString(e));
+    if (count == 0) return fail(HMS_ERR_DEVICE, "no HIP device available");
     HIPTRY(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     HIPTRY(hipGetDeviceProperties(&prop, dev));
@@ -614,7 +615,9 @@ std::vector<int32_t> tune_candidates(int32_t R, int loss_mode) {
     return out;
 }
 
-// Average device time of one (non-evaluation) step under schedule `code`.
+// Average device time of one step under schedule `code`, counting every
+// eval_every steps as a solve does (the counting passes weigh heavily when
+// eval_every is small).
 hms_status time_steps(const hms_cnf* cnf, const hms_solve_params* p0, int32_t code, int32_t iters, double& ms) {
     hms_solve_params p = *p0;
     p.schedule = code;
@@ -625,9 +628,11 @@ hms_status time_steps(const hms_cnf* cnf, const hms_solve_params* p0, int32_t co
     hipStream_t s = (hipStream_t)p.stream;
     Events E;
     for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
-    HIPTRY(enqueue_step(Z.L, false, s));
+    const int32_t K = std::max(p.eval_every, 1);
+    iters = std::max(iters, std::min(K, 64));  // at least one counting step when K is small
+    HIPTRY(enqueue_step(Z.L, true, s));
     HIPTRY(hipEventRecord(E.e[0], s));
-    for (int32_t i = 0; i < iters; ++i) HIPTRY(enqueue_step(Z.L, false, s));
+    for (int32_t i = 0; i < iters; ++i) HIPTRY(enqueue_step(Z.L, i % K == 0, s));
     HIPTRY(hipEventRecord(E.e[1], s));
     HIPTRY(hipStreamSynchronize(s));
     float t = 0;
@@ -871,15 +876,23 @@ hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_sol
 }
 
 // Device time per step of a short resident solve.
+// Device time per step of the resident solver: the difference between a
+// short and a three times longer solve, so the launch and set-up cost (paid
+// once per solve) does not count as per-step time.
 hms_status time_resident(const hms_cnf* cnf, const hms_solve_params* p0, int32_t iters, double& ms) {
     hms_solve_params p = *p0;
-    p.steps = std::max(iters, 8) * 4;
     p.eval_every = std::max(p0->eval_every, 1);
     p.x0 = nullptr;
-    hms_solve_result r{};
-    hms_status rc = solve_resident(cnf, &p, &r);
-    if (rc) return rc;
-    ms = r.device_ms / p.steps;
+    const int32_t S = std::max(iters, 16) * 4;
+    double t[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {  // the first solve only warms the device up
+        p.steps = k == 2 ? 3 * S : S;
+        hms_solve_result r{};
+        hms_status rc = solve_resident(cnf, &p, &r);
+        if (rc) return rc;
+        t[k] = r.device_ms;
+    }
+    ms = std::max(t[2] - t[1], 0.0) / (2.0 * S);
     return HMS_OK;
 }
 
