@@ -757,7 +757,8 @@ size_t lds_limit(int dev) {
     if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
-    const size_t lim = (size_t)v > 4096 ? (size_t)v - 4096 : 0;  // keep room for the static LDS
+    const size_t stat = hms::small_static_lds();  // the kernel's own LDS comes on top
+    const size_t lim = (size_t)v > stat ? (size_t)v - stat : 0;
     if (dev >= 0 && dev < 64) cached[dev] = lim;
     return lim;
 }
@@ -765,6 +766,11 @@ size_t lds_limit(int dev) {
 bool resident_ok(const hms_cnf* cnf, const hms_solve_params* p) {
     const hms::HostPlan& P = cnf->plan;
     return P.n_heavy_wide == 0 && p->time_limit_s <= 0 && hms::small_lds_bytes(P) <= lds_limit(cnf->device);
+}
+
+// LDS of one resident workgroup for this instance: state plus the staged plan.
+size_t resident_lds(const hms_cnf* cnf) {
+    return hms::small_lds_total(cnf->plan, lds_limit(cnf->device), nullptr);
 }
 
 hms::SmallDesc make_desc(const hms_cnf* cnf, const hms_solve_params* p) {
@@ -786,6 +792,9 @@ hms::SmallDesc make_desc(const hms_cnf* cnf, const hms_solve_params* p) {
     D.seg_tiles = P.seg_tiles;
     D.seg_rows = P.seg_rows;
     D.n_empty = P.m_empty;
+    D.c_ent_len = (int32_t)P.c_ent.size();
+    D.v_ent_len = (int32_t)P.v_ent.size();
+    hms::small_lds_total(P, lds_limit(cnf->device), &D.stage);
     D.R = p->restarts;
     D.T = p->steps;
     D.K = p->eval_every;
@@ -842,7 +851,7 @@ hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_sol
     for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
     HIPTRY(hipMemcpyAsync(A.base + o_desc, &D, sizeof(D), hipMemcpyHostToDevice, s));
     HIPTRY(hipEventRecord(E.e[0], s));
-    HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc), 1, R, hms::small_lds_bytes(P), s));
+    HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc), 1, R, resident_lds(cnf), s));
     HIPTRY(hipEventRecord(E.e[1], s));
     std::vector<int64_t> best(R);
     std::vector<int32_t> bstep(R);
@@ -1107,7 +1116,7 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
     std::string worst_msg;
     if (!res_idx.empty()) {
         std::sort(res_idx.begin(), res_idx.end(), [&](int32_t a, int32_t b) {
-            return hms::small_lds_bytes(cnfs[a]->plan) > hms::small_lds_bytes(cnfs[b]->plan);
+            return resident_lds(cnfs[a]) > resident_lds(cnfs[b]);
         });
         // device arena: descriptors, then each instance's outputs
         Layout lay;
@@ -1132,9 +1141,9 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
         size_t k0 = 0;
         std::vector<std::pair<size_t, size_t>> groups;
         while (k0 < res_idx.size()) {
-            const size_t big = hms::small_lds_bytes(cnfs[res_idx[k0]]->plan);
+            const size_t big = resident_lds(cnfs[res_idx[k0]]);
             size_t k1 = k0 + 1;
-            while (k1 < res_idx.size() && 2 * hms::small_lds_bytes(cnfs[res_idx[k1]]->plan) >= big) ++k1;
+            while (k1 < res_idx.size() && 2 * resident_lds(cnfs[res_idx[k1]]) >= big) ++k1;
             groups.emplace_back(k0, k1);
             k0 = k1;
         }
@@ -1153,7 +1162,7 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
             int32_t blocks = 0;
             for (size_t k = g.first; k < g.second; ++k) blocks += params[res_idx[k]].restarts;
             HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc) + g.first, (int32_t)(g.second - g.first), blocks,
-                                     hms::small_lds_bytes(cnfs[res_idx[g.first]]->plan), s));
+                                     resident_lds(cnfs[res_idx[g.first]]), s));
         }
         HIPTRY(hipEventRecord(E.e[1], s));
         // read back every resident result

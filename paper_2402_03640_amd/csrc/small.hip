@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device_common.hpp"
@@ -19,6 +20,9 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / 64;
+// Adam step scalars are computed kScal steps ahead (the same FP64 expression
+// as the tiled path), so no step waits on a pow.
+constexpr int kScal = 1024;
 
 struct SmallLds {
     float* t;      // [n + 1]
@@ -29,15 +33,32 @@ struct SmallLds {
     double* seg;   // [seg_rows]
 };
 
-__device__ __forceinline__ size_t align8(size_t b) { return (b + 7) & ~size_t(7); }
+__host__ __device__ __forceinline__ size_t align8(size_t b) { return (b + 7) & ~size_t(7); }
+__host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+
+// Byte size of one staged plan side: tile descriptors, then entries.
+__host__ __device__ __forceinline__ size_t side_bytes(int32_t tiles, int64_t ents) {
+    return align16((size_t)tiles * sizeof(TileDesc)) + align16((size_t)ents * 4);
+}
+
+// Copy one plan side into LDS (all threads); returns the bytes used.
+__device__ size_t stage_side(unsigned char* dst, const TileDesc* tiles, int32_t ntiles, const uint32_t* ent,
+                             int64_t nent, const TileDesc*& tl, const uint32_t*& el) {
+    TileDesc* t = reinterpret_cast<TileDesc*>(dst);
+    for (int i = threadIdx.x; i < ntiles; i += kThreads) t[i] = tiles[i];
+    uint32_t* e = reinterpret_cast<uint32_t*>(dst + align16((size_t)ntiles * sizeof(TileDesc)));
+    for (int64_t i = threadIdx.x; i < nent; i += kThreads) e[i] = ent[i];
+    tl = t;
+    el = e;
+    return side_bytes(ntiles, nent);
+}
 
 __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict__ descs, int32_t n_desc) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t red_c[kWaves];
     __shared__ double red_l[kWaves];
-    __shared__ float s_ss, s_ib2;
+    __shared__ float2 s_sc[kScal];
     __shared__ int s_improved;
-    __shared__ int64_t s_best;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -68,6 +89,14 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
     L.v = reinterpret_cast<float*>(smem + off);
     off += (size_t)n * 4;
     L.seg = reinterpret_cast<double*>(smem + align8(off));
+    off = align16(align8(off) + (size_t)D.seg_rows * 8);
+    // plan sides read every step: from LDS when staged, else global memory
+    const TileDesc* ctile = D.c_tile;
+    const uint32_t* cent = D.c_ent;
+    const TileDesc* vtile = D.v_tile;
+    const uint32_t* vent = D.v_ent;
+    if (D.stage & 1) off += stage_side(smem + off, D.c_tile, D.c_tiles, D.c_ent, D.c_ent_len, ctile, cent);
+    if (D.stage & 2) off += stage_side(smem + off, D.v_tile, D.v_tiles, D.v_ent, D.v_ent_len, vtile, vent);
 
     const AdamCoef co{D.b1, D.b2, D.eps, D.omb1, D.omb2};
     uint8_t* best_a = D.best_a + (size_t)r * n;
@@ -91,21 +120,31 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
     if (tid == 0) {
         L.t[n] = -0.0f;
         L.a[crows] = 0.0f;
-        s_best = D.m;
     }
+    int64_t best = D.m;  // thread 0's copy is the one kept
     int best_step = -1;
     __syncthreads();
 
     for (int step = 0; step <= D.T; ++step) {
         const bool eval = (step % D.K == 0) || step == D.T;
+        if (D.opt != kSgd && step % kScal == 0 && step < D.T) {
+            // the previous block of scalars is no longer read: the last step
+            // ended with a barrier
+            for (int k = tid; k < kScal && step + k < D.T; k += kThreads) {
+                float ss, ib2;
+                adam_scalars((double)(step + k) + 1.0, D.lr_d, D.b1_d, D.b2_d, ss, ib2);
+                s_sc[k] = make_float2(ss, ib2);
+            }
+            __syncthreads();
+        }
         // ---- clause scores, mask, adjoint ------------------------------------
         int cnt = 0;
         double los = 0.0;
         for (int row = tid; row < crows; row += kThreads) {
             const int tile = row >> 6;
             const int rowin = row & 63;
-            const TileDesc d = D.c_tile[tile];
-            const uint32_t* e = D.c_ent + d.base + rowin;
+            const TileDesc d = ctile[tile];
+            const uint32_t* e = cent + d.base + rowin;
             float f = 0.0f;
             uint32_t allf = ~0u;
             if (d.len <= 16) {
@@ -146,10 +185,10 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
                 red_l[wave] = los;
             }
         }
-        if (tid == 0 && step < D.T)
-            adam_scalars((double)step + 1.0, D.lr_d, D.b1_d, D.b2_d, s_ss, s_ib2);
         __syncthreads();
         if (eval) {
+            // one thread sums the wave partials in wave order and broadcasts
+            // whether the count improved
             if (tid == 0) {
                 int64_t c = 0;
                 double l = 0.0;
@@ -158,26 +197,27 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
                     l = l + red_l[w];
                 }
                 c += D.n_empty;
-                s_improved = c < s_best ? 1 : 0;
-                if (s_improved) s_best = c;
+                s_improved = c < best ? 1 : 0;
+                if (c < best) best = c;
                 if (step == D.T) D.final_loss[r] = l * D.inv_m;
             }
             __syncthreads();
             if (s_improved) {
                 best_step = step;
                 for (int i = tid; i < D.n_act; i += kThreads) best_a[D.var_old[i]] = L.x[i] > 0.0f ? 1 : 0;
-                __syncthreads();  // x is read above and rewritten below
+                __syncthreads();
             }
         }
         if (step == D.T) break;
         // ---- transposed sums, fused optimizer step ---------------------------
-        const float ss = s_ss, ib2 = s_ib2;
+        const float2 sc = D.opt != kSgd ? s_sc[step % kScal] : make_float2(0.0f, 1.0f);
+        const float ss = sc.x, ib2 = sc.y;
         for (int row = tid; row < vrows; row += kThreads) {
             const int tile = row >> 6;
             const int rowin = row & 63;
-            const TileDesc d = D.v_tile[tile];
+            const TileDesc d = vtile[tile];
             if (rowin >= (int)d.nreal) continue;
-            const uint32_t* e = D.v_ent + d.base + rowin;
+            const uint32_t* e = vent + d.base + rowin;
             double G = 0.0;
 #pragma unroll 4
             for (uint32_t c = 0; c < d.len; ++c) {
@@ -229,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
         __syncthreads();
     }
     if (tid == 0) {
-        D.best[r] = s_best;
+        D.best[r] = best;
         D.best_step[r] = best_step;
     }
     if (D.x_final != nullptr)
@@ -243,6 +283,29 @@ size_t small_lds_bytes(const HostPlan& P) {
     b = (b + 7) & ~size_t(7);
     b += (size_t)P.seg_rows * 8;
     return b;
+}
+
+size_t small_lds_total(const HostPlan& P, size_t limit, int32_t* stage) {
+    size_t total = align16(small_lds_bytes(P));
+    int32_t st = 0;
+    const size_t cb = side_bytes(P.c_tiles, (int64_t)P.c_ent.size());
+    const size_t vb = side_bytes(P.v_tiles, (int64_t)P.v_ent.size());
+    if (total + cb <= limit) {
+        st |= 1;
+        total += cb;
+    }
+    if (total + vb <= limit) {
+        st |= 2;
+        total += vb;
+    }
+    if (stage) *stage = st;
+    return total;
+}
+
+size_t small_static_lds() {
+    hipFuncAttributes attr{};
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_small)) != hipSuccess) return 16384;
+    return attr.sharedSizeBytes;
 }
 
 hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s) {

@@ -23,6 +23,8 @@ struct SmallDesc {
     const int32_t* seg_row;
     const int32_t* var_old;
     int32_t n, m, n_act, n_heavy, c_tiles, v_tiles, seg_tiles, seg_rows, n_empty;
+    int32_t c_ent_len, v_ent_len;
+    int32_t stage;        // bit 0: clause tiles and entries copied to LDS, bit 1: variable side
     // solve parameters
     int32_t R, T, K, opt, all_mode, block0;
     float two_over_m;
@@ -38,8 +40,14 @@ struct SmallDesc {
     float* x_final;       // caller order [n][R] or null
 };
 
-// LDS bytes the resident solver needs for an instance (per workgroup).
+// LDS bytes the resident solver needs for an instance's state (per workgroup).
 size_t small_lds_bytes(const HostPlan& P);
+// State plus the plan sides that also fit within `limit` bytes (clause side
+// first), staged in LDS so the loop reads no plan data from global memory;
+// *stage receives the SmallDesc::stage bits.
+size_t small_lds_total(const HostPlan& P, size_t limit, int32_t* stage);
+// LDS the resident kernel declares statically (on top of small_lds_bytes).
+size_t small_static_lds();
 
 // Launch one workgroup per (instance, restart): descs[i].block0 must be the
 // running sum of the restart counts, `blocks` the total.
