@@ -160,6 +160,26 @@ def sweep(cnf, wl, iters):
     print("# fastest: " + ", ".join(f"{c} ({t * 1e3:.2f} us)" for t, c in res[:5]), flush=True)
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: best of `reps` device-to-device copies of
+    `nbytes` (bytes read + bytes written per second), HIP events."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        best = t if best is None else min(best, t)
+    del src, dst
+    return 2.0 * nbytes / best / 1e9
+
+
 def make_workload(name):
     import cnfgen
     if name == "cfg2":
@@ -189,25 +209,31 @@ def make_workload(name):
     return dict(name=name, n=n, m=m, R=R, T=T, K=K, lits=lits, desc=desc)
 
 
-def cpu_baseline(wl, L, max_threads=16, sample_steps=None):
-    """The FP64 oracle on this host, on a bounded sample of the workload."""
-    import numpy as np
+def cpu_baseline(wl, L, max_threads=16, sample_steps=None, min_wall=2.0):
+    """The FP64 oracle on this host, on a bounded sample of the workload
+    (repeated until it has run at least ``min_wall`` seconds when the whole
+    workload is tiny)."""
     import oracle as O
     oracle_lib = O.build(force=False)
     del oracle_lib
     oc = O.OracleCNF(wl["n"], wl["lits"])
-    threads = max(1, min(os.cpu_count() or 1, max_threads))
     R = wl["R"]
+    threads = max(1, min(os.cpu_count() or 1, max_threads, R))  # OpenMP over restarts
     if sample_steps is None:
         # about 6e10 literal visits: 10-30 s of the oracle on 8-16 host cores
         sample_steps = min(wl["T"], max(1, int(6.0e10 / max(1, 2 * L * R))))
+    reps = 0
     t0 = time.perf_counter()
-    oc.solve(steps=sample_steps, restarts=R, eval_every=wl["K"], seed=0, lr=1e-4, threads=threads)
-    dt = time.perf_counter() - t0
-    nnz = 2.0 * L * R * sample_steps
+    while True:
+        oc.solve(steps=sample_steps, restarts=R, eval_every=wl["K"], seed=reps, lr=1e-4, threads=threads)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_wall:
+            break
+    nnz = 2.0 * L * R * sample_steps * reps
     return {"value": nnz / dt, "unit": "nnz/s", "cores": threads, "kind": "oracle",
-            "sample": f"{R} restarts x {sample_steps} of {wl['T']} steps (eval every {wl['K']}), "
-                      f"FP64, OpenMP over restarts, {dt:.2f} s wall"}
+            "sample": f"{reps} x ({R} restarts x {sample_steps} of {wl['T']} steps, eval every {wl['K']}), "
+                      f"FP64, OpenMP over restarts on {threads} threads, {dt:.2f} s wall"}
 
 
 def serve_bench(args):
@@ -405,6 +431,10 @@ def main():
                                  "algorithmic_bytes_per_launch": obytes,
                                  "achieved_GBps": round(obytes / (oms * 1e-3) / 1e9, 1)}}
     step_bytes = fb + bb
+    copy_gbps = copy_bandwidth()
+    log(f"[bench] device copy: {copy_gbps:.0f} GB/s (read + write)")
+    if roof is not None:
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbps, 4)
     out = {
         "metric": "fwd+bwd literal nnz/s",
         "value": value,
@@ -422,6 +452,7 @@ def main():
                    "grad_steps_per_solve": T, "eval_every": K, "schedule": r.schedule},
         "roofline": roof,
         "effective_GBps_per_step": round(step_bytes / (step_ms * 1e-3) / 1e9, 1),
+        "copy_GBps": round(copy_gbps, 1),
         "device_ms_per_solve": round(float(np.median(dev_ms)), 3),
         "us_per_grad_step": round(1e3 * float(np.median(dev_ms)) / max(T, 1), 3),
         "best_cost": int(min(best)),

@@ -41,6 +41,27 @@ __host__ __device__ __forceinline__ size_t side_bytes(int32_t tiles, int64_t ent
     return align16((size_t)tiles * sizeof(TileDesc)) + align16((size_t)ents * 4);
 }
 
+// Reads of one plan side, from LDS when it is staged (S) and from global
+// memory otherwise.  The address space is explicit so that the loads are LDS
+// or global loads, not flat loads (which wait on both counters).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool S>
+struct Side {
+    const TileDesc* tiles;
+    const uint32_t* ent;
+    __device__ __forceinline__ TileDesc tile(int i) const {
+        u32x4 q;
+        if constexpr (S) q = ((const __attribute__((address_space(3))) u32x4*)tiles)[i];
+        else q = ((const __attribute__((address_space(1))) u32x4*)tiles)[i];
+        return TileDesc{q.x, q.y, q.z, q.w};
+    }
+    __device__ __forceinline__ uint32_t entry(size_t i) const {
+        if constexpr (S) return ((const __attribute__((address_space(3))) uint32_t*)ent)[i];
+        else return ((const __attribute__((address_space(1))) uint32_t*)ent)[i];
+    }
+};
+
 // Copy one plan side into LDS (all threads); returns the bytes used.
 __device__ size_t stage_side(unsigned char* dst, const TileDesc* tiles, int32_t ntiles, const uint32_t* ent,
                              int64_t nent, const TileDesc*& tl, const uint32_t*& el) {
@@ -53,6 +74,9 @@ __device__ size_t stage_side(unsigned char* dst, const TileDesc* tiles, int32_t 
     return side_bytes(ntiles, nent);
 }
 
+// SC / SV: the clause / variable side is staged in LDS (for every instance of
+// the launch).
+template <bool SC, bool SV>
 __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict__ descs, int32_t n_desc) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t red_c[kWaves];
@@ -91,12 +115,10 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
     L.seg = reinterpret_cast<double*>(smem + align8(off));
     off = align16(align8(off) + (size_t)D.seg_rows * 8);
     // plan sides read every step: from LDS when staged, else global memory
-    const TileDesc* ctile = D.c_tile;
-    const uint32_t* cent = D.c_ent;
-    const TileDesc* vtile = D.v_tile;
-    const uint32_t* vent = D.v_ent;
-    if (D.stage & 1) off += stage_side(smem + off, D.c_tile, D.c_tiles, D.c_ent, D.c_ent_len, ctile, cent);
-    if (D.stage & 2) off += stage_side(smem + off, D.v_tile, D.v_tiles, D.v_ent, D.v_ent_len, vtile, vent);
+    Side<SC> cs{D.c_tile, D.c_ent};
+    Side<SV> vs{D.v_tile, D.v_ent};
+    if constexpr (SC) off += stage_side(smem + off, D.c_tile, D.c_tiles, D.c_ent, D.c_ent_len, cs.tiles, cs.ent);
+    if constexpr (SV) off += stage_side(smem + off, D.v_tile, D.v_tiles, D.v_ent, D.v_ent_len, vs.tiles, vs.ent);
 
     const AdamCoef co{D.b1, D.b2, D.eps, D.omb1, D.omb2};
     uint8_t* best_a = D.best_a + (size_t)r * n;
@@ -143,14 +165,14 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
         for (int row = tid; row < crows; row += kThreads) {
             const int tile = row >> 6;
             const int rowin = row & 63;
-            const TileDesc d = ctile[tile];
-            const uint32_t* e = cent + d.base + rowin;
+            const TileDesc d = cs.tile(tile);
+            const size_t e = (size_t)d.base + rowin;
             float f = 0.0f;
             uint32_t allf = ~0u;
             if (d.len <= 16) {
 #pragma unroll 4
                 for (uint32_t c = 0; c < d.len; ++c) {
-                    const uint32_t en = e[(size_t)c * kTile];
+                    const uint32_t en = cs.entry(e + (size_t)c * kTile);
                     const uint32_t b = __float_as_uint(L.t[en & kIdx]) ^ (en & kSign);
                     f = f + __uint_as_float(b);
                     allf &= b;
@@ -159,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
                 double fd = 0.0;
 #pragma unroll 4
                 for (uint32_t c = 0; c < d.len; ++c) {
-                    const uint32_t en = e[(size_t)c * kTile];
+                    const uint32_t en = cs.entry(e + (size_t)c * kTile);
                     const uint32_t b = __float_as_uint(L.t[en & kIdx]) ^ (en & kSign);
                     fd = fd + (double)__uint_as_float(b);
                     allf &= b;
@@ -215,13 +237,13 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
         for (int row = tid; row < vrows; row += kThreads) {
             const int tile = row >> 6;
             const int rowin = row & 63;
-            const TileDesc d = vtile[tile];
+            const TileDesc d = vs.tile(tile);
             if (rowin >= (int)d.nreal) continue;
-            const uint32_t* e = vent + d.base + rowin;
+            const size_t e = (size_t)d.base + rowin;
             double G = 0.0;
 #pragma unroll 4
             for (uint32_t c = 0; c < d.len; ++c) {
-                const uint32_t en = e[(size_t)c * kTile];
+                const uint32_t en = vs.entry(e + (size_t)c * kTile);
                 G = G + (double)__uint_as_float(__float_as_uint(L.a[en & kIdx]) ^ (en & kSign));
             }
             if (tile < D.seg_tiles) {
@@ -304,17 +326,28 @@ size_t small_lds_total(const HostPlan& P, size_t limit, int32_t* stage) {
 
 size_t small_static_lds() {
     hipFuncAttributes attr{};
-    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_small)) != hipSuccess) return 16384;
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_small<true, true>)) != hipSuccess) return 16384;
     return attr.sharedSizeBytes;
 }
 
-hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s) {
+template <bool SC, bool SV>
+hipError_t launch_small_as(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_small, dim3(blocks), dim3(kThreads), lds_bytes, s, d_descs, n_desc);
+    hipLaunchKernelGGL((k_small<SC, SV>), dim3(blocks), dim3(kThreads), lds_bytes, s, d_descs, n_desc);
     return hipGetLastError();
+}
+
+hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
+                        hipStream_t s) {
+    switch (stage & 3) {
+        case 0: return launch_small_as<false, false>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 1: return launch_small_as<true, false>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 2: return launch_small_as<false, true>(d_descs, n_desc, blocks, lds_bytes, s);
+        default: return launch_small_as<true, true>(d_descs, n_desc, blocks, lds_bytes, s);
+    }
 }
 
 }  // namespace hms

@@ -24,7 +24,7 @@ struct SmallDesc {
     const int32_t* var_old;
     int32_t n, m, n_act, n_heavy, c_tiles, v_tiles, seg_tiles, seg_rows, n_empty;
     int32_t c_ent_len, v_ent_len;
-    int32_t stage;        // bit 0: clause tiles and entries copied to LDS, bit 1: variable side
+    int32_t stage;        // bit 0: clause tiles and entries fit in LDS beside the state, bit 1: variable side
     // solve parameters
     int32_t R, T, K, opt, all_mode, block0;
     float two_over_m;
@@ -50,7 +50,10 @@ size_t small_lds_total(const HostPlan& P, size_t limit, int32_t* stage);
 size_t small_static_lds();
 
 // Launch one workgroup per (instance, restart): descs[i].block0 must be the
-// running sum of the restart counts, `blocks` the total.
-hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s);
+// running sum of the restart counts, `blocks` the total.  `stage` (SmallDesc
+// bits) names the plan sides staged in LDS; every instance of the launch must
+// have them (its stage bits include these).
+hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
+                        hipStream_t s);
 
 }  // namespace hms

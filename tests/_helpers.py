@@ -1,4 +1,6 @@
 """Shared test helpers: tolerance scaffolding built from the clause lists."""
+import sys
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -50,10 +52,13 @@ def assert_eval_parity(oc, Wabs, x_np, loss, grad, unsat, mode, rtol=1e-5):
     lo, go, uo, fo, muo = oc.loss_grad(x_np, mode, want_f=True)
     np.testing.assert_array_equal(np.asarray(unsat), uo)
     lscale, S = tolerance_terms(Wabs, x_np, muo, oc.m)
-    assert np.all(np.abs(np.asarray(loss) - lo) <= rtol * lscale + 1e-300), (loss, lo, lscale)
+    lerr = np.abs(np.asarray(loss) - lo)
+    assert np.all(lerr <= rtol * lscale + 1e-300), (loss, lo, lscale)
+    msg = f"parity n={oc.n} m={oc.m}: loss err / scale max {np.max(lerr / np.maximum(lscale, 1e-300)):.2e}"
     if grad is not None:
         g = np.asarray(grad, dtype=np.float64).reshape(go.shape)
         err = np.abs(g - go)
+        msg += f", grad err / S max {np.max(np.where(S > 0, err / np.maximum(S, 1e-300), 0.0)):.2e}"
         bound = rtol * S + 1e-30
         bad = np.argwhere(err > bound)
         assert bad.size == 0, (bad[:5], g[tuple(bad[0])], go[tuple(bad[0])], S[tuple(bad[0])])
@@ -62,6 +67,7 @@ def assert_eval_parity(oc, Wabs, x_np, loss, grad, unsat, mode, rtol=1e-5):
         for r in range(G2.shape[1]):
             nrm = np.linalg.norm(G2[:, r])
             assert np.linalg.norm(g.reshape(G2.shape)[:, r] - G2[:, r]) <= rtol * nrm + 1e-30
+    print(msg, file=sys.stderr, flush=True)
     return lo, go, uo
 
 
