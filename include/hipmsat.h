@@ -160,9 +160,14 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* params, 
  * Batched solve of `count` instances (Algorithm 1 for each, as hms_solve):
  * cnfs[i] with params[i] into results[i] (statuses[i], may be NULL, receives each
  * instance's status).  Instances that fit the resident solver share launches,
- * one workgroup per (instance, restart); the rest run one after the other on
- * the tiled kernels.  All work goes on params[0].stream.  Each result is bitwise
- * the one hms_solve gives for that instance alone.  Returns the first error.
+ * one workgroup per (instance, restart).  The others are grouped by restarts,
+ * steps, eval_every, optimizer, loss mode and requested schedule: each step of
+ * a group is one launch per kernel over all its instances (a work queue of
+ * (instance, work unit) items, replayed as a HIP graph), with the schedule of
+ * its largest instance.  A group of one, or a solve with a time limit, runs as
+ * hms_solve.  All work goes on params[0].stream.  Each result is bitwise the
+ * one hms_solve gives for that instance alone (restart_loss and final_loss may
+ * differ in the last bits when the schedule does).  Returns the first error.
  */
 hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* params, int32_t count,
                            hms_solve_result* results, hms_status* statuses);

@@ -299,10 +299,11 @@ def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, s
 
 def solve_batch(cnfs, steps=1000, restarts=1, eval_every=1, seeds=0, optimizer: int = ADAM,
                 lr: float = 1e-4, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
-                loss_mode: int = LOSS_UNSAT, schedule: int = 0, stream=None):
+                loss_mode: int = LOSS_UNSAT, schedule: int = 0, stream=None, want_x: bool = False):
     """Solve many instances in one call (see ``hms_solve_batch``).  Scalar
     arguments apply to every instance; lists give one value per instance.
-    Returns one SolveOutput per instance (``status`` set on each)."""
+    Returns one SolveOutput per instance (``status`` set on each; ``x_final``
+    a device tensor when ``want_x``)."""
     cnfs = list(cnfs)
     N = len(cnfs)
 
@@ -328,15 +329,20 @@ def solve_batch(cnfs, steps=1000, restarts=1, eval_every=1, seeds=0, optimizer: 
         results[i].restart_best = rb.ctypes.data
         results[i].restart_step = rs.ctypes.data
         results[i].restart_loss = rl.ctypes.data
-        bufs.append((ba, rb, rs, rl))
+        xf = None
+        if want_x:
+            import torch
+            xf = torch.empty((cnf.n, R), dtype=torch.float32, device="cuda")
+            results[i].x_final = xf.data_ptr()
+        bufs.append((ba, rb, rs, rl, xf))
     handles = (C.c_void_p * N)(*[c.handle.value for c in cnfs])
     rc = lib().hms_solve_batch(handles, params, N, results, statuses)
     outs = []
     for i, cnf in enumerate(cnfs):
-        ba, rb, rs, rl = bufs[i]
+        ba, rb, rs, rl, xf = bufs[i]
         r = results[i]
         o = SolveOutput(r.best_cost, r.best_restart, r.best_step, r.steps_done, r.schedule,
-                        r.final_loss, r.device_ms, ba[:cnf.n].copy(), rb, rs, rl, None)
+                        r.final_loss, r.device_ms, ba[:cnf.n].copy(), rb, rs, rl, xf)
         o.status = int(statuses[i])
         outs.append(o)
     if rc != HMS_OK and rc != -6:

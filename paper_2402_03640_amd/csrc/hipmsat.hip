@@ -7,8 +7,10 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "hipmsat.h"
@@ -905,6 +907,191 @@ hms_status time_resident(const hms_cnf* cnf, const hms_solve_params* p0, int32_t
     return HMS_OK;
 }
 
+// The count at x_T (always taken) and the snapshot of the best assignment.
+hipError_t count_final(const hms_cnf* cnf, const SolveSetup& Z, hipStream_t s) {
+    const Shape& sh = Z.sh;
+    hipError_t e = hms::launch_fwd(sh.sched, true, Z.L.fa, sh.fwd_blocks, s);
+    if (e == hipSuccess) e = hms::launch_reduce(Z.L.ra, s);
+    if (e == hipSuccess) e = hms::launch_snapshot(cnf->plan.n_act, sh.B, Z.S.x, Z.S.improved, Z.S.best_a, s);
+    return e;
+}
+
+// Read a finished solve's outcome into `res` (synchronises s).
+hms_status read_result(const hms_cnf* cnf, const SolveSetup& Z, int32_t done, float ms, hipStream_t s,
+                       hms_solve_result* res) {
+    const hms::HostPlan& P = cnf->plan;
+    const Shape& sh = Z.sh;
+    const State& S = Z.S;
+    const int32_t R = sh.B.R;
+    std::vector<int64_t> best(R);
+    std::vector<int32_t> bstep(R);
+    std::vector<double> closs(R);
+    HIPTRY(hipMemcpyAsync(best.data(), S.best, R * 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(bstep.data(), S.best_step, R * 4, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(closs.data(), S.cur_loss, R * 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    int32_t br = 0;
+    for (int32_t r = 1; r < R; ++r)
+        if (best[r] < best[br]) br = r;
+    if (res->best_assignment && P.n > 0) {
+        HIPTRY(hms::launch_extract(P.n, sh.B, br, cnf->var_old, S.best_a, S.out_assign, s));
+        HIPTRY(hipMemcpyAsync(res->best_assignment, S.out_assign, P.n, hipMemcpyDeviceToHost, s));
+    }
+    if (res->x_final) HIPTRY(hms::launch_scatter(P.n, P.n, sh.B, cnf->var_old, S.x, res->x_final, s));
+    HIPTRY(hipStreamSynchronize(s));
+    res->best_cost = best[br];
+    res->best_restart = br;
+    res->best_step = bstep[br];
+    res->steps_done = done;
+    res->schedule = sh.code;
+    res->final_loss = closs[br];
+    res->device_ms = ms;
+    if (res->restart_best) std::memcpy(res->restart_best, best.data(), R * 8);
+    if (res->restart_step) std::memcpy(res->restart_step, bstep.data(), R * 4);
+    if (res->restart_loss) std::memcpy(res->restart_loss, closs.data(), R * 8);
+    for (int32_t r = 0; r < R; ++r)
+        if (!std::isfinite(closs[r])) return fail(HMS_ERR_NONFINITE, "the loss at the final iterate is not finite");
+    return HMS_OK;
+}
+
+// Steps of the graph body: a multiple of K starting at a multiple of K.
+int32_t graph_body(int32_t K) { return K * std::max(1, (32 + K - 1) / K); }
+
+// Tiled instances of a batch that share restarts, steps, counting period,
+// optimizer and loss mode: every step is one launch per kernel for all of
+// them (each workgroup finds its instance from the running block counts),
+// replayed as a HIP graph.  Each instance's arguments are those of its own
+// solve, so its result is bitwise the one it gets alone.
+hms_status solve_tiled_group(const hms_cnf* const* cnfs, const hms_solve_params* params, const int32_t* idx,
+                             int32_t cnt, int32_t code, hipStream_t s, hms_solve_result* results,
+                             hms_status* statuses) {
+    std::vector<std::unique_ptr<SolveSetup>> Z(cnt);
+    for (int32_t k = 0; k < cnt; ++k) {
+        hms_solve_params p = params[idx[k]];
+        p.schedule = code;
+        p.stream = s;
+        Z[k].reset(new SolveSetup());
+        hms_status rc = setup_solve(cnfs[idx[k]], &p, *Z[k]);
+        if (rc) return rc;
+    }
+    const hms_solve_params& p0 = params[idx[0]];
+    const int32_t T = p0.steps, K = p0.eval_every, R = p0.restarts;
+    const int sched = Z[0]->sh.sched;
+    const int opt = Z[0]->L.opt;
+    for (int32_t k = 1; k < cnt; ++k)
+        if (Z[k]->sh.sched != sched || Z[k]->sh.U != Z[0]->sh.U || Z[k]->sh.Ub != Z[0]->sh.Ub || Z[k]->L.opt != opt ||
+            Z[k]->sh.B.R != R)
+            return fail(HMS_ERR_ARG, "the instances of a grouped launch must share one schedule");
+    // argument arrays and running block counts
+    std::vector<hms::FwdArgs> fa(cnt);
+    std::vector<hms::BwdArgs> ba0(cnt), ba1(cnt);
+    std::vector<hms::ReduceArgs> ra(cnt);
+    std::vector<int32_t> b0[5];
+    for (auto& v : b0) v.assign(1, 0);
+    const int32_t gx = (R + 63) / 64;
+    for (int32_t k = 0; k < cnt; ++k) {
+        const Shape& sh = Z[k]->sh;
+        const hms::HostPlan& P = cnfs[idx[k]]->plan;
+        fa[k] = Z[k]->L.fa;
+        ba0[k] = ba1[k] = Z[k]->L.ba;
+        ba0[k].eval = 0;
+        ba1[k].eval = 1;
+        ra[k] = Z[k]->L.ra;
+        const int64_t nblk[5] = {
+            std::max<int64_t>(sh.fwd_blocks, 1),  // block 0 publishes the step scalars
+            std::max<int64_t>(sh.bwd_blocks, 1),  // block 0 advances the step counter
+            (int64_t)P.n_heavy_wide * R + ((int64_t)(P.n_heavy - P.n_heavy_wide) * R + 15) / 16,
+            ra[k].n_chunks > 0 ? (int64_t)gx * ra[k].n_chunks : 0, (int64_t)gx};
+        for (int j = 0; j < 5; ++j) {
+            const int64_t tot = (int64_t)b0[j].back() + nblk[j];
+            if (tot >= INT32_MAX / 2) return fail(HMS_ERR_TOO_LARGE, "too many work units in one batched launch");
+            b0[j].push_back((int32_t)tot);
+        }
+    }
+    Layout lay;
+    const size_t o_fa = lay.add(sizeof(hms::FwdArgs) * cnt);
+    const size_t o_b0 = lay.add(sizeof(hms::BwdArgs) * cnt);
+    const size_t o_b1 = lay.add(sizeof(hms::BwdArgs) * cnt);
+    const size_t o_ra = lay.add(sizeof(hms::ReduceArgs) * cnt);
+    size_t o_blk[5];
+    for (int j = 0; j < 5; ++j) o_blk[j] = lay.add(sizeof(int32_t) * (cnt + 1));
+    Arena A;
+    A.s = s;
+    HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+    HIPTRY(hipMemcpyAsync(A.base + o_fa, fa.data(), sizeof(hms::FwdArgs) * cnt, hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(A.base + o_b0, ba0.data(), sizeof(hms::BwdArgs) * cnt, hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(A.base + o_b1, ba1.data(), sizeof(hms::BwdArgs) * cnt, hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(A.base + o_ra, ra.data(), sizeof(hms::ReduceArgs) * cnt, hipMemcpyHostToDevice, s));
+    for (int j = 0; j < 5; ++j)
+        HIPTRY(hipMemcpyAsync(A.base + o_blk[j], b0[j].data(), sizeof(int32_t) * (cnt + 1), hipMemcpyHostToDevice, s));
+    HIPTRY(hipStreamSynchronize(s));  // the host vectors above are temporaries
+    auto ml = [&](size_t o_args, int j) {
+        return hms::MultiLaunch{A.at<void>(o_args), A.at<int32_t>(o_blk[j]), cnt, b0[j].back()};
+    };
+    const hms::MultiLaunch mf = ml(o_fa, 0), mb0 = ml(o_b0, 1), mb1 = ml(o_b1, 1), mc0 = ml(o_b0, 2),
+                           mc1 = ml(o_b1, 2), mr1 = ml(o_ra, 3), mr2 = ml(o_ra, 4);
+    auto step = [&](bool eval, hipStream_t st) -> hipError_t {
+        hipError_t e = hms::launch_fwd_multi(sched, eval, mf, st);
+        if (e == hipSuccess && eval) e = hms::launch_reduce_multi(mr1, mr2, st);
+        if (e == hipSuccess) e = hms::launch_bwd_multi(sched, opt, eval ? mb1 : mb0, st);
+        if (e == hipSuccess) e = hms::launch_combine_multi(opt, eval ? mc1 : mc0, st);
+        return e;
+    };
+
+    Events E;
+    for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
+    HIPTRY(hipEventRecord(E.e[0], s));
+    int32_t done = 0;
+    const int32_t B = graph_body(K);
+    if (p0.use_graph && T >= 2 * B) {
+        hipStream_t cs = nullptr;
+        HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        struct GFree {
+            hipStream_t user;
+            hipStream_t& s;
+            hipGraph_t& g;
+            hipGraphExec_t& x;
+            ~GFree() {
+                (void)hipStreamSynchronize(user);
+                if (x) (void)hipGraphExecDestroy(x);
+                if (g) (void)hipGraphDestroy(g);
+                if (s) (void)hipStreamDestroy(s);
+            }
+        } gf{s, cs, graph, exec};
+        HIPTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        hipError_t ce = hipSuccess;
+        for (int32_t i = 0; i < B && ce == hipSuccess; ++i) ce = step(i % K == 0, cs);
+        hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (ce != hipSuccess) return fail(HMS_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(ce));
+        if (ee != hipSuccess) return fail(HMS_ERR_DEVICE, std::string("end capture: ") + hipGetErrorString(ee));
+        HIPTRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        for (int32_t r = 0; r < T / B; ++r) {
+            HIPTRY(hipGraphLaunch(exec, s));
+            done += B;
+        }
+    }
+    for (; done < T; ++done) HIPTRY(step(done % K == 0, s));
+    for (int32_t k = 0; k < cnt; ++k) HIPTRY(count_final(cnfs[idx[k]], *Z[k], s));
+    HIPTRY(hipEventRecord(E.e[1], s));
+    HIPTRY(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    HIPTRY(hipEventElapsedTime(&ms, E.e[0], E.e[1]));
+    hms_status worst = HMS_OK;
+    std::string msg;
+    for (int32_t k = 0; k < cnt; ++k) {
+        hms_status st = read_result(cnfs[idx[k]], *Z[k], done, ms, s, &results[idx[k]]);
+        if (statuses) statuses[idx[k]] = st;
+        if (st && !worst) {
+            worst = st;
+            msg = "instance " + std::to_string(idx[k]) + ": " + g_err;
+        }
+    }
+    if (worst) return fail(worst, msg);
+    return HMS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -926,11 +1113,8 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     SolveSetup Z;
     rc0 = setup_solve(cnf, p, Z);
     if (rc0) return rc0;
-    const hms::HostPlan& P = cnf->plan;
-    const int32_t R = p->restarts, T = p->steps, K = p->eval_every;
+    const int32_t T = p->steps, K = p->eval_every;
     hipStream_t s = (hipStream_t)p->stream;
-    const Shape& sh = Z.sh;
-    const State& S = Z.S;
     const Launch& L = Z.L;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -954,7 +1138,7 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
 
     int32_t done = 0;
     // body of B steps (a multiple of K, starting at a multiple of K)
-    const int32_t B = K * std::max(1, (32 + K - 1) / K);
+    const int32_t B = graph_body(K);
     if (p->use_graph && T >= 2 * B) {
         hipStream_t cs = nullptr;
         HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -998,42 +1182,12 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
         }
     }
     // x_T is always counted
-    HIPTRY(hms::launch_fwd(sh.sched, true, L.fa, sh.fwd_blocks, s));
-    HIPTRY(hms::launch_reduce(L.ra, s));
-    HIPTRY(hms::launch_snapshot(P.n_act, sh.B, S.x, S.improved, S.best_a, s));
+    HIPTRY(count_final(cnf, Z, s));
     HIPTRY(hipEventRecord(ev1, s));
-
-    std::vector<int64_t> best(R);
-    std::vector<int32_t> bstep(R);
-    std::vector<double> closs(R);
-    HIPTRY(hipMemcpyAsync(best.data(), S.best, R * 8, hipMemcpyDeviceToHost, s));
-    HIPTRY(hipMemcpyAsync(bstep.data(), S.best_step, R * 4, hipMemcpyDeviceToHost, s));
-    HIPTRY(hipMemcpyAsync(closs.data(), S.cur_loss, R * 8, hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     float ms = 0.0f;
     HIPTRY(hipEventElapsedTime(&ms, ev0, ev1));
-    int32_t br = 0;
-    for (int32_t r = 1; r < R; ++r)
-        if (best[r] < best[br]) br = r;
-    if (res->best_assignment && P.n > 0) {
-        HIPTRY(hms::launch_extract(P.n, sh.B, br, cnf->var_old, S.best_a, S.out_assign, s));
-        HIPTRY(hipMemcpyAsync(res->best_assignment, S.out_assign, P.n, hipMemcpyDeviceToHost, s));
-    }
-    if (res->x_final) HIPTRY(hms::launch_scatter(P.n, P.n, sh.B, cnf->var_old, S.x, res->x_final, s));
-    HIPTRY(hipStreamSynchronize(s));
-    res->best_cost = best[br];
-    res->best_restart = br;
-    res->best_step = bstep[br];
-    res->steps_done = done;
-    res->schedule = sh.code;
-    res->final_loss = closs[br];
-    res->device_ms = ms;
-    if (res->restart_best) std::memcpy(res->restart_best, best.data(), R * 8);
-    if (res->restart_step) std::memcpy(res->restart_step, bstep.data(), R * 4);
-    if (res->restart_loss) std::memcpy(res->restart_loss, closs.data(), R * 8);
-    for (int32_t r = 0; r < R; ++r)
-        if (!std::isfinite(closs[r])) return fail(HMS_ERR_NONFINITE, "the loss at the final iterate is not finite");
-    return HMS_OK;
+    return read_result(cnf, Z, done, ms, s, res);
 }
 
 hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* p, int32_t iters, double* fwd_ms,
@@ -1094,6 +1248,8 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
     g_err.clear();
     if (count < 0 || (count > 0 && (!cnfs || !params || !results))) return fail(HMS_ERR_ARG, "null argument");
     if (count == 0) return HMS_OK;
+    if (statuses)
+        for (int32_t i = 0; i < count; ++i) statuses[i] = HMS_OK;
     hipStream_t s = (hipStream_t)params[0].stream;
     int dev = cnfs[0] ? cnfs[0]->device : -1;
     for (int32_t i = 0; i < count; ++i) {
@@ -1217,16 +1373,63 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
         }
         HIPTRY(hipStreamSynchronize(s));
     }
+    // tiled instances: groups that share restarts, steps, counting period,
+    // optimizer, loss mode and requested schedule run together (largest
+    // first, at most kGroup per launch) with the schedule of their largest
+    // instance; a group of one, or a solve with a time limit, runs alone
+    constexpr size_t kGroup = 64;
+    std::map<std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>, std::vector<int32_t>> groups;
+    std::vector<int32_t> alone;
     for (int32_t i : tiled_idx) {
+        const hms_solve_params& p = params[i];
+        if (p.time_limit_s > 0) {
+            alone.push_back(i);
+            continue;
+        }
+        const int32_t sch = p.schedule == kResidentId ? 0 : p.schedule;
+        groups[std::make_tuple(p.restarts, p.steps, p.eval_every, p.optimizer, p.loss_mode, sch)].push_back(i);
+    }
+    auto note = [&](hms_status st, int32_t i) {
+        if (st && !worst) {
+            worst = st;
+            worst_msg = "instance " + std::to_string(i) + ": " + g_err;
+        }
+    };
+    for (auto& kv : groups) {
+        std::vector<int32_t>& g = kv.second;
+        std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) { return cnfs[a]->plan.nnz > cnfs[b]->plan.nnz; });
+        for (size_t k0 = 0; k0 < g.size(); k0 += kGroup) {
+            const int32_t cnt = (int32_t)std::min(kGroup, g.size() - k0);
+            if (cnt == 1) {
+                alone.push_back(g[k0]);
+                continue;
+            }
+            hms_solve_params p = params[g[k0]];
+            p.stream = params[0].stream;
+            if (p.schedule == kResidentId) p.schedule = 0;
+            int32_t code = 0;
+            hms_status st = resolve_schedule(cnfs[g[k0]], &p, code);
+            if (!st && code == kResidentId) code = 0;
+            // one explicit schedule for the whole group (the automatic choice
+            // depends on the instance)
+            Shape sh0;
+            if (!st) st = make_shape(cnfs[g[k0]]->plan, p.restarts, code, p.loss_mode, sh0);
+            if (!st) st = solve_tiled_group(cnfs, params, g.data() + k0, cnt, sh0.code, s, results, statuses);
+            if (st) {
+                if (statuses)
+                    for (int32_t k = 0; k < cnt; ++k)
+                        if (statuses[g[k0 + k]] == HMS_OK) statuses[g[k0 + k]] = st;
+                note(st, g[k0]);
+            }
+        }
+    }
+    for (int32_t i : alone) {
         hms_solve_params p = params[i];
         p.stream = params[0].stream;
         if (p.schedule == kResidentId) p.schedule = 0;
         hms_status st = hms_solve(cnfs[i], &p, &results[i]);
         if (statuses) statuses[i] = st;
-        if (st && !worst) {
-            worst = st;
-            worst_msg = "instance " + std::to_string(i) + ": " + g_err;
-        }
+        note(st, i);
     }
     if (worst) return fail(worst, worst_msg);
     g_err.clear();

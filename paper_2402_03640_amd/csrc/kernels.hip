@@ -122,17 +122,18 @@ __device__ __forceinline__ uint64_t compact_bits(uint64_t x) {
 // the clause is unsatisfied in some restart of the group, and the adjoint is
 // written only for rows whose bit is set.
 // ---------------------------------------------------------------------------
+// `bx` is the workgroup's index within the instance's grid.
 template <int P, int V, int UR, bool EVAL, bool MASK>
-__global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
+__device__ __forceinline__ void fwd_body(const FwdArgs& A, const int bx) {
     constexpr int W = 64 / P;
     const int lane = threadIdx.x & 63;
     const int s = lane / P;
     const int q = lane % P;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && A.st != nullptr)
+    if (bx == 0 && threadIdx.x == 0 && A.st != nullptr)
         adam_scalars((double)A.st->t + 1.0, A.lr, A.b1, A.b2, A.st->step_size, A.st->inv_sqrt_bc2);
     const Blocking B = A.B;
-    const int rg = blockIdx.x % B.RG;
-    const int tc = __builtin_amdgcn_readfirstlane((blockIdx.x / B.RG) * 4 + (threadIdx.x >> 6));
+    const int rg = bx % B.RG;
+    const int tc = __builtin_amdgcn_readfirstlane((bx / B.RG) * 4 + (threadIdx.x >> 6));
     if (tc >= A.ntiles * A.chunks) return;
     const int tile = tc / A.chunks;
     const int chunk = tc % A.chunks;
@@ -273,6 +274,31 @@ __global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
     }
 }
 
+// Index of the instance owning workgroup `b` of a multi-instance launch:
+// the last i with b0[i] <= b (b0 is the running sum of the grids).
+__device__ __forceinline__ int owner(const int32_t* __restrict__ b0, int32_t n, int b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int P, int V, int UR, bool EVAL, bool MASK>
+__global__ __launch_bounds__(256) void k_fwd(FwdArgs A) {
+    fwd_body<P, V, UR, EVAL, MASK>(A, blockIdx.x);
+}
+
+// Many instances in one launch: instance i owns workgroups [b0[i], b0[i+1]).
+template <int P, int V, int UR, bool EVAL, bool MASK>
+__global__ __launch_bounds__(256) void k_fwd_multi(const FwdArgs* __restrict__ As, const int32_t* __restrict__ b0,
+                                                   int32_t n) {
+    const int i = owner(b0, n, blockIdx.x);
+    fwd_body<P, V, UR, EVAL, MASK>(As[i], blockIdx.x - b0[i]);
+}
+
 // ---------------------------------------------------------------------------
 // Epilogue of a variable: g = sech^2(x) G, then the optimizer step (or the
 // gradient itself), t = signed tanh of the new x.  `base` is the element
@@ -356,16 +382,16 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int 
 // otherwise).
 // ---------------------------------------------------------------------------
 template <int P, int V, int UR, int OPT, bool MASK>
-__global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
+__device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
     constexpr int W = 64 / P;
     constexpr int CB = kChunkB;
     const int lane = threadIdx.x & 63;
     const int s = lane / P;
     const int q = lane % P;
-    if (OPT != kGrad && blockIdx.x == 0 && threadIdx.x == 0) A.st->t += 1;
+    if (OPT != kGrad && bx == 0 && threadIdx.x == 0) A.st->t += 1;
     const Blocking B = A.B;
-    const int rg = blockIdx.x % B.RG;
-    const int tc = __builtin_amdgcn_readfirstlane((blockIdx.x / B.RG) * 4 + (threadIdx.x >> 6));
+    const int rg = bx % B.RG;
+    const int tc = __builtin_amdgcn_readfirstlane((bx / B.RG) * 4 + (threadIdx.x >> 6));
     if (tc >= A.ntiles * A.chunks) return;
     const int tile = tc / A.chunks;
     const int chunk = tc % A.chunks;
@@ -447,6 +473,18 @@ __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
     }
 }
 
+template <int P, int V, int UR, int OPT, bool MASK>
+__global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
+    bwd_body<P, V, UR, OPT, MASK>(A, blockIdx.x);
+}
+
+template <int P, int V, int UR, int OPT, bool MASK>
+__global__ __launch_bounds__(256) void k_bwd_multi(const BwdArgs* __restrict__ As, const int32_t* __restrict__ b0,
+                                                   int32_t n) {
+    const int i = owner(b0, n, blockIdx.x);
+    bwd_body<P, V, UR, OPT, MASK>(As[i], blockIdx.x - b0[i]);
+}
+
 // Heavy variables: combine segment partials in a fixed order that depends on
 // the instance only.  A variable with at most kWideSegs segments uses 64
 // slots (one wavefront): slot q sums segments q, q+64, ... in order, then a
@@ -455,17 +493,16 @@ __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
 // workgroups take one wide (variable, restart) each, the rest take sixteen
 // narrow ones (one per wavefront).
 template <int OPT>
-__global__ __launch_bounds__(1024) void k_combine(BwdArgs A) {
-    __shared__ double su[1024];
+__device__ __forceinline__ void combine_body(const BwdArgs& A, const int bx, double* su) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const Blocking B = A.B;
     const int nwide = A.n_heavy_wide * B.R;
     int h, r;
     double u = 0.0;
-    if ((int)blockIdx.x < nwide) {
-        h = blockIdx.x / B.R;
-        r = blockIdx.x % B.R;
+    if (bx < nwide) {
+        h = bx / B.R;
+        r = bx % B.R;
         const double* sg = A.seg_part + (size_t)(r / B.G) * B.rows_seg * B.G + r % B.G;
         const int p1 = A.seg_first[h + 1];
 #pragma unroll 8
@@ -479,7 +516,7 @@ __global__ __launch_bounds__(1024) void k_combine(BwdArgs A) {
         if (tid != 0) return;
         u = su[0];
     } else {
-        const int w = (blockIdx.x - nwide) * 16 + (tid >> 6);
+        const int w = (bx - nwide) * 16 + (tid >> 6);
         if (w >= (A.n_heavy - A.n_heavy_wide) * B.R) return;
         h = A.n_heavy_wide + w / B.R;
         r = w % B.R;
@@ -495,6 +532,20 @@ __global__ __launch_bounds__(1024) void k_combine(BwdArgs A) {
     var_epilogue<1, OPT>(A, ((size_t)(r / B.G) * B.rows_x + h) * B.G + r % B.G, r, G);
 }
 
+template <int OPT>
+__global__ __launch_bounds__(1024) void k_combine(BwdArgs A) {
+    __shared__ double su[1024];
+    combine_body<OPT>(A, blockIdx.x, su);
+}
+
+template <int OPT>
+__global__ __launch_bounds__(1024) void k_combine_multi(const BwdArgs* __restrict__ As,
+                                                        const int32_t* __restrict__ b0, int32_t n) {
+    __shared__ double su[1024];
+    const int i = owner(b0, n, blockIdx.x);
+    combine_body<OPT>(As[i], blockIdx.x - b0[i], su);
+}
+
 // Count/loss partials are summed in two fixed stages.  Stage 1: block
 // (restart block rb, chunk c) sums units [c * CH, (c + 1) * CH) for 64
 // restarts: lane l of the 256 threads holds restart 64 rb + (l % RP) and slot
@@ -507,16 +558,15 @@ __device__ __forceinline__ int restart_lanes(int R) {
     return RP;
 }
 
-__global__ __launch_bounds__(256) void k_reduce1(ReduceArgs A) {
-    __shared__ int32_t sc[256];
-    __shared__ double sl[256];
+__device__ __forceinline__ void reduce1_body(const ReduceArgs& A, const int bx, const int by, int32_t* sc,
+                                             double* sl) {
     const int tid = threadIdx.x;
     const int RP = restart_lanes(A.R);
     const int NS = 256 / RP;
     const int rloc = tid % RP;
     const int slot = tid / RP;
-    const int r = blockIdx.x * 64 + rloc;
-    const int u0 = blockIdx.y * A.chunk;
+    const int r = bx * 64 + rloc;
+    const int u0 = by * A.chunk;
     const int u1 = min(u0 + A.chunk, A.n_units);
     int32_t c = 0;
     double l = 0.0;
@@ -537,20 +587,36 @@ __global__ __launch_bounds__(256) void k_reduce1(ReduceArgs A) {
         __syncthreads();
     }
     if (slot == 0 && r < A.R) {
-        A.cnt_mid[(size_t)blockIdx.y * A.R + r] = sc[tid];
-        A.loss_mid[(size_t)blockIdx.y * A.R + r] = sl[tid];
+        A.cnt_mid[(size_t)by * A.R + r] = sc[tid];
+        A.loss_mid[(size_t)by * A.R + r] = sl[tid];
     }
 }
 
-__global__ __launch_bounds__(1024) void k_reduce(ReduceArgs A) {
-    __shared__ int64_t sc[1024];
-    __shared__ double sl[1024];
+__global__ __launch_bounds__(256) void k_reduce1(ReduceArgs A) {
+    __shared__ int32_t sc[256];
+    __shared__ double sl[256];
+    reduce1_body(A, blockIdx.x, blockIdx.y, sc, sl);
+}
+
+// Multi-instance stage 1: instance i's grid is ceil(R/64) x n_chunks, flattened.
+__global__ __launch_bounds__(256) void k_reduce1_multi(const ReduceArgs* __restrict__ As,
+                                                       const int32_t* __restrict__ b0, int32_t n) {
+    __shared__ int32_t sc[256];
+    __shared__ double sl[256];
+    const int i = owner(b0, n, blockIdx.x);
+    const ReduceArgs& A = As[i];
+    const int gx = (A.R + 63) / 64;
+    const int lb = blockIdx.x - b0[i];
+    reduce1_body(A, lb % gx, lb / gx, sc, sl);
+}
+
+__device__ __forceinline__ void reduce2_body(const ReduceArgs& A, const int bx, int64_t* sc, double* sl) {
     const int tid = threadIdx.x;
     const int RP = restart_lanes(A.R);
     const int NS = 1024 / RP;
     const int rloc = tid % RP;
     const int slot = tid / RP;
-    const int r = blockIdx.x * 64 + rloc;
+    const int r = bx * 64 + rloc;
     int64_t c = 0;
     double l = 0.0;
     if (r < A.R) {
@@ -583,6 +649,21 @@ __global__ __launch_bounds__(1024) void k_reduce(ReduceArgs A) {
             }
         }
     }
+}
+
+__global__ __launch_bounds__(1024) void k_reduce(ReduceArgs A) {
+    __shared__ int64_t sc[1024];
+    __shared__ double sl[1024];
+    reduce2_body(A, blockIdx.x, sc, sl);
+}
+
+// Multi-instance stage 2: instance i's grid is ceil(R/64).
+__global__ __launch_bounds__(1024) void k_reduce_multi(const ReduceArgs* __restrict__ As,
+                                                       const int32_t* __restrict__ b0, int32_t n) {
+    __shared__ int64_t sc[1024];
+    __shared__ double sl[1024];
+    const int i = owner(b0, n, blockIdx.x);
+    reduce2_body(As[i], blockIdx.x - b0[i], sc, sl);
 }
 
 // Element offset of (row, restart r) in a blocked array with `rows` rows.
@@ -676,6 +757,27 @@ hipError_t fwd_for(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
 }
 
 template <int P, int V, int UR, int MASK>
+hipError_t fwd_multi_for(bool eval, const MultiLaunch& M, hipStream_t s) {
+    if (eval)
+        hipLaunchKernelGGL((k_fwd_multi<P, V, UR, true, MASK != 0>), dim3(M.blocks), dim3(256), 0, s,
+                           static_cast<const FwdArgs*>(M.args), M.b0, M.n);
+    else
+        hipLaunchKernelGGL((k_fwd_multi<P, V, UR, false, MASK != 0>), dim3(M.blocks), dim3(256), 0, s,
+                           static_cast<const FwdArgs*>(M.args), M.b0, M.n);
+    return hipGetLastError();
+}
+
+template <int P, int V, int UR, int MASK>
+hipError_t bwd_multi_for(int opt, const MultiLaunch& M, hipStream_t s) {
+    const BwdArgs* a = static_cast<const BwdArgs*>(M.args);
+    if (opt == kAdam)
+        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kAdam, MASK != 0>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
+    else
+        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kSgd, MASK != 0>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
+    return hipGetLastError();
+}
+
+template <int P, int V, int UR, int MASK>
 hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
     if (opt == kAdam)
         hipLaunchKernelGGL((k_bwd<P, V, UR, kAdam, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
@@ -756,6 +858,42 @@ hipError_t launch_combine(int opt, const BwdArgs& A, hipStream_t s) {
         hipLaunchKernelGGL((k_combine<kSgd>), dim3((int)blocks), dim3(1024), 0, s, A);
     else
         hipLaunchKernelGGL((k_combine<kGrad>), dim3((int)blocks), dim3(1024), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_multi(int sched, bool eval, const MultiLaunch& M, hipStream_t s) {
+    if (M.blocks <= 0) return hipSuccess;
+    HMS_SCHED_SWITCH(fwd_multi_for, eval, M, s)
+}
+
+hipError_t launch_bwd_multi(int sched, int opt, const MultiLaunch& M, hipStream_t s) {
+    if (M.blocks <= 0) return hipSuccess;
+    if (opt != kAdam && opt != kSgd) return hipErrorInvalidValue;
+    HMS_SCHED_SWITCH(bwd_multi_for, opt, M, s)
+}
+
+hipError_t launch_combine_multi(int opt, const MultiLaunch& M, hipStream_t s) {
+    if (M.blocks <= 0) return hipSuccess;
+    const BwdArgs* a = static_cast<const BwdArgs*>(M.args);
+    if (opt == kAdam)
+        hipLaunchKernelGGL((k_combine_multi<kAdam>), dim3(M.blocks), dim3(1024), 0, s, a, M.b0, M.n);
+    else if (opt == kSgd)
+        hipLaunchKernelGGL((k_combine_multi<kSgd>), dim3(M.blocks), dim3(1024), 0, s, a, M.b0, M.n);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_multi(const MultiLaunch& stage1, const MultiLaunch& stage2, hipStream_t s) {
+    const ReduceArgs* a1 = static_cast<const ReduceArgs*>(stage1.args);
+    const ReduceArgs* a2 = static_cast<const ReduceArgs*>(stage2.args);
+    if (stage1.blocks > 0) {
+        hipLaunchKernelGGL(k_reduce1_multi, dim3(stage1.blocks), dim3(256), 0, s, a1, stage1.b0, stage1.n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (stage2.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_multi, dim3(stage2.blocks), dim3(1024), 0, s, a2, stage2.b0, stage2.n);
     return hipGetLastError();
 }
 

@@ -150,6 +150,21 @@ hipError_t launch_fwd(int sched, bool eval, const FwdArgs& A, int blocks, hipStr
 hipError_t launch_bwd(int sched, int opt, const BwdArgs& A, int blocks, hipStream_t s);
 hipError_t launch_combine(int opt, const BwdArgs& A, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& A, hipStream_t s);
+
+// One launch over many instances: `args` is a device array of n argument
+// structs (FwdArgs, BwdArgs or ReduceArgs), instance i owns workgroups
+// [b0[i], b0[i+1]) of a `blocks`-workgroup grid (b0: device, n + 1 entries).
+// Every instance runs exactly what its own launch would.
+struct MultiLaunch {
+    const void* args;
+    const int32_t* b0;
+    int32_t n, blocks;
+};
+hipError_t launch_fwd_multi(int sched, bool eval, const MultiLaunch& M, hipStream_t s);
+hipError_t launch_bwd_multi(int sched, int opt, const MultiLaunch& M, hipStream_t s);
+hipError_t launch_combine_multi(int opt, const MultiLaunch& M, hipStream_t s);
+// Stage 1 (grids ceil(R/64) x n_chunks, flattened) then stage 2 (ceil(R/64)).
+hipError_t launch_reduce_multi(const MultiLaunch& stage1, const MultiLaunch& stage2, hipStream_t s);
 hipError_t launch_init(const InitArgs& A, hipStream_t s);
 hipError_t launch_snapshot(int32_t n_act, const Blocking& B, const float* x, const int32_t* improved,
                            uint8_t* best_a, hipStream_t s);

@@ -4,8 +4,10 @@ Requests (a CNF plus solve parameters) arrive at any time.  A dispatcher admits
 them in arrival order while their estimated device footprint fits the budget;
 worker threads, each with its own HIP stream, build and upload the instance plan
 and solve it, so requests admitted while others are running overlap on the
-device.  Queued requests small enough for the resident solver are taken
-together and solved in one launch (one workgroup per instance and restart).
+device.  Queued requests with the same step count, restart count, counting
+period, optimizer and loss mode are taken together: those small enough for the
+resident solver share one launch (one workgroup per instance and restart), the
+others share one launch per kernel per step (a work queue over their units).
 Every instance's result is bitwise what a solo ``solve`` gives: the kernels'
 summation order depends on the instance only, never on the batch.
 """
@@ -63,7 +65,7 @@ class Server:
     """Admit by footprint, overlap on device, batch the small ones."""
 
     def __init__(self, workers: int = 8, hbm_budget: int | None = None, small_batch: int = 64,
-                 device: int = 0):
+                 tiled_batch: int = 8, device: int = 0):
         import torch
         self._torch = torch
         torch.cuda.set_device(device)
@@ -73,6 +75,9 @@ class Server:
         self.budget = int(hbm_budget)
         self.in_use = 0
         self.small_batch = int(small_batch)
+        # tiled groups stay small: their plans are built on the host by the
+        # worker that takes the group, which is the slow part of a request
+        self.tiled_batch = int(tiled_batch)
         self._queue: collections.deque[Request] = collections.deque()
         self._cv = threading.Condition()
         self._closed = False
@@ -135,18 +140,19 @@ class Server:
                     self._cv.wait()
                 job = [self._queue.popleft()]
                 self.in_use += job[0].footprint
-                if job[0].small:
-                    # take the other queued small requests that fit as well
-                    keep = collections.deque()
-                    while self._queue and len(job) < self.small_batch:
-                        r = self._queue.popleft()
-                        if r.small and self.in_use + r.footprint <= self.budget:
-                            job.append(r)
-                            self.in_use += r.footprint
-                        else:
-                            keep.append(r)
-                    keep.extend(self._queue)
-                    self._queue = keep
+                # take the other queued requests of the same kind that fit as well
+                key = _group_key(job[0])
+                cap = self.small_batch if job[0].small else self.tiled_batch
+                keep = collections.deque()
+                while self._queue and len(job) < cap:
+                    r = self._queue.popleft()
+                    if _group_key(r) == key and self.in_use + r.footprint <= self.budget:
+                        job.append(r)
+                        self.in_use += r.footprint
+                    else:
+                        keep.append(r)
+                keep.extend(self._queue)
+                self._queue = keep
                 now = time.perf_counter()
                 for r in job:
                     r.params["_admitted"] = now
@@ -200,6 +206,16 @@ class Server:
         done = time.perf_counter()
         for r, o in zip(job, outs):
             r.future.set_result(ServeResult(r.rid, o, r.arrival, r.params["_admitted"], done))
+
+
+def _group_key(r: Request):
+    """Requests that can share launches: same resident/tiled kind, steps,
+    restarts, counting period, optimizer and loss mode."""
+    p = r.params
+    if p.get("time_limit_s", 0.0) > 0:
+        return ("alone", r.rid)  # a time limit applies to one solve
+    return (r.small, p.get("steps", 1000), p.get("restarts", 1), p.get("eval_every", 1),
+            p.get("optimizer", _lib.ADAM), p.get("loss_mode", _lib.LOSS_UNSAT))
 
 
 def percentile(xs, q):

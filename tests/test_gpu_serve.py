@@ -57,6 +57,36 @@ def test_solve_batch_equals_solo():
     assert kinds.get(True, 0) > 0 and kinds.get(False, 0) > 0
 
 
+@pytest.mark.parametrize("opt,mode", [(hm.ADAM, hm.LOSS_UNSAT), (hm.SGD, hm.LOSS_ALL)])
+def test_grouped_tiled_batch_equals_solo(opt, mode):
+    """Instances too large for the resident solver, of uneven sizes (some with
+    heavy rows), solved in grouped launches: each result is bitwise the solo
+    result, with per-instance learning rates and seeds."""
+    # the largest has more than 2^21 literals: its automatic schedule differs
+    # from the others', and the group runs them all with the largest's
+    sizes = [(20000, 86000, "u"), (9000, 40000, "s"), (15000, 64000, "u"), (30000, 120000, "s"),
+             (12000, 50000, "u"), (200000, 860000, "u")]
+    cnfs, lrs = [], []
+    for i, (n, m, kind) in enumerate(sizes):
+        lits = (cnfgen.uniform_kcnf(n, m, 3, seed=40 + i) if kind == "u"
+                else cnfgen.structured_cnf(n, m, seed=40 + i))
+        cnfs.append(hm.load_cnf(n, lits))
+        lrs.append((1e-2 if opt == hm.ADAM else 0.5) * (1 + 0.1 * i))
+    assert any(c.info["n_heavy"] > 0 for c in cnfs)
+    # one restart with the masked loss: the largest instance's automatic
+    # schedule (bitset) differs from the others'
+    kw = dict(steps=75, restarts=1 if mode == hm.LOSS_UNSAT else 2, eval_every=7, optimizer=opt, loss_mode=mode)
+    batch = hm.solve_batch(cnfs, seeds=list(range(len(cnfs))), lr=lrs, want_x=True, **kw)
+    for i, (c, b) in enumerate(zip(cnfs, batch)):
+        assert b.status == 0 and b.schedule != 255
+        a = hm.solve(c, seed=i, lr=lrs[i], want_x=True, autotune=False, **kw)
+        _same(a, b)
+        np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32),
+                                      b.x_final.cpu().numpy().view(np.uint32))
+        assert b.steps_done == 75
+    _say(f"grouped batch of {len(cnfs)}: device {batch[0].device_ms:.2f} ms, schedule {batch[0].schedule}")
+
+
 def test_served_equals_solo_and_overlaps():
     from paper_2402_03640_amd.serve import Server
     reqs = _requests(40, seed=2)
