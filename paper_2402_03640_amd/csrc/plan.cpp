@@ -45,6 +45,22 @@ template <typename LenFn, typename EntFn>
 int32_t tile_rows(int32_t nrows, LenFn len_of, EntFn ent_of,
                   uint32_t pad, uint32_t flags, std::vector<TileDesc>& tiles,
                   std::vector<uint32_t>& ent, std::string& err) {
+    {
+        // room for every tile up front (no regrowth)
+        uint64_t total = ent.size();
+        for (int32_t t0 = 0; t0 < nrows; t0 += kTile) {
+            uint32_t len = 0;
+            for (int32_t q = t0; q < std::min<int32_t>(nrows, t0 + kTile); ++q)
+                len = std::max<uint32_t>(len, (uint32_t)len_of(q));
+            total += (uint64_t)len * kTile;
+        }
+        if (total > 0xffffffffull) {
+            err = "instance too large: more than 2^32 padded entries";
+            return kErrTooLarge;
+        }
+        ent.reserve(total);
+        tiles.reserve(tiles.size() + (nrows + kTile - 1) / kTile);
+    }
     for (int32_t t0 = 0; t0 < nrows; t0 += kTile) {
         int32_t nreal = std::min<int32_t>(kTile, nrows - t0);
         uint32_t len = 0;
@@ -112,9 +128,48 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
     std::vector<uint8_t> seen((size_t)n + 1, 0);   // bit0 positive, bit1 negative, bit2 emitted
     int64_t start = 0;
     int32_t j = 0;
+    constexpr int kShort = 16;  // clauses up to this length are deduplicated in registers
     for (int64_t p = 0; p < nlits; ++p) {
         if (lits[p] != 0) continue;
         bool taut = false;
+        if (p - start <= kShort) {
+            // the same rule by pairwise comparison: a variable is emitted at its
+            // first appearance with its sign, unless it also appears negated
+            const int k = (int)(p - start);
+            int32_t v[kShort];
+            uint8_t sg[kShort];
+            for (int q = 0; q < k; ++q) {
+                v[q] = std::abs(lits[start + q]) - 1;
+                sg[q] = lits[start + q] > 0 ? 1 : 2;
+            }
+            const int64_t off = (int64_t)flat.size();
+            for (int q = 0; q < k; ++q) {
+                bool first = true;
+                uint8_t both = sg[q];
+                for (int u = 0; u < k; ++u) {
+                    if (v[u] != v[q]) continue;
+                    if (u < q) first = false;
+                    both |= sg[u];
+                }
+                if (!first) continue;
+                if (both == 3) {
+                    taut = true;
+                    continue;
+                }
+                flat.push_back((uint32_t)v[q] | ((both & 2) ? kSign : 0u));
+            }
+            const int32_t len = (int32_t)((int64_t)flat.size() - off);
+            if (p == start) {
+                P.m_empty++;
+            } else if (taut) {
+                P.m_taut++;
+                if (len == 0) P.m_taut_dropped++;
+            }
+            if (len > 0) rows.push_back(Row{off, len, j, 0, taut});
+            ++j;
+            start = p + 1;
+            continue;
+        }
         for (int64_t q = start; q < p; ++q) {
             int32_t v = std::abs(lits[q]) - 1;
             if (stamp[v] != j) {
@@ -168,6 +223,8 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
         if (P.degree[i] > 0) P.n_act = i + 1;
         if (P.degree[i] > kSeg) P.n_heavy = i + 1;
     }
+    // from here on the flat entries hold the new variable index
+    for (uint32_t& e : flat) e = (uint32_t)P.var_new[e & kIdx] | (e & kSign);
 
     // ---- clause rows: plain rows by length desc, then tautological rows; ---
     // within a length, by the smallest (hottest) new variable index, so that
@@ -175,26 +232,50 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
     // reads neighbouring adjoint entries.
     for (Row& r : rows) {
         int32_t mv = INT32_MAX;
-        for (int32_t c = 0; c < r.len; ++c) mv = std::min(mv, P.var_new[flat[r.off + c] & kIdx]);
+        for (int32_t c = 0; c < r.len; ++c) mv = std::min(mv, (int32_t)(flat[r.off + c] & kIdx));
         r.minvar = mv;
     }
-    // stable two-pass counting sort: by smallest variable, then by (tautology
-    // flag, length descending)
+    // stable two-pass counting sort of row indices: by smallest variable,
+    // then by (tautology flag, length descending); then the rows and their
+    // entries are gathered into that order once, so every later pass reads
+    // them sequentially
     {
-        std::vector<Row> tmp(rows.size());
-        std::vector<int64_t> cnt((size_t)n + 2, 0);
-        for (const Row& r : rows) cnt[(size_t)r.minvar + 1]++;
-        for (int32_t v = 0; v <= n; ++v) cnt[v + 1] += cnt[v];
-        for (const Row& r : rows) tmp[cnt[r.minvar]++] = r;
+        const size_t nr = rows.size();
         int32_t maxl = 0;
-        for (const Row& r : tmp) maxl = std::max(maxl, r.len);
+        for (const Row& r : rows) maxl = std::max(maxl, r.len);
         // bucket b: plain rows of length maxl - b for b <= maxl, then tautologies likewise
         const size_t nb = 2 * ((size_t)maxl + 1);
-        std::vector<int64_t> c2(nb + 1, 0);
-        auto bucket = [&](const Row& r) { return (size_t)(r.taut ? maxl + 1 : 0) + (size_t)(maxl - r.len); };
-        for (const Row& r : tmp) c2[bucket(r) + 1]++;
+        std::vector<uint32_t> bucket_of(nr);
+        std::vector<int64_t> cnt((size_t)n + 2, 0), c2(nb + 1, 0);
+        for (size_t i = 0; i < nr; ++i) {
+            const Row& r = rows[i];
+            bucket_of[i] = (uint32_t)((r.taut ? maxl + 1 : 0) + (maxl - r.len));
+            cnt[(size_t)r.minvar + 1]++;
+            c2[bucket_of[i] + 1]++;
+        }
+        for (int32_t v = 0; v <= n; ++v) cnt[v + 1] += cnt[v];
         for (size_t b = 0; b < nb; ++b) c2[b + 1] += c2[b];
-        for (const Row& r : tmp) rows[c2[bucket(r)]++] = r;
+        std::vector<int32_t> tmp(nr), ord(nr);
+        for (size_t i = 0; i < nr; ++i) tmp[cnt[rows[i].minvar]++] = (int32_t)i;
+        for (int32_t i : tmp) ord[c2[bucket_of[i]]++] = i;
+        std::vector<Row> sorted(nr);
+        std::vector<uint32_t> flat2(flat.size());
+        int64_t o = 0;
+        constexpr size_t kAhead = 16;  // rows fetched ahead of the copy
+        for (size_t r = 0; r < nr; ++r) {
+            if (r + kAhead < nr) {
+                const Row& f = rows[ord[r + kAhead]];
+                __builtin_prefetch(&f);
+                __builtin_prefetch(&flat[f.off]);
+            }
+            Row R = rows[ord[r]];
+            std::memcpy(&flat2[o], &flat[R.off], (size_t)R.len * 4);
+            R.off = o;
+            o += R.len;
+            sorted[r] = R;
+        }
+        rows.swap(sorted);
+        flat.swap(flat2);
     }
     int32_t n_plain = 0;
     while (n_plain < (int32_t)rows.size() && !rows[n_plain].taut) ++n_plain;
@@ -202,18 +283,11 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
     const uint32_t cpad = (uint32_t)n;  // dummy variable whose relaxed value stays -0.0
     int32_t rc;
     rc = tile_rows(n_plain, [&](int32_t r) { return rows[r].len; },
-                   [&](int32_t r, int32_t c) {
-                       uint32_t e = flat[rows[r].off + c];
-                       return (uint32_t)P.var_new[e & kIdx] | (e & kSign);
-                   },
-                   cpad, 0u, P.c_tile, P.c_ent, err);
+                   [&](int32_t r, int32_t c) { return flat[rows[r].off + c]; }, cpad, 0u, P.c_tile, P.c_ent, err);
     if (rc) return rc;
     rc = tile_rows(n_tr, [&](int32_t r) { return rows[n_plain + r].len; },
-                   [&](int32_t r, int32_t c) {
-                       uint32_t e = flat[rows[n_plain + r].off + c];
-                       return (uint32_t)P.var_new[e & kIdx] | (e & kSign);
-                   },
-                   cpad, 1u, P.c_tile, P.c_ent, err);
+                   [&](int32_t r, int32_t c) { return flat[rows[n_plain + r].off + c]; }, cpad, 1u, P.c_tile,
+                   P.c_ent, err);
     if (rc) return rc;
     P.c_tiles = (int32_t)P.c_tile.size();
     if ((int64_t)P.c_tiles * kTile + 1 >= (int64_t)kIdx) {
@@ -236,16 +310,28 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
     for (int32_t i = 0; i < n; ++i) voff[i + 1] = voff[i] + P.degree[i];
     std::vector<uint32_t> occ((size_t)P.nnz);
     {
-        std::vector<int64_t> fill(voff.begin(), voff.end() - 1);
-        // rows are already in increasing kernel-row order
+        // Two passes, each with few write streams: (1) scatter (variable,
+        // kernel row) pairs into blocks of 1024 consecutive variables, (2)
+        // scatter each block into its variables' lists.  Rows are visited in
+        // increasing kernel-row order and both passes are stable, so every
+        // list ends in increasing kernel-row order.
+        constexpr int kShift = 10;
+        const int32_t nblk = (n >> kShift) + 1;
+        std::vector<int64_t> bstart((size_t)nblk + 1, 0);
+        for (int32_t b = 0; b < nblk; ++b)
+            bstart[b + 1] = voff[std::min<int64_t>((int64_t)(b + 1) << kShift, n)];
+        std::vector<uint64_t> pairs((size_t)P.nnz);  // variable << 32 | (row | sign)
+        std::vector<int64_t> bfill(bstart.begin(), bstart.end() - 1);
         for (size_t r = 0; r < rows.size(); ++r) {
             const Row& R = rows[r];
             for (int32_t c = 0; c < R.len; ++c) {
-                uint32_t e = flat[R.off + c];
-                int32_t v = P.var_new[e & kIdx];
-                occ[fill[v]++] = (uint32_t)krow[r] | (e & kSign);
+                const uint32_t e = flat[R.off + c];
+                const uint32_t v = e & kIdx;
+                pairs[bfill[v >> kShift]++] = ((uint64_t)v << 32) | (uint32_t)krow[r] | (e & kSign);
             }
         }
+        std::vector<int64_t> fill(voff.begin(), voff.end() - 1);
+        for (const uint64_t q : pairs) occ[fill[q >> 32]++] = (uint32_t)q;
     }
 
     // ---- segments of heavy variables ---------------------------------------
