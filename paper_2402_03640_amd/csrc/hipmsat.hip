@@ -1137,6 +1137,7 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     };
 
     int32_t done = 0;
+    bool stopped = false;  // the time limit ran out
     // body of B steps (a multiple of K, starting at a multiple of K)
     const int32_t B = graph_body(K);
     if (p->use_graph && T >= 2 * B) {
@@ -1169,16 +1170,16 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
             done += B;
             if (p->time_limit_s > 0) {
                 HIPTRY(hipStreamSynchronize(s));
-                if (over_time()) break;
+                if ((stopped = over_time())) break;
             }
         }
     }
-    while (done < T) {
+    while (done < T && !stopped) {
         HIPTRY(enqueue_step(L, done % K == 0, s));
         ++done;
         if (p->time_limit_s > 0 && done % K == 0) {
             HIPTRY(hipStreamSynchronize(s));
-            if (over_time()) break;
+            stopped = over_time();
         }
     }
     // x_T is always counted

@@ -360,6 +360,24 @@ def test_degenerate_instances():
     assert u[0] == 1
 
 
+def test_time_limit_stops_at_a_counting_boundary():
+    """A wall-clock limit (the paper runs Algorithm 1 under time limits) stops
+    the loop at a K-step boundary; the steps taken are exactly those of a
+    fixed-step solve of the same length (bitwise), and the best is consistent."""
+    n, m = 20000, 86000
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=2)
+    cnf = hm.load_cnf(n, lits)
+    K = 25
+    a = hm.solve(cnf, steps=10 ** 7, restarts=4, eval_every=K, seed=3, lr=1e-2, time_limit_s=0.05, want_x=True)
+    _say(f"time limit: {a.steps_done} steps, best {a.best_cost}")
+    assert 0 < a.steps_done < 10 ** 7 and a.steps_done % K == 0
+    b = hm.solve(cnf, steps=a.steps_done, restarts=4, eval_every=K, seed=3, lr=1e-2, want_x=True)
+    np.testing.assert_array_equal(a.restart_best, b.restart_best)
+    np.testing.assert_array_equal(a.restart_step, b.restart_step)
+    np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32), b.x_final.cpu().numpy().view(np.uint32))
+    assert hm.evaluate(cnf, a.best_assignment) == a.best_cost
+
+
 def test_nonfinite_x0_reported():
     n, lits = 3, np.array([1, 2, 0, -3, 0], np.int32)
     cnf = hm.load_cnf(n, lits)
