@@ -328,7 +328,7 @@ def main():
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-steps", type=int, default=1000)
-    ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--serve-workers", type=int, default=16)
     ap.add_argument("--sweep", action="store_true", help="time every candidate schedule and exit")
     ap.add_argument("--tune-iters", type=int, default=20)
     ap.add_argument("--counters-summary", nargs="*", default=None, metavar="DIR",
