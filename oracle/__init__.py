@@ -64,6 +64,10 @@ def lib():
         L.oracle_solve.restype = I64
         L.oracle_bruteforce.argtypes = [P, P, P, P]
         L.oracle_bruteforce.restype = C.c_int
+        L.oracle_set_weights.argtypes = [P, P]
+        L.oracle_set_weights.restype = C.c_int
+        L.oracle_total_weight.argtypes = [P]
+        L.oracle_total_weight.restype = I64
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = C.c_int
         _lib = L
@@ -83,7 +87,9 @@ class OracleError(RuntimeError):
 class OracleCNF:
     """A canonicalized CNF held by the oracle."""
 
-    def __init__(self, n_vars: int, lits):
+    def __init__(self, n_vars: int, lits, weights=None):
+        """weights: one positive integer per clause (weighted MaxSAT), or None
+        for weight 1 everywhere."""
         self._lits = np.ascontiguousarray(lits, dtype=np.int32)
         h = C.c_void_p()
         rc = lib().oracle_build(int(n_vars), _ptr(self._lits), self._lits.size, C.byref(h))
@@ -92,6 +98,13 @@ class OracleCNF:
         self._h = h
         self.n = lib().oracle_n(h)
         self.m = lib().oracle_m(h)
+        if weights is not None:
+            self._w = np.ascontiguousarray(weights, dtype=np.int64)
+            assert self._w.shape == (self.m,)
+            rc = lib().oracle_set_weights(h, _ptr(self._w))
+            if rc != 0:
+                raise OracleError(rc)
+        self.total_weight = int(lib().oracle_total_weight(h))
 
     def __del__(self):
         h = getattr(self, "_h", None)

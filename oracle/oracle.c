@@ -31,6 +31,11 @@
  *   - Algorithm 1 loop: best_cost starts at m; at every evaluation step the
  *     rounded iterate is counted and kept when strictly better; then one step.
  *   - brute force (n <= 24): Gray-code enumeration of all assignments.
+ *   - clause weights (weighted MaxSAT, which the paper names in Section 3 and
+ *     leaves to future work, Section 7): with positive integer weights w_j the
+ *     cost is the total weight of the unsatisfied clauses, the loss is
+ *     (1/m) sum_j mu_j w_j f_j^2 and the best cost starts at the total weight.
+ *     Without weights every w_j is 1 and every formula above is unchanged.
  *   - SplitMix64 (Steele, Lea, Flood 2014) for the U(-1,1) initial values.
  */
 #include <math.h>
@@ -55,11 +60,13 @@ typedef struct {
     int32_t *wvar;   /* 0-based variable with a nonzero W entry                 */
     int8_t *wcoef;   /* that entry: +1 or -1                                    */
     uint8_t *taut;   /* 1 if the clause holds a variable and its negation       */
+    int64_t *w;      /* clause weights (m), or NULL: every clause weighs 1      */
+    int64_t wtot;    /* total weight (m without weights)                        */
 } ocnf;
 
 void oracle_free(ocnf *c) {
     if (!c) return;
-    free(c->loff); free(c->lit); free(c->woff); free(c->wvar); free(c->wcoef); free(c->taut);
+    free(c->loff); free(c->lit); free(c->woff); free(c->wvar); free(c->wcoef); free(c->taut); free(c->w);
     free(c);
 }
 
@@ -80,7 +87,7 @@ int oracle_build(int32_t n, const int32_t *lits, int64_t nlits, ocnf **out) {
     }
     ocnf *c = (ocnf *)calloc(1, sizeof(ocnf));
     if (!c) return OR_ERR_NOMEM;
-    c->n = n; c->m = (int32_t)m;
+    c->n = n; c->m = (int32_t)m; c->wtot = m;
     c->loff = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
     c->woff = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
     c->lit = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nlits + 1));
@@ -125,6 +132,28 @@ int oracle_build(int32_t n, const int32_t *lits, int64_t nlits, ocnf **out) {
     return OR_OK;
 }
 
+/* Give every clause a weight (m positive integers); NULL restores weight 1. */
+int oracle_set_weights(ocnf *c, const int64_t *w) {
+    free(c->w);
+    c->w = NULL;
+    c->wtot = c->m;
+    if (!w) return OR_OK;
+    int64_t tot = 0;
+    for (int32_t j = 0; j < c->m; ++j) {
+        if (w[j] <= 0 || w[j] > ((int64_t)1 << 53) || tot > INT64_MAX - w[j]) return OR_ERR_ARG;
+        tot += w[j];
+    }
+    c->w = (int64_t *)malloc(sizeof(int64_t) * ((size_t)c->m + 1));
+    if (!c->w) return OR_ERR_NOMEM;
+    memcpy(c->w, w, sizeof(int64_t) * (size_t)c->m);
+    c->wtot = tot;
+    return OR_OK;
+}
+
+int64_t oracle_total_weight(const ocnf *c) { return c->wtot; }
+
+static int64_t weight(const ocnf *c, int32_t j) { return c->w ? c->w[j] : 1; }
+
 static int lit_false(int32_t l, const uint8_t *a) {
     int32_t v = abs(l) - 1;
     return l > 0 ? (a[v] == 0) : (a[v] == 1);
@@ -138,10 +167,11 @@ static int clause_unsat(const ocnf *c, int32_t j, const uint8_t *a) {
     return 1; /* includes the empty clause */
 }
 
-/* Number of unsatisfied clauses of assignment a (n bytes, 0/1). */
+/* Cost of assignment a (n bytes, 0/1): the number of unsatisfied clauses,
+ * or their total weight. */
 int64_t oracle_count(const ocnf *c, const uint8_t *a) {
     int64_t u = 0;
-    for (int32_t j = 0; j < c->m; ++j) u += clause_unsat(c, j, a);
+    for (int32_t j = 0; j < c->m; ++j) u += weight(c, j) * clause_unsat(c, j, a);
     return u;
 }
 
@@ -175,12 +205,13 @@ double oracle_loss_grad_d(const ocnf *c, const double *x, int mode, double *f_ou
         for (int64_t r = c->woff[j]; r < c->woff[j + 1]; ++r)
             fj += (double)c->wcoef[r] * t[c->wvar[r]];
         int un = clause_unsat(c, j, a);
-        u += un;
+        double wj = (double)weight(c, j);
+        u += weight(c, j) * un;
         double mu = mode == 1 ? 1.0 : (double)un;
         if (f_out) f_out[j] = fj;
         if (mu_out) mu_out[j] = (uint8_t)(mu != 0.0);
-        loss += mu * fj * fj;
-        double aj = m > 0 ? 2.0 / (double)m * mu * fj : 0.0;
+        loss += wj * mu * fj * fj;
+        double aj = m > 0 ? 2.0 / (double)m * mu * wj * fj : 0.0;
         for (int64_t r = c->woff[j]; r < c->woff[j + 1]; ++r)
             G[c->wvar[r]] += (double)c->wcoef[r] * aj;
     }
@@ -253,7 +284,7 @@ int64_t oracle_solve(const ocnf *c, int32_t T, int32_t R, int32_t K, uint64_t se
                      const float *x0, int32_t threads, int64_t *restart_best,
                      int32_t *restart_step, double *final_loss, uint8_t *best_assign,
                      int32_t *best_restart, double *x_out) {
-    int32_t n = c->n, m = c->m;
+    int32_t n = c->n;
     if (R <= 0 || T < 0 || K <= 0) return -1;
     float *xi = (float *)malloc(sizeof(float) * ((size_t)n * R + 1));
     if (x0) memcpy(xi, x0, sizeof(float) * (size_t)n * R);
@@ -273,7 +304,7 @@ int64_t oracle_solve(const ocnf *c, int32_t T, int32_t R, int32_t K, uint64_t se
         uint8_t *a = (uint8_t *)malloc((size_t)n + 1);
         uint8_t *best_a = ra + (size_t)r * n;
         for (int32_t i = 0; i < n; ++i) x[i] = (double)xi[(int64_t)i * R + r];
-        int64_t best = m;
+        int64_t best = c->wtot;  /* every clause unsatisfied */
         int32_t best_step = -1;
         for (int32_t i = 0; i < n; ++i) best_a[i] = (uint8_t)(x[i] > 0.0);
         for (int32_t t = 0; t <= T; ++t) {
@@ -337,7 +368,7 @@ int oracle_bruteforce(const ocnf *c, int64_t *opt, int64_t *n_opt, uint8_t *arg)
     for (int32_t j = 0; j < m; ++j) {
         for (int64_t r = c->loff[j]; r < c->loff[j + 1]; ++r)
             if (!lit_false(c->lit[r], a)) ntrue[j]++;
-        if (!c->taut[j] && ntrue[j] == 0) u++;
+        if (!c->taut[j] && ntrue[j] == 0) u += weight(c, j);
     }
     int64_t best = u, nb = 1;
     if (arg) memcpy(arg, a, (size_t)n);
@@ -352,8 +383,8 @@ int oracle_bruteforce(const ocnf *c, int64_t *opt, int64_t *n_opt, uint8_t *arg)
             int before = ntrue[j];
             ntrue[j] += now_true ? 1 : -1;
             if (c->taut[j]) continue;
-            if (before == 0 && ntrue[j] > 0) u--;
-            else if (before > 0 && ntrue[j] == 0) u++;
+            if (before == 0 && ntrue[j] > 0) u -= weight(c, j);
+            else if (before > 0 && ntrue[j] == 0) u += weight(c, j);
         }
         if (u < best) {
             best = u; nb = 1;

@@ -421,3 +421,123 @@ def test_solve_x0_and_best_monotone():
         cur = c.solve(steps=T, restarts=1, eval_every=5, seed=7, lr=0.05)["best_cost"]
         assert cur <= prev
         prev = cur
+
+
+# ---- clause weights (weighted MaxSAT: the problem of Section 3 with weights;
+# the paper leaves it to future work, so the reading is ours: cost = total
+# weight of the unsatisfied clauses, loss = (1/m) sum mu_j w_j f_j^2) --------
+
+def _weighted_cost_direct(n, clauses, weights, assign):
+    """Total weight of the unsatisfied clauses, straight from the clause lists."""
+    tot = 0
+    for cl, w in zip(clauses, weights):
+        lits = set(cl)
+        if any(-l in lits for l in lits):
+            continue  # complementary pair: always satisfied
+        if not any((assign[abs(l) - 1] == 1) == (l > 0) for l in lits):
+            tot += w
+    return tot
+
+
+def test_unit_weights_equal_unweighted():
+    n, m, R = 300, 1300, 3
+    lits = cnfgen.mixed_kcnf(n, m, seed=8)
+    a, b = O.OracleCNF(n, lits), O.OracleCNF(n, lits, weights=np.ones(m, np.int64))
+    x = cnfgen.random_x(n, R, seed=9, specials=True)
+    for mode in (O.UNSAT, O.ALL):
+        ra, rb = a.loss_grad(x, mode, want_f=True), b.loss_grad(x, mode, want_f=True)
+        for u, v in zip(ra, rb):
+            np.testing.assert_array_equal(u, v)
+    sa = a.solve(steps=40, restarts=2, eval_every=3, seed=1, lr=1e-2, want_x=True)
+    sb = b.solve(steps=40, restarts=2, eval_every=3, seed=1, lr=1e-2, want_x=True)
+    np.testing.assert_array_equal(sa["restart_best"], sb["restart_best"])
+    np.testing.assert_array_equal(sa["x"], sb["x"])
+    assert a.total_weight == b.total_weight == m
+
+
+def test_weight_equals_repeated_clause():
+    """A clause of weight c is the same clause written c times: equal cost,
+    and equal loss and gradient once each is multiplied by its own m."""
+    rng = np.random.default_rng(3)
+    n, m = 40, 150
+    clauses = cnfgen.to_clauses(cnfgen.mixed_kcnf(n, m, seed=3))
+    w = rng.integers(1, 5, size=m)
+    rep = [cl for cl, c in zip(clauses, w) for _ in range(int(c))]
+    ow = O.OracleCNF(n, cnfgen.from_clauses(clauses), weights=w)
+    orp = O.OracleCNF(n, cnfgen.from_clauses(rep))
+    assert ow.total_weight == orp.m == int(w.sum())
+    x = cnfgen.random_x(n, 4, seed=4, lo=-2, hi=2)
+    for mode in (O.UNSAT, O.ALL):
+        lw, gw, uw = ow.loss_grad(x, mode)
+        lr_, gr, ur = orp.loss_grad(x, mode)
+        np.testing.assert_array_equal(uw, ur)
+        np.testing.assert_allclose(lw * ow.m, lr_ * orp.m, rtol=1e-12)
+        np.testing.assert_allclose(gw * ow.m, gr * orp.m, rtol=1e-12, atol=1e-15)
+    for _ in range(20):
+        a = rng.integers(0, 2, size=n).astype(np.uint8)
+        assert ow.count(a) == orp.count(a)
+
+
+def test_weight_scaling_by_a_power_of_two_is_exact():
+    n, m = 200, 860
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=5)
+    w = np.random.default_rng(5).integers(1, 100, size=m)
+    a, b = O.OracleCNF(n, lits, weights=w), O.OracleCNF(n, lits, weights=4 * w)
+    x = cnfgen.random_x(n, 2, seed=6)
+    for mode in (O.UNSAT, O.ALL):
+        la, ga, ua = a.loss_grad(x, mode)
+        lb, gb, ub = b.loss_grad(x, mode)
+        np.testing.assert_array_equal(4 * la, lb)
+        np.testing.assert_array_equal(4 * ga, gb)
+        np.testing.assert_array_equal(4 * ua, ub)
+    assert b.total_weight == 4 * a.total_weight
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_weighted_bruteforce_matches_direct_enumeration(seed):
+    rng = np.random.default_rng(seed)
+    n = 9
+    clauses = []
+    for _ in range(30):
+        k = int(rng.integers(0, 5))
+        clauses.append([int(v) * (1 if rng.random() < 0.5 else -1) for v in rng.integers(1, n + 1, size=k)])
+    w = rng.integers(1, 1000, size=len(clauses))
+    oc = O.OracleCNF(n, cnfgen.from_clauses(clauses), weights=w)
+    best, n_opt = None, 0
+    for code in range(1 << n):
+        a = np.array([(code >> i) & 1 for i in range(n)], dtype=np.uint8)
+        c = _weighted_cost_direct(n, clauses, w, a)
+        assert oc.count(a) == c
+        if best is None or c < best:
+            best, n_opt = c, 1
+        elif c == best:
+            n_opt += 1
+    opt, cnt, arg = oc.bruteforce()
+    assert (opt, cnt) == (best, n_opt)
+    assert oc.count(arg) == opt
+
+
+def test_hard_clauses_kept_at_the_optimum():
+    """Partial MaxSAT as large weights: a satisfiable hard part (planted) with
+    weight above the total soft weight is never violated at the optimum."""
+    n = 12
+    hard = cnfgen.to_clauses(cnfgen.planted_kcnf(n, 40, 3, seed=7)[0])
+    rng = np.random.default_rng(7)
+    soft = [[int(v) * (1 if rng.random() < 0.5 else -1)] for v in rng.integers(1, n + 1, size=20)]
+    top = len(soft) * 10 + 1
+    w = [top] * len(hard) + [int(x) for x in rng.integers(1, 11, size=len(soft))]
+    oc = O.OracleCNF(n, cnfgen.from_clauses(hard + soft), weights=w)
+    opt, _, arg = oc.bruteforce()
+    assert opt < top
+    assert O.OracleCNF(n, cnfgen.from_clauses(hard)).count(arg) == 0
+
+
+def test_weighted_solve_invariants():
+    n, m = 100, 430
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=11)
+    w = np.random.default_rng(11).integers(1, 20, size=m)
+    oc = O.OracleCNF(n, lits, weights=w)
+    out = oc.solve(steps=100, restarts=3, eval_every=5, seed=2, lr=5e-2)
+    assert 0 <= out["best_cost"] <= oc.total_weight
+    assert oc.count(out["best_assignment"]) == out["best_cost"]
+    assert min(out["restart_best"]) == out["best_cost"]
