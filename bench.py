@@ -29,9 +29,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(n, m, L, R):
+def kernel_bytes(n, m, L, R, weighted=False):
     """Algorithmic bytes per launch (index arrays once, state per restart)."""
     fwd = 4 * L + 4 * (m + 1) + R * (4 * n + 4 * m)      # literals, offsets, x gather, a write
+    if weighted:
+        fwd += 8 * m                                     # clause weights, once
     bwd = 4 * L + 4 * (n + 1) + R * (4 * m + 24 * n)     # occurrences, offsets, a gather, x/m/v r+w
     return fwd, bwd
 
@@ -115,7 +117,7 @@ def counters_summary(dirs):
         import paper_2402_03640_amd as hm
         wl = make_workload(config)
         L = int(hm.Plan(wl["n"], wl["lits"]).nnz)  # canonical literal count (host-only plan)
-        fb, bb = kernel_bytes(wl["n"], wl["m"], L, wl["R"])
+        fb, bb = kernel_bytes(wl["n"], wl["m"], L, wl["R"], wl["weights"] is not None)
         fcopy, fper = ctr["FETCH_SIZE"]
         wcopy, wper = ctr["WRITE_SIZE"]
         ff = copy_bytes / (fcopy * 1024) if fcopy else None
@@ -181,11 +183,18 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
 
 
 def make_workload(name):
+    import numpy as np
+
     import cnfgen
     if name == "cfg2":
         n, m, R, T, K = 20000, 86000, 64, 2000, 50
         lits = cnfgen.uniform_kcnf(n, m, 3, seed=2)
         desc = ("uniform random 3-CNF n=20000 m=86000 (ratio 4.3), 64 restarts in one solve, "
+                "2000 Adam steps lr 1e-4, round+count every 50")
+    elif name == "cfg2-weighted":
+        n, m, R, T, K = 20000, 86000, 64, 2000, 50
+        lits = cnfgen.uniform_kcnf(n, m, 3, seed=2)
+        desc = ("weighted MaxSAT: the uniform 3-CNF n=20000 m=86000 with clause weights U{1..100}, 64 restarts, "
                 "2000 Adam steps lr 1e-4, round+count every 50")
     elif name == "cfg2-plain":
         n, m, R, T, K = 20000, 86000, 1, 2000, 50
@@ -206,7 +215,10 @@ def make_workload(name):
         desc = "mixed 2/3/4-CNF n=1000 m=4200, 16 restarts, 1000 Adam steps, K=1"
     else:
         raise SystemExit(f"unknown config {name}")
-    return dict(name=name, n=n, m=m, R=R, T=T, K=K, lits=lits, desc=desc)
+    weights = None
+    if name.endswith("-weighted"):
+        weights = np.random.default_rng(20).integers(1, 101, size=m).astype(np.int64)
+    return dict(name=name, n=n, m=m, R=R, T=T, K=K, lits=lits, desc=desc, weights=weights)
 
 
 def cpu_baseline(wl, L, max_threads=16, sample_steps=None, min_wall=2.0):
@@ -216,7 +228,7 @@ def cpu_baseline(wl, L, max_threads=16, sample_steps=None, min_wall=2.0):
     import oracle as O
     oracle_lib = O.build(force=False)
     del oracle_lib
-    oc = O.OracleCNF(wl["n"], wl["lits"])
+    oc = O.OracleCNF(wl["n"], wl["lits"], weights=wl["weights"])
     R = wl["R"]
     threads = max(1, min(os.cpu_count() or 1, max_threads, R))  # OpenMP over restarts
     if sample_steps is None:
@@ -358,7 +370,7 @@ def main():
     wl = make_workload(args.config)
     log(f"[bench] workload {wl['name']}: {wl['desc']}")
     t0 = time.perf_counter()
-    cnf = hm.load_cnf(wl["n"], wl["lits"])
+    cnf = hm.load_cnf(wl["n"], wl["lits"], weights=wl["weights"])
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
     L = cnf.info["nnz"]
@@ -382,7 +394,7 @@ def main():
         dst.copy_(src)  # calibration: 256 MiB read, 256 MiB written
         torch.cuda.synchronize()
         f, b, st = hm.time_kernels(cnf, restarts=R, iters=args.kernel_iters, lr=1e-4, schedule=code)
-        fb, bb = kernel_bytes(n, m, L, R)
+        fb, bb = kernel_bytes(n, m, L, R, wl['weights'] is not None)
         print(json.dumps({"config": wl["name"], "schedule": code, "fwd_us": f * 1e3, "bwd_us": b * 1e3,
                           "step_us": st * 1e3, "fwd_bytes": fb, "bwd_bytes": bb,
                           "kernel_iters": args.kernel_iters, "calibration_copy_bytes": 2 * 4 * src.numel()}),
@@ -408,7 +420,7 @@ def main():
 
     fwd_ms, bwd_ms, step_ms = hm.time_kernels(cnf, restarts=R, iters=args.kernel_iters, lr=1e-4,
                                               schedule=code)
-    fb, bb = kernel_bytes(n, m, L, R)
+    fb, bb = kernel_bytes(n, m, L, R, wl['weights'] is not None)
     log(f"[bench] kernels: fwd {fwd_ms*1e3:.2f} us, bwd {bwd_ms*1e3:.2f} us, step {step_ms*1e3:.2f} us")
     if fwd_ms <= 0 or bwd_ms <= 0:
         # resident schedule: the whole loop is one launch with the state in LDS;

@@ -66,6 +66,8 @@ typedef struct {
     int32_t n_heavy;        /* variables whose transposed row is split into segments */
     int64_t struct_bytes;   /* device bytes held by the handle */
     int64_t state_bytes_r1; /* device bytes of solver state per restart */
+    int32_t weighted;       /* 1 if the clauses carry weights */
+    int64_t total_weight;   /* total clause weight (n_clauses without weights) */
 } hms_cnf_info;
 
 /*
@@ -83,7 +85,24 @@ typedef struct {
 hms_status hms_load_cnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, void* stream,
                         hms_cnf** out);
 
-/* Same, from a DIMACS .cnf file ("p cnf n m" header, "c" comments). */
+/*
+ * Weighted MaxSAT (the problem of Section 3 with clause weights; the paper
+ * leaves weights to future work, Section 7, so the loss is our reading):
+ * clause j has weight weights[j] > 0 (HOST, one per clause, at most 2^53,
+ * total below 2^63).  The cost of an assignment is the total weight of its
+ * unsatisfied clauses, the loss is (1/m) sum_j mu_j w_j f_j^2, and the best
+ * cost starts at the total weight.  Hard clauses (partial MaxSAT) are clauses
+ * whose weight exceeds the total soft weight.  With weights all 1 every
+ * result equals the unweighted one bit for bit.  Otherwise as hms_load_cnf;
+ * HMS_ERR_ARG for a weight out of range.
+ */
+hms_status hms_load_wcnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, const int64_t* weights, void* stream,
+                         hms_cnf** out);
+
+/* Same, from a DIMACS file ("c" comments): "p cnf n m" (unweighted); "p wcnf
+ * n m top" (each clause led by its weight, kept as given); or no header with
+ * each clause led by its weight or by "h" (hard: weight 1 + total soft
+ * weight).  Clauses end with 0 and may span lines. */
 hms_status hms_load_cnf_dimacs(const char* path, void* stream, hms_cnf** out);
 
 /* Sizes of a loaded instance. */

@@ -40,7 +40,7 @@ class CnfInfo(C.Structure):
     _fields_ = [("n_vars", C.c_int32), ("n_clauses", C.c_int32), ("n_lits", C.c_int64),
                 ("nnz", C.c_int64), ("n_empty", C.c_int32), ("n_taut", C.c_int32),
                 ("n_active", C.c_int32), ("n_heavy", C.c_int32), ("struct_bytes", C.c_int64),
-                ("state_bytes_r1", C.c_int64)]
+                ("state_bytes_r1", C.c_int64), ("weighted", C.c_int32), ("total_weight", C.c_int64)]
 
 
 class SolveParams(C.Structure):
@@ -75,7 +75,7 @@ EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_
            "hms_solve_params_default", "hms_solve", "hms_evaluate", "hms_eval_relaxed",
            "hms_last_error", "hms_version", "hms_plan_view_build", "hms_plan_view_free",
            "hms_time_kernels", "hms_tune", "hms_adjoint_bytes", "hms_forward", "hms_backward",
-           "hms_solve_batch", "hms_tune_candidates"]
+           "hms_solve_batch", "hms_tune_candidates", "hms_load_wcnf"]
 
 _lib = None
 
@@ -96,6 +96,7 @@ def lib():
     P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
     L.hms_load_cnf.argtypes = [I32, P, I64, P, C.POINTER(P)]
     L.hms_load_cnf_dimacs.argtypes = [C.c_char_p, P, C.POINTER(P)]
+    L.hms_load_wcnf.argtypes = [I32, P, I64, P, P, C.POINTER(P)]
     L.hms_cnf_info_get.argtypes = [P, C.POINTER(CnfInfo)]
     L.hms_free_cnf.argtypes = [P]
     L.hms_free_cnf.restype = None
@@ -118,7 +119,7 @@ def lib():
     L.hms_plan_view_free.argtypes = [C.POINTER(PlanView)]
     L.hms_plan_view_free.restype = None
     L.hms_tune_candidates.argtypes = [I32, I32, P, I32, P]
-    for name in ("hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_solve",
+    for name in ("hms_load_cnf", "hms_load_wcnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_solve",
                  "hms_evaluate", "hms_eval_relaxed", "hms_plan_view_build", "hms_time_kernels", "hms_tune", "hms_adjoint_bytes",
                  "hms_forward", "hms_backward", "hms_solve_batch", "hms_tune_candidates"):
         getattr(L, name).restype = I32
@@ -178,12 +179,18 @@ class Cnf:
         self.free()
 
 
-def load_cnf(n_vars: int, lits, stream=None) -> Cnf:
-    """Load a DIMACS-style flat literal array (clauses ended by 0)."""
+def load_cnf(n_vars: int, lits, stream=None, weights=None) -> Cnf:
+    """Load a DIMACS-style flat literal array (clauses ended by 0); `weights`
+    (one positive integer per clause) makes it a weighted MaxSAT instance."""
     a = _lits(lits)
     h = C.c_void_p()
-    _check(lib().hms_load_cnf(int(n_vars), a.ctypes.data_as(C.c_void_p), a.size,
-                              _stream_ptr(stream), C.byref(h)))
+    if weights is None:
+        _check(lib().hms_load_cnf(int(n_vars), a.ctypes.data_as(C.c_void_p), a.size,
+                                  _stream_ptr(stream), C.byref(h)))
+    else:
+        w = np.ascontiguousarray(weights, dtype=np.int64)
+        _check(lib().hms_load_wcnf(int(n_vars), a.ctypes.data_as(C.c_void_p), a.size,
+                                   w.ctypes.data_as(C.c_void_p), _stream_ptr(stream), C.byref(h)))
     return Cnf(h)
 
 

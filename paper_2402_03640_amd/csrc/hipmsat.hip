@@ -29,6 +29,7 @@ struct hms_cnf {
     int32_t* seg_first = nullptr;
     int32_t* seg_row = nullptr;
     int32_t* var_old = nullptr;
+    int64_t* c_w = nullptr;  // clause-row weights (weighted instances only)
     int64_t struct_bytes = 0;
     // autotuned schedule per (restarts, optimizer, loss mode); results do not
     // depend on the schedule, only the speed does
@@ -175,14 +176,14 @@ hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_m
 struct State {
     float *x, *m, *v, *t, *a, *g;
     double* seg_part;
-    int32_t* cnt_part;
+    int64_t* cnt_part;
     double* loss_part;
     uint8_t* best_a;
     uint32_t* umask;
     int64_t *best, *cur_count;
     int32_t *best_step, *improved;
     double* cur_loss;
-    int32_t* cnt_mid;
+    int64_t* cnt_mid;
     double* loss_mid;
     hms::StepState* st;
     uint8_t* out_assign;
@@ -209,7 +210,7 @@ void layout_state(const hms::HostPlan& P, const Shape& sh, bool moments, bool gr
     off[kOffA] = L.add((size_t)sh.B.rows_a * Rp * 4);
     off[kOffG] = grad ? L.add(nR * 4) : 0;
     off[kOffSeg] = L.add((size_t)sh.B.rows_seg * Rp * 8);
-    off[kOffCnt] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 4);
+    off[kOffCnt] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 8);
     off[kOffLoss] = L.add((size_t)std::max<int64_t>(sh.n_tc, 1) * R * 8);
     off[kOffBest] = best ? L.add(nR) : 0;
     off[kOffMask] = L.add((size_t)umask_words(P) * sh.B.RG * 4);
@@ -218,7 +219,7 @@ void layout_state(const hms::HostPlan& P, const Shape& sh, bool moments, bool gr
     off[kOffBestS] = L.add((size_t)R * 4);
     off[kOffImp] = L.add((size_t)R * 4);
     off[kOffCurL] = L.add((size_t)R * 8);
-    off[kOffCntMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc), 1) * R * 4);
+    off[kOffCntMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc), 1) * R * 8);
     off[kOffLossMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc), 1) * R * 8);
     off[kOffSt] = L.add(256 + (size_t)std::max(P.n, 1));  // step state, then out_assign at +256
 }
@@ -232,7 +233,7 @@ State bind_state(const Arena& A, const size_t off[kOffN], bool moments, bool gra
     S.a = A.at<float>(off[kOffA]);
     S.g = grad ? A.at<float>(off[kOffG]) : nullptr;
     S.seg_part = A.at<double>(off[kOffSeg]);
-    S.cnt_part = A.at<int32_t>(off[kOffCnt]);
+    S.cnt_part = A.at<int64_t>(off[kOffCnt]);
     S.loss_part = A.at<double>(off[kOffLoss]);
     S.best_a = best ? A.at<uint8_t>(off[kOffBest]) : nullptr;
     S.umask = A.at<uint32_t>(off[kOffMask]);
@@ -241,7 +242,7 @@ State bind_state(const Arena& A, const size_t off[kOffN], bool moments, bool gra
     S.best_step = A.at<int32_t>(off[kOffBestS]);
     S.improved = A.at<int32_t>(off[kOffImp]);
     S.cur_loss = A.at<double>(off[kOffCurL]);
-    S.cnt_mid = A.at<int32_t>(off[kOffCntMid]);
+    S.cnt_mid = A.at<int64_t>(off[kOffCntMid]);
     S.loss_mid = A.at<double>(off[kOffLossMid]);
     S.st = A.at<hms::StepState>(off[kOffSt]);
     S.out_assign = A.at<uint8_t>(off[kOffSt] + 256);
@@ -255,6 +256,7 @@ hms::InitArgs make_init(const hms_cnf* C, const Shape& sh, const State& S) {
     ia.m = P.m;
     ia.a_zero_row = P.a_zero_row();
     ia.umask_words = umask_words(P) * sh.B.RG;
+    ia.best0 = P.w_total;
     ia.B = sh.B;
     ia.var_old = C->var_old;
     ia.x = S.x;
@@ -300,6 +302,7 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     f.a = S.a;
     f.umask = S.umask;
     f.umask_words = umask_words(P);
+    f.w = C->c_w;
     f.two_over_m = P.m > 0 ? (float)(2.0 / (double)P.m) : 0.0f;
     f.cnt_part = S.cnt_part;
     f.loss_part = S.loss_part;
@@ -350,7 +353,7 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     r.loss_mid = S.loss_mid;
     r.R = sh.B.R;
     r.track = 1;
-    r.n_empty = P.m_empty;
+    r.n_empty = P.w_empty;
     r.inv_m = P.m > 0 ? 1.0 / (double)P.m : 0.0;
     r.cur_count = S.cur_count;
     r.cur_loss = S.cur_loss;
@@ -406,6 +409,7 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     size_t o_sf = L.add(P.seg_first.size() * 4);
     size_t o_sr = L.add(P.seg_row.size() * 4);
     size_t o_vo = L.add(P.var_old.size() * 4);
+    size_t o_w = L.add(P.c_w.size() * 8);
     void* base = nullptr;
     hipError_t e = hipMalloc(&base, std::max<size_t>(L.off, 256));
     if (e != hipSuccess) {
@@ -422,6 +426,7 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     C->seg_first = (int32_t*)(b + o_sf);
     C->seg_row = (int32_t*)(b + o_sr);
     C->var_old = (int32_t*)(b + o_vo);
+    C->c_w = P.c_w.empty() ? nullptr : (int64_t*)(b + o_w);
     C->struct_bytes = (int64_t)L.off;
     hms_status r = HMS_OK;
     if (!r) r = upload(P.c_tile, C->c_tile, s);
@@ -431,6 +436,7 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     if (!r) r = upload(P.seg_first, C->seg_first, s);
     if (!r) r = upload(P.seg_row, C->seg_row, s);
     if (!r) r = upload(P.var_old, C->var_old, s);
+    if (!r) r = upload(P.c_w, C->c_w, s);
     if (!r) {
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) r = fail(HMS_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
@@ -451,15 +457,20 @@ const char* hms_last_error(void) { return g_err.c_str(); }
 
 const char* hms_version(void) { return "hipmsat 0.1 (gfx950)"; }
 
-hms_status hms_load_cnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, void* stream, hms_cnf** out) {
+hms_status hms_load_wcnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, const int64_t* weights, void* stream,
+                         hms_cnf** out) {
     g_err.clear();
     if (!out) return fail(HMS_ERR_ARG, "null output pointer");
     *out = nullptr;
     hms::HostPlan plan;
     std::string err;
-    int32_t rc = hms::build_plan(n_vars, lits, n_lits, plan, err);
+    int32_t rc = hms::build_plan(n_vars, lits, n_lits, weights, plan, err);
     if (rc) return fail(rc, err);
     return load_plan(std::move(plan), stream, out);
+}
+
+hms_status hms_load_cnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, void* stream, hms_cnf** out) {
+    return hms_load_wcnf(n_vars, lits, n_lits, nullptr, stream, out);
 }
 
 hms_status hms_load_cnf_dimacs(const char* path, void* stream, hms_cnf** out) {
@@ -468,10 +479,12 @@ hms_status hms_load_cnf_dimacs(const char* path, void* stream, hms_cnf** out) {
     *out = nullptr;
     int32_t n = 0;
     std::vector<int32_t> lits;
+    std::vector<int64_t> weights;
     std::string err;
-    int32_t rc = hms::read_dimacs(path, n, lits, err);
+    int32_t rc = hms::read_dimacs(path, n, lits, weights, err);
     if (rc) return fail(rc, err);
-    return hms_load_cnf(n, lits.data(), (int64_t)lits.size(), stream, out);
+    return hms_load_wcnf(n, lits.data(), (int64_t)lits.size(), weights.empty() ? nullptr : weights.data(), stream,
+                         out);
 }
 
 void hms_free_cnf(hms_cnf* cnf) {
@@ -498,6 +511,8 @@ hms_status hms_cnf_info_get(const hms_cnf* cnf, hms_cnf_info* out) {
     out->struct_bytes = cnf->struct_bytes;
     // x, m, v, t, best bytes, a, heavy partials per restart
     out->state_bytes_r1 = (int64_t)(P.n + 1) * 16 + P.n + (int64_t)P.a_rows() * 4 + (int64_t)P.seg_rows * 8;
+    out->weighted = P.weighted ? 1 : 0;
+    out->total_weight = P.w_total;
     return HMS_OK;
 }
 
@@ -793,7 +808,9 @@ hms::SmallDesc make_desc(const hms_cnf* cnf, const hms_solve_params* p) {
     D.v_tiles = P.v_tiles;
     D.seg_tiles = P.seg_tiles;
     D.seg_rows = P.seg_rows;
-    D.n_empty = P.m_empty;
+    D.w_empty = P.w_empty;
+    D.best0 = P.w_total;
+    D.c_w = cnf->c_w;
     D.c_ent_len = (int32_t)P.c_ent.size();
     D.v_ent_len = (int32_t)P.v_ent.size();
     hms::small_lds_total(P, lds_limit(cnf->device), &D.stage);
@@ -1619,7 +1636,7 @@ hms_status hms_plan_view_build(int32_t n_vars, const int32_t* lits, int64_t n_li
     hms::HostPlan* P = new (std::nothrow) hms::HostPlan();
     if (!P) return fail(HMS_ERR_NOMEM, "host allocation failed");
     std::string err;
-    int32_t rc = hms::build_plan(n_vars, lits, n_lits, *P, err);
+    int32_t rc = hms::build_plan(n_vars, lits, n_lits, nullptr, *P, err);
     if (rc) {
         delete P;
         return fail(rc, err);

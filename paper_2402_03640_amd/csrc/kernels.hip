@@ -145,7 +145,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& A, const int bx) {
     const float* tg = A.t + (size_t)rg * B.rows_x * B.G;
     float* ag = A.a + (size_t)rg * B.rows_a * B.G;
     const int passes = A.U / (W * UR);
-    int cnt[V];
+    int64_t cnt[V];
     double los[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) {
@@ -222,17 +222,22 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& A, const int bx) {
 #pragma unroll
         for (int j = 0; j < UR; ++j) {
             const bool real = ract && rowin0 + j < (int)d.nreal;
+            // clause weight: a_j = (2/m) mu_j w_j f_j, cost and loss weighted
+            // (w = 1 leaves every value bitwise unchanged)
+            int64_t wj = 1;
+            if (A.w != nullptr && real) wj = A.w[(size_t)tile * kTile + rowin0 + j];
+            const float wf = (float)wj;
             VecF<V> av;
             bool any_mu = false;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
                 const bool unsat = real && !taut && (allf[j][k] >> 31) != 0;
                 const bool mu = real && (A.all_mode ? true : unsat);
-                av.v[k] = mu ? f[j][k] * A.two_over_m : 0.0f;
+                av.v[k] = mu ? (f[j][k] * wf) * A.two_over_m : 0.0f;
                 any_mu = any_mu || mu;
                 if (EVAL) {
-                    cnt[k] += unsat ? 1 : 0;
-                    los[k] += mu ? (double)f[j][k] * (double)f[j][k] : 0.0;
+                    cnt[k] += unsat ? wj : 0;
+                    los[k] += mu ? ((double)f[j][k] * (double)f[j][k]) * (double)wj : 0.0;
                 }
             }
             if constexpr (MASK) {
@@ -558,7 +563,7 @@ __device__ __forceinline__ int restart_lanes(int R) {
     return RP;
 }
 
-__device__ __forceinline__ void reduce1_body(const ReduceArgs& A, const int bx, const int by, int32_t* sc,
+__device__ __forceinline__ void reduce1_body(const ReduceArgs& A, const int bx, const int by, int64_t* sc,
                                              double* sl) {
     const int tid = threadIdx.x;
     const int RP = restart_lanes(A.R);
@@ -568,7 +573,7 @@ __device__ __forceinline__ void reduce1_body(const ReduceArgs& A, const int bx, 
     const int r = bx * 64 + rloc;
     const int u0 = by * A.chunk;
     const int u1 = min(u0 + A.chunk, A.n_units);
-    int32_t c = 0;
+    int64_t c = 0;
     double l = 0.0;
     if (r < A.R) {
         for (int u = u0 + slot; u < u1; u += NS) {
@@ -593,7 +598,7 @@ __device__ __forceinline__ void reduce1_body(const ReduceArgs& A, const int bx, 
 }
 
 __global__ __launch_bounds__(256) void k_reduce1(ReduceArgs A) {
-    __shared__ int32_t sc[256];
+    __shared__ int64_t sc[256];
     __shared__ double sl[256];
     reduce1_body(A, blockIdx.x, blockIdx.y, sc, sl);
 }
@@ -601,7 +606,7 @@ __global__ __launch_bounds__(256) void k_reduce1(ReduceArgs A) {
 // Multi-instance stage 1: instance i's grid is ceil(R/64) x n_chunks, flattened.
 __global__ __launch_bounds__(256) void k_reduce1_multi(const ReduceArgs* __restrict__ As,
                                                        const int32_t* __restrict__ b0, int32_t n) {
-    __shared__ int32_t sc[256];
+    __shared__ int64_t sc[256];
     __shared__ double sl[256];
     const int i = owner(b0, n, blockIdx.x);
     const ReduceArgs& A = As[i];
@@ -704,7 +709,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
         A.t[boff(B, B.rows_x, A.n, r)] = -0.0f;
         if (A.a != nullptr) A.a[boff(B, B.rows_a, A.a_zero_row, r)] = 0.0f;
         if (A.best != nullptr) {
-            A.best[r] = A.m;
+            A.best[r] = A.best0;
             A.best_step[r] = -1;
             A.improved[r] = 0;
         }

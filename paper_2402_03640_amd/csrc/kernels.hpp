@@ -13,7 +13,7 @@
 //   a          : [RG][c_tiles * 64 + 1][G] FP32   adjoint of the scores (last row 0)
 //   seg_part   : [RG][seg_rows][G] FP64   partial transposed sums of heavy rows
 //   best_a     : [RG][n + 1][G] bytes     rounded iterate at each restart's best step
-//   cnt_part, loss_part : [units][R]     per-unit count / loss partials
+//   cnt_part, loss_part : [units][R]     per-unit unsatisfied weight (int64) / loss partials
 //   umask      : [RG][c_tiles * 2 + 1] bitset words over clause rows: bit j of group g =
 //                clause j unsatisfied for some restart of group g (unsat-masked loss)
 //
@@ -60,8 +60,9 @@ struct FwdArgs {
     const float* t;
     float* a;
     uint32_t* umask;     // written when the schedule keeps the unsat bitset
+    const int64_t* w;    // weight of each clause row (weighted MaxSAT), or null: weight 1
     float two_over_m;
-    int32_t* cnt_part;
+    int64_t* cnt_part;   // unsatisfied weight per unit
     double* loss_part;
     StepState* st;       // block 0 publishes the step scalars for the next update
     double lr, b1, b2;
@@ -92,12 +93,12 @@ struct BwdArgs {
 };
 
 struct ReduceArgs {
-    const int32_t* cnt_part;
+    const int64_t* cnt_part;
     const double* loss_part;
-    int32_t* cnt_mid;        // [n_chunks][R] stage-1 partials
+    int64_t* cnt_mid;        // [n_chunks][R] stage-1 partials
     double* loss_mid;
     int32_t n_units, chunk, n_chunks, R, track;
-    int64_t n_empty;
+    int64_t n_empty;         // weight of the empty clauses (always unsatisfied)
     double inv_m;
     int64_t* cur_count;
     double* cur_loss;
@@ -109,6 +110,7 @@ struct ReduceArgs {
 
 struct InitArgs {
     int32_t n, m, a_zero_row, umask_words;
+    int64_t best0;            // initial best: the total clause weight (m without weights)
     Blocking B;
     const int32_t* var_old;
     const float* x0;          // caller order [n][R] or null

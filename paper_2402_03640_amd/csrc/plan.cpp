@@ -83,7 +83,8 @@ int32_t tile_rows(int32_t nrows, LenFn len_of, EntFn ent_of,
 
 }  // namespace
 
-int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, std::string& err) {
+int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t* weights, HostPlan& P,
+                   std::string& err) {
     P = HostPlan{};
     if (n < 0 || nlits < 0 || (nlits > 0 && lits == nullptr)) {
         err = "bad arguments: n_vars < 0, n_lits < 0 or null literal array";
@@ -118,6 +119,19 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
     }
     P.n = n;
     P.m = (int32_t)m;
+    P.w_total = m;
+    if (weights) {
+        int64_t tot = 0;
+        for (int64_t j = 0; j < m; ++j) {
+            if (weights[j] <= 0 || weights[j] > ((int64_t)1 << 53) || tot > INT64_MAX - weights[j]) {
+                err = "clause weights must be positive, at most 2^53, with a total below 2^63";
+                return kErrArg;
+            }
+            tot += weights[j];
+        }
+        P.weighted = true;
+        P.w_total = tot;
+    }
 
     // ---- canonical clauses: W entries in order of first appearance --------
     std::vector<uint32_t> flat;          // original variable | sign
@@ -161,6 +175,7 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
             const int32_t len = (int32_t)((int64_t)flat.size() - off);
             if (p == start) {
                 P.m_empty++;
+                P.w_empty += weights ? weights[j] : 1;
             } else if (taut) {
                 P.m_taut++;
                 if (len == 0) P.m_taut_dropped++;
@@ -192,6 +207,7 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
         int32_t len = (int32_t)((int64_t)flat.size() - off);
         if (p == start) {
             P.m_empty++;
+            P.w_empty += weights ? weights[j] : 1;
         } else if (taut) {
             P.m_taut++;
             if (len == 0) P.m_taut_dropped++;
@@ -303,6 +319,10 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
         for (int32_t r = 0; r < n_plain; ++r) krow[r] = r;
         for (int32_t r = 0; r < n_tr; ++r) krow[n_plain + r] = tp * kTile + r;
         for (size_t r = 0; r < rows.size(); ++r) P.c_row_orig[krow[r]] = rows[r].orig;
+        if (weights) {
+            P.c_w.assign((size_t)P.c_tiles * kTile, 0);
+            for (size_t r = 0; r < rows.size(); ++r) P.c_w[krow[r]] = weights[rows[r].orig];
+        }
     }
 
     // ---- variable-major occurrence lists (clause rows ascending) ----------
@@ -376,50 +396,95 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& P, s
     return kOk;
 }
 
-int32_t read_dimacs(const char* path, int32_t& n, std::vector<int32_t>& lits, std::string& err) {
+int32_t read_dimacs(const char* path, int32_t& n, std::vector<int32_t>& lits, std::vector<int64_t>& weights,
+                    std::string& err) {
     FILE* f = fopen(path, "rb");
     if (!f) {
         err = std::string("cannot open ") + path + ": " + strerror(errno);
         return kErrIO;
     }
+    std::string buf;
+    {
+        char chunk[1 << 16];
+        size_t got;
+        while ((got = fread(chunk, 1, sizeof chunk, f)) > 0) buf.append(chunk, got);
+    }
+    fclose(f);
     n = -1;
-    int64_t m_decl = -1;
     lits.clear();
-    char line[4096];
-    bool in_clause = false;
+    weights.clear();
+    enum { kCnf, kWcnf, kWcnfNoHeader } mode = kCnf;
+    bool header = false, in_clause = false, any_hard = false;
+    int64_t soft_total = 0;
     int32_t maxv = 0;
-    while (fgets(line, sizeof line, f)) {
-        char* s = line;
-        while (*s == ' ' || *s == '\t') ++s;
-        if (*s == 'c' || *s == '%' || *s == '\n' || *s == '\r' || *s == 0) continue;
-        if (*s == 'p') {
+    const char* s = buf.c_str();
+    const char* end = s + buf.size();
+    while (s < end) {
+        // one line
+        const char* eol = (const char*)memchr(s, '\n', (size_t)(end - s));
+        if (!eol) eol = end;
+        std::string line(s, eol);
+        s = eol + 1;
+        size_t q = line.find_first_not_of(" \t\r");
+        if (q == std::string::npos) continue;
+        const char c0 = line[q];
+        if (c0 == 'c' || c0 == '%') continue;
+        if (c0 == 'p') {
             char fmt[16] = {0};
             long long nv = -1, nc = -1;
-            if (sscanf(s, "p %15s %lld %lld", fmt, &nv, &nc) != 3 || strcmp(fmt, "cnf") != 0 || nv < 0 ||
-                nc < 0 || nv >= (long long)kIdx) {
-                fclose(f);
+            if (header || sscanf(line.c_str() + q, "p %15s %lld %lld", fmt, &nv, &nc) != 3 || nv < 0 || nc < 0 ||
+                nv >= (long long)kIdx || (strcmp(fmt, "cnf") != 0 && strcmp(fmt, "wcnf") != 0)) {
                 err = "bad problem line";
                 return kErrParse;
             }
+            header = true;
+            mode = strcmp(fmt, "wcnf") == 0 ? kWcnf : kCnf;
             n = (int32_t)nv;
-            m_decl = nc;
             continue;
         }
-        // literals (a clause may span lines)
-        char* e = nullptr;
+        if (!header && !in_clause && c0 == 'h') mode = kWcnfNoHeader;
+        const char* t = line.c_str() + q;
         while (true) {
-            while (*s == ' ' || *s == '\t' || *s == '\n' || *s == '\r') ++s;
-            if (*s == 0) break;
+            while (*t == ' ' || *t == '\t' || *t == '\r') ++t;
+            if (*t == 0) break;
+            if (!in_clause && mode != kCnf) {
+                // the clause's weight, or "h" for a hard clause
+                if (*t == 'h' && mode == kWcnfNoHeader) {
+                    weights.push_back(-1);
+                    any_hard = true;
+                    ++t;
+                } else {
+                    char* e = nullptr;
+                    errno = 0;
+                    long long w = strtoll(t, &e, 10);
+                    if (e == t || errno || w <= 0) {
+                        err = "bad clause weight";
+                        return kErrParse;
+                    }
+                    weights.push_back(w);
+                    if (soft_total > INT64_MAX - w) {
+                        err = "clause weights overflow";
+                        return kErrParse;
+                    }
+                    soft_total += w;
+                    t = e;
+                }
+                in_clause = true;
+                if (*t != ' ' && *t != '\t' && *t != 0 && *t != '\r') {
+                    err = "bad clause weight";
+                    return kErrParse;
+                }
+                continue;
+            }
+            char* e = nullptr;
             errno = 0;
-            long v = strtol(s, &e, 10);
-            if (e == s || errno) {
-                fclose(f);
+            long v = strtol(t, &e, 10);
+            if (e == t || errno) {
                 err = "bad literal token";
                 return kErrParse;
             }
-            s = e;
+            t = e;
             if (v < -(long)kIdx || v > (long)kIdx) {
-                fclose(f);
                 err = "literal out of range";
                 return kErrRange;
             }
@@ -428,11 +493,18 @@ int32_t read_dimacs(const char* path, int32_t& n, std::vector<int32_t>& lits, st
             if (v != 0) maxv = std::max<int32_t>(maxv, (int32_t)std::labs(v));
         }
     }
-    fclose(f);
-    (void)m_decl;
     if (in_clause) {
         err = "last clause is not terminated by 0";
         return kErrParse;
+    }
+    if (any_hard) {
+        // a hard clause outweighs every soft clause together
+        if (soft_total == INT64_MAX) {
+            err = "clause weights overflow";
+            return kErrParse;
+        }
+        for (int64_t& w : weights)
+            if (w < 0) w = soft_total + 1;
     }
     if (n < 0) n = maxv;
     return kOk;

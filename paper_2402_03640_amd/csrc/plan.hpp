@@ -32,6 +32,11 @@ struct HostPlan {
     int32_t m_taut = 0;         // clauses holding v and not-v: always satisfied
     int32_t m_taut_dropped = 0; // tautologies whose every entry cancelled
     int64_t nnz = 0;            // nonzero entries of W over the kernel rows
+    // clause weights (weighted MaxSAT); without weights every clause weighs 1
+    bool weighted = false;
+    int64_t w_total = 0;        // total weight (m without weights): the cost of "all unsatisfied"
+    int64_t w_empty = 0;        // total weight of the empty clauses (always unsatisfied)
+    std::vector<int64_t> c_w;   // [c_tiles * kTile] weight of each kernel row (0 = padding); empty if unweighted
 
     // clause side (scores / mask / adjoint)
     int32_t mk = 0;             // kernel clause rows
@@ -77,7 +82,14 @@ enum : int32_t {
     kErrTooLarge = -9,
 };
 
-int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, HostPlan& plan, std::string& err);
-int32_t read_dimacs(const char* path, int32_t& n, std::vector<int32_t>& lits, std::string& err);
+// weights: one positive weight per clause (at most 2^53, total below 2^63), or null.
+int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t* weights, HostPlan& plan,
+                   std::string& err);
+// DIMACS "p cnf", weighted "p wcnf n m top" (each clause led by its weight),
+// or the header-less weighted form whose clauses are led by a weight or by
+// "h" (hard: weight 1 + the total soft weight).  weights is left empty for
+// plain CNF.
+int32_t read_dimacs(const char* path, int32_t& n, std::vector<int32_t>& lits, std::vector<int64_t>& weights,
+                    std::string& err);
 
 }  // namespace hms

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
         L.t[n] = -0.0f;
         L.a[crows] = 0.0f;
     }
-    int64_t best = D.m;  // thread 0's copy is the one kept
+    int64_t best = D.best0;  // thread 0's copy is the one kept
     int best_step = -1;
     __syncthreads();
 
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
             __syncthreads();
         }
         // ---- clause scores, mask, adjoint ------------------------------------
-        int cnt = 0;
+        int64_t cnt = 0;
         double los = 0.0;
         for (int row = tid; row < crows; row += kThreads) {
             const int tile = row >> 6;
@@ -191,10 +191,12 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
             const bool real = rowin < (int)d.nreal;
             const bool unsat = real && !(d.flags & 1u) && (allf >> 31) != 0;
             const bool mu = real && (D.all_mode ? true : unsat);
-            L.a[row] = mu ? f * D.two_over_m : 0.0f;
+            // clause weight (1 without weights), as in the tiled forward pass
+            const int64_t wj = (D.c_w != nullptr && real) ? D.c_w[row] : 1;
+            L.a[row] = mu ? (f * (float)wj) * D.two_over_m : 0.0f;
             if (eval) {
-                cnt += unsat ? 1 : 0;
-                los += mu ? (double)f * (double)f : 0.0;
+                cnt += unsat ? wj : 0;
+                los += mu ? ((double)f * (double)f) * (double)wj : 0.0;
             }
         }
         if (eval) {
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
                     c += red_c[w];
                     l = l + red_l[w];
                 }
-                c += D.n_empty;
+                c += D.w_empty;
                 s_improved = c < best ? 1 : 0;
                 if (c < best) best = c;
                 if (step == D.T) D.final_loss[r] = l * D.inv_m;

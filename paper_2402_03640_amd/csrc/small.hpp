@@ -22,7 +22,10 @@ struct SmallDesc {
     const int32_t* seg_first;
     const int32_t* seg_row;
     const int32_t* var_old;
-    int32_t n, m, n_act, n_heavy, c_tiles, v_tiles, seg_tiles, seg_rows, n_empty;
+    const int64_t* c_w;   // weight of each clause row, or null (weight 1)
+    int32_t n, m, n_act, n_heavy, c_tiles, v_tiles, seg_tiles, seg_rows;
+    int64_t w_empty;      // weight of the empty clauses
+    int64_t best0;        // initial best: the total clause weight
     int32_t c_ent_len, v_ent_len;
     int32_t stage;        // bit 0: clause tiles and entries fit in LDS beside the state, bit 1: variable side
     // solve parameters

@@ -36,22 +36,25 @@ def sech2(x):
     return 4.0 * e / (1.0 + e) ** 2
 
 
-def tolerance_terms(Wabs, x, mu, m):
-    """Per restart: loss bound scale (1/m) sum mu F^2 and S_i for the gradient."""
+def tolerance_terms(Wabs, x, mu, m, weights=None):
+    """Per restart: loss bound scale (1/m) sum mu w F^2 and S_i for the
+    gradient, F_j = sum |tanh| over clause j (w = 1 without weights)."""
     X = np.asarray(x, dtype=np.float64).reshape(Wabs.shape[0], -1)
     T = np.abs(np.tanh(X))
     F = Wabs.T @ T                       # [m][R]
     mu = np.asarray(mu, dtype=np.float64).reshape(F.shape)
+    if weights is not None:
+        mu = mu * np.asarray(weights, dtype=np.float64).reshape(-1, 1)
     lscale = (mu * F * F).sum(axis=0) / max(m, 1)
     S = sech2(X) * (2.0 / max(m, 1)) * (Wabs @ (mu * F))
     return lscale, S
 
 
-def assert_eval_parity(oc, Wabs, x_np, loss, grad, unsat, mode, rtol=1e-5):
+def assert_eval_parity(oc, Wabs, x_np, loss, grad, unsat, mode, rtol=1e-5, weights=None):
     """GPU (loss, grad, unsat) at float32 x vs the FP64 oracle."""
     lo, go, uo, fo, muo = oc.loss_grad(x_np, mode, want_f=True)
     np.testing.assert_array_equal(np.asarray(unsat), uo)
-    lscale, S = tolerance_terms(Wabs, x_np, muo, oc.m)
+    lscale, S = tolerance_terms(Wabs, x_np, muo, oc.m, weights)
     lerr = np.abs(np.asarray(loss) - lo)
     assert np.all(lerr <= rtol * lscale + 1e-300), (loss, lo, lscale)
     msg = f"parity n={oc.n} m={oc.m}: loss err / scale max {np.max(lerr / np.maximum(lscale, 1e-300)):.2e}"
