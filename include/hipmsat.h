@@ -86,8 +86,8 @@ hms_status hms_load_cnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, voi
                         hms_cnf** out);
 
 /*
- * Weighted MaxSAT (the problem of Section 3 with clause weights; the paper
- * leaves weights to future work, Section 7, so the loss is our reading):
+ * Weighted MaxSAT (weighted partial CNF is defined in Section 2; Section 6
+ * leaves weights to future work, so the loss is our reading):
  * clause j has weight weights[j] > 0 (HOST, one per clause, at most 2^53,
  * total below 2^63).  The cost of an assignment is the total weight of its
  * unsatisfied clauses, the loss is (1/m) sum_j mu_j w_j f_j^2, and the best

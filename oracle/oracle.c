@@ -31,8 +31,8 @@
  *   - Algorithm 1 loop: best_cost starts at m; at every evaluation step the
  *     rounded iterate is counted and kept when strictly better; then one step.
  *   - brute force (n <= 24): Gray-code enumeration of all assignments.
- *   - clause weights (weighted MaxSAT, which the paper names in Section 3 and
- *     leaves to future work, Section 7): with positive integer weights w_j the
+ *   - clause weights (weighted partial CNF, defined in Section 2 and left to
+ *     future work in Section 6): with positive integer weights w_j the
  *     cost is the total weight of the unsatisfied clauses, the loss is
  *     (1/m) sum_j mu_j w_j f_j^2 and the best cost starts at the total weight.
  *     Without weights every w_j is 1 and every formula above is unchanged.

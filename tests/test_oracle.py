@@ -423,7 +423,7 @@ def test_solve_x0_and_best_monotone():
         prev = cur
 
 
-# ---- clause weights (weighted MaxSAT: the problem of Section 3 with weights;
+# ---- clause weights (weighted partial CNF of Section 2, future work in Section 6;
 # the paper leaves it to future work, so the reading is ours: cost = total
 # weight of the unsatisfied clauses, loss = (1/m) sum mu_j w_j f_j^2) --------
 
