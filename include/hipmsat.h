@@ -43,7 +43,7 @@ typedef int32_t hms_status;
 #define HMS_ERR_DEVICE (-4)        /* no usable gfx950 device or a HIP runtime error */
 #define HMS_ERR_NOMEM (-5)         /* host or device allocation failed */
 #define HMS_ERR_NONFINITE (-6)     /* a relaxed value or the loss became NaN/Inf */
-#define HMS_ERR_CANCELLED (-7)     /* reserved */
+#define HMS_ERR_CANCELLED (-7)     /* the caller's cancel flag stopped the solve (result filled) */
 #define HMS_ERR_IO (-8)            /* file could not be read */
 #define HMS_ERR_TOO_LARGE (-9)     /* instance exceeds the 31-bit index space */
 
@@ -127,6 +127,9 @@ typedef struct {
     double time_limit_s; /* > 0: stop at a K-step boundary once exceeded (not reproducible) */
     const float* x0;     /* DEVICE [n][R] initial values, or NULL for SplitMix64 U(-1,1) */
     void* stream;        /* hipStream_t */
+    const volatile int32_t* cancel; /* HOST flag or NULL: once nonzero (set by another thread), the
+                            solve stops at the next K-step boundary, fills the result with the
+                            best so far and returns HMS_ERR_CANCELLED */
 } hms_solve_params;
 
 typedef struct {

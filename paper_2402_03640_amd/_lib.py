@@ -49,7 +49,7 @@ class SolveParams(C.Structure):
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("loss_mode", C.c_int32), ("schedule", C.c_int32), ("use_graph", C.c_int32),
                 ("autotune", C.c_int32), ("time_limit_s", C.c_double), ("x0", C.c_void_p),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("cancel", C.c_void_p)]
 
 
 class SolveResult(C.Structure):
@@ -269,15 +269,33 @@ def tune_candidates(restarts: int = 1, loss_mode: int = LOSS_UNSAT) -> list[int]
     return [int(buf[i]) for i in range(cnt.value)]
 
 
+class CancelFlag:
+    """A host flag a running ``solve`` polls at its counting boundaries; set
+    it from another thread to stop the solve (HMS_ERR_CANCELLED, with the
+    best so far on the raised error's ``result``)."""
+
+    def __init__(self):
+        self._v = C.c_int32(0)
+
+    def set(self):
+        self._v.value = 1
+
+    @property
+    def address(self):
+        return C.addressof(self._v)
+
+
 def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, seed: int = 0,
           optimizer: int = ADAM, lr: float = 1e-4, beta1: float = 0.9, beta2: float = 0.999,
           eps: float = 1e-8, loss_mode: int = LOSS_UNSAT, schedule: int = 0, use_graph: bool = True,
           time_limit_s: float = 0.0, x0=None, want_x: bool = False, stream=None,
-          autotune: bool = True) -> SolveOutput:
+          autotune: bool = True, cancel: CancelFlag | None = None) -> SolveOutput:
     """Algorithm 1 over ``restarts`` relaxed points (see ``hms_solve``)."""
     R = int(restarts)
     p = _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2, eps, loss_mode,
                 schedule, use_graph, time_limit_s, x0, stream, autotune)
+    if cancel is not None:
+        p.cancel = cancel.address
     res = SolveResult()
     ba = np.zeros(max(cnf.n, 1), dtype=np.uint8)
     rb = np.zeros(R, dtype=np.int64)
@@ -293,11 +311,11 @@ def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, s
         xf = torch.empty((cnf.n, R), dtype=torch.float32, device="cuda")
         res.x_final = xf.data_ptr()
     rc = lib().hms_solve(cnf.handle, C.byref(p), C.byref(res))
-    if rc != HMS_OK and rc != -6:
+    if rc != HMS_OK and rc not in (-6, -7):
         _check(rc)
     out = SolveOutput(res.best_cost, res.best_restart, res.best_step, res.steps_done, res.schedule,
                       res.final_loss, res.device_ms, ba[:cnf.n].copy(), rb, rs, rl, xf)
-    if rc == -6:
+    if rc in (-6, -7):  # non-finite loss or cancelled: the result holds the best so far
         err = HipMsatError(rc, lib().hms_last_error().decode())
         err.result = out
         raise err

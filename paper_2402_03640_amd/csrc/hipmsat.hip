@@ -782,7 +782,9 @@ size_t lds_limit(int dev) {
 
 bool resident_ok(const hms_cnf* cnf, const hms_solve_params* p) {
     const hms::HostPlan& P = cnf->plan;
-    return P.n_heavy_wide == 0 && p->time_limit_s <= 0 && hms::small_lds_bytes(P) <= lds_limit(cnf->device);
+    // the resident solver runs the whole loop in one launch: no time limit or cancel flag can stop it
+    return P.n_heavy_wide == 0 && p->time_limit_s <= 0 && p->cancel == nullptr &&
+           hms::small_lds_bytes(P) <= lds_limit(cnf->device);
 }
 
 // LDS of one resident workgroup for this instance: state plus the staged plan.
@@ -1147,11 +1149,17 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     HIPTRY(hipEventRecord(ev0, s));
 
     const auto t_host0 = std::chrono::steady_clock::now();
+    bool cancelled = false;
     auto over_time = [&]() {
+        if (p->cancel && *p->cancel) {
+            cancelled = true;
+            return true;
+        }
         if (p->time_limit_s <= 0) return false;
         double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_host0).count();
         return el >= p->time_limit_s;
     };
+    const bool watch = p->time_limit_s > 0 || p->cancel != nullptr;  // poll at K-step boundaries
 
     int32_t done = 0;
     bool stopped = false;  // the time limit ran out
@@ -1185,7 +1193,7 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
         for (int32_t r = 0; r < reps; ++r) {
             HIPTRY(hipGraphLaunch(exec, s));
             done += B;
-            if (p->time_limit_s > 0) {
+            if (watch) {
                 HIPTRY(hipStreamSynchronize(s));
                 if ((stopped = over_time())) break;
             }
@@ -1194,7 +1202,7 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     while (done < T && !stopped) {
         HIPTRY(enqueue_step(L, done % K == 0, s));
         ++done;
-        if (p->time_limit_s > 0 && done % K == 0) {
+        if (watch && done % K == 0) {
             HIPTRY(hipStreamSynchronize(s));
             stopped = over_time();
         }
@@ -1205,7 +1213,9 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     HIPTRY(hipStreamSynchronize(s));
     float ms = 0.0f;
     HIPTRY(hipEventElapsedTime(&ms, ev0, ev1));
-    return read_result(cnf, Z, done, ms, s, res);
+    const hms_status rr = read_result(cnf, Z, done, ms, s, res);
+    if (cancelled && rr == HMS_OK) return fail(HMS_ERR_CANCELLED, "cancelled by the caller; the best so far is filled");
+    return rr;
 }
 
 hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* p, int32_t iters, double* fwd_ms,
@@ -1400,7 +1410,7 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
     std::vector<int32_t> alone;
     for (int32_t i : tiled_idx) {
         const hms_solve_params& p = params[i];
-        if (p.time_limit_s > 0) {
+        if (p.time_limit_s > 0 || p.cancel != nullptr) {
             alone.push_back(i);
             continue;
         }

@@ -378,6 +378,34 @@ def test_time_limit_stops_at_a_counting_boundary():
     assert hm.evaluate(cnf, a.best_assignment) == a.best_cost
 
 
+def test_cancel_flag_returns_best_so_far():
+    """Failure handling forced from the host: a cancel flag set by another
+    thread stops the solve at a counting boundary with HMS_ERR_CANCELLED and
+    the best so far, which is consistent and equals the fixed-step solve of
+    that length."""
+    import threading
+    import time
+    n, m = 20000, 86000
+    cnf = hm.load_cnf(n, cnfgen.uniform_kcnf(n, m, 3, seed=2))
+    flag = hm.CancelFlag()
+    threading.Thread(target=lambda: (time.sleep(0.05), flag.set()), daemon=True).start()
+    with pytest.raises(hm.HipMsatError) as ei:
+        hm.solve(cnf, steps=10 ** 7, restarts=2, eval_every=10, seed=1, lr=1e-2, cancel=flag, want_x=True)
+    assert ei.value.name == "HMS_ERR_CANCELLED"
+    a = ei.value.result
+    assert 0 < a.steps_done < 10 ** 7 and a.steps_done % 10 == 0
+    assert hm.evaluate(cnf, a.best_assignment) == a.best_cost
+    b = hm.solve(cnf, steps=a.steps_done, restarts=2, eval_every=10, seed=1, lr=1e-2, want_x=True)
+    np.testing.assert_array_equal(a.restart_best, b.restart_best)
+    np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32), b.x_final.cpu().numpy().view(np.uint32))
+    # a flag set before the solve stops it at the first boundary
+    flag2 = hm.CancelFlag()
+    flag2.set()
+    with pytest.raises(hm.HipMsatError) as ei:
+        hm.solve(cnf, steps=1000, restarts=1, eval_every=10, cancel=flag2)
+    assert ei.value.result.steps_done <= 32 * 2
+
+
 def test_nonfinite_x0_reported():
     n, lits = 3, np.array([1, 2, 0, -3, 0], np.int32)
     cnf = hm.load_cnf(n, lits)
