@@ -46,6 +46,7 @@ class Request:
     footprint: int = 0
     small: bool = False
     rid: int = 0
+    weights: object = None  # clause weights (weighted MaxSAT) or None
 
 
 @dataclass
@@ -92,12 +93,15 @@ class Server:
         self._disp.start()
 
     # -- client side -------------------------------------------------------------
-    def submit(self, n: int, lits, arrival: float | None = None, **params) -> Future:
+    def submit(self, n: int, lits, arrival: float | None = None, weights=None, **params) -> Future:
+        """Queue one instance (``weights``: one positive integer per clause for
+        weighted MaxSAT); the future resolves to a ServeResult."""
         lits = np.ascontiguousarray(lits, dtype=np.int32)
         m = int(np.count_nonzero(lits == 0))
         R = int(params.get("restarts", 1))
         req = Request(n=int(n), lits=lits, params=params,
-                      arrival=time.perf_counter() if arrival is None else arrival)
+                      arrival=time.perf_counter() if arrival is None else arrival,
+                      weights=None if weights is None else np.ascontiguousarray(weights, dtype=np.int64))
         req.footprint = footprint_bytes(n, m, lits.size - m, R)
         req.small = (n + m) <= SMALL_ROWS
         with self._cv:
@@ -186,7 +190,7 @@ class Server:
                     self._cv.notify_all()
 
     def _run(self, job, stream):
-        cnfs = [_lib.load_cnf(r.n, r.lits, stream=stream) for r in job]
+        cnfs = [_lib.load_cnf(r.n, r.lits, stream=stream, weights=r.weights) for r in job]
         try:
             clean = []
             for r in job:

@@ -174,3 +174,19 @@ def test_weighted_batch_equals_solo():
         np.testing.assert_array_equal(a.restart_best, b.restart_best)
         np.testing.assert_array_equal(a.best_assignment, b.best_assignment)
         assert hm.evaluate(c, b.best_assignment) == b.best_cost
+
+
+def test_weighted_served_equals_solo():
+    from paper_2402_03640_amd.serve import Server
+    reqs = []
+    for i, (n, m) in enumerate([(50, 215), (3000, 12900), (8000, 34400), (60, 250)]):
+        lits = cnfgen.uniform_kcnf(n, m, 3, seed=80 + i)
+        reqs.append((n, lits, _weights(m, seed=80 + i)))
+    kw = dict(steps=60, restarts=1, eval_every=6, lr=1e-2)
+    solo = [hm.solve(hm.load_cnf(n, l, weights=w), seed=i, **kw) for i, (n, l, w) in enumerate(reqs)]
+    with Server(workers=2) as srv:
+        futs = [srv.submit(n, l, weights=w, seed=i, **kw) for i, (n, l, w) in enumerate(reqs)]
+        res = [f.result(timeout=120) for f in futs]
+    for a, r in zip(solo, res):
+        np.testing.assert_array_equal(a.restart_best, r.output.restart_best)
+        np.testing.assert_array_equal(a.best_assignment, r.output.best_assignment)
