@@ -14,9 +14,12 @@
 //  * clause rows sorted by (tautology flag, length descending, smallest
 //    variable), cut into tiles of 64 rows stored column-major, padded to the
 //    tile's longest row;
-//  * variables renumbered by degree descending; variables with more than kSeg
-//    entries are split into segments of kSeg consecutive entries whose
-//    partial sums are combined afterwards;
+//  * variables renumbered by degree descending; a variable with d > kSeg
+//    entries is split into ns = ceil(d / kSeg) segments, segment s holding
+//    entries s, s + ns, s + 2 ns, ... of its list, and the segments' partial
+//    sums are combined afterwards.  Interleaving puts consecutive entries in
+//    neighbouring segment rows, so one column of a tile of a hot variable's
+//    segments reads neighbouring adjoint entries;
 //  * variable rows (segments first, then whole light variables) tiled the same
 //    way; the entries of a row follow increasing clause-row index.
 #include "plan.hpp"
@@ -356,10 +359,10 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
 
     // ---- segments of heavy variables ---------------------------------------
     struct Seg {
-        int32_t var, idx, len;
+        int32_t var, idx, len, stride;
         int64_t off;
     };
-    std::vector<Seg> full, part;
+    std::vector<Seg> segs;
     P.seg_first.assign((size_t)P.n_heavy + 1, 0);
     for (int32_t h = 0; h < P.n_heavy; ++h) {
         int32_t d = P.degree[h];
@@ -367,23 +370,17 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
         P.max_segs = std::max(P.max_segs, ns);
         if (ns > kWideSegs) P.n_heavy_wide = h + 1;
         P.seg_first[h + 1] = P.seg_first[h] + ns;
-        for (int32_t s = 0; s < ns; ++s) {
-            int32_t L = std::min(kSeg, d - s * kSeg);
-            Seg g{h, s, L, voff[h] + (int64_t)s * kSeg};
-            (L == kSeg ? full : part).push_back(g);
-        }
+        for (int32_t s = 0; s < ns; ++s) segs.push_back(Seg{h, s, (d - s + ns - 1) / ns, ns, voff[h] + s});
     }
-    std::stable_sort(part.begin(), part.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
-    std::vector<Seg> segs;
-    segs.reserve(full.size() + part.size());
-    segs.insert(segs.end(), full.begin(), full.end());
-    segs.insert(segs.end(), part.begin(), part.end());
+    // longest first (tiles pad to their longest row); stable, so a variable's
+    // segments of one length stay adjacent and in order
+    std::stable_sort(segs.begin(), segs.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
     P.seg_rows = (int32_t)segs.size();
     P.seg_row.assign((size_t)P.seg_rows, 0);
     for (int32_t r = 0; r < P.seg_rows; ++r) P.seg_row[P.seg_first[segs[r].var] + segs[r].idx] = r;
     const uint32_t vpad = (uint32_t)P.a_zero_row();
     rc = tile_rows(P.seg_rows, [&](int32_t r) { return segs[r].len; },
-                   [&](int32_t r, int32_t c) { return occ[segs[r].off + c]; }, vpad, 0u, P.v_tile,
+                   [&](int32_t r, int32_t c) { return occ[segs[r].off + (int64_t)c * segs[r].stride]; }, vpad, 0u, P.v_tile,
                    P.v_ent, err);
     if (rc) return rc;
     P.seg_tiles = (int32_t)P.v_tile.size();

@@ -99,12 +99,15 @@ def _check_plan(n, lits):
     azero = P.c_tiles * 64
     seg_rows_pad = P.seg_tiles * 64
     for i in range(P.n_heavy):
-        segs = P.seg_row[P.seg_first[i]:P.seg_first[i + 1]]
-        got = []
-        for sr in segs.tolist():
+        # segment s of ns holds entries s, s + ns, s + 2 ns, ... of the list
+        segs = P.seg_row[P.seg_first[i]:P.seg_first[i + 1]].tolist()
+        ns = len(segs)
+        assert ns == -(-deg[i] // P.seg_len)
+        for s, sr in enumerate(segs):
             assert sr < P.seg_rows
-            got.extend(e for e in vrows[sr] if e != azero)
-        assert got == occ[i]
+            got = [e for e in vrows[sr] if e != azero]
+            assert got == occ[i][s::ns]
+            assert all(e == azero for e in vrows[sr][len(got):])
     assert sorted(P.seg_row.tolist()) == list(range(P.seg_rows))
     for i in range(P.n_heavy, P.n_act):
         r = seg_rows_pad + (i - P.n_heavy)
