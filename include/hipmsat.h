@@ -272,7 +272,8 @@ typedef struct {
     const uint32_t* v_tile;          /* [v_tiles][4] */
     const uint32_t* v_ent;           /* [v_ent_len] clause row | sign << 31 */
     const int32_t* seg_first;        /* [n_heavy + 1] */
-    const int32_t* seg_row;          /* [seg_rows] */
+    const int32_t* seg_row;          /* [seg_rows] row of each segment; the identity, since a heavy
+                                        variable's segments are consecutive rows in segment order */
     const int32_t* var_old;          /* [n] new -> original */
     void* priv;
 } hms_plan_view;

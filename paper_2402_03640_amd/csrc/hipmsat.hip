@@ -27,7 +27,6 @@ struct hms_cnf {
     hms::TileDesc* v_tile = nullptr;
     uint32_t* v_ent = nullptr;
     int32_t* seg_first = nullptr;
-    int32_t* seg_row = nullptr;
     int32_t* var_old = nullptr;
     int64_t* c_w = nullptr;  // clause-row weights (weighted instances only)
     int64_t struct_bytes = 0;
@@ -103,7 +102,7 @@ struct Arena {
 
 // Default kernel schedule for R restarts (table index into hms::kSchedules).
 int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0) {
-    if (R <= 1) return loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 21) ? 23 : 2;
+    if (R <= 1) return loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 21) ? 37 : 2;
     if (R <= 2) return 2;
     if (R <= 4) return 3;
     if (R <= 8) return 5;
@@ -114,7 +113,7 @@ int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0) {
 }
 
 struct Shape {
-    int sched, P, V, UR, U, chunks, mask;
+    int sched, P, V, UR, U, chunks, mask, nt;
     int Ub, chunks_b;  // rows per work unit and units per tile of the backward pass
     hms::Blocking B;
     int64_t n_tc, fwd_blocks64, bwd_blocks64;
@@ -147,6 +146,7 @@ hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_m
     const int per_pass = (64 / sh.P) * sh.UR;
     if (U % per_pass != 0 || hms::kTile % U != 0 || (sh.mask && U < 32) || Ub % per_pass != 0 || hms::kTile % Ub != 0)
         return fail(HMS_ERR_ARG, "rows per unit must be a multiple of the rows per pass and divide 64");
+    sh.nt = c.nt;  // whole clause tiles per forward work unit (rows per unit then stay 64)
     sh.U = U;
     sh.Ub = Ub;
     sh.code = sh.sched | (U << 8) | (Ub != U ? Ub << 16 : 0);
@@ -162,9 +162,10 @@ hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_m
     sh.B.rows_x = P.n + 1;
     sh.B.rows_a = P.a_rows();
     sh.B.rows_seg = std::max(P.seg_rows, 1);
-    sh.n_tc = (int64_t)P.c_tiles * sh.chunks;
+    sh.n_tc = sh.nt > 1 ? ((int64_t)P.c_tiles + sh.nt - 1) / sh.nt : (int64_t)P.c_tiles * sh.chunks;
+    const int64_t n_vu = (int64_t)P.v_tiles * sh.chunks_b;
     sh.fwd_blocks64 = (int64_t)sh.B.RG * ((sh.n_tc + 3) / 4);
-    sh.bwd_blocks64 = (int64_t)sh.B.RG * (((int64_t)P.v_tiles * sh.chunks_b + 3) / 4);
+    sh.bwd_blocks64 = (int64_t)sh.B.RG * ((n_vu + 3) / 4);
     if (sh.fwd_blocks64 >= INT32_MAX / 2 || sh.bwd_blocks64 >= INT32_MAX / 2)
         return fail(HMS_ERR_TOO_LARGE, "too many work units");
     sh.fwd_blocks = (int)sh.fwd_blocks64;
@@ -342,7 +343,6 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     b.omb1 = 1.0f - b1;
     b.omb2 = 1.0f - b2;
     b.seg_first = C->seg_first;
-    b.seg_row = C->seg_row;
     hms::ReduceArgs& r = L.ra;
     r.cnt_part = S.cnt_part;
     r.loss_part = S.loss_part;
@@ -407,7 +407,6 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     size_t o_vt = L.add(P.v_tile.size() * sizeof(hms::TileDesc));
     size_t o_ve = L.add((P.v_ent.size() + hms::kEntrySlack) * 4);
     size_t o_sf = L.add(P.seg_first.size() * 4);
-    size_t o_sr = L.add(P.seg_row.size() * 4);
     size_t o_vo = L.add(P.var_old.size() * 4);
     size_t o_w = L.add(P.c_w.size() * 8);
     void* base = nullptr;
@@ -424,7 +423,6 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     C->v_tile = (hms::TileDesc*)(b + o_vt);
     C->v_ent = (uint32_t*)(b + o_ve);
     C->seg_first = (int32_t*)(b + o_sf);
-    C->seg_row = (int32_t*)(b + o_sr);
     C->var_old = (int32_t*)(b + o_vo);
     C->c_w = P.c_w.empty() ? nullptr : (int64_t*)(b + o_w);
     C->struct_bytes = (int64_t)L.off;
@@ -434,7 +432,6 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     if (!r) r = upload(P.v_tile, C->v_tile, s);
     if (!r) r = upload(P.v_ent, C->v_ent, s);
     if (!r) r = upload(P.seg_first, C->seg_first, s);
-    if (!r) r = upload(P.seg_row, C->seg_row, s);
     if (!r) r = upload(P.var_old, C->var_old, s);
     if (!r) r = upload(P.c_w, C->c_w, s);
     if (!r) {
@@ -623,6 +620,7 @@ std::vector<int32_t> tune_candidates(int32_t R, int loss_mode) {
         if (R % c.V) continue;
         if (c.mask && loss_mode != HMS_LOSS_UNSAT) continue;
         if (c.P * c.V > 2 * std::max(R, 1) && c.P * c.V > 2) continue;  // mostly idle lanes
+        if (c.nt > 1 && R > 4) continue;  // many restarts already give every wavefront enough reads
         const int per = (64 / c.P) * c.UR;
         for (int U = per; U <= 64; U *= 2) {
             if (64 % U || (c.mask && U < 32)) continue;
@@ -800,7 +798,6 @@ hms::SmallDesc make_desc(const hms_cnf* cnf, const hms_solve_params* p) {
     D.v_tile = cnf->v_tile;
     D.v_ent = cnf->v_ent;
     D.seg_first = cnf->seg_first;
-    D.seg_row = cnf->seg_row;
     D.var_old = cnf->var_old;
     D.n = P.n;
     D.m = P.m;

@@ -27,6 +27,7 @@ const Schedule kSchedules[kNumSchedules + 1] = {
     {2, 4, 1, 0, 0},  {4, 2, 1, 0, 0},  {8, 1, 4, 0, 0},                                      // 26..28
     {1, 2, 1, 1, 27}, {1, 4, 1, 1, 26}, {2, 4, 1, 1, 26}, {4, 2, 1, 1, 27},                  // 29..32
     {4, 4, 1, 0, 0},  {8, 4, 1, 0, 0},  {8, 2, 1, 0, 0},                                      // 33..35
+    {1, 1, 1, 0, 0, 2}, {1, 1, 1, 1, 36, 2},                                                  // 36..37
 };
 
 int default_rows_per_unit(int sched) {
@@ -304,6 +305,154 @@ __global__ __launch_bounds__(256) void k_fwd_multi(const FwdArgs* __restrict__ A
     fwd_body<P, V, UR, EVAL, MASK>(As[i], blockIdx.x - b0[i]);
 }
 
+// Descriptors of the NT tiles of work unit tc, all loads issued together
+// (indexes clamped into the array; tiles past the end get no rows).
+template <int NT>
+__device__ __forceinline__ void unit_tiles(const TileDesc* tiles, int ntiles, int tc, TileDesc (&d)[NT]) {
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        const int tile = tc * NT + u;
+        d[u] = ldtile(tiles + (tile < ntiles ? tile : ntiles - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+        if (tc * NT + u >= ntiles) d[u] = TileDesc{0u, 0u, 0u, 0u};
+}
+
+// Entry (column c, row `lane`) of a tile, or the padding entry past the row's
+// end or when !use.  The load always issues, from a column clamped into the
+// tile, so no branch splits a batch of loads.
+__device__ __forceinline__ uint32_t unit_entry(const uint32_t* ent, const TileDesc& d, uint32_t c, bool use,
+                                               int lane, uint32_t pad) {
+    const uint32_t last = d.len > 0 ? d.len - 1 : 0;
+    const uint32_t v = ldc(ent + (size_t)d.base + (size_t)(c < last ? c : last) * kTile + lane);
+    return use && c < d.len ? v : pad;
+}
+
+// ---------------------------------------------------------------------------
+// Forward over NT whole tiles per wavefront, one row per lane and one restart
+// per row (P = V = 1, 64 rows per tile).  The NT tiles' entry loads, then all
+// their gathers, are issued together, so each wavefront keeps NT times the
+// reads of the one-tile schedule in flight (it pays where a wavefront's time
+// is mostly the wait on its dependent loads: large instances, one restart).
+// Work unit u covers tiles [u NT, u NT + NT) and owns one count/loss partial.
+// Every row is computed exactly as the one-tile kernel computes it (FP32 sum
+// in column order up to 16 columns, FP64 beyond).
+// ---------------------------------------------------------------------------
+template <int NT, bool EVAL, bool MASK>
+__device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
+    const int lane = threadIdx.x & 63;
+    if (bx == 0 && threadIdx.x == 0 && A.st != nullptr)
+        adam_scalars((double)A.st->t + 1.0, A.lr, A.b1, A.b2, A.st->step_size, A.st->inv_sqrt_bc2);
+    const Blocking B = A.B;  // G = 1: restart group rg is restart rg
+    const int rg = bx % B.RG;
+    const int tc = __builtin_amdgcn_readfirstlane((bx / B.RG) * 4 + (threadIdx.x >> 6));
+    if (tc >= (A.ntiles + NT - 1) / NT) return;
+    const float* tg = A.t + (size_t)rg * B.rows_x;
+    float* ag = A.a + (size_t)rg * B.rows_a;
+    TileDesc d[NT];
+    unit_tiles<NT>(A.tiles, A.ntiles, tc, d);
+    uint32_t lmax = 0;  // longest short (<= 16 column) tile of the unit
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+        if (d[u].len <= 16) lmax = d[u].len > lmax ? d[u].len : lmax;
+    float f[NT];
+    uint32_t allf[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        f[u] = 0.0f;
+        allf[u] = ~0u;
+    }
+    for (uint32_t c0 = 0; c0 < lmax; c0 += kChunkF) {
+        uint32_t en[kChunkF][NT];
+#pragma unroll
+        for (int cc = 0; cc < kChunkF; ++cc)
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+                en[cc][u] = unit_entry(A.ent, d[u], c0 + cc, d[u].len <= 16, lane, A.pad_entry);
+        float tv[kChunkF][NT];
+#pragma unroll
+        for (int cc = 0; cc < kChunkF; ++cc)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) tv[cc][u] = tg[en[cc][u] & kIdx];
+#pragma unroll
+        for (int cc = 0; cc < kChunkF; ++cc)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                const uint32_t b = __float_as_uint(tv[cc][u]) ^ (en[cc][u] & kSign);
+                f[u] = f[u] + __uint_as_float(b);
+                allf[u] &= b;
+            }
+    }
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        if (d[u].len <= 16) continue;
+        // long clauses: FP64 accumulation, as in the one-tile kernel
+        double fd = 0.0;
+        for (uint32_t c = 0; c < d[u].len; ++c) {
+            const uint32_t en = ldc(A.ent + d[u].base + (size_t)c * kTile + lane);
+            const uint32_t b = __float_as_uint(tg[en & kIdx]) ^ (en & kSign);
+            fd = fd + (double)__uint_as_float(b);
+            allf[u] &= b;
+        }
+        f[u] = (float)fd;
+    }
+    int64_t cnt = 0;
+    double los = 0.0;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        const int tile = tc * NT + u;
+        if (tile >= A.ntiles) break;
+        const bool real = lane < (int)d[u].nreal;
+        const bool taut = (d[u].flags & 1u) != 0;
+        const size_t row = (size_t)tile * kTile + lane;
+        int64_t wj = 1;
+        if (A.w != nullptr && real) wj = A.w[row];
+        const float wf = (float)wj;
+        const bool unsat = real && !taut && (allf[u] >> 31) != 0;
+        const bool mu = real && (A.all_mode ? true : unsat);
+        const float av = mu ? (f[u] * wf) * A.two_over_m : 0.0f;
+        if (EVAL) {
+            cnt += unsat ? wj : 0;
+            los += mu ? ((double)f[u] * (double)f[u]) * (double)wj : 0.0;
+        }
+        if constexpr (MASK) {
+            const uint64_t bits = __ballot(mu ? 1 : 0);
+            if (mu) ag[row] = av;
+            if (lane == 0) {
+                uint32_t* w = A.umask + (size_t)rg * A.umask_words + (size_t)tile * 2;
+                w[0] = (uint32_t)bits;
+                w[1] = (uint32_t)(bits >> 32);
+            }
+        } else {
+            ag[row] = av;
+        }
+    }
+    if (EVAL) {
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            cnt += __shfl_xor(cnt, off);
+            los += __shfl_xor(los, off);
+        }
+        if (lane == 0) {
+            A.cnt_part[(size_t)tc * B.R + rg] = cnt;
+            A.loss_part[(size_t)tc * B.R + rg] = los;
+        }
+    }
+}
+
+template <int NT, bool EVAL, bool MASK>
+__global__ __launch_bounds__(256) void k_fwd_nt(FwdArgs A) {
+    fwd_nt_body<NT, EVAL, MASK>(A, blockIdx.x);
+}
+
+template <int NT, bool EVAL, bool MASK>
+__global__ __launch_bounds__(256) void k_fwd_nt_multi(const FwdArgs* __restrict__ As,
+                                                      const int32_t* __restrict__ b0, int32_t n) {
+    const int i = owner(b0, n, blockIdx.x);
+    fwd_nt_body<NT, EVAL, MASK>(As[i], blockIdx.x - b0[i]);
+}
+
 // ---------------------------------------------------------------------------
 // Epilogue of a variable: g = sech^2(x) G, then the optimizer step (or the
 // gradient itself), t = signed tanh of the new x.  `base` is the element
@@ -511,7 +660,7 @@ __device__ __forceinline__ void combine_body(const BwdArgs& A, const int bx, dou
         const double* sg = A.seg_part + (size_t)(r / B.G) * B.rows_seg * B.G + r % B.G;
         const int p1 = A.seg_first[h + 1];
 #pragma unroll 8
-        for (int p = A.seg_first[h] + tid; p < p1; p += 1024) u = u + sg[(size_t)A.seg_row[p] * B.G];
+        for (int p = A.seg_first[h] + tid; p < p1; p += 1024) u = u + sg[(size_t)p * B.G];
         su[tid] = u;
         __syncthreads();
         for (int s = 512; s >= 1; s >>= 1) {
@@ -528,7 +677,7 @@ __device__ __forceinline__ void combine_body(const BwdArgs& A, const int bx, dou
         const double* sg = A.seg_part + (size_t)(r / B.G) * B.rows_seg * B.G + r % B.G;
         const int p1 = A.seg_first[h + 1];
 #pragma unroll 8
-        for (int p = A.seg_first[h] + lane; p < p1; p += 64) u = u + sg[(size_t)A.seg_row[p] * B.G];
+        for (int p = A.seg_first[h] + lane; p < p1; p += 64) u = u + sg[(size_t)p * B.G];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) u = u + __shfl_down(u, off);
         if (lane != 0) return;
@@ -782,6 +931,25 @@ hipError_t bwd_multi_for(int opt, const MultiLaunch& M, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int NT, int MASK>
+hipError_t fwd_for_nt(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
+    if (eval)
+        hipLaunchKernelGGL((k_fwd_nt<NT, true, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_fwd_nt<NT, false, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+template <int NT, int MASK>
+hipError_t fwd_multi_for_nt(bool eval, const MultiLaunch& M, hipStream_t s) {
+    const FwdArgs* a = static_cast<const FwdArgs*>(M.args);
+    if (eval)
+        hipLaunchKernelGGL((k_fwd_nt_multi<NT, true, MASK != 0>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
+    else
+        hipLaunchKernelGGL((k_fwd_nt_multi<NT, false, MASK != 0>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
+    return hipGetLastError();
+}
+
 template <int P, int V, int UR, int MASK>
 hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
     if (opt == kAdam)
@@ -791,6 +959,18 @@ hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
     else
         hipLaunchKernelGGL((k_bwd<P, V, UR, kGrad, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
+}
+
+// The multi-tile entries differ in the forward only: their backward is the
+// one-row-per-lane kernel.
+template <int NT, int MASK>
+hipError_t bwd_for_nt(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
+    return bwd_for<1, 1, 1, MASK>(opt, A, blocks, s);
+}
+
+template <int NT, int MASK>
+hipError_t bwd_multi_for_nt(int opt, const MultiLaunch& M, hipStream_t s) {
+    return bwd_multi_for<1, 1, 1, MASK>(opt, M, s);
 }
 
 }  // namespace
@@ -832,6 +1012,8 @@ hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
         case 33: return FN<4, 4, 1, 0>(__VA_ARGS__);       \
         case 34: return FN<8, 4, 1, 0>(__VA_ARGS__);       \
         case 35: return FN<8, 2, 1, 0>(__VA_ARGS__);       \
+        case 36: return FN##_nt<2, 0>(__VA_ARGS__);        \
+        case 37: return FN##_nt<2, 1>(__VA_ARGS__);        \
         default: return hipErrorInvalidValue;              \
     }
 

@@ -89,7 +89,6 @@ struct BwdArgs {
     StepState* st;
     float lr, b1, b2, eps, omb1, omb2;
     const int32_t* seg_first;
-    const int32_t* seg_row;
 };
 
 struct ReduceArgs {
@@ -142,8 +141,9 @@ constexpr int kEntrySlack = 16 * kTile;
 // and no bitset that runs in their place when the loss is not masked.
 struct Schedule {
     int P, V, UR, mask, twin;
+    int nt = 1;  // whole clause tiles per forward wavefront (more than 1 only with P = V = UR = 1)
 };
-constexpr int kNumSchedules = 35;
+constexpr int kNumSchedules = 37;
 extern const Schedule kSchedules[kNumSchedules + 1];
 
 int default_rows_per_unit(int sched);

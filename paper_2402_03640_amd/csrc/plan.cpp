@@ -372,12 +372,11 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
         P.seg_first[h + 1] = P.seg_first[h] + ns;
         for (int32_t s = 0; s < ns; ++s) segs.push_back(Seg{h, s, (d - s + ns - 1) / ns, ns, voff[h] + s});
     }
-    // longest first (tiles pad to their longest row); stable, so a variable's
-    // segments of one length stay adjacent and in order
-    std::stable_sort(segs.begin(), segs.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
+    // rows in (variable, segment) order: a variable's partial sums sit side by
+    // side for the combine, and its segments' lengths differ by at most one
     P.seg_rows = (int32_t)segs.size();
-    P.seg_row.assign((size_t)P.seg_rows, 0);
-    for (int32_t r = 0; r < P.seg_rows; ++r) P.seg_row[P.seg_first[segs[r].var] + segs[r].idx] = r;
+    P.seg_row.resize((size_t)P.seg_rows);
+    std::iota(P.seg_row.begin(), P.seg_row.end(), 0);
     const uint32_t vpad = (uint32_t)P.a_zero_row();
     rc = tile_rows(P.seg_rows, [&](int32_t r) { return segs[r].len; },
                    [&](int32_t r, int32_t c) { return occ[segs[r].off + (int64_t)c * segs[r].stride]; }, vpad, 0u, P.v_tile,

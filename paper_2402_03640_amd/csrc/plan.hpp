@@ -55,7 +55,7 @@ struct HostPlan {
     std::vector<TileDesc> v_tile;
     std::vector<uint32_t> v_ent;     // clause row index | sign bit
     std::vector<int32_t> seg_first;  // [n_heavy + 1] into seg_row
-    std::vector<int32_t> seg_row;    // segment rows of each heavy variable, in order
+    std::vector<int32_t> seg_row;    // segment row of each segment: the identity (rows are in segment order)
     int32_t max_segs = 0;            // most segments of one variable
     int32_t n_heavy_wide = 0;        // heavy variables with more than kWideSegs segments (come first)
 

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
             for (int h = wave; h < D.n_heavy; h += kWaves) {
                 double u = 0.0;
                 const int p1 = D.seg_first[h + 1];
-                for (int p = D.seg_first[h] + lane; p < p1; p += 64) u = u + L.seg[D.seg_row[p]];
+                for (int p = D.seg_first[h] + lane; p < p1; p += 64) u = u + L.seg[p];
 #pragma unroll
                 for (int o2 = 32; o2 >= 1; o2 >>= 1) u = u + __shfl_down(u, o2);
                 if (lane == 0) {

@@ -20,7 +20,6 @@ struct SmallDesc {
     const TileDesc* v_tile;
     const uint32_t* v_ent;
     const int32_t* seg_first;
-    const int32_t* seg_row;
     const int32_t* var_old;
     const int64_t* c_w;   // weight of each clause row, or null (weight 1)
     int32_t n, m, n_act, n_heavy, c_tiles, v_tiles, seg_tiles, seg_rows;

@@ -88,7 +88,7 @@ def test_eval_cfg4_all_schedules():
     cnf = hm.load_cnf(n, lits)
     xt = torch.from_numpy(x).cuda()
     ref = None
-    codes = list(range(1, 36)) + [34 | (32 << 8) | (8 << 16), 26 | (32 << 8) | (64 << 16),
+    codes = list(range(1, 38)) + [34 | (32 << 8) | (8 << 16), 26 | (32 << 8) | (64 << 16),
                                   25 | (32 << 8) | (16 << 16), 14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
                                   7 | (64 << 8), 1 | (64 << 8), 255]
     for sched in codes:
@@ -112,7 +112,7 @@ def test_single_restart_schedules_bitwise():
     cnf = hm.load_cnf(n, lits)
     assert cnf.info["n_heavy"] > 0
     ref = None
-    for sched in [1, 2, 3, 4, 11, 23, 24, 25, 24 | (32 << 8), 25 | (64 << 8), 2 | (32 << 8)]:
+    for sched in [1, 2, 3, 4, 11, 23, 24, 25, 24 | (32 << 8), 25 | (64 << 8), 2 | (32 << 8), 36, 37]:
         res = hm.solve(cnf, steps=60, restarts=1, eval_every=7, seed=5, lr=1e-2, schedule=sched,
                        want_x=True)
         cur = (res.restart_best.copy(), res.restart_step.copy(),
@@ -128,7 +128,7 @@ def test_single_restart_schedules_bitwise():
 def test_schedule_id_errors():
     n, lits = 200, cnfgen.uniform_kcnf(200, 860, 3, seed=1)
     cnf = hm.load_cnf(n, lits)
-    for bad in (26 | (32 << 8) | (3 << 16), 26 | (3 << 8), 1 << 24, 36, 26 | (128 << 8)):
+    for bad in (26 | (32 << 8) | (3 << 16), 26 | (3 << 8), 1 << 24, 38, 26 | (128 << 8), 36 | (32 << 8)):
         with pytest.raises(hm.HipMsatError):
             hm.solve(cnf, steps=2, restarts=8, schedule=bad)
     code, ms = hm.tune(cnf, restarts=8, iters=3)

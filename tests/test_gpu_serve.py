@@ -87,6 +87,27 @@ def test_grouped_tiled_batch_equals_solo(opt, mode):
     _say(f"grouped batch of {len(cnfs)}: device {batch[0].device_ms:.2f} ms, schedule {batch[0].schedule}")
 
 
+@pytest.mark.parametrize("sched", [36, 37])
+def test_grouped_batch_multi_tile_schedules(sched):
+    """Grouped launches under the schedules that give each wavefront several
+    whole tiles: each result is bitwise the solo result under the default
+    schedule."""
+    sizes = [(9000, 40000, "s"), (20000, 86000, "u"), (30000, 120000, "s"), (3000, 12000, "u")]
+    cnfs = []
+    for i, (n, m, kind) in enumerate(sizes):
+        lits = (cnfgen.uniform_kcnf(n, m, 3, seed=60 + i) if kind == "u"
+                else cnfgen.structured_cnf(n, m, seed=60 + i))
+        cnfs.append(hm.load_cnf(n, lits))
+    kw = dict(steps=40, restarts=1, eval_every=5, lr=1e-2)
+    batch = hm.solve_batch(cnfs, seeds=list(range(len(cnfs))), schedule=sched, want_x=True, **kw)
+    for i, (c, b) in enumerate(zip(cnfs, batch)):
+        assert b.status == 0 and (b.schedule & 0xff) == sched
+        a = hm.solve(c, seed=i, want_x=True, autotune=False, **kw)
+        _same(a, b)
+        np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32),
+                                      b.x_final.cpu().numpy().view(np.uint32))
+
+
 def test_served_equals_solo_and_overlaps():
     from paper_2402_03640_amd.serve import Server
     reqs = _requests(40, seed=2)

@@ -108,7 +108,7 @@ def _check_plan(n, lits):
             got = [e for e in vrows[sr] if e != azero]
             assert got == occ[i][s::ns]
             assert all(e == azero for e in vrows[sr][len(got):])
-    assert sorted(P.seg_row.tolist()) == list(range(P.seg_rows))
+    assert P.seg_row.tolist() == list(range(P.seg_rows))
     for i in range(P.n_heavy, P.n_act):
         r = seg_rows_pad + (i - P.n_heavy)
         got = [e for e in vrows[r] if e != azero]
@@ -142,7 +142,7 @@ def test_tune_candidates():
         assert codes and len(set(codes)) == len(codes)
         for c in codes:
             idx, U = c & 0xFF, c >> 8
-            assert 1 <= idx <= 35 and U >= 1 and 64 % U == 0
+            assert 1 <= idx <= 37 and U >= 1 and 64 % U == 0
         has_mask = any((c & 0xFF) in (23, 24, 25, 29, 30, 31, 32) for c in codes)
         assert has_mask == (mode == hm.LOSS_UNSAT)
     assert (26 | (32 << 8)) in hm.tune_candidates(64)
