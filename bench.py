@@ -94,7 +94,7 @@ def counters_summary(dirs):
         per = {}
         for r in rows:
             name = r["Kernel_Name"]
-            key = "fwd" if "k_fwd<" in name else ("bwd" if "k_bwd<" in name else None)
+            key = "fwd" if ("k_fwd<" in name or "k_fwd_nt<" in name) else ("bwd" if "k_bwd<" in name else None)
             if key:
                 per.setdefault(key, [name, []])[1].append(float(r["Counter_Value"]))
         runs.setdefault((config, sched), {})[counter] = (max(copies) if copies else None, per)
