@@ -265,6 +265,8 @@ const char* hms_version(void);
 typedef struct {
     int32_t n, m, mk, c_tiles, n_act, n_heavy, seg_rows, seg_tiles, v_tiles, n_empty, n_taut;
     int32_t tile_rows, seg_len;      /* rows per tile (64), entries per segment */
+    int32_t split_len;               /* longest variable row kept whole; longer ones are split into
+                                        ceil(degree / seg_len) interleaved segments */
     int64_t nnz, c_ent_len, v_ent_len;
     const uint32_t* c_tile;          /* [c_tiles][4]: base, len, nreal, flags */
     const uint32_t* c_ent;           /* [c_ent_len] new variable | sign << 31 */

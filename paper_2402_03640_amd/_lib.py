@@ -64,7 +64,7 @@ class PlanView(C.Structure):
     _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("mk", C.c_int32), ("c_tiles", C.c_int32),
                 ("n_act", C.c_int32), ("n_heavy", C.c_int32), ("seg_rows", C.c_int32),
                 ("seg_tiles", C.c_int32), ("v_tiles", C.c_int32), ("n_empty", C.c_int32),
-                ("n_taut", C.c_int32), ("tile_rows", C.c_int32), ("seg_len", C.c_int32),
+                ("n_taut", C.c_int32), ("tile_rows", C.c_int32), ("seg_len", C.c_int32), ("split_len", C.c_int32),
                 ("nnz", C.c_int64), ("c_ent_len", C.c_int64), ("v_ent_len", C.c_int64),
                 ("c_tile", C.c_void_p), ("c_ent", C.c_void_p), ("c_row_orig", C.c_void_p),
                 ("v_tile", C.c_void_p), ("v_ent", C.c_void_p), ("seg_first", C.c_void_p),

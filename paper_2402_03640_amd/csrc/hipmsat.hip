@@ -1661,6 +1661,7 @@ hms_status hms_plan_view_build(int32_t n_vars, const int32_t* lits, int64_t n_li
     out->n_taut = P->m_taut;
     out->tile_rows = hms::kTile;
     out->seg_len = hms::kSeg;
+    out->split_len = P->split_len;
     out->nnz = P->nnz;
     out->c_ent_len = (int64_t)P->c_ent.size();
     out->v_ent_len = (int64_t)P->v_ent.size();

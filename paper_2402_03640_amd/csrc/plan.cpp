@@ -14,8 +14,9 @@
 //  * clause rows sorted by (tautology flag, length descending, smallest
 //    variable), cut into tiles of 64 rows stored column-major, padded to the
 //    tile's longest row;
-//  * variables renumbered by degree descending; a variable with d > kSeg
-//    entries is split into ns = ceil(d / kSeg) segments, segment s holding
+//  * variables renumbered by degree descending; a variable with more than
+//    split_len entries (kSeg, or on dense instances the largest degree up to
+//    kSplitDense) is split into ns = ceil(d / kSeg) segments, segment s holding
 //    entries s, s + ns, s + 2 ns, ... of its list, and the segments' partial
 //    sums are combined afterwards.  Interleaving puts consecutive entries in
 //    neighbouring segment rows, so one column of a tile of a hot variable's
@@ -236,12 +237,20 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
     }
     P.var_new.assign((size_t)n, 0);
     P.degree.assign((size_t)n, 0);
+    int32_t n_long = 0;  // variables with more than kSeg entries
     for (int32_t i = 0; i < n; ++i) {
         P.var_new[P.var_old[i]] = i;
         P.degree[i] = deg_orig[P.var_old[i]];
         if (P.degree[i] > 0) P.n_act = i + 1;
-        if (P.degree[i] > kSeg) P.n_heavy = i + 1;
+        if (P.degree[i] > kSeg) n_long = i + 1;
     }
+    // A split row costs its segments' partial sums and a combine pass.  When a
+    // quarter or more of the variables are long (dense uniform instances,
+    // where nearly every row is) and none exceeds kSplitDense, no row is
+    // split: each lane sums its whole row.  Otherwise rows above kSeg are.
+    const int32_t maxd = n > 0 ? P.degree[0] : 0;
+    P.split_len = ((int64_t)n_long * 4 >= (int64_t)P.n_act && n_long > 0 && maxd <= kSplitDense) ? maxd : kSeg;
+    while (P.n_heavy < n && P.degree[P.n_heavy] > P.split_len) ++P.n_heavy;
     // from here on the flat entries hold the new variable index
     for (uint32_t& e : flat) e = (uint32_t)P.var_new[e & kIdx] | (e & kSign);
 

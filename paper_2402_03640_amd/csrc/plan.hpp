@@ -10,7 +10,8 @@
 namespace hms {
 
 constexpr int kTile = 64;          // rows per tile; one wavefront lane per row at R = 1
-constexpr int kSeg = 64;           // longest variable row kept whole; longer rows are split
+constexpr int kSeg = 64;           // entries per segment of a split variable row; rows up to kSeg stay whole
+constexpr int kSplitDense = 256;   // longest row kept whole when most rows exceed kSeg
 constexpr int kWideSegs = 1024;    // variables with more segments combine over 1024 slots (else 64)
 constexpr uint32_t kSign = 0x80000000u;
 constexpr uint32_t kIdx = 0x7fffffffu;
@@ -48,7 +49,8 @@ struct HostPlan {
     // variable side (transposed sums); rows are whole light variables or
     // fixed-length segments of heavy variables
     int32_t n_act = 0;          // variables with at least one nonzero entry
-    int32_t n_heavy = 0;        // variables with more than kSeg entries
+    int32_t split_len = kSeg;   // longest variable row kept whole
+    int32_t n_heavy = 0;        // variables with more than split_len entries
     int32_t seg_rows = 0;       // real segment rows
     int32_t seg_tiles = 0;      // tiles holding segment rows (come first)
     int32_t v_tiles = 0;        // all variable-side tiles

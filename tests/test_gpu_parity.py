@@ -166,7 +166,7 @@ RESIDENT = 255
 @pytest.mark.parametrize("kind,R,opt,mode", [
     ("uniform", 1, hm.ADAM, hm.LOSS_UNSAT), ("uniform", 4, hm.SGD, hm.LOSS_ALL),
     ("mixed", 16, hm.ADAM, hm.LOSS_UNSAT), ("skewed", 1, hm.ADAM, hm.LOSS_UNSAT),
-    ("skewed", 3, hm.SGD, hm.LOSS_UNSAT), ("edge", 2, hm.ADAM, hm.LOSS_ALL)])
+    ("skewed", 3, hm.SGD, hm.LOSS_UNSAT), ("edge", 2, hm.ADAM, hm.LOSS_ALL), ("dense", 2, hm.ADAM, hm.LOSS_UNSAT)])
 def test_resident_matches_tiled(kind, R, opt, mode):
     """The resident solver (whole loop in one workgroup, state in LDS) is
     bitwise equal to the tiled kernels: per-restart bests, steps, final x and
@@ -177,6 +177,8 @@ def test_resident_matches_tiled(kind, R, opt, mode):
         n, lits = 1000, cnfgen.mixed_kcnf(1000, 4200, seed=4)
     elif kind == "skewed":
         n, lits = 3000, cnfgen.structured_cnf(3000, 15000, seed=4)
+    elif kind == "dense":  # rows of about 85 entries, kept whole
+        n, lits = 400, cnfgen.uniform_kcnf(400, 6800, 5, seed=6)
     else:
         n, lits = edge_case_cnf()
     cnf = hm.load_cnf(n, lits)
@@ -213,6 +215,18 @@ def test_eval_structured_heavy_rows():
         _say(f"structured n={n} m={m} R={R} heavy={cnf.info['n_heavy']}")
         _eval_both(n, lits, _x(n, R, seed=33 + R), hm.LOSS_UNSAT)
     _eval_both(n, lits, _x(n, 1, seed=35), hm.LOSS_ALL)
+
+
+def test_eval_dense_rows_whole():
+    """Uniform 5-CNF at ratio 17: every variable has about 85 entries and no
+    row is split (one lane sums a whole row of up to 256 entries)."""
+    n, m = 20000, 340000
+    lits = cnfgen.uniform_kcnf(n, m, 5, seed=5)
+    cnf = hm.load_cnf(n, lits)
+    assert cnf.info["n_heavy"] == 0
+    for R, mode in ((1, hm.LOSS_UNSAT), (4, hm.LOSS_UNSAT), (1, hm.LOSS_ALL)):
+        _say(f"dense 5-CNF n={n} m={m} R={R}")
+        _eval_both(n, lits, _x(n, R, seed=55 + R), mode)
 
 
 def test_eval_cfg3_full_size():

@@ -94,7 +94,10 @@ def _check_plan(n, lits):
     deg = [len(o) for o in occ]
     assert deg == sorted(deg, reverse=True)
     assert P.n_act == sum(1 for d in deg if d > 0)
-    assert P.n_heavy == sum(1 for d in deg if d > P.seg_len)
+    assert P.n_heavy == sum(1 for d in deg if d > P.split_len)
+    long = sum(1 for d in deg if d > P.seg_len)
+    dense = long > 0 and 4 * long >= P.n_act and max(deg) <= 256
+    assert P.split_len == (max(deg) if dense else P.seg_len)
     vrows = _decode_tiles(P.v_tile, P.v_ent)
     azero = P.c_tiles * 64
     seg_rows_pad = P.seg_tiles * 64
@@ -131,7 +134,16 @@ def test_plan_random_mixed():
 def test_plan_skewed_heavy_rows():
     lits = cnfgen.structured_cnf(3000, 15000, seed=4)
     P = _check_plan(3000, lits)
-    assert P.n_heavy > 0 and P.seg_rows > P.n_heavy
+    assert P.n_heavy > 0 and P.seg_rows > P.n_heavy and P.split_len == P.seg_len
+
+
+def test_plan_dense_rows_kept_whole():
+    """Dense uniform 5-CNF: every variable has about 85 entries, so no row is
+    split; a denser one with rows above 256 entries splits them."""
+    P = _check_plan(2000, cnfgen.uniform_kcnf(2000, 34000, 5, seed=7))
+    assert P.n_heavy == 0 and P.seg_rows == 0 and P.split_len > P.seg_len
+    P = _check_plan(300, cnfgen.uniform_kcnf(300, 20000, 5, seed=8))
+    assert P.split_len == P.seg_len and P.n_heavy > 0
 
 
 def test_tune_candidates():
