@@ -785,6 +785,11 @@ bool resident_ok(const hms_cnf* cnf, const hms_solve_params* p) {
            hms::small_lds_bytes(P) <= lds_limit(cnf->device);
 }
 
+// Rows a resident workgroup walks per phase: the larger plan side.
+int32_t resident_rows(const hms_cnf* cnf) {
+    return std::max(cnf->plan.c_tiles, cnf->plan.v_tiles) * hms::kTile;
+}
+
 // LDS of one resident workgroup for this instance: state plus the staged plan.
 size_t resident_lds(const hms_cnf* cnf) {
     return hms::small_lds_total(cnf->plan, lds_limit(cnf->device), nullptr);
@@ -869,7 +874,7 @@ hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_sol
     for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
     HIPTRY(hipMemcpyAsync(A.base + o_desc, &D, sizeof(D), hipMemcpyHostToDevice, s));
     HIPTRY(hipEventRecord(E.e[0], s));
-    HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc), 1, R, resident_lds(cnf), D.stage, s));
+    HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc), 1, R, resident_lds(cnf), D.stage, resident_rows(cnf), s));
     HIPTRY(hipEventRecord(E.e[1], s));
     std::vector<int64_t> best(R);
     std::vector<int32_t> bstep(R);
@@ -1342,12 +1347,14 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
         for (auto& g : groups) {
             int32_t blocks = 0;
             int32_t stage = 3;  // the sides every instance of the group stages
+            int32_t rows = 0;
             for (size_t k = g.first; k < g.second; ++k) {
                 blocks += params[res_idx[k]].restarts;
                 stage &= D[k].stage;
+                rows = std::max(rows, resident_rows(cnfs[res_idx[k]]));
             }
             HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc) + g.first, (int32_t)(g.second - g.first), blocks,
-                                     resident_lds(cnfs[res_idx[g.first]]), stage, s));
+                                     resident_lds(cnfs[res_idx[g.first]]), stage, rows, s));
         }
         HIPTRY(hipEventRecord(E.e[1], s));
         // read back every resident result

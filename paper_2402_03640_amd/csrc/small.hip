@@ -18,8 +18,6 @@ namespace hms {
 
 namespace {
 
-constexpr int kThreads = 1024;
-constexpr int kWaves = kThreads / 64;
 // Adam step scalars are computed kScal steps ahead (the same FP64 expression
 // as the tiled path), so no step waits on a pow.
 constexpr int kScal = 1024;
@@ -62,7 +60,8 @@ struct Side {
     }
 };
 
-// Copy one plan side into LDS (all threads); returns the bytes used.
+// Copy one plan side into LDS (all kThreads threads); returns the bytes used.
+template <int kThreads>
 __device__ size_t stage_side(unsigned char* dst, const TileDesc* tiles, int32_t ntiles, const uint32_t* ent,
                              int64_t nent, const TileDesc*& tl, const uint32_t*& el) {
     TileDesc* t = reinterpret_cast<TileDesc*>(dst);
@@ -75,9 +74,12 @@ __device__ size_t stage_side(unsigned char* dst, const TileDesc* tiles, int32_t 
 }
 
 // SC / SV: the clause / variable side is staged in LDS (for every instance of
-// the launch).
-template <bool SC, bool SV>
-__global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict__ descs, int32_t n_desc) {
+// the launch).  NW wavefronts per workgroup: four when one pass of them covers
+// every row (the barriers and the count reduction then cost less), else 16.
+template <bool SC, bool SV, int NW>
+__global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__ descs, int32_t n_desc) {
+    constexpr int kThreads = NW * 64;
+    constexpr int kWaves = NW;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t red_c[kWaves];
     __shared__ double red_l[kWaves];
@@ -117,8 +119,10 @@ __global__ __launch_bounds__(kThreads) void k_small(const SmallDesc* __restrict_
     // plan sides read every step: from LDS when staged, else global memory
     Side<SC> cs{D.c_tile, D.c_ent};
     Side<SV> vs{D.v_tile, D.v_ent};
-    if constexpr (SC) off += stage_side(smem + off, D.c_tile, D.c_tiles, D.c_ent, D.c_ent_len, cs.tiles, cs.ent);
-    if constexpr (SV) off += stage_side(smem + off, D.v_tile, D.v_tiles, D.v_ent, D.v_ent_len, vs.tiles, vs.ent);
+    if constexpr (SC)
+        off += stage_side<kThreads>(smem + off, D.c_tile, D.c_tiles, D.c_ent, D.c_ent_len, cs.tiles, cs.ent);
+    if constexpr (SV)
+        off += stage_side<kThreads>(smem + off, D.v_tile, D.v_tiles, D.v_ent, D.v_ent_len, vs.tiles, vs.ent);
 
     const AdamCoef co{D.b1, D.b2, D.eps, D.omb1, D.omb2};
     uint8_t* best_a = D.best_a + (size_t)r * n;
@@ -328,28 +332,38 @@ size_t small_lds_total(const HostPlan& P, size_t limit, int32_t* stage) {
 
 size_t small_static_lds() {
     hipFuncAttributes attr{};
-    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_small<true, true>)) != hipSuccess) return 16384;
+    // the widest workgroup has the most static LDS (the per-wavefront partials)
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_small<true, true, 16>)) != hipSuccess) return 16384;
     return attr.sharedSizeBytes;
 }
 
-template <bool SC, bool SV>
+template <bool SC, bool SV, int NW>
 hipError_t launch_small_as(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV, NW>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_small<SC, SV>), dim3(blocks), dim3(kThreads), lds_bytes, s, d_descs, n_desc);
+    hipLaunchKernelGGL((k_small<SC, SV, NW>), dim3(blocks), dim3(NW * 64), lds_bytes, s, d_descs, n_desc);
     return hipGetLastError();
 }
 
-hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
-                        hipStream_t s) {
+template <int NW>
+hipError_t launch_small_nw(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
+                           hipStream_t s) {
     switch (stage & 3) {
-        case 0: return launch_small_as<false, false>(d_descs, n_desc, blocks, lds_bytes, s);
-        case 1: return launch_small_as<true, false>(d_descs, n_desc, blocks, lds_bytes, s);
-        case 2: return launch_small_as<false, true>(d_descs, n_desc, blocks, lds_bytes, s);
-        default: return launch_small_as<true, true>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 0: return launch_small_as<false, false, NW>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 1: return launch_small_as<true, false, NW>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 2: return launch_small_as<false, true, NW>(d_descs, n_desc, blocks, lds_bytes, s);
+        default: return launch_small_as<true, true, NW>(d_descs, n_desc, blocks, lds_bytes, s);
     }
+}
+
+int small_waves(int32_t rows) { return rows <= kSmallRows4 ? 4 : 16; }
+
+hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
+                        int32_t rows, hipStream_t s) {
+    if (small_waves(rows) == 4) return launch_small_nw<4>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+    return launch_small_nw<16>(d_descs, n_desc, blocks, lds_bytes, stage, s);
 }
 
 }  // namespace hms

@@ -55,7 +55,12 @@ size_t small_static_lds();
 // running sum of the restart counts, `blocks` the total.  `stage` (SmallDesc
 // bits) names the plan sides staged in LDS; every instance of the launch must
 // have them (its stage bits include these).
+// `rows` is the largest clause-side or variable-side row count (tiles * 64)
+// among the launch's instances; it picks the wavefronts per workgroup: four
+// when one pass of them covers every row (up to kSmallRows4), else sixteen.
+constexpr int32_t kSmallRows4 = 256;
+int small_waves(int32_t rows);
 hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
-                        hipStream_t s);
+                        int32_t rows, hipStream_t s);
 
 }  // namespace hms
