@@ -136,7 +136,7 @@ typedef struct {
     int64_t best_cost;        /* fewest unsatisfied clauses seen over all restarts */
     int32_t best_restart;     /* restart that found it (lowest index on ties) */
     int32_t best_step;        /* step at which it was found (-1: the initial point never beaten) */
-    int32_t steps_done;       /* steps taken (< steps only with a time limit) */
+    int32_t steps_done;       /* steps taken (< steps only with a time limit or a cancel) */
     int32_t schedule;         /* kernel schedule that ran */
     double final_loss;        /* loss at x_T of best_restart */
     uint8_t* best_assignment; /* caller HOST buffer of n bytes (0/1), or NULL */
