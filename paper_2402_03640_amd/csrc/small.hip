@@ -84,7 +84,6 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
     __shared__ int64_t red_c[kWaves];
     __shared__ double red_l[kWaves];
     __shared__ float2 s_sc[kScal];
-    __shared__ int s_improved;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -147,12 +146,13 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
         L.t[n] = -0.0f;
         L.a[crows] = 0.0f;
     }
-    int64_t best = D.best0;  // thread 0's copy is the one kept
+    int64_t best = D.best0;  // every thread tracks it; thread 0's copy is stored
     int best_step = -1;
     __syncthreads();
 
     for (int step = 0; step <= D.T; ++step) {
         const bool eval = (step % D.K == 0) || step == D.T;
+        const bool want_loss = step == D.T;  // the loss is reported at x_T only
         if (D.opt != kSgd && step % kScal == 0 && step < D.T) {
             // the previous block of scalars is no longer read: the last step
             // ended with a barrier
@@ -200,14 +200,20 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
             L.a[row] = mu ? (f * (float)wj) * D.two_over_m : 0.0f;
             if (eval) {
                 cnt += unsat ? wj : 0;
-                los += mu ? ((double)f * (double)f) * (double)wj : 0.0;
+                if (want_loss) los += mu ? ((double)f * (double)f) * (double)wj : 0.0;
             }
         }
         if (eval) {
-            for (int o2 = 32; o2 >= 1; o2 >>= 1) {
-                cnt += __shfl_xor(cnt, o2);
-                los += __shfl_xor(los, o2);
+            if (D.c_w == nullptr) {
+                // unweighted: a wavefront's count fits 32 bits
+                int c32 = (int)cnt;
+                for (int o2 = 32; o2 >= 1; o2 >>= 1) c32 += __shfl_xor(c32, o2);
+                cnt = c32;
+            } else {
+                for (int o2 = 32; o2 >= 1; o2 >>= 1) cnt += __shfl_xor(cnt, o2);
             }
+            if (want_loss)
+                for (int o2 = 32; o2 >= 1; o2 >>= 1) los += __shfl_xor(los, o2);
             if (lane == 0) {
                 red_c[wave] = cnt;
                 red_l[wave] = los;
@@ -215,22 +221,20 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
         }
         __syncthreads();
         if (eval) {
-            // one thread sums the wave partials in wave order and broadcasts
-            // whether the count improved
-            if (tid == 0) {
-                int64_t c = 0;
+            // every thread sums the wavefront partials itself (the same exact
+            // total everywhere) and keeps its own copy of the best, so no
+            // second barrier has to broadcast the outcome; the partials are
+            // rewritten only after the barrier that ends this step
+            int64_t c = D.w_empty;
+            for (int w = 0; w < kWaves; ++w) c += red_c[w];
+            const bool improved = c < best;
+            if (improved) best = c;
+            if (want_loss && tid == 0) {
                 double l = 0.0;
-                for (int w = 0; w < kWaves; ++w) {
-                    c += red_c[w];
-                    l = l + red_l[w];
-                }
-                c += D.w_empty;
-                s_improved = c < best ? 1 : 0;
-                if (c < best) best = c;
-                if (step == D.T) D.final_loss[r] = l * D.inv_m;
+                for (int w = 0; w < kWaves; ++w) l = l + red_l[w];
+                D.final_loss[r] = l * D.inv_m;
             }
-            __syncthreads();
-            if (s_improved) {
+            if (improved) {
                 best_step = step;
                 for (int i = tid; i < D.n_act; i += kThreads) best_a[D.var_old[i]] = L.x[i] > 0.0f ? 1 : 0;
                 __syncthreads();
