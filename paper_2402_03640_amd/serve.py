@@ -27,11 +27,12 @@ from . import _lib
 SMALL_ROWS = 12000
 
 
-def footprint_bytes(n: int, m: int, n_lits: int, restarts: int = 1) -> int:
-    """Device bytes of one solve: plan (both sparse layouts, tiles, offsets)
-    plus per-restart state (x, m, v, t, adjoint, best bytes, heavy partials)."""
+def footprint_bytes(n: int, m: int, n_lits: int, restarts: int = 1, weighted: bool = False) -> int:
+    """Device bytes of one solve: plan (both sparse layouts, tiles, offsets,
+    clause weights) plus per-restart state (x, m, v, t, adjoint, best bytes,
+    heavy partials)."""
     L = max(n_lits, 0)
-    struct = 4 * (2 * L + m + n + 2) + 16 * (m + n) // 64 + 4 * n + 8 * L // 64
+    struct = 4 * (2 * L + m + n + 2) + 16 * (m + n) // 64 + 4 * n + 8 * L // 64 + (8 * (m + 64) if weighted else 0)
     state = restarts * (16 * (n + 1) + 4 * (m + 64) + (n + 1) + 8 * L // 64) + 4096
     return int(1.25 * (struct + state)) + (1 << 16)
 
@@ -102,7 +103,9 @@ class Server:
         req = Request(n=int(n), lits=lits, params=params,
                       arrival=time.perf_counter() if arrival is None else arrival,
                       weights=None if weights is None else np.ascontiguousarray(weights, dtype=np.int64))
-        req.footprint = footprint_bytes(n, m, lits.size - m, R)
+        if req.weights is not None and req.weights.size != m:
+            raise ValueError(f"{req.weights.size} clause weights for {m} clauses")
+        req.footprint = footprint_bytes(n, m, lits.size - m, R, req.weights is not None)
         req.small = (n + m) <= SMALL_ROWS
         with self._cv:
             if self._closed:
