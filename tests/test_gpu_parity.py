@@ -14,7 +14,7 @@ import pytest
 import cnfgen
 import oracle as O
 
-from _helpers import assert_eval_parity, edge_case_cnf, w_abs_matrix
+from _helpers import assert_eval_parity, edge_case_cnf, tolerance_terms, w_abs_matrix
 
 pytestmark = pytest.mark.gpu
 
@@ -284,6 +284,48 @@ def test_step_parity_adam():
         d_o = ro["x"] - x0
         assert np.all(np.abs(d_g - d_o) <= 1e-5 * np.abs(d_o) * steps + 2e-7 * np.abs(x0) + 1e-12), steps
         np.testing.assert_array_equal(res.restart_best, ro["restart_best"])
+
+
+@pytest.mark.parametrize("kind", ["headline", "structured"])
+def test_bench_schedule_full_size_step(kind):
+    """At the benchmark sizes and in the schedules the benchmark times (64
+    restarts: table entry 34 with 32/8 rows per unit; one restart on the
+    structured instance: entry 37), one Adam step from x0 with |x| >= 0.05:
+    bitwise equal to another schedule's step, counts equal to the
+    oracle's, and the step within tolerance of the oracle's wherever the
+    gradient's sign is well determined (|g| > 1e-3 S_i)."""
+    if kind == "headline":
+        n, m, R, sched, other = 20000, 86000, 64, 34 | (32 << 8) | (8 << 16), 15
+        lits = cnfgen.uniform_kcnf(n, m, 3, seed=21)
+    else:
+        n, m, R, sched, other = 500000, 2500000, 1, 37, 23
+        lits = cnfgen.structured_cnf(n, m, seed=3)
+    rng = np.random.default_rng(77)
+    x0 = (rng.uniform(0.05, 1.0, (n, R)) * np.where(rng.random((n, R)) < 0.5, -1, 1)).astype(np.float32)
+    cnf = hm.load_cnf(n, lits)
+    xt = torch.from_numpy(x0).cuda()
+    kw = dict(steps=1, restarts=R, eval_every=1, x0=xt, lr=1e-4, want_x=True)
+    a = hm.solve(cnf, schedule=sched, **kw)
+    b = hm.solve(cnf, schedule=other, **kw)
+    _say(f"{kind}: schedule {a.schedule} vs {b.schedule}")
+    assert (a.schedule & 0xff) == (sched & 0xff) and (b.schedule & 0xff) == other
+    xa = a.x_final.cpu().numpy()
+    np.testing.assert_array_equal(xa.view(np.uint32), b.x_final.cpu().numpy().view(np.uint32))
+    np.testing.assert_array_equal(a.restart_best, b.restart_best)
+    oc = O.OracleCNF(n, lits)
+    ro = oc.solve(steps=1, restarts=R, eval_every=1, x0=x0, lr=1e-4, want_x=True)
+    np.testing.assert_array_equal(a.restart_best, ro["restart_best"])
+    _, go, _, _, muo = oc.loss_grad(x0, hm.LOSS_UNSAT, want_f=True)
+    _, S = tolerance_terms(w_abs_matrix(n, lits), x0, muo, m)
+    go = go.reshape(n, R)
+    robust = np.abs(go) > 1e-3 * S
+    d_g = xa.astype(np.float64) - x0
+    d_o = ro["x"].reshape(n, R) - x0
+    err = np.abs(d_g - d_o)[robust]
+    bound = (1e-5 * np.abs(d_o) + 2e-7 * np.abs(x0) + 1e-12)[robust]
+    _say(f"{kind}: {robust.sum()} of {robust.size} coordinates compared, max err / bound {np.max(err / bound):.2e}")
+    assert robust.sum() >= 0.5 * np.count_nonzero(S)
+    assert np.all(err <= bound)
 
 
 def test_sgd_worked_example_step(golden):
