@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -814,13 +815,16 @@ hms_status resolve_schedule(const hms_cnf* cnf, const hms_solve_params* p, int32
 constexpr int32_t kResident = kResidentId;  // schedule id of the resident solver
 
 size_t lds_limit(int dev) {
-    static size_t cached[64] = {0};
-    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    static std::atomic<size_t> cached[64] = {};  // per device; solves on several threads may fill it at once
+    if (dev >= 0 && dev < 64) {
+        const size_t c = cached[dev].load(std::memory_order_relaxed);
+        if (c) return c;
+    }
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
     const size_t stat = hms::small_static_lds();  // the kernel's own LDS comes on top
     const size_t lim = (size_t)v > stat ? (size_t)v - stat : 0;
-    if (dev >= 0 && dev < 64) cached[dev] = lim;
+    if (dev >= 0 && dev < 64) cached[dev].store(lim, std::memory_order_relaxed);
     return lim;
 }
 
