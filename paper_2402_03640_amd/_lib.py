@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import threading
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -78,13 +79,19 @@ EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_
            "hms_solve_batch", "hms_tune_candidates", "hms_load_wcnf"]
 
 _lib = None
+_lib_lock = threading.Lock()
 
 
 def lib():
     """Load the library (raises if it has not been built)."""
-    global _lib
     if _lib is not None:
         return _lib
+    with _lib_lock:
+        return _lib if _lib is not None else _load()
+
+
+def _load():
+    global _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_03640_amd.build`")
     # torch first: it brings its own HIP runtime (same soname), which the
