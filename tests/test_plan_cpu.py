@@ -146,6 +146,36 @@ def test_plan_dense_rows_kept_whole():
     assert P.split_len == P.seg_len and P.n_heavy > 0
 
 
+def _random_clauses(data, n, m, lo, hi):
+    """Clauses of lo..hi literals over n variables, with repeats, complementary
+    pairs and empty clauses all possible."""
+    from hypothesis import strategies as st
+    lit = st.integers(1, n).flatmap(lambda v: st.sampled_from([v, -v]))
+    return data.draw(st.lists(st.lists(lit, min_size=lo, max_size=hi), min_size=m, max_size=m))
+
+
+def test_plan_random_formulas_property():
+    """Random formulas (any mix of lengths, repeats, tautologies and empty
+    clauses; sparse and dense): both layouts are exact, the interleaved
+    segments hold every entry once, and the split threshold follows the rule."""
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+
+    @settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+    @given(st.data())
+    def run(data):
+        n = data.draw(st.integers(1, 40))
+        m = data.draw(st.integers(0, 120))
+        if data.draw(st.booleans()):
+            clauses = _random_clauses(data, n, m, 0, 14)
+        else:  # few variables, many long clauses: long rows, heavy or dense
+            clauses = _random_clauses(data, min(n, 6), max(m, 60), 3, 14)
+            n = min(n, 6)
+        _check_plan(n, cnfgen.from_clauses(clauses))
+
+    run()
+
+
 def test_tune_candidates():
     """The autotuner's candidate list (host only): valid table entries and
     rows per unit, bitset variants only with the unsat-masked loss."""
