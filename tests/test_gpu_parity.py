@@ -60,6 +60,31 @@ def test_eval_edge_cases(mode, R):
     _eval_both(n, lits, x, mode)
 
 
+def _random_formula(rng, n, m):
+    """Clauses of 0..20 literals (some past the 16 of the FP32 score path),
+    with repeated literals and complementary pairs."""
+    clauses = []
+    for _ in range(m):
+        k = int(rng.choice([0, 1, 2, 3, 3, 4, 5, 8, 17, 20], p=[.02, .05, .2, .3, .15, .1, .08, .05, .03, .02]))
+        vs = rng.integers(1, n + 1, k)
+        clauses.append([int(v) * (1 if rng.random() < 0.5 else -1) for v in vs])
+    return cnfgen.from_clauses(clauses)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_eval_random_formulas(seed):
+    """Seeded random formulas of mixed shape, 1 to 5 restarts, both loss
+    modes (special x values included): counts exact, loss and gradient within
+    tolerance of the oracle."""
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 300))
+    m = int(rng.integers(1, 6 * n))
+    lits = _random_formula(rng, n, m)
+    R = int(rng.integers(1, 6))
+    for mode in (hm.LOSS_UNSAT, hm.LOSS_ALL):
+        _eval_both(n, lits, _x(n, R, seed=2000 + seed, lo=-3, hi=3, specials=True), mode)
+
+
 @pytest.mark.parametrize("mode", [hm.LOSS_UNSAT, hm.LOSS_ALL])
 def test_eval_worked_example(mode, golden):
     g = golden("worked_example.txt")
