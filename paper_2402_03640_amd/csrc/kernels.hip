@@ -568,6 +568,18 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
         for (int j = 0; j < UR; ++j)
 #pragma unroll
             for (int k = 0; k < V; ++k) G[j][k] = 0.0;
+        // with one value per lane the epilogue's x, m, v loads go out before
+        // the transposed sums, so they wait alongside the gathers (wider
+        // schedules would lose a wave per SIMD to the registers)
+        constexpr bool kEarly = V * UR == 1;
+        VarState<V, OPT> st[UR];
+        if (kEarly && !segtile) {
+#pragma unroll
+            for (int j = 0; j < UR; ++j)
+                if (rowin0 + j < (int)d.nreal)
+                    st[j] = var_load<V, OPT>(
+                        A, xbase + (size_t)(A.n_heavy + (tile * kTile + rowin0 + j - A.seg_tiles * kTile)) * B.G + rl);
+        }
         for (uint32_t c0 = 0; c0 < d.len; c0 += CB) {
             // all entry loads of the chunk, then all gathers, then the sums in
             // column order; columns past the row's end read the padding entry
@@ -621,7 +633,10 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
                 for (int k = 0; k < V; ++k) sg[(size_t)row * B.G + rl + k] = G[j][k];
             } else {
                 const int var = A.n_heavy + (row - A.seg_tiles * kTile);
-                var_epilogue<V, OPT>(A, xbase + (size_t)var * B.G + rl, r0, G[j]);
+                if constexpr (kEarly)
+                    var_epilogue<V, OPT>(A, xbase + (size_t)var * B.G + rl, r0, G[j], st[j]);
+                else
+                    var_epilogue<V, OPT>(A, xbase + (size_t)var * B.G + rl, r0, G[j]);
             }
         }
     }
