@@ -354,7 +354,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solve loop is benchmarked on a single MI355X; "
-              "restarts and instances shard across GPUs without communication (see DESIGN.md), "
+              "restarts and instances shard across GPUs without communication, "
               "no multi-GPU figure is produced.", file=sys.stderr)
         sys.exit(2)
 
