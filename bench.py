@@ -103,12 +103,13 @@ def counters_summary(dirs):
                      "over launches, each scaled by (256 MiB / the counter's reading for the 256 MiB device "
                      "copy made in the same run)",
            "configs": {}}
+    base = os.path.dirname(os.path.normpath(dirs[0])) if dirs else "."
     lines = ["# HBM traffic per launch from rocprofv3 counters (calibrated)",
              "# commands (one run per counter, config and schedule):",
-             "#   rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d gpurun_out/pmc_<cfg>_<sched>_FETCH_SIZE -o pmc "
+             f"#   rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d {base}/pmc_<cfg>_<sched>_FETCH_SIZE -o pmc "
              "-- python -u bench.py --config <cfg> --kernels-only --kernel-iters 20 --schedule <sched>",
              "#   (the same with WRITE_SIZE)",
-             "#   python bench.py --counters-summary gpurun_out/pmc_*",
+             f"#   python bench.py --counters-summary {base}/pmc_<cfg>_<sched>_<counter> ...",
              "# columns: config, schedule, kernel, launches, FETCH KiB avg, WRITE KiB avg, FETCH factor, "
              "WRITE factor, calibrated MB per launch, algorithmic MB per launch"]
     for (config, sched), ctr in sorted(runs.items()):
