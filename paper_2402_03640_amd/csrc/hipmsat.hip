@@ -557,7 +557,8 @@ hms_status setup_solve(const hms_cnf* cnf, const hms_solve_params* p, SolveSetup
     if (!std::isfinite(p->lr) || !std::isfinite(p->beta1) || !std::isfinite(p->beta2) || !std::isfinite(p->eps))
         return fail(HMS_ERR_ARG, "non-finite optimizer parameter");
     const hms::HostPlan& P = cnf->plan;
-    if ((int64_t)(P.n + 1) * R > ((int64_t)1 << 40)) return fail(HMS_ERR_TOO_LARGE, "state too large");
+    // state elements per array; the element-wise kernels' grids (256 per workgroup) stay within 2^31
+    if ((int64_t)(P.n + 1) * R > ((int64_t)1 << 38)) return fail(HMS_ERR_TOO_LARGE, "state too large");
     hipStream_t s = (hipStream_t)p->stream;
     hms_status rc = make_shape(P, R, p->schedule, p->loss_mode, Z.sh);
     if (rc) return rc;

@@ -353,6 +353,26 @@ def test_bench_schedule_full_size_step(kind):
     assert np.all(err <= bound)
 
 
+def test_state_past_2_31_elements():
+    """64-bit indexing: 4.2M variables x 512 restarts puts 2.15e9 elements in
+    each state array, past 2^31.  Restarts of the batched solve equal
+    single-restart solves with seed + r, bit for bit, at sampled r."""
+    n, m, R = 4_200_000, 1_000_000, 512
+    assert n * R > 2 ** 31
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=31)
+    cnf = hm.load_cnf(n, lits)
+    kw = dict(steps=2, eval_every=1, lr=1e-2, want_x=True, autotune=False)
+    a = hm.solve(cnf, restarts=R, seed=7, **kw)
+    _say(f"n={n} R={R}: schedule {a.schedule}, best {a.best_cost}")
+    for r in (0, 1, 257, 511):
+        b = hm.solve(cnf, restarts=1, seed=7 + r, **kw)
+        assert a.restart_best[r] == b.restart_best[0]
+        np.testing.assert_array_equal(a.x_final[:, r].cpu().numpy().view(np.uint32),
+                                      b.x_final[:, 0].cpu().numpy().view(np.uint32))
+    del a
+    torch.cuda.empty_cache()
+
+
 def test_sgd_worked_example_step(golden):
     g = golden("worked_example.txt")
     lits = np.array(g["clauses"], np.int32)
