@@ -254,6 +254,17 @@ def test_eval_dense_rows_whole():
         _eval_both(n, lits, _x(n, R, seed=55 + R), mode)
 
 
+def test_eval_very_long_clause():
+    """One clause over 20000 distinct variables (one FP64 row of 20000
+    columns; its tile pads the other 63 rows to that length) among short ones."""
+    n = 30000
+    rng = np.random.default_rng(41)
+    long = (rng.permutation(n)[:20000] + 1) * np.where(rng.random(20000) < 0.5, -1, 1)
+    lits = np.concatenate([cnfgen.uniform_kcnf(n, 60000, 3, seed=41), long.astype(np.int32), [0]]).astype(np.int32)
+    for R, mode in ((1, hm.LOSS_ALL), (2, hm.LOSS_UNSAT)):
+        _eval_both(n, lits, _x(n, R, seed=410 + R), mode)
+
+
 def test_eval_cfg3_full_size():
     n, m = 500000, 2500000
     lits = cnfgen.structured_cnf(n, m, seed=3)
