@@ -740,6 +740,7 @@ __device__ __forceinline__ void reduce1_body(const ReduceArgs& A, const int bx, 
     int64_t c = 0;
     double l = 0.0;
     if (r < A.R) {
+#pragma unroll 8
         for (int u = u0 + slot; u < u1; u += NS) {
             c += A.cnt_part[(size_t)u * A.R + r];
             l = l + A.loss_part[(size_t)u * A.R + r];
@@ -789,6 +790,7 @@ __device__ __forceinline__ void reduce2_body(const ReduceArgs& A, const int bx, 
     int64_t c = 0;
     double l = 0.0;
     if (r < A.R) {
+#pragma unroll 8
         for (int u = slot; u < A.n_chunks; u += NS) {
             c += A.cnt_mid[(size_t)u * A.R + r];
             l = l + A.loss_mid[(size_t)u * A.R + r];
