@@ -676,6 +676,18 @@ hms_status time_steps(const hms_cnf* cnf, const hms_solve_params* p0, int32_t co
         HIPTRY(hipEventRecord(E.e[0], s));
         HIPTRY(hipGraphLaunch(gr.x, s));
         HIPTRY(hipEventRecord(E.e[1], s));
+        HIPTRY(hipStreamSynchronize(s));
+        float t1 = 0;
+        HIPTRY(hipEventElapsedTime(&t1, E.e[0], E.e[1]));
+        // short steps: replay until about 2 ms are timed, so launch jitter
+        // does not decide between near-equal schedules
+        const int reps = t1 > 0 ? std::min(64, (int)std::ceil(2.0 / t1)) : 1;
+        if (reps > 1) {
+            HIPTRY(hipEventRecord(E.e[0], s));
+            for (int k = 0; k < reps; ++k) HIPTRY(hipGraphLaunch(gr.x, s));
+            HIPTRY(hipEventRecord(E.e[1], s));
+            iters *= reps;
+        }
     } else {
         HIPTRY(hipEventRecord(E.e[0], s));
         for (int32_t i = 0; i < iters; ++i) HIPTRY(enqueue_step(Z.L, i % K == 0, s));
