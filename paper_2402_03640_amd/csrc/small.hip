@@ -73,10 +73,18 @@ __device__ size_t stage_side(unsigned char* dst, const TileDesc* tiles, int32_t 
     return side_bytes(ntiles, nent);
 }
 
+// Register-cached plan: with one clause row and one variable row per thread,
+// a thread keeps its rows' entries in registers for the whole solve (clause
+// rows up to kRegF entries, variable rows up to kRegB).
+constexpr int kRegF = 16;
+constexpr int kRegB = 32;
+
 // SC / SV: the clause / variable side is staged in LDS (for every instance of
 // the launch).  NW wavefronts per workgroup: four when one pass of them covers
 // every row (the barriers and the count reduction then cost less), else 16.
-template <bool SC, bool SV, int NW>
+// REG (four wavefronts only): the thread's two rows' entries are kept in
+// registers, so a step reads only the relaxed values and adjoints from LDS.
+template <bool SC, bool SV, int NW, bool REG>
 __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__ descs, int32_t n_desc) {
     constexpr int kThreads = NW * 64;
     constexpr int kWaves = NW;
@@ -148,6 +156,35 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
     }
     int64_t best = D.best0;  // every thread tracks it; thread 0's copy is stored
     int best_step = -1;
+
+    // this thread's clause row and variable row, entries in registers (REG);
+    // entries past a row's end are the padding entries, which add nothing
+    uint32_t fen[kRegF], ben[kRegB];
+    uint32_t f_len = 0, b_len = 0;
+    bool f_real = false, f_taut = false, b_real = false;
+    int64_t f_w = 1;
+    if constexpr (REG) {
+        if (tid < crows) {
+            const TileDesc d = cs.tile(tid >> 6);
+            const int rowin = tid & 63;
+            f_len = d.len;
+            f_real = rowin < (int)d.nreal;
+            f_taut = (d.flags & 1u) != 0;
+            f_w = (D.c_w != nullptr && f_real) ? D.c_w[tid] : 1;
+#pragma unroll
+            for (int c = 0; c < kRegF; ++c)
+                fen[c] = c < (int)d.len ? cs.entry((size_t)d.base + rowin + (size_t)c * kTile) : (uint32_t)n;
+        }
+        if (tid < vrows) {
+            const TileDesc d = vs.tile(tid >> 6);
+            const int rowin = tid & 63;
+            b_len = d.len;
+            b_real = rowin < (int)d.nreal;
+#pragma unroll
+            for (int c = 0; c < kRegB; ++c)
+                ben[c] = c < (int)d.len ? vs.entry((size_t)d.base + rowin + (size_t)c * kTile) : (uint32_t)crows;
+        }
+    }
     __syncthreads();
 
     for (int step = 0; step <= D.T; ++step) {
@@ -166,6 +203,34 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
         // ---- clause scores, mask, adjoint ------------------------------------
         int64_t cnt = 0;
         double los = 0.0;
+        // a clause row's outputs: adjoint, count and loss partials
+        auto clause_out = [&](int row, float f, uint32_t allf, bool real, bool taut, int64_t wj) {
+            const bool unsat = real && !taut && (allf >> 31) != 0;
+            const bool mu = real && (D.all_mode ? true : unsat);
+            L.a[row] = mu ? (f * (float)wj) * D.two_over_m : 0.0f;
+            if (eval) {
+                cnt += unsat ? wj : 0;
+                if (want_loss) los += mu ? ((double)f * (double)f) * (double)wj : 0.0;
+            }
+        };
+        if constexpr (REG) {
+            if (tid < crows) {
+                float f = 0.0f;
+                uint32_t allf = ~0u;
+#pragma unroll
+                for (int c0 = 0; c0 < kRegF; c0 += 4)
+                    if (c0 < (int)f_len) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const uint32_t en = fen[c0 + k];
+                            const uint32_t b = __float_as_uint(L.t[en & kIdx]) ^ (en & kSign);
+                            f = f + __uint_as_float(b);
+                            allf &= b;
+                        }
+                    }
+                clause_out(tid, f, allf, f_real, f_taut, f_w);
+            }
+        } else
         for (int row = tid; row < crows; row += kThreads) {
             const int tile = row >> 6;
             const int rowin = row & 63;
@@ -193,15 +258,9 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
                 f = (float)fd;
             }
             const bool real = rowin < (int)d.nreal;
-            const bool unsat = real && !(d.flags & 1u) && (allf >> 31) != 0;
-            const bool mu = real && (D.all_mode ? true : unsat);
             // clause weight (1 without weights), as in the tiled forward pass
             const int64_t wj = (D.c_w != nullptr && real) ? D.c_w[row] : 1;
-            L.a[row] = mu ? (f * (float)wj) * D.two_over_m : 0.0f;
-            if (eval) {
-                cnt += unsat ? wj : 0;
-                if (want_loss) los += mu ? ((double)f * (double)f) * (double)wj : 0.0;
-            }
+            clause_out(row, f, allf, real, (d.flags & 1u) != 0, wj);
         }
         if (eval) {
             if (D.c_w == nullptr) {
@@ -244,18 +303,10 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
         // ---- transposed sums, fused optimizer step ---------------------------
         const float2 sc = D.opt != kSgd ? s_sc[step % kScal] : make_float2(0.0f, 1.0f);
         const float ss = sc.x, ib2 = sc.y;
-        for (int row = tid; row < vrows; row += kThreads) {
+        // a variable row's outputs: a segment partial, or the gradient and the
+        // optimizer step
+        auto var_out = [&](int row, double G) {
             const int tile = row >> 6;
-            const int rowin = row & 63;
-            const TileDesc d = vs.tile(tile);
-            if (rowin >= (int)d.nreal) continue;
-            const size_t e = (size_t)d.base + rowin;
-            double G = 0.0;
-#pragma unroll 4
-            for (uint32_t c = 0; c < d.len; ++c) {
-                const uint32_t en = vs.entry(e + (size_t)c * kTile);
-                G = G + (double)__uint_as_float(__float_as_uint(L.a[en & kIdx]) ^ (en & kSign));
-            }
             if (tile < D.seg_tiles) {
                 L.seg[row] = G;
             } else {
@@ -273,6 +324,35 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
                 L.x[var] = x;
                 L.t[var] = signed_tanh(x);
             }
+        };
+        if constexpr (REG) {
+            if (tid < vrows && b_real) {
+                double G = 0.0;
+#pragma unroll
+                for (int c0 = 0; c0 < kRegB; c0 += 8)
+                    if (c0 < (int)b_len) {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const uint32_t en = ben[c0 + k];
+                            G = G + (double)__uint_as_float(__float_as_uint(L.a[en & kIdx]) ^ (en & kSign));
+                        }
+                    }
+                var_out(tid, G);
+            }
+        } else
+        for (int row = tid; row < vrows; row += kThreads) {
+            const int tile = row >> 6;
+            const int rowin = row & 63;
+            const TileDesc d = vs.tile(tile);
+            if (rowin >= (int)d.nreal) continue;
+            const size_t e = (size_t)d.base + rowin;
+            double G = 0.0;
+#pragma unroll 4
+            for (uint32_t c = 0; c < d.len; ++c) {
+                const uint32_t en = vs.entry(e + (size_t)c * kTile);
+                G = G + (double)__uint_as_float(__float_as_uint(L.a[en & kIdx]) ^ (en & kSign));
+            }
+            var_out(row, G);
         }
         if (D.n_heavy > 0) {
             __syncthreads();
@@ -337,37 +417,49 @@ size_t small_lds_total(const HostPlan& P, size_t limit, int32_t* stage) {
 size_t small_static_lds() {
     hipFuncAttributes attr{};
     // the widest workgroup has the most static LDS (the per-wavefront partials)
-    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_small<true, true, 16>)) != hipSuccess) return 16384;
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_small<true, true, 16, false>)) != hipSuccess) return 16384;
     return attr.sharedSizeBytes;
 }
 
-template <bool SC, bool SV, int NW>
+template <bool SC, bool SV, int NW, bool REG>
 hipError_t launch_small_as(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV, NW>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV, NW, REG>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_small<SC, SV, NW>), dim3(blocks), dim3(NW * 64), lds_bytes, s, d_descs, n_desc);
+    hipLaunchKernelGGL((k_small<SC, SV, NW, REG>), dim3(blocks), dim3(NW * 64), lds_bytes, s, d_descs, n_desc);
     return hipGetLastError();
 }
 
-template <int NW>
+template <int NW, bool REG>
 hipError_t launch_small_nw(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
                            hipStream_t s) {
     switch (stage & 3) {
-        case 0: return launch_small_as<false, false, NW>(d_descs, n_desc, blocks, lds_bytes, s);
-        case 1: return launch_small_as<true, false, NW>(d_descs, n_desc, blocks, lds_bytes, s);
-        case 2: return launch_small_as<false, true, NW>(d_descs, n_desc, blocks, lds_bytes, s);
-        default: return launch_small_as<true, true, NW>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 0: return launch_small_as<false, false, NW, REG>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 1: return launch_small_as<true, false, NW, REG>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 2: return launch_small_as<false, true, NW, REG>(d_descs, n_desc, blocks, lds_bytes, s);
+        default: return launch_small_as<true, true, NW, REG>(d_descs, n_desc, blocks, lds_bytes, s);
     }
 }
 
 int small_waves(int32_t rows) { return rows <= kSmallRows4 ? 4 : 16; }
 
+bool small_reg_ok(const HostPlan& P) {
+    if (std::max(P.c_tiles, P.v_tiles) * kTile > kSmallRows4) return false;
+    for (const TileDesc& d : P.c_tile)
+        if (d.len > (uint32_t)kRegF) return false;
+    for (const TileDesc& d : P.v_tile)
+        if (d.len > (uint32_t)kRegB) return false;
+    return true;
+}
+
 hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
-                        int32_t rows, hipStream_t s) {
-    if (small_waves(rows) == 4) return launch_small_nw<4>(d_descs, n_desc, blocks, lds_bytes, stage, s);
-    return launch_small_nw<16>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+                        int32_t rows, bool reg, hipStream_t s) {
+    if (small_waves(rows) == 4) {
+        if (reg) return launch_small_nw<4, true>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+        return launch_small_nw<4, false>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+    }
+    return launch_small_nw<16, false>(d_descs, n_desc, blocks, lds_bytes, stage, s);
 }
 
 }  // namespace hms

@@ -60,7 +60,11 @@ size_t small_static_lds();
 // when one pass of them covers every row (up to kSmallRows4), else sixteen.
 constexpr int32_t kSmallRows4 = 256;
 int small_waves(int32_t rows);
+// True when a four-wavefront workgroup can keep each thread's clause row (up
+// to 16 entries) and variable row (up to 32) in registers; `reg` of a launch
+// must hold for every instance in it.
+bool small_reg_ok(const HostPlan& P);
 hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
-                        int32_t rows, hipStream_t s);
+                        int32_t rows, bool reg, hipStream_t s);
 
 }  // namespace hms
