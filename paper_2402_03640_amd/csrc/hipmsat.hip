@@ -938,7 +938,7 @@ hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_sol
     HIPTRY(hipMemcpyAsync(A.base + o_desc, &D, sizeof(D), hipMemcpyHostToDevice, s));
     HIPTRY(hipEventRecord(E.e[0], s));
     HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc), 1, R, resident_lds(cnf), D.stage, resident_rows(cnf),
-                             hms::small_reg_ok(cnf->plan), s));
+                             hms::small_reg_ok(cnf->plan, resident_rows(cnf)), s));
     HIPTRY(hipEventRecord(E.e[1], s));
     std::vector<int64_t> best(R);
     std::vector<int32_t> bstep(R);
@@ -1412,13 +1412,13 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
             int32_t blocks = 0;
             int32_t stage = 3;  // the sides every instance of the group stages
             int32_t rows = 0;
-            bool reg = true;  // every instance keeps its rows in registers
             for (size_t k = g.first; k < g.second; ++k) {
                 blocks += params[res_idx[k]].restarts;
                 stage &= D[k].stage;
                 rows = std::max(rows, resident_rows(cnfs[res_idx[k]]));
-                reg = reg && hms::small_reg_ok(cnfs[res_idx[k]]->plan);
             }
+            bool reg = true;  // every instance keeps its rows in registers
+            for (size_t k = g.first; k < g.second; ++k) reg = reg && hms::small_reg_ok(cnfs[res_idx[k]]->plan, rows);
             HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc) + g.first, (int32_t)(g.second - g.first), blocks,
                                      resident_lds(cnfs[res_idx[g.first]]), stage, rows, reg, s));
         }

@@ -73,18 +73,18 @@ __device__ size_t stage_side(unsigned char* dst, const TileDesc* tiles, int32_t 
     return side_bytes(ntiles, nent);
 }
 
-// Register-cached plan: with one clause row and one variable row per thread,
-// a thread keeps its rows' entries in registers for the whole solve (clause
-// rows up to kRegF entries, variable rows up to kRegB).
-constexpr int kRegF = 16;
+// Register-cached plan: a thread keeps the entries of its RF clause rows (up
+// to FE entries each) and of its one variable row (up to kRegB) in registers
+// for the whole solve.
 constexpr int kRegB = 32;
 
 // SC / SV: the clause / variable side is staged in LDS (for every instance of
 // the launch).  NW wavefronts per workgroup: four when one pass of them covers
 // every row (the barriers and the count reduction then cost less), else 16.
-// REG (four wavefronts only): the thread's two rows' entries are kept in
-// registers, so a step reads only the relaxed values and adjoints from LDS.
-template <bool SC, bool SV, int NW, bool REG>
+// RF > 0: the thread's rows' entries are kept in registers (RF clause rows of
+// up to FE entries, one variable row), so a step reads only the relaxed values
+// and adjoints from LDS.
+template <bool SC, bool SV, int NW, int RF, int FE>
 __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__ descs, int32_t n_desc) {
     constexpr int kThreads = NW * 64;
     constexpr int kWaves = NW;
@@ -157,31 +157,46 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
     int64_t best = D.best0;  // every thread tracks it; thread 0's copy is stored
     int best_step = -1;
 
-    // this thread's clause row and variable row, entries in registers (REG);
-    // entries past a row's end are the padding entries, which add nothing
-    uint32_t fen[kRegF], ben[kRegB];
-    uint32_t f_len = 0, b_len = 0;
-    bool f_real = false, f_taut = false, b_real = false;
-    int64_t f_w = 1;
-    if constexpr (REG) {
-        if (tid < crows) {
-            const TileDesc d = cs.tile(tid >> 6);
-            const int rowin = tid & 63;
-            f_len = d.len;
-            f_real = rowin < (int)d.nreal;
-            f_taut = (d.flags & 1u) != 0;
-            f_w = (D.c_w != nullptr && f_real) ? D.c_w[tid] : 1;
+    // this thread's clause rows and variable row, entries in registers (RF >
+    // 0); entries past a row's end are the padding entries, which add nothing.
+    // A clause row's length, real and tautology flags are packed in fmeta;
+    // the several-row caches serve unweighted instances only (weight 1).
+    constexpr int kRF = RF > 0 ? RF : 1;
+    constexpr int kFE = FE > 0 ? FE : 1;
+    constexpr int kRW = RF == 1 ? 1 : 0;  // the one-row cache keeps the weight
+    // the variable row is cached only beside a one-row clause cache (sixteen
+    // wavefronts would run out of registers)
+    constexpr int kRB = RF == 1 ? kRegB : 0;
+    uint32_t fen[kRF][kFE], ben[kRB > 0 ? kRB : 1], fmeta[kRF];
+    int64_t fw[kRW > 0 ? kRF : 1];
+    uint32_t b_len = 0;
+    bool b_real = false;
+    if constexpr (RF > 0) {
 #pragma unroll
-            for (int c = 0; c < kRegF; ++c)
-                fen[c] = c < (int)d.len ? cs.entry((size_t)d.base + rowin + (size_t)c * kTile) : (uint32_t)n;
+        for (int q = 0; q < RF; ++q) {
+            const int row = tid + q * kThreads;
+            fmeta[q] = 0;
+            if constexpr (kRW > 0) fw[q] = 1;
+#pragma unroll
+            for (int c = 0; c < FE; ++c) fen[q][c] = (uint32_t)n;
+            if (row < crows) {
+                const TileDesc d = cs.tile(row >> 6);
+                const int rowin = row & 63;
+                const bool real = rowin < (int)d.nreal;
+                fmeta[q] = d.len | (real ? 1u << 8 : 0u) | ((d.flags & 1u) ? 1u << 9 : 0u);
+                if constexpr (kRW > 0) fw[q] = (D.c_w != nullptr && real) ? D.c_w[row] : 1;
+#pragma unroll
+                for (int c = 0; c < FE; ++c)
+                    if (c < (int)d.len) fen[q][c] = cs.entry((size_t)d.base + rowin + (size_t)c * kTile);
+            }
         }
-        if (tid < vrows) {
+        if (kRB > 0 && tid < vrows) {
             const TileDesc d = vs.tile(tid >> 6);
             const int rowin = tid & 63;
             b_len = d.len;
             b_real = rowin < (int)d.nreal;
 #pragma unroll
-            for (int c = 0; c < kRegB; ++c)
+            for (int c = 0; c < kRB; ++c)
                 ben[c] = c < (int)d.len ? vs.entry((size_t)d.base + rowin + (size_t)c * kTile) : (uint32_t)crows;
         }
     }
@@ -213,22 +228,29 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
                 if (want_loss) los += mu ? ((double)f * (double)f) * (double)wj : 0.0;
             }
         };
-        if constexpr (REG) {
-            if (tid < crows) {
-                float f = 0.0f;
-                uint32_t allf = ~0u;
+        if constexpr (RF > 0) {
 #pragma unroll
-                for (int c0 = 0; c0 < kRegF; c0 += 4)
-                    if (c0 < (int)f_len) {
+            for (int q = 0; q < RF; ++q) {
+                const int row = tid + q * kThreads;
+                if (row < crows) {
+                    const uint32_t len = fmeta[q] & 0xffu;
+                    float f = 0.0f;
+                    uint32_t allf = ~0u;
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const uint32_t en = fen[c0 + k];
-                            const uint32_t b = __float_as_uint(L.t[en & kIdx]) ^ (en & kSign);
-                            f = f + __uint_as_float(b);
-                            allf &= b;
+                    for (int c0 = 0; c0 < FE; c0 += 4)
+                        if (c0 < (int)len) {
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                const uint32_t en = fen[q][c0 + k];
+                                const uint32_t b = __float_as_uint(L.t[en & kIdx]) ^ (en & kSign);
+                                f = f + __uint_as_float(b);
+                                allf &= b;
+                            }
                         }
-                    }
-                clause_out(tid, f, allf, f_real, f_taut, f_w);
+                    int64_t wj = 1;
+                    if constexpr (kRW > 0) wj = fw[q];
+                    clause_out(row, f, allf, (fmeta[q] >> 8) & 1u, (fmeta[q] >> 9) & 1u, wj);
+                }
             }
         } else
         for (int row = tid; row < crows; row += kThreads) {
@@ -325,11 +347,11 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
                 L.t[var] = signed_tanh(x);
             }
         };
-        if constexpr (REG) {
+        if constexpr (kRB > 0) {
             if (tid < vrows && b_real) {
                 double G = 0.0;
 #pragma unroll
-                for (int c0 = 0; c0 < kRegB; c0 += 8)
+                for (int c0 = 0; c0 < kRB; c0 += 8)
                     if (c0 < (int)b_len) {
 #pragma unroll
                         for (int k = 0; k < 8; ++k) {
@@ -417,49 +439,62 @@ size_t small_lds_total(const HostPlan& P, size_t limit, int32_t* stage) {
 size_t small_static_lds() {
     hipFuncAttributes attr{};
     // the widest workgroup has the most static LDS (the per-wavefront partials)
-    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_small<true, true, 16, false>)) != hipSuccess) return 16384;
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_small<true, true, 16, 0, 0>)) != hipSuccess) return 16384;
     return attr.sharedSizeBytes;
 }
 
-template <bool SC, bool SV, int NW, bool REG>
+template <bool SC, bool SV, int NW, int RF, int FE>
 hipError_t launch_small_as(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV, NW, REG>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV, NW, RF, FE>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_small<SC, SV, NW, REG>), dim3(blocks), dim3(NW * 64), lds_bytes, s, d_descs, n_desc);
+    hipLaunchKernelGGL((k_small<SC, SV, NW, RF, FE>), dim3(blocks), dim3(NW * 64), lds_bytes, s, d_descs, n_desc);
     return hipGetLastError();
 }
 
-template <int NW, bool REG>
+template <int NW, int RF, int FE>
 hipError_t launch_small_nw(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
                            hipStream_t s) {
     switch (stage & 3) {
-        case 0: return launch_small_as<false, false, NW, REG>(d_descs, n_desc, blocks, lds_bytes, s);
-        case 1: return launch_small_as<true, false, NW, REG>(d_descs, n_desc, blocks, lds_bytes, s);
-        case 2: return launch_small_as<false, true, NW, REG>(d_descs, n_desc, blocks, lds_bytes, s);
-        default: return launch_small_as<true, true, NW, REG>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 0: return launch_small_as<false, false, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 1: return launch_small_as<true, false, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 2: return launch_small_as<false, true, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, s);
+        default: return launch_small_as<true, true, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, s);
     }
 }
 
+// Register-cache shapes: four wavefronts with one clause row of up to 16
+// entries per thread, sixteen with up to kRF16 clause rows of up to 4.
+constexpr int kRF4 = 1, kFE4 = 16;
+constexpr int kRF16 = 5, kFE16 = 4;
+
 int small_waves(int32_t rows) { return rows <= kSmallRows4 ? 4 : 16; }
 
-bool small_reg_ok(const HostPlan& P) {
-    if (std::max(P.c_tiles, P.v_tiles) * kTile > kSmallRows4) return false;
+bool small_reg_ok(const HostPlan& P, int32_t launch_rows) {
+    const int32_t crows = P.c_tiles * kTile, vrows = P.v_tiles * kTile;
+    const int nw = small_waves(launch_rows);
+    const int rf = nw == 4 ? kRF4 : kRF16, fe = nw == 4 ? kFE4 : kFE16;
+    if (crows > rf * nw * 64) return false;
+    if (rf > 1 && P.weighted) return false;  // the several-row caches keep no weights
     for (const TileDesc& d : P.c_tile)
-        if (d.len > (uint32_t)kRegF) return false;
-    for (const TileDesc& d : P.v_tile)
-        if (d.len > (uint32_t)kRegB) return false;
+        if (d.len > (uint32_t)fe) return false;
+    if (rf == 1) {  // the variable row is cached too
+        if (vrows > nw * 64) return false;
+        for (const TileDesc& d : P.v_tile)
+            if (d.len > (uint32_t)kRegB) return false;
+    }
     return true;
 }
 
 hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
                         int32_t rows, bool reg, hipStream_t s) {
     if (small_waves(rows) == 4) {
-        if (reg) return launch_small_nw<4, true>(d_descs, n_desc, blocks, lds_bytes, stage, s);
-        return launch_small_nw<4, false>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+        if (reg) return launch_small_nw<4, kRF4, kFE4>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+        return launch_small_nw<4, 0, 0>(d_descs, n_desc, blocks, lds_bytes, stage, s);
     }
-    return launch_small_nw<16, false>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+    if (reg) return launch_small_nw<16, kRF16, kFE16>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+    return launch_small_nw<16, 0, 0>(d_descs, n_desc, blocks, lds_bytes, stage, s);
 }
 
 }  // namespace hms

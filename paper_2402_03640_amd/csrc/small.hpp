@@ -60,10 +60,13 @@ size_t small_static_lds();
 // when one pass of them covers every row (up to kSmallRows4), else sixteen.
 constexpr int32_t kSmallRows4 = 256;
 int small_waves(int32_t rows);
-// True when a four-wavefront workgroup can keep each thread's clause row (up
-// to 16 entries) and variable row (up to 32) in registers; `reg` of a launch
-// must hold for every instance in it.
-bool small_reg_ok(const HostPlan& P);
+// True when the instance's rows fit the register cache of a launch whose
+// largest instance has `launch_rows` rows (which fixes the wavefront count):
+// with four wavefronts one clause row of up to 16 entries and one variable row
+// of up to 32 per thread; with sixteen, unweighted, up to five clause rows of
+// up to 4 entries per thread (the variable side stays in LDS).
+// `reg` of a launch must hold for every instance in it.
+bool small_reg_ok(const HostPlan& P, int32_t launch_rows);
 hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
                         int32_t rows, bool reg, hipStream_t s);
 

@@ -190,7 +190,7 @@ RESIDENT = 255
 
 @pytest.mark.parametrize("kind,R,opt,mode", [
     ("uniform", 1, hm.ADAM, hm.LOSS_UNSAT), ("uniform", 4, hm.SGD, hm.LOSS_ALL),
-    ("mixed", 16, hm.ADAM, hm.LOSS_UNSAT), ("skewed", 1, hm.ADAM, hm.LOSS_UNSAT),
+    ("mixed", 16, hm.ADAM, hm.LOSS_UNSAT), ("mixed", 8, hm.SGD, hm.LOSS_ALL), ("skewed", 1, hm.ADAM, hm.LOSS_UNSAT),
     ("skewed", 3, hm.SGD, hm.LOSS_UNSAT), ("edge", 2, hm.ADAM, hm.LOSS_ALL), ("dense", 2, hm.ADAM, hm.LOSS_UNSAT)])
 def test_resident_matches_tiled(kind, R, opt, mode):
     """The resident solver (whole loop in one workgroup, state in LDS) is
@@ -211,7 +211,7 @@ def test_resident_matches_tiled(kind, R, opt, mode):
     kw = dict(steps=150, restarts=R, eval_every=5, seed=9, optimizer=opt, lr=lr, loss_mode=mode,
               want_x=True)
     a = hm.solve(cnf, schedule=RESIDENT, **kw)
-    b = hm.solve(cnf, schedule={1: 1, 2: 2, 3: 3, 4: 3, 16: 4}[R], **kw)
+    b = hm.solve(cnf, schedule={1: 1, 2: 2, 3: 3, 4: 3, 8: 4, 16: 4}[R], **kw)
     _say(f"resident {kind} R={R}: best {a.best_cost} vs tiled {b.best_cost} (sched {b.schedule})")
     assert a.schedule == RESIDENT and b.schedule != RESIDENT
     np.testing.assert_array_equal(a.restart_best, b.restart_best)
