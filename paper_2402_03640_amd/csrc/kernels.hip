@@ -661,6 +661,28 @@ __global__ __launch_bounds__(256) void k_bwd_multi(const BwdArgs* __restrict__ A
 // way.  One launch of 1024-thread workgroups: the first n_heavy_wide * R
 // workgroups take one wide (variable, restart) each, the rest take sixteen
 // narrow ones (one per wavefront).
+//
+// The kernel moves little data and is bound by its chain of dependent loads,
+// so the epilogue's inputs are loaded before the sums, a slot's partials load
+// NB at a time (a wide slot has at most ~13, so one batch) with the address of
+// a slot past the end clamped to a valid one and its value not added, and the
+// last six levels of the wide tree run as wavefront shuffles (the pairing is
+// the same as in LDS).
+template <int NB>
+__device__ __forceinline__ double slot_sum(const double* __restrict__ sg, const int G, const int q0, const int p1,
+                                           const int stride) {
+    double u = 0.0;
+    for (int q = q0; q < p1; q += stride * NB) {
+        double val[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) val[k] = sg[(size_t)min(q + k * stride, p1 - 1) * G];
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (q + k * stride < p1) u = u + val[k];
+    }
+    return u;
+}
+
 template <int OPT>
 __device__ __forceinline__ void combine_body(const BwdArgs& A, const int bx, double* su) {
     const int tid = threadIdx.x;
@@ -668,37 +690,39 @@ __device__ __forceinline__ void combine_body(const BwdArgs& A, const int bx, dou
     const Blocking B = A.B;
     const int nwide = A.n_heavy_wide * B.R;
     int h, r;
-    double u = 0.0;
     if (bx < nwide) {
         h = bx / B.R;
         r = bx % B.R;
-        const double* sg = A.seg_part + (size_t)(r / B.G) * B.rows_seg * B.G + r % B.G;
-        const int p1 = A.seg_first[h + 1];
-#pragma unroll 8
-        for (int p = A.seg_first[h] + tid; p < p1; p += 1024) u = u + sg[(size_t)p * B.G];
-        su[tid] = u;
-        __syncthreads();
-        for (int s = 512; s >= 1; s >>= 1) {
-            if (tid < s) su[tid] = su[tid] + su[tid + s];
-            __syncthreads();
-        }
-        if (tid != 0) return;
-        u = su[0];
     } else {
         const int w = (bx - nwide) * 16 + (tid >> 6);
         if (w >= (A.n_heavy - A.n_heavy_wide) * B.R) return;
         h = A.n_heavy_wide + w / B.R;
         r = w % B.R;
-        const double* sg = A.seg_part + (size_t)(r / B.G) * B.rows_seg * B.G + r % B.G;
-        const int p1 = A.seg_first[h + 1];
-#pragma unroll 8
-        for (int p = A.seg_first[h] + lane; p < p1; p += 64) u = u + sg[(size_t)p * B.G];
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) u = u + __shfl_down(u, off);
-        if (lane != 0) return;
     }
+    const size_t base = ((size_t)(r / B.G) * B.rows_x + h) * B.G + r % B.G;
+    const VarState<1, OPT> st = var_load<1, OPT>(A, base);
+    const double* sg = A.seg_part + (size_t)(r / B.G) * B.rows_seg * B.G + r % B.G;
+    const int p0 = A.seg_first[h];
+    const int p1 = A.seg_first[h + 1];
+    double u;
+    if (bx < nwide) {
+        u = slot_sum<8>(sg, B.G, p0 + tid, p1, 1024);
+        su[tid] = u;
+        __syncthreads();
+        for (int s = 512; s >= 64; s >>= 1) {
+            if (tid < s) su[tid] = su[tid] + su[tid + s];
+            __syncthreads();
+        }
+        if (tid >= 64) return;
+        u = su[tid];
+    } else {
+        u = slot_sum<4>(sg, B.G, p0 + lane, p1, 64);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) u = u + __shfl_down(u, off);
+    if (lane != 0) return;
     double G[1] = {u};
-    var_epilogue<1, OPT>(A, ((size_t)(r / B.G) * B.rows_x + h) * B.G + r % B.G, r, G);
+    var_epilogue<1, OPT>(A, base, r, G, st);
 }
 
 template <int OPT>
