@@ -210,6 +210,11 @@ def make_workload(name):
         lits = cnfgen.structured_cnf(n, m, seed=3)
         desc = ("structured CNF n=500000 m=2.5M, length 2+Geometric(0.4) capped at 12, Zipf(1.1) "
                 "occurrences, one restart, 200 Adam steps, K=50")
+    elif name == "cfg3-r8":
+        n, m, R, T, K = 500000, 2500000, 8, 200, 50
+        lits = cnfgen.structured_cnf(n, m, seed=3)
+        desc = ("structured CNF n=500000 m=2.5M as above with 8 restarts (state and adjoint past the 256 MB "
+                "Infinity Cache), 200 Adam steps, K=50")
     elif name == "cfg4":
         n, m, R, T, K = 1000, 4200, 16, 1000, 1
         lits = cnfgen.mixed_kcnf(n, m, seed=4)
