@@ -156,6 +156,12 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
     }
     int64_t best = D.best0;  // every thread tracks it; thread 0's copy is stored
     int best_step = -1;
+    // with no split rows and at most one variable per thread, thread i owns
+    // variable i (row i of the variable side): it keeps that variable's best
+    // bit in a register and stores it once at the end
+    const bool own = D.n_heavy == 0 && n <= kThreads;
+    const int own_o = (own && tid < n) ? D.var_old[tid] : 0;
+    bool own_bit = own && tid < n && L.x[tid] > 0.0f;
 
     // this thread's clause rows and variable row, entries in registers (RF >
     // 0); entries past a row's end are the padding entries, which add nothing.
@@ -202,8 +208,10 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
     }
     __syncthreads();
 
+    int kc = 0;  // step modulo K, kept by counting
     for (int step = 0; step <= D.T; ++step) {
-        const bool eval = (step % D.K == 0) || step == D.T;
+        const bool eval = kc == 0 || step == D.T;
+        if (++kc == D.K) kc = 0;
         const bool want_loss = step == D.T;  // the loss is reported at x_T only
         if (D.opt != kSgd && step % kScal == 0 && step < D.T) {
             // the previous block of scalars is no longer read: the last step
@@ -286,10 +294,15 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
         }
         if (eval) {
             if (D.c_w == nullptr) {
-                // unweighted: a wavefront's count fits 32 bits
-                int c32 = (int)cnt;
-                for (int o2 = 32; o2 >= 1; o2 >>= 1) c32 += __shfl_xor(c32, o2);
-                cnt = c32;
+                // unweighted: each lane counts a few rows; the wavefront sum
+                // is taken bit by bit with ballots, shorter than a shuffle tree
+                uint32_t c32 = (uint32_t)cnt;
+                int64_t tot = 0;
+                for (int b = 0; __ballot(c32 != 0u) != 0ull; ++b) {
+                    tot += (int64_t)__popcll(__ballot((c32 & 1u) != 0u)) << b;
+                    c32 >>= 1;
+                }
+                cnt = tot;
             } else {
                 for (int o2 = 32; o2 >= 1; o2 >>= 1) cnt += __shfl_xor(cnt, o2);
             }
@@ -317,8 +330,13 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
             }
             if (improved) {
                 best_step = step;
-                for (int i = tid; i < D.n_act; i += kThreads) best_a[D.var_old[i]] = L.x[i] > 0.0f ? 1 : 0;
-                __syncthreads();
+                if (own) {
+                    // only this thread writes x[tid] (in the transposed pass)
+                    if (tid < n) own_bit = L.x[tid] > 0.0f;
+                } else {
+                    for (int i = tid; i < D.n_act; i += kThreads) best_a[D.var_old[i]] = L.x[i] > 0.0f ? 1 : 0;
+                    __syncthreads();
+                }
             }
         }
         if (step == D.T) break;
@@ -402,6 +420,7 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
         }
         __syncthreads();
     }
+    if (own && tid < n) best_a[own_o] = own_bit ? 1 : 0;
     if (tid == 0) {
         D.best[r] = best;
         D.best_step[r] = best_step;
