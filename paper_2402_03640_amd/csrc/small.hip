@@ -208,12 +208,28 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
     }
     __syncthreads();
 
+    // parameters read every step, pinned in registers by an empty asm: left
+    // as descriptor reads, the compiler re-issues the scalar loads inside the
+    // loop, and each one's wait also waits for the LDS accesses in flight
+    // (the values are uniform: readfirstlane moves them to scalar registers)
+    int p_all = __builtin_amdgcn_readfirstlane(D.all_mode), p_opt = __builtin_amdgcn_readfirstlane(D.opt);
+    int p_segt = __builtin_amdgcn_readfirstlane(D.seg_tiles), p_nh = __builtin_amdgcn_readfirstlane(D.n_heavy);
+    int p_nact = __builtin_amdgcn_readfirstlane(D.n_act);
+    int p_unw = __builtin_amdgcn_readfirstlane(D.c_w == nullptr ? 1 : 0);
+    int p_tomb = __builtin_amdgcn_readfirstlane(__float_as_int(D.two_over_m));
+    int p_lrb = __builtin_amdgcn_readfirstlane(__float_as_int(D.lr));
+    int p_we0 = __builtin_amdgcn_readfirstlane((int)(uint32_t)D.w_empty);
+    int p_we1 = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)D.w_empty >> 32));
+    asm volatile("" : "+s"(p_all), "+s"(p_opt), "+s"(p_segt), "+s"(p_nh), "+s"(p_nact), "+s"(p_unw), "+s"(p_tomb),
+                 "+s"(p_lrb), "+s"(p_we0), "+s"(p_we1));
+    const float p_tom = __int_as_float(p_tomb), p_lr = __int_as_float(p_lrb);
+    const int64_t p_wempty = (int64_t)(((uint64_t)(uint32_t)p_we1 << 32) | (uint32_t)p_we0);
     int kc = 0;  // step modulo K, kept by counting
     for (int step = 0; step <= D.T; ++step) {
         const bool eval = kc == 0 || step == D.T;
         if (++kc == D.K) kc = 0;
         const bool want_loss = step == D.T;  // the loss is reported at x_T only
-        if (D.opt != kSgd && step % kScal == 0 && step < D.T) {
+        if (p_opt != kSgd && step % kScal == 0 && step < D.T) {
             // the previous block of scalars is no longer read: the last step
             // ended with a barrier
             for (int k = tid; k < kScal && step + k < D.T; k += kThreads) {
@@ -229,8 +245,8 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
         // a clause row's outputs: adjoint, count and loss partials
         auto clause_out = [&](int row, float f, uint32_t allf, bool real, bool taut, int64_t wj) {
             const bool unsat = real && !taut && (allf >> 31) != 0;
-            const bool mu = real && (D.all_mode ? true : unsat);
-            L.a[row] = mu ? (f * (float)wj) * D.two_over_m : 0.0f;
+            const bool mu = real && (p_all ? true : unsat);
+            L.a[row] = mu ? (f * (float)wj) * p_tom : 0.0f;
             if (eval) {
                 cnt += unsat ? wj : 0;
                 if (want_loss) los += mu ? ((double)f * (double)f) * (double)wj : 0.0;
@@ -289,11 +305,11 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
             }
             const bool real = rowin < (int)d.nreal;
             // clause weight (1 without weights), as in the tiled forward pass
-            const int64_t wj = (D.c_w != nullptr && real) ? D.c_w[row] : 1;
+            const int64_t wj = (!p_unw && real) ? D.c_w[row] : 1;
             clause_out(row, f, allf, real, (d.flags & 1u) != 0, wj);
         }
         if (eval) {
-            if (D.c_w == nullptr) {
+            if (p_unw) {
                 // unweighted: each lane counts a few rows; the wavefront sum
                 // is taken bit by bit with ballots, shorter than a shuffle tree
                 uint32_t c32 = (uint32_t)cnt;
@@ -319,7 +335,7 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
             // total everywhere) and keeps its own copy of the best, so no
             // second barrier has to broadcast the outcome; the partials are
             // rewritten only after the barrier that ends this step
-            int64_t c = D.w_empty;
+            int64_t c = p_wempty;
             for (int w = 0; w < kWaves; ++w) c += red_c[w];
             const bool improved = c < best;
             if (improved) best = c;
@@ -334,27 +350,27 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
                     // only this thread writes x[tid] (in the transposed pass)
                     if (tid < n) own_bit = L.x[tid] > 0.0f;
                 } else {
-                    for (int i = tid; i < D.n_act; i += kThreads) best_a[D.var_old[i]] = L.x[i] > 0.0f ? 1 : 0;
+                    for (int i = tid; i < p_nact; i += kThreads) best_a[D.var_old[i]] = L.x[i] > 0.0f ? 1 : 0;
                     __syncthreads();
                 }
             }
         }
         if (step == D.T) break;
         // ---- transposed sums, fused optimizer step ---------------------------
-        const float2 sc = D.opt != kSgd ? s_sc[step % kScal] : make_float2(0.0f, 1.0f);
+        const float2 sc = p_opt != kSgd ? s_sc[step % kScal] : make_float2(0.0f, 1.0f);
         const float ss = sc.x, ib2 = sc.y;
         // a variable row's outputs: a segment partial, or the gradient and the
         // optimizer step
         auto var_out = [&](int row, double G) {
             const int tile = row >> 6;
-            if (tile < D.seg_tiles) {
+            if (tile < p_segt) {
                 L.seg[row] = G;
             } else {
-                const int var = D.n_heavy + (row - D.seg_tiles * kTile);
+                const int var = p_nh + (row - p_segt * kTile);
                 float x = L.x[var];
                 const float g = grad_of(x, G);
-                if (D.opt == kSgd) {
-                    x = x - D.lr * g;
+                if (p_opt == kSgd) {
+                    x = x - p_lr * g;
                 } else {
                     float mm = L.m[var], vv = L.v[var];
                     adam_update(x, mm, vv, g, ss, ib2, co);
@@ -394,9 +410,9 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
             }
             var_out(row, G);
         }
-        if (D.n_heavy > 0) {
+        if (p_nh > 0) {
             __syncthreads();
-            for (int h = wave; h < D.n_heavy; h += kWaves) {
+            for (int h = wave; h < p_nh; h += kWaves) {
                 double u = 0.0;
                 const int p1 = D.seg_first[h + 1];
                 for (int p = D.seg_first[h] + lane; p < p1; p += 64) u = u + L.seg[p];
@@ -405,8 +421,8 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
                 if (lane == 0) {
                     float x = L.x[h];
                     const float g = grad_of(x, u);
-                    if (D.opt == kSgd) {
-                        x = x - D.lr * g;
+                    if (p_opt == kSgd) {
+                        x = x - p_lr * g;
                     } else {
                         float mm = L.m[h], vv = L.v[h];
                         adam_update(x, mm, vv, g, ss, ib2, co);
