@@ -101,6 +101,14 @@ struct Arena {
     }
 };
 
+// Waits for the stream when it goes out of scope: declared right after an
+// asynchronous copy from a host buffer, it keeps an early error return from
+// freeing that buffer while the copy may still read it.
+struct SyncOnExit {
+    hipStream_t s;
+    ~SyncOnExit() { (void)hipStreamSynchronize(s); }
+};
+
 // Default kernel schedule for R restarts (table index into hms::kSchedules).
 int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0) {
     if (R <= 1) return loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 21) ? 37 : 2;
@@ -440,6 +448,7 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
         if (e != hipSuccess) r = fail(HMS_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
     if (r) {
+        (void)hipStreamSynchronize(s);  // copies already queued read the plan
         hms_free_cnf(C);
         return r;
     }
@@ -936,9 +945,10 @@ hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_sol
     Events E;
     for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
     HIPTRY(hipMemcpyAsync(A.base + o_desc, &D, sizeof(D), hipMemcpyHostToDevice, s));
+    SyncOnExit d_done{s};
     HIPTRY(hipEventRecord(E.e[0], s));
-    HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc), 1, R, resident_lds(cnf), D.stage, resident_rows(cnf),
-                             hms::small_reg_ok(cnf->plan, resident_rows(cnf)), s));
+    HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc), 1, R, resident_lds(cnf), lds_limit(cnf->device), D.stage,
+                             resident_rows(cnf), hms::small_reg_ok(cnf->plan, resident_rows(cnf)), s));
     HIPTRY(hipEventRecord(E.e[1], s));
     std::vector<int64_t> best(R);
     std::vector<int32_t> bstep(R);
@@ -1103,6 +1113,7 @@ hms_status solve_tiled_group(const hms_cnf* const* cnfs, const hms_solve_params*
     Arena A;
     A.s = s;
     HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+    SyncOnExit args_done{s};
     HIPTRY(hipMemcpyAsync(A.base + o_fa, fa.data(), sizeof(hms::FwdArgs) * cnt, hipMemcpyHostToDevice, s));
     HIPTRY(hipMemcpyAsync(A.base + o_b0, ba0.data(), sizeof(hms::BwdArgs) * cnt, hipMemcpyHostToDevice, s));
     HIPTRY(hipMemcpyAsync(A.base + o_b1, ba1.data(), sizeof(hms::BwdArgs) * cnt, hipMemcpyHostToDevice, s));
@@ -1405,6 +1416,7 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
             }
         }
         HIPTRY(hipMemcpyAsync(A.base + o_desc, D.data(), sizeof(hms::SmallDesc) * D.size(), hipMemcpyHostToDevice, s));
+        SyncOnExit d_done{s};
         Events E;
         for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
         HIPTRY(hipEventRecord(E.e[0], s));
@@ -1420,7 +1432,7 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
             bool reg = true;  // every instance keeps its rows in registers
             for (size_t k = g.first; k < g.second; ++k) reg = reg && hms::small_reg_ok(cnfs[res_idx[k]]->plan, rows);
             HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc) + g.first, (int32_t)(g.second - g.first), blocks,
-                                     resident_lds(cnfs[res_idx[g.first]]), stage, rows, reg, s));
+                                     resident_lds(cnfs[res_idx[g.first]]), lds_limit(dev), stage, rows, reg, s));
         }
         HIPTRY(hipEventRecord(E.e[1], s));
         // read back every resident result
@@ -1695,6 +1707,7 @@ hms_status hms_evaluate(const hms_cnf* cnf, const uint8_t* assignment, int64_t* 
     HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
     State S = bind_state(A, off, false, false, false);
     uint8_t* d_in = A.at<uint8_t>(o_in);
+    SyncOnExit in_done{s};  // the caller's buffers are in use until the stream drains
     if (P.n > 0) HIPTRY(hipMemcpyAsync(d_in, assignment, P.n, hipMemcpyHostToDevice, s));
     hms::InitArgs ia = make_init(cnf, sh, S);
     ia.assign0 = d_in;

@@ -478,24 +478,29 @@ size_t small_static_lds() {
     return attr.sharedSizeBytes;
 }
 
+// The dynamic-LDS attribute belongs to the kernel, not to the launch: it is
+// always set to the device's cap, so solves on several threads that launch
+// the same kernel write the same value and none can shrink it under another.
 template <bool SC, bool SV, int NW, int RF, int FE>
-hipError_t launch_small_as(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_small_as(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, size_t lds_cap,
+                           hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
+    if (lds_bytes > lds_cap) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV, NW, RF, FE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_small<SC, SV, NW, RF, FE>), dim3(blocks), dim3(NW * 64), lds_bytes, s, d_descs, n_desc);
     return hipGetLastError();
 }
 
 template <int NW, int RF, int FE>
-hipError_t launch_small_nw(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
-                           hipStream_t s) {
+hipError_t launch_small_nw(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, size_t lds_cap,
+                           int32_t stage, hipStream_t s) {
     switch (stage & 3) {
-        case 0: return launch_small_as<false, false, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, s);
-        case 1: return launch_small_as<true, false, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, s);
-        case 2: return launch_small_as<false, true, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, s);
-        default: return launch_small_as<true, true, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, s);
+        case 0: return launch_small_as<false, false, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, lds_cap, s);
+        case 1: return launch_small_as<true, false, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, lds_cap, s);
+        case 2: return launch_small_as<false, true, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, lds_cap, s);
+        default: return launch_small_as<true, true, NW, RF, FE>(d_descs, n_desc, blocks, lds_bytes, lds_cap, s);
     }
 }
 
@@ -522,14 +527,14 @@ bool small_reg_ok(const HostPlan& P, int32_t launch_rows) {
     return true;
 }
 
-hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
-                        int32_t rows, bool reg, hipStream_t s) {
+hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, size_t lds_cap,
+                        int32_t stage, int32_t rows, bool reg, hipStream_t s) {
     if (small_waves(rows) == 4) {
-        if (reg) return launch_small_nw<4, kRF4, kFE4>(d_descs, n_desc, blocks, lds_bytes, stage, s);
-        return launch_small_nw<4, 0, 0>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+        if (reg) return launch_small_nw<4, kRF4, kFE4>(d_descs, n_desc, blocks, lds_bytes, lds_cap, stage, s);
+        return launch_small_nw<4, 0, 0>(d_descs, n_desc, blocks, lds_bytes, lds_cap, stage, s);
     }
-    if (reg) return launch_small_nw<16, kRF16, kFE16>(d_descs, n_desc, blocks, lds_bytes, stage, s);
-    return launch_small_nw<16, 0, 0>(d_descs, n_desc, blocks, lds_bytes, stage, s);
+    if (reg) return launch_small_nw<16, kRF16, kFE16>(d_descs, n_desc, blocks, lds_bytes, lds_cap, stage, s);
+    return launch_small_nw<16, 0, 0>(d_descs, n_desc, blocks, lds_bytes, lds_cap, stage, s);
 }
 
 }  // namespace hms

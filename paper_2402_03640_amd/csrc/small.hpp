@@ -67,7 +67,9 @@ int small_waves(int32_t rows);
 // up to 4 entries per thread (the variable side stays in LDS).
 // `reg` of a launch must hold for every instance in it.
 bool small_reg_ok(const HostPlan& P, int32_t launch_rows);
-hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, int32_t stage,
-                        int32_t rows, bool reg, hipStream_t s);
+// `lds_cap` is the device's dynamic-LDS cap (the same on every call for one
+// device); lds_bytes above it is an invalid value.
+hipError_t launch_small(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, size_t lds_cap,
+                        int32_t stage, int32_t rows, bool reg, hipStream_t s);
 
 }  // namespace hms

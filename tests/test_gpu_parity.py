@@ -223,6 +223,43 @@ def test_resident_matches_tiled(kind, R, opt, mode):
     np.testing.assert_allclose(a.restart_loss, b.restart_loss, rtol=1e-12)
 
 
+def test_resident_concurrent_threads():
+    """Resident solves of different LDS sizes on several threads at once (the
+    kernel's dynamic-LDS attribute is shared by all of them): every result
+    equals the same solve alone, bit for bit."""
+    import threading
+
+    import torch
+    inst = [(50, cnfgen.uniform_kcnf(50, 215, 3, seed=1)), (400, cnfgen.uniform_kcnf(400, 1700, 3, seed=2)),
+            (1000, cnfgen.mixed_kcnf(1000, 4200, seed=4)), (120, cnfgen.uniform_kcnf(120, 510, 3, seed=3))]
+    cnfs = [hm.load_cnf(n, lits) for n, lits in inst]
+    kw = dict(steps=200, restarts=2, eval_every=5, seed=3, lr=1e-2, schedule=RESIDENT, want_x=True)
+    solo = [hm.solve(c, **kw) for c in cnfs]
+    _say("resident solves on 4 threads, 3 rounds each")
+    errors = []
+
+    def run(i):
+        try:
+            torch.cuda.set_device(0)
+            st = torch.cuda.Stream()
+            for _ in range(3):
+                r = hm.solve(cnfs[i], stream=st, **kw)
+                if not (np.array_equal(r.restart_best, solo[i].restart_best)
+                        and np.array_equal(r.best_assignment, solo[i].best_assignment)
+                        and np.array_equal(r.x_final.cpu().numpy().view(np.uint32),
+                                           solo[i].x_final.cpu().numpy().view(np.uint32))):
+                    errors.append(f"instance {i} differs from its solo solve")
+        except Exception as e:  # reported below, on the test's thread
+            errors.append(f"instance {i}: {e!r}")
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(len(cnfs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+
+
 def test_eval_cfg2_full_size():
     n, m, R = 20000, 86000, 64
     lits = cnfgen.uniform_kcnf(n, m, 3, seed=2)
