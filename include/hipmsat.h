@@ -123,7 +123,10 @@ typedef struct {
                             | backward rows-per-unit << 16 (0 = the same; see hms_tune) */
     int32_t use_graph;   /* 1 = replay the step body as a HIP graph, 0 = direct launches */
     int32_t autotune;    /* 1 = with schedule 0, time the candidate schedules once per handle,
-                            restart count, optimizer and loss mode, and keep the fastest */
+                            restart count, optimizer and loss mode, and keep the fastest
+                            (small instances skip the timing); 0 = take the resident solver
+                            (255) when the state fits it and nnz <= 2^15 (2^16 with K = 1),
+                            else a fixed tiled schedule for R */
     double time_limit_s; /* > 0: stop at a K-step boundary once exceeded (not reproducible) */
     const float* x0;     /* DEVICE [n][R] initial values, or NULL for SplitMix64 U(-1,1) */
     void* stream;        /* hipStream_t */
@@ -181,8 +184,9 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* params, 
 /*
  * Batched solve of `count` instances (Algorithm 1 for each, as hms_solve):
  * cnfs[i] with params[i] into results[i] (statuses[i], may be NULL, receives each
- * instance's status).  Instances that fit the resident solver share launches,
- * one workgroup per (instance, restart).  The others are grouped by restarts,
+ * instance's status).  Instances that request the resident solver, or leave
+ * the schedule automatic and fit it with at most 2^15 nonzeros (2^16 when
+ * eval_every is 1), share launches, one workgroup per (instance, restart).  The others are grouped by restarts,
  * steps, eval_every, optimizer, loss mode and requested schedule: each step of
  * a group is one launch per kernel over all its instances (a work queue of
  * (instance, work unit) items, replayed as a HIP graph), with the schedule of

@@ -597,8 +597,10 @@ struct Events {
 
 
 bool resident_ok(const hms_cnf* cnf, const hms_solve_params* p);
+bool resident_preferred(const hms_cnf* cnf, const hms_solve_params* p);
 hms_status time_resident(const hms_cnf* cnf, const hms_solve_params* p0, int32_t iters, double& ms);
 constexpr int32_t kResidentId = 0xff;
+constexpr int64_t kResidentNnz = 1 << 15;  // largest instance the untimed choice sends to the resident solver
 
 uint64_t tune_key(const hms_solve_params* p) {
     return (uint64_t)(uint32_t)p->restarts | ((uint64_t)(uint32_t)p->optimizer << 32) |
@@ -826,7 +828,7 @@ hms_status resolve_schedule(const hms_cnf* cnf, const hms_solve_params* p, int32
         }
     }
     if (!p->autotune || (double)cnf->plan.nnz * p->restarts < (double)(1 << 18)) {
-        if (resident_ok(cnf, p)) code = kResidentId;  // small: launch latency dominates
+        if (resident_preferred(cnf, p)) code = kResidentId;  // small: launch latency dominates
         return HMS_OK;
     }
     double ms = 0;
@@ -848,6 +850,15 @@ size_t lds_limit(int dev) {
     const size_t lim = (size_t)v > stat ? (size_t)v - stat : 0;
     if (dev >= 0 && dev < 64) cached[dev].store(lim, std::memory_order_relaxed);
     return lim;
+}
+
+// Without timing, the resident solver is taken for instances of at most
+// kResidentNnz nonzeros (twice that when every step is counted): one
+// workgroup then costs about 1.4 us + 0.2 ns per nonzero per step, the tiled
+// launches 7-8 us per step (about 14 with a count every step).
+bool resident_preferred(const hms_cnf* cnf, const hms_solve_params* p) {
+    const int64_t lim = p->eval_every <= 1 ? 2 * kResidentNnz : kResidentNnz;
+    return cnf->plan.nnz <= lim && resident_ok(cnf, p);
 }
 
 bool resident_ok(const hms_cnf* cnf, const hms_solve_params* p) {
@@ -1369,7 +1380,7 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
     std::vector<int32_t> res_idx, tiled_idx;
     for (int32_t i = 0; i < count; ++i) {
         const bool want_res = params[i].schedule == kResidentId ||
-                              (params[i].schedule == 0 && resident_ok(cnfs[i], &params[i]));
+                              (params[i].schedule == 0 && resident_preferred(cnfs[i], &params[i]));
         if (want_res && resident_ok(cnfs[i], &params[i])) res_idx.push_back(i);
         else tiled_idx.push_back(i);
     }
