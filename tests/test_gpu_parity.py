@@ -223,6 +223,21 @@ def test_resident_matches_tiled(kind, R, opt, mode):
     np.testing.assert_allclose(a.restart_loss, b.restart_loss, rtol=1e-12)
 
 
+def test_untimed_choice_of_resident():
+    """Without timing, the resident solver takes instances of at most 2^15
+    nonzeros (2^16 when every step is counted); larger ones run tiled."""
+    small = hm.load_cnf(50, cnfgen.uniform_kcnf(50, 215, 3, seed=1))
+    mid = hm.load_cnf(4000, cnfgen.uniform_kcnf(4000, 17200, 3, seed=2))  # 51600 nonzeros
+    assert 1 << 15 < mid.info["nnz"] <= 1 << 16
+    kw = dict(steps=20, restarts=1, seed=0, autotune=False)
+    assert hm.solve(small, eval_every=5, **kw).schedule == RESIDENT
+    assert hm.solve(mid, eval_every=5, **kw).schedule != RESIDENT
+    assert hm.solve(mid, eval_every=1, **kw).schedule == RESIDENT
+    # the batch path routes the same way
+    out = hm.solve_batch([small, mid], steps=20, eval_every=5, seeds=[0, 1])
+    assert out[0].schedule == RESIDENT and out[1].schedule != RESIDENT
+
+
 def test_resident_concurrent_threads():
     """Resident solves of different LDS sizes on several threads at once (the
     kernel's dynamic-LDS attribute is shared by all of them): every result
