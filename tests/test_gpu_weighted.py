@@ -47,9 +47,12 @@ def test_unit_weights_equal_unweighted_bitwise():
         np.testing.assert_array_equal(ua, ub)
         np.testing.assert_array_equal(ga.cpu().numpy().view(np.uint32), gb.cpu().numpy().view(np.uint32))
     kw = dict(steps=60, restarts=R, eval_every=7, seed=5, lr=1e-2, want_x=True)
-    ra, rb = hm.solve(a, **kw), hm.solve(b, **kw)
-    np.testing.assert_array_equal(ra.restart_best, rb.restart_best)
-    np.testing.assert_array_equal(ra.x_final.cpu().numpy().view(np.uint32), rb.x_final.cpu().numpy().view(np.uint32))
+    for sched in (0, 255):  # the automatic (tiled) choice and the resident solver
+        ra, rb = hm.solve(a, schedule=sched, **kw), hm.solve(b, schedule=sched, **kw)
+        assert ra.schedule == rb.schedule and (ra.schedule == 255) == (sched == 255)
+        np.testing.assert_array_equal(ra.restart_best, rb.restart_best)
+        np.testing.assert_array_equal(ra.x_final.cpu().numpy().view(np.uint32),
+                                      rb.x_final.cpu().numpy().view(np.uint32))
 
 
 @pytest.mark.parametrize("mode", [hm.LOSS_UNSAT, hm.LOSS_ALL])
