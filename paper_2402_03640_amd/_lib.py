@@ -153,6 +153,22 @@ def _lits(lits) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(lits, dtype=np.int32))
 
 
+def _device_points(x, cnf, name: str):
+    """x as its [n][R] view, after checking it can be handed to the kernels:
+    a contiguous float32 tensor on the instance's device with n rows."""
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 tensor on the GPU")
+    if x.device.index != cnf.device:
+        raise ValueError(f"{name} is on device {x.device.index}, the instance on device {cnf.device}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    X = x if x.dim() == 2 else (x.view(-1, 1) if x.dim() == 1 else None)
+    if X is None or X.shape[0] != cnf.n or X.shape[1] < 1:
+        raise ValueError(f"{name} must have shape [{cnf.n}] or [{cnf.n}][R], got {tuple(x.shape)}")
+    return X
+
+
 class Cnf:
     """A loaded instance (owns its device structure)."""
 
@@ -163,6 +179,8 @@ class Cnf:
         self.info = {k: getattr(info, k) for k, _ in CnfInfo._fields_}
         self.n = info.n_vars
         self.m = info.n_clauses
+        import torch
+        self.device = torch.cuda.current_device()  # where the library put the instance
 
     @property
     def handle(self):
@@ -191,11 +209,15 @@ def load_cnf(n_vars: int, lits, stream=None, weights=None) -> Cnf:
     (one positive integer per clause) makes it a weighted MaxSAT instance."""
     a = _lits(lits)
     h = C.c_void_p()
+    if weights is not None:
+        w = np.ascontiguousarray(weights, dtype=np.int64)
+        m = int(np.count_nonzero(a == 0))
+        if w.ndim != 1 or w.size != m:
+            raise ValueError(f"{w.size} clause weights for {m} clauses")
     if weights is None:
         _check(lib().hms_load_cnf(int(n_vars), a.ctypes.data_as(C.c_void_p), a.size,
                                   _stream_ptr(stream), C.byref(h)))
     else:
-        w = np.ascontiguousarray(weights, dtype=np.int64)
         _check(lib().hms_load_wcnf(int(n_vars), a.ctypes.data_as(C.c_void_p), a.size,
                                    w.ctypes.data_as(C.c_void_p), _stream_ptr(stream), C.byref(h)))
     return Cnf(h)
@@ -235,10 +257,10 @@ def _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2,
     p.time_limit_s = float(time_limit_s)
     p.autotune = int(bool(autotune))
     if x0 is not None:
-        import torch
-        assert x0.is_cuda and x0.dtype == torch.float32 and x0.is_contiguous()
-        assert tuple(x0.shape) in ((cnf.n, R),) or (R == 1 and tuple(x0.shape) == (cnf.n,))
-        p.x0 = x0.data_ptr()
+        X0 = _device_points(x0, cnf, "x0")
+        if X0.shape[1] != R:
+            raise ValueError(f"x0 has {X0.shape[1]} columns for {R} restarts")
+        p.x0 = X0.data_ptr()
     p.stream = _stream_ptr(stream)
     return p
 
@@ -385,7 +407,8 @@ def solve_batch(cnfs, steps=1000, restarts=1, eval_every=1, seeds=0, optimizer: 
 def evaluate(cnf: Cnf, assignment, stream=None) -> int:
     """Unsatisfied clauses of a 0/1 assignment (host array of n entries)."""
     a = np.ascontiguousarray(np.asarray(assignment) != 0, dtype=np.uint8)
-    assert a.shape == (cnf.n,)
+    if a.shape != (cnf.n,):
+        raise ValueError(f"assignment must have {cnf.n} entries, got shape {a.shape}")
     out = C.c_int64()
     _check(lib().hms_evaluate(cnf.handle, a.ctypes.data_as(C.c_void_p), C.byref(out),
                               _stream_ptr(stream)))
@@ -398,15 +421,15 @@ def eval_relaxed(cnf: Cnf, x, loss_mode: int = LOSS_UNSAT, want_grad: bool = Tru
 
     Returns (loss: float64[R], grad: torch [n][R] or None, unsat: int64[R])."""
     import torch
-    assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
-    X = x if x.dim() == 2 else x.view(-1, 1)
-    assert X.shape[0] == cnf.n
+    X = _device_points(x, cnf, "x")
     R = X.shape[1]
     loss = np.zeros(R, dtype=np.float64)
     unsat = np.zeros(R, dtype=np.int64)
     g = None
     if want_grad:
-        g = grad_out if grad_out is not None else torch.empty_like(X)
+        g = torch.empty_like(X) if grad_out is None else _device_points(grad_out, cnf, "grad_out")
+        if g.shape != X.shape:
+            raise ValueError(f"grad_out must have the shape of x, {tuple(X.shape)}")
     _check(lib().hms_eval_relaxed(cnf.handle, C.c_void_p(X.data_ptr()), R, int(loss_mode),
                                   loss.ctypes.data_as(C.c_void_p),
                                   C.c_void_p(g.data_ptr()) if g is not None else None,

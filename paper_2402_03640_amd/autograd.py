@@ -15,7 +15,7 @@ import ctypes as C
 
 import torch
 
-from ._lib import LOSS_UNSAT, Cnf, _check, _stream_ptr, lib
+from ._lib import LOSS_UNSAT, Cnf, _check, _device_points, _stream_ptr, lib
 
 
 def adjoint_bytes(cnf: Cnf, restarts: int) -> int:
@@ -27,11 +27,7 @@ def adjoint_bytes(cnf: Cnf, restarts: int) -> int:
 class _MaxSatLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, cnf, loss_mode, checkpoint):
-        X = x.detach()
-        if X.dim() == 1:
-            X = X.view(-1, 1)
-        X = X.contiguous()
-        assert X.is_cuda and X.dtype == torch.float32 and X.shape[0] == cnf.n
+        X = _device_points(x.detach().contiguous(), cnf, "x")
         R = X.shape[1]
         loss = torch.empty(R, dtype=torch.float64, device=X.device)
         unsat = torch.empty(R, dtype=torch.int64, device=X.device)

@@ -223,6 +223,28 @@ def test_resident_matches_tiled(kind, R, opt, mode):
     np.testing.assert_allclose(a.restart_loss, b.restart_loss, rtol=1e-12)
 
 
+def test_binding_rejects_bad_points():
+    """Relaxed points that the kernels cannot take are refused before any
+    launch: wrong dtype, not contiguous, wrong row count, a gradient buffer of
+    another shape, an initial point with the wrong restart count."""
+    import torch
+    n = 50
+    cnf = hm.load_cnf(n, cnfgen.uniform_kcnf(n, 215, 3, seed=1))
+    good = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(TypeError):
+        hm.eval_relaxed(cnf, good.double())
+    with pytest.raises(ValueError, match="contiguous"):
+        hm.eval_relaxed(cnf, torch.zeros((4, n), dtype=torch.float32, device="cuda").t())
+    with pytest.raises(ValueError, match="shape"):
+        hm.eval_relaxed(cnf, torch.zeros((n + 1, 4), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError, match="grad_out"):
+        hm.eval_relaxed(cnf, good, grad_out=torch.zeros((n, 3), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError, match="restarts"):
+        hm.solve(cnf, steps=2, restarts=3, x0=good)
+    loss, g, unsat = hm.eval_relaxed(cnf, good)  # the good one still works
+    assert g.shape == (n, 4) and unsat.shape == (4,)
+
+
 def test_untimed_choice_of_resident():
     """Without timing, the resident solver takes instances of at most 2^15
     nonzeros (2^16 when every step is counted); larger ones run tiled."""

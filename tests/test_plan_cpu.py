@@ -218,3 +218,11 @@ def test_load_without_gpu_reports_device_error():
     with pytest.raises(hm.HipMsatError) as e:
         hm.load_cnf(3, np.array([1, 2, 0], np.int32), stream=0)
     assert e.value.name == "HMS_ERR_DEVICE"
+
+
+def test_weights_count_checked_before_any_device_call():
+    """A weight array whose length is not the clause count is refused by the
+    binding (the C entry point reads one weight per clause)."""
+    import paper_2402_03640_amd as hm
+    with pytest.raises(ValueError, match="2 clause weights for 3 clauses"):
+        hm.load_cnf(3, [1, 2, 0, -1, 3, 0, 2, 0], weights=[1, 2])
