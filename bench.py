@@ -251,7 +251,19 @@ def cpu_baseline(wl, L, max_threads=16, sample_steps=None, min_wall=2.0):
     nnz = 2.0 * L * R * sample_steps * reps
     return {"value": nnz / dt, "unit": "nnz/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} x ({R} restarts x {sample_steps} of {wl['T']} steps, eval every {wl['K']}), "
-                      f"FP64, OpenMP over restarts on {threads} threads, {dt:.2f} s wall"}
+                      f"FP64, OpenMP over restarts on {threads} threads, {dt:.2f} s wall",
+            "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def serve_bench(args):
