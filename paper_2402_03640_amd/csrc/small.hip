@@ -8,6 +8,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 
@@ -478,17 +481,31 @@ size_t small_static_lds() {
     return attr.sharedSizeBytes;
 }
 
+std::mutex g_attr_mu;  // serialises the one-time attribute settings below
+
 // The dynamic-LDS attribute belongs to the kernel, not to the launch: it is
-// always set to the device's cap, so solves on several threads that launch
-// the same kernel write the same value and none can shrink it under another.
+// set to the device's cap once per kernel and device, under a lock, before
+// that kernel's first launch there, so no solve on another thread changes it
+// while a launch of the kernel is being prepared.
 template <bool SC, bool SV, int NW, int RF, int FE>
 hipError_t launch_small_as(const SmallDesc* d_descs, int32_t n_desc, int32_t blocks, size_t lds_bytes, size_t lds_cap,
                            hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     if (lds_bytes > lds_cap) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV, NW, RF, FE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
+    static std::atomic<uint64_t> set_on{0};  // bit d: done on device d (< 64)
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    const uint64_t bit = dev >= 0 && dev < 64 ? uint64_t(1) << dev : 0;
+    if (!bit || !(set_on.load(std::memory_order_acquire) & bit)) {
+        std::lock_guard<std::mutex> lk(g_attr_mu);
+        if (!bit || !(set_on.load(std::memory_order_relaxed) & bit)) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<SC, SV, NW, RF, FE>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap);
+            if (e != hipSuccess) return e;
+            set_on.fetch_or(bit, std::memory_order_release);
+        }
+    }
     hipLaunchKernelGGL((k_small<SC, SV, NW, RF, FE>), dim3(blocks), dim3(NW * 64), lds_bytes, s, d_descs, n_desc);
     return hipGetLastError();
 }

@@ -1,13 +1,16 @@
 """Continuous-batching solve server.
 
-Requests (a CNF plus solve parameters) arrive at any time.  A dispatcher admits
-them in arrival order while their estimated device footprint fits the budget;
-worker threads, each with its own HIP stream, build and upload the instance plan
-and solve it, so requests admitted while others are running overlap on the
-device.  Queued requests with the same step count, restart count, counting
-period, optimizer and loss mode are taken together: those small enough for the
-resident solver share one launch (one workgroup per instance and restart), the
-others share one launch per kernel per step (a work queue over their units).
+Requests (a CNF plus solve parameters) arrive at any time and queue in arrival
+order.  A worker thread (each with its own HIP stream) that becomes free takes
+the head of the queue, if its estimated device footprint fits the budget, and
+with it every queued request of the same kind that fits too; it builds and
+uploads their plans and solves them, so requests taken while others run overlap
+on the device.  Under light load a request is taken alone as soon as it arrives;
+as the queue grows, the requests taken together grow with it.  Requests of the
+same kind have the same step count, restart count, counting period, optimizer
+and loss mode: those small enough for the resident solver share one launch (one
+workgroup per instance and restart), the others share one launch per kernel per
+step (a work queue over their units).
 Every instance's result is bitwise what a solo ``solve`` gives: the kernels'
 summation order depends on the instance only, never on the batch.
 """
@@ -84,14 +87,11 @@ class Server:
         self._cv = threading.Condition()
         self._closed = False
         self._ids = 0
-        self._jobs: collections.deque[list[Request]] = collections.deque()
         self._workers = []
         for w in range(workers):
             t = threading.Thread(target=self._work, args=(w, device), daemon=True)
             t.start()
             self._workers.append(t)
-        self._disp = threading.Thread(target=self._dispatch, daemon=True)
-        self._disp.start()
 
     # -- client side -------------------------------------------------------------
     def submit(self, n: int, lits, arrival: float | None = None, weights=None, **params) -> Future:
@@ -121,7 +121,6 @@ class Server:
             self._closed = True
             self._cv.notify_all()
         if wait:
-            self._disp.join()
             for t in self._workers:
                 t.join()
 
@@ -131,54 +130,46 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    # -- dispatcher: admission control and grouping -----------------------------
-    def _dispatch(self):
+    # -- workers: admission control, grouping, solving -------------------------
+    def _take(self):
+        """Under the lock: the next job (the admitted head of the queue and the
+        queued requests of its kind that fit), or None once closed and empty."""
         while True:
-            with self._cv:
-                while True:
-                    if self._queue:
-                        head = self._queue[0]
-                        if self.in_use + head.footprint <= self.budget or self.in_use == 0:
-                            break
-                    elif self._closed:
-                        self._jobs.append(None)
-                        self._cv.notify_all()
-                        return
-                    self._cv.wait()
-                job = [self._queue.popleft()]
-                self.in_use += job[0].footprint
-                # take the other queued requests of the same kind that fit as well
-                key = _group_key(job[0])
-                cap = self.small_batch if job[0].small else self.tiled_batch
-                keep = collections.deque()
-                while self._queue and len(job) < cap:
-                    r = self._queue.popleft()
-                    if _group_key(r) == key and self.in_use + r.footprint <= self.budget:
-                        job.append(r)
-                        self.in_use += r.footprint
-                    else:
-                        keep.append(r)
-                keep.extend(self._queue)
-                self._queue = keep
-                now = time.perf_counter()
-                for r in job:
-                    r.params["_admitted"] = now
-                self._jobs.append(job)
-                self._cv.notify_all()
+            if self._queue:
+                head = self._queue[0]
+                if self.in_use + head.footprint <= self.budget or self.in_use == 0:
+                    break
+            elif self._closed:
+                return None
+            self._cv.wait()
+        job = [self._queue.popleft()]
+        self.in_use += job[0].footprint
+        key = _group_key(job[0])
+        cap = self.small_batch if job[0].small else self.tiled_batch
+        keep = collections.deque()
+        while self._queue and len(job) < cap:
+            r = self._queue.popleft()
+            if _group_key(r) == key and self.in_use + r.footprint <= self.budget:
+                job.append(r)
+                self.in_use += r.footprint
+            else:
+                keep.append(r)
+        keep.extend(self._queue)
+        self._queue = keep
+        now = time.perf_counter()
+        for r in job:
+            r.params["_admitted"] = now
+        return job
 
-    # -- workers ------------------------------------------------------------------
     def _work(self, w: int, device: int):
         torch = self._torch
         torch.cuda.set_device(device)
         stream = torch.cuda.Stream(device=device)
         while True:
             with self._cv:
-                while not self._jobs:
-                    self._cv.wait()
-                job = self._jobs.popleft()
+                job = self._take()
                 if job is None:
-                    self._jobs.append(None)  # let the other workers see it
-                    self._cv.notify_all()
+                    self._cv.notify_all()  # let the other workers see the end too
                     return
             try:
                 self._run(job, stream)
