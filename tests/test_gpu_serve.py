@@ -145,3 +145,29 @@ def test_admission_respects_budget():
     # with room for about one request at a time the admissions do not overlap much
     assert all(r.output.best_cost >= 0 for r in res)
     assert srv.in_use == 0
+
+
+def test_large_tiled_group_equals_solo():
+    """Sixteen uneven tiled instances (3- to 5-CNF, 20k to 4M literals) in
+    one grouped launch: each result is bitwise its solo result, the group
+    running the schedule of its largest instance."""
+    rng = np.random.default_rng(77)
+    cnfs, seeds = [], []
+    for i in range(16):
+        k = int(rng.integers(3, 6))
+        n = int(rng.integers(2000, 40000))
+        m = int(n * (3.5 + 1.5 * rng.random()) * 2 ** k / 8)
+        cnfs.append(hm.load_cnf(n, cnfgen.uniform_kcnf(n, m, k, seed=100 + i)))
+        seeds.append(1000 + i)
+    kw = dict(steps=80, restarts=1, eval_every=10, lr=1e-2)
+    batch = hm.solve_batch(cnfs, seeds=seeds, want_x=True, **kw)
+    tiled = 0
+    for c, s, b in zip(cnfs, seeds, batch):
+        a = hm.solve(c, seed=s, autotune=False, want_x=True, **kw)
+        assert b.status == 0
+        _same(a, b)
+        np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32),
+                                      b.x_final.cpu().numpy().view(np.uint32))
+        tiled += b.schedule != 255
+    _say(f"large group: {tiled} of 16 tiled")
+    assert tiled >= 9
