@@ -171,3 +171,34 @@ def test_large_tiled_group_equals_solo():
         tiled += b.schedule != 255
     _say(f"large group: {tiled} of 16 tiled")
     assert tiled >= 9
+
+
+def test_queued_requests_are_taken_together():
+    """With its one worker busy, requests of one kind that queue up are taken
+    together when the worker frees (one job, shared launches), and each
+    result still equals its solo solve."""
+    from paper_2402_03640_amd import serve as S
+    n0, lits0 = 3000, cnfgen.uniform_kcnf(3000, 12900, 3, seed=60)
+    reqs = [(400 + 10 * i, cnfgen.uniform_kcnf(400 + 10 * i, 1700 + 43 * i, 3, seed=61 + i)) for i in range(12)]
+    kw = dict(steps=150, restarts=1, eval_every=10, lr=1e-2, autotune=False)
+    solo = []
+    for i, (n, lits) in enumerate(reqs):
+        c = hm.load_cnf(n, lits)
+        solo.append(hm.solve(c, seed=i, **kw))
+        c.free()
+    sizes = []
+
+    class Logged(S.Server):
+        def _run(self, job, stream):
+            sizes.append(len(job))
+            return super()._run(job, stream)
+
+    with Logged(workers=1) as srv:
+        first = srv.submit(n0, lits0, seed=99, **dict(kw, steps=3000))  # keeps the worker busy
+        futs = [srv.submit(n, lits, seed=i, **kw) for i, (n, lits) in enumerate(reqs)]
+        res = [f.result(timeout=120) for f in futs]
+        first.result(timeout=120)
+    _say(f"job sizes {sizes}")
+    for a, r in zip(solo, res):
+        _same(a, r.output)
+    assert sizes[0] == 1 and max(sizes[1:]) >= 6 and len(sizes) <= 4
