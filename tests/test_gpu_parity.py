@@ -223,6 +223,50 @@ def test_resident_matches_tiled(kind, R, opt, mode):
     np.testing.assert_allclose(a.restart_loss, b.restart_loss, rtol=1e-12)
 
 
+def test_random_instances_schedule_independent():
+    """Random instances (uniform k-CNF with k from 2 to 7, skewed, mixed, a
+    third weighted) with random restart counts, counting periods, optimizers
+    and loss modes: three random tuner schedules and the resident solver all
+    give the automatic schedule's result bit for bit."""
+    rng = np.random.default_rng(2026)
+    checked = 0
+    for it in range(120):
+        kind = rng.choice(["uniform", "structured", "mixed"])
+        n = int(rng.integers(30, 6000))
+        if kind == "uniform":
+            k = int(rng.integers(2, 8))
+            lits = cnfgen.uniform_kcnf(n, max(int(n * rng.uniform(1.5, 0.6 * 2 ** k)), 1), k, seed=it)
+        elif kind == "structured":
+            lits = cnfgen.structured_cnf(n, int(n * rng.uniform(2, 6)), seed=it)
+        else:
+            lits = cnfgen.mixed_kcnf(n, int(n * rng.uniform(2, 5)), seed=it)
+        m = int(np.count_nonzero(lits == 0))
+        weights = rng.integers(1, 50, size=m).astype(np.int64) if rng.random() < 0.3 else None
+        cnf = hm.load_cnf(n, lits, weights=weights)
+        R = int(rng.choice([1, 2, 3, 5, 8, 16, 33, 64]))
+        opt = int(rng.choice([hm.ADAM, hm.SGD]))
+        mode = int(rng.choice([hm.LOSS_UNSAT, hm.LOSS_ALL]))
+        kw = dict(steps=int(rng.integers(20, 120)), restarts=R, eval_every=int(rng.choice([1, 3, 10, 25])),
+                  optimizer=opt, loss_mode=mode, lr=0.05 if opt == hm.SGD else 1e-2, seed=it, want_x=True,
+                  autotune=False)
+        ref = hm.solve(cnf, **kw)
+        cands = hm.tune_candidates(R, mode)
+        for s in list(rng.choice(cands, size=min(3, len(cands)), replace=False)) + [RESIDENT]:
+            try:
+                o = hm.solve(cnf, schedule=int(s), **kw)
+            except hm.HipMsatError:
+                continue  # the resident solver does not fit this instance
+            np.testing.assert_array_equal(o.restart_best, ref.restart_best)
+            np.testing.assert_array_equal(o.restart_step, ref.restart_step)
+            np.testing.assert_array_equal(o.best_assignment, ref.best_assignment)
+            np.testing.assert_array_equal(o.x_final.cpu().numpy().view(np.uint32),
+                                          ref.x_final.cpu().numpy().view(np.uint32))
+            checked += 1
+        assert hm.evaluate(cnf, ref.best_assignment) == ref.best_cost
+        cnf.free()
+    _say(f"{checked} schedule pairs checked")
+
+
 def test_binding_rejects_bad_points():
     """Relaxed points that the kernels cannot take are refused before any
     launch: wrong dtype, not contiguous, wrong row count, a gradient buffer of
