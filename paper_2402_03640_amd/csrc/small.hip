@@ -133,6 +133,9 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
         off += stage_side<kThreads>(smem + off, D.c_tile, D.c_tiles, D.c_ent, D.c_ent_len, cs.tiles, cs.ent);
     if constexpr (SV)
         off += stage_side<kThreads>(smem + off, D.v_tile, D.v_tiles, D.v_ent, D.v_ent_len, vs.tiles, vs.ent);
+    // every thread staged a strided share of the sides; the register cache
+    // below reads other threads' shares
+    if constexpr (SC || SV) __syncthreads();
 
     const AdamCoef co{D.b1, D.b2, D.eps, D.omb1, D.omb2};
     uint8_t* best_a = D.best_a + (size_t)r * n;

@@ -202,3 +202,52 @@ def test_queued_requests_are_taken_together():
     for a, r in zip(solo, res):
         _same(a, r.output)
     assert sizes[0] == 1 and max(sizes[1:]) >= 6 and len(sizes) <= 4
+
+
+def test_concurrent_batches_equal_solo():
+    """Sixteen threads, each on its own stream, solve random groups of one to
+    sixteen instances at once (resident and tiled): every result equals the
+    instance's solo solve.  Concurrent kernels make a workgroup's wavefronts
+    progress unevenly, which exposes a missing barrier inside a workgroup."""
+    import threading
+
+    import torch
+    rng = np.random.default_rng(3)
+    cnfs = []
+    for i in range(80):
+        n = int(np.exp(rng.uniform(np.log(30), np.log(6000))))
+        k = int(rng.integers(3, 6))
+        cnfs.append(hm.load_cnf(n, cnfgen.uniform_kcnf(n, max(int(n * rng.uniform(3.5, 5) * 2 ** k / 8), 1), k,
+                                                       seed=5000 + i)))
+    kw = dict(steps=200, restarts=1, eval_every=50, lr=1e-4)
+    solo = [hm.solve(c, seed=i, autotune=False, **kw) for i, c in enumerate(cnfs)]
+    bad, done, lock = [], [0], threading.Lock()
+
+    def worker(w):
+        try:
+            torch.cuda.set_device(0)
+            st = torch.cuda.Stream()
+            r = np.random.default_rng(100 + w)
+            for _ in range(20):
+                idx = [int(x) for x in r.choice(len(cnfs), size=int(r.integers(1, 17)), replace=False)]
+                if len(idx) == 1:
+                    outs = [hm.solve(cnfs[idx[0]], seed=idx[0], stream=st, autotune=False, **kw)]
+                else:
+                    outs = hm.solve_batch([cnfs[i] for i in idx], seeds=idx, stream=st, **kw)
+                with lock:
+                    for i, o in zip(idx, outs):
+                        done[0] += 1
+                        if not (o.best_cost == solo[i].best_cost
+                                and np.array_equal(o.best_assignment, solo[i].best_assignment)):
+                            bad.append((w, i, len(idx), o.schedule))
+        except Exception as e:  # reported on the test's thread
+            with lock:
+                bad.append((w, repr(e)))
+
+    th = [threading.Thread(target=worker, args=(w,)) for w in range(16)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    _say(f"{done[0]} concurrent results")
+    assert not bad, bad[:10]
