@@ -123,3 +123,56 @@ def test_torch_driven_descent_reduces_unsat():
     last = int(maxsat_loss(cnf, x)[1].item())
     _say(f"torch-driven: unsat {first} -> {last}")
     assert last < 0.7 * first
+
+
+def test_concurrent_evaluations_bitwise():
+    """Sixteen threads on their own streams evaluate the loss, gradient and
+    unsat counts (eval_relaxed, and the autograd loss with and without
+    recomputation) of random instances at once: every result equals the one
+    computed alone, bit for bit."""
+    import threading
+
+    from paper_2402_03640_amd.autograd import maxsat_loss
+    rng = np.random.default_rng(5)
+    cases = []
+    for i in range(24):
+        n = int(np.exp(rng.uniform(np.log(30), np.log(20000))))
+        lits = (cnfgen.structured_cnf(n, int(n * rng.uniform(2, 5)), seed=900 + i) if i % 2
+                else cnfgen.uniform_kcnf(n, int(n * 4.2), 3, seed=900 + i))
+        c = hm.load_cnf(n, lits)
+        x = torch.from_numpy(cnfgen.random_x(n, int(rng.choice([1, 4, 16, 64])), seed=i)).cuda()
+        mode, ck = int(rng.choice([hm.LOSS_UNSAT, hm.LOSS_ALL])), bool(rng.random() < 0.5)
+        l0, g0, u0 = hm.eval_relaxed(c, x, loss_mode=mode)
+        cases.append((c, x, mode, ck, l0.copy(), g0.clone(), u0.copy(), _grad(c, x, mode, ck)[2]))
+    torch.cuda.synchronize()
+    bad, lock = [], threading.Lock()
+
+    def worker(w):
+        try:
+            torch.cuda.set_device(0)
+            st = torch.cuda.Stream()
+            r = np.random.default_rng(w)
+            with torch.cuda.stream(st):
+                for _ in range(40):
+                    c, x, mode, ck, l0, g0, u0, ag0 = cases[int(r.integers(0, len(cases)))]
+                    l, g, u = hm.eval_relaxed(c, x, loss_mode=mode, stream=st)
+                    xt = x.clone().requires_grad_(True)
+                    loss, _ = maxsat_loss(c, xt, loss_mode=mode, checkpoint=ck)
+                    loss.sum().backward()
+                    st.synchronize()
+                    ok = (np.array_equal(l, l0) and np.array_equal(u, u0)
+                          and torch.equal(g.view(torch.int32), g0.view(torch.int32))
+                          and np.array_equal(xt.grad.cpu().numpy().view(np.uint32), ag0.view(np.uint32)))
+                    if not ok:
+                        with lock:
+                            bad.append((w, c.n))
+        except Exception as e:  # reported on the test's thread
+            with lock:
+                bad.append((w, repr(e)))
+
+    th = [threading.Thread(target=worker, args=(w,)) for w in range(16)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not bad, bad[:10]
