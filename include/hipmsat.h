@@ -24,6 +24,8 @@
  *  - An hms_cnf handle is immutable after loading; several solves may use one
  *    handle at once (each call allocates its own state).  No call keeps a
  *    caller pointer after it returns.
+ *  - Calls may run on several host threads at once, each on its own stream;
+ *    their results are the same as when run one after the other.
  */
 #ifndef HIPMSAT_H
 #define HIPMSAT_H
