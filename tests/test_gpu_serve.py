@@ -251,3 +251,31 @@ def test_concurrent_batches_equal_solo():
         t.join()
     _say(f"{done[0]} concurrent results")
     assert not bad, bad[:10]
+
+
+def test_repeated_solves_do_not_grow_device_memory():
+    """Loading, solving (alone and batched) and freeing the same instances
+    twice over: device memory after the second round equals that after the
+    first (the stream-ordered pool keeps its high-water mark, nothing more)."""
+    import torch
+    rng = np.random.default_rng(1)
+    inst = []
+    for i in range(20):
+        n = int(np.exp(rng.uniform(np.log(30), np.log(20000))))
+        inst.append((n, cnfgen.uniform_kcnf(n, int(n * 4.2), 3, seed=i)))
+
+    def one_round():
+        for _ in range(8):
+            cnfs = [hm.load_cnf(n, lits) for n, lits in inst]
+            for i, c in enumerate(cnfs):
+                hm.solve(c, steps=30, restarts=1 + i % 4, eval_every=10, seed=i, autotune=False)
+            hm.solve_batch(cnfs, steps=30, eval_every=10, seeds=list(range(len(cnfs))))
+            for c in cnfs:
+                c.free()
+        torch.cuda.synchronize()
+        return torch.cuda.mem_get_info()[0]
+
+    f1 = one_round()
+    f2 = one_round()
+    _say(f"free after round 1: {f1 / 2**20:.0f} MiB, after round 2: {f2 / 2**20:.0f} MiB")
+    assert f1 - f2 <= 16 << 20
