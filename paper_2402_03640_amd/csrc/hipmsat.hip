@@ -204,7 +204,15 @@ enum { kOffX, kOffM, kOffV, kOffT, kOffA, kOffG, kOffSeg, kOffCnt, kOffLoss, kOf
 
 // Units per stage-1 reduce chunk: a fixed function of the unit count.
 int32_t reduce_chunk(int64_t n_units) { return (int32_t)std::max<int64_t>(64, (n_units + 1023) / 1024); }
-int32_t reduce_chunks(int64_t n_units) { return (int32_t)((n_units + reduce_chunk(n_units) - 1) / reduce_chunk(n_units)); }
+// Stage-1 chunks of the count/loss reduction; 0 when the final stage can sum
+// the unit partials itself with at most 16 loads per thread (its 1024 threads
+// hold `restart lanes` restarts side by side), which saves a launch.
+int32_t reduce_chunks(int64_t n_units, int32_t R) {
+    int64_t rp = 1;
+    while (rp < 64 && rp < R) rp <<= 1;
+    if (n_units * rp <= 16 * 1024) return 0;
+    return (int32_t)((n_units + reduce_chunk(n_units) - 1) / reduce_chunk(n_units));
+}
 
 int32_t umask_words(const hms::HostPlan& P) { return P.c_tiles * 2 + 1; }
 
@@ -229,8 +237,8 @@ void layout_state(const hms::HostPlan& P, const Shape& sh, bool moments, bool gr
     off[kOffBestS] = L.add((size_t)R * 4);
     off[kOffImp] = L.add((size_t)R * 4);
     off[kOffCurL] = L.add((size_t)R * 8);
-    off[kOffCntMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc), 1) * R * 8);
-    off[kOffLossMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc), 1) * R * 8);
+    off[kOffCntMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc, R), 1) * R * 8);
+    off[kOffLossMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc, R), 1) * R * 8);
     off[kOffSt] = L.add(256 + (size_t)std::max(P.n, 1));  // step state, then out_assign at +256
 }
 
@@ -357,7 +365,7 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     r.loss_part = S.loss_part;
     r.n_units = (int32_t)sh.n_tc;
     r.chunk = reduce_chunk(sh.n_tc);
-    r.n_chunks = reduce_chunks(sh.n_tc);
+    r.n_chunks = reduce_chunks(sh.n_tc, sh.B.R);
     r.cnt_mid = S.cnt_mid;
     r.loss_mid = S.loss_mid;
     r.R = sh.B.R;

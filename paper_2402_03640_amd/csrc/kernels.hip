@@ -744,7 +744,9 @@ __global__ __launch_bounds__(1024) void k_combine_multi(const BwdArgs* __restric
 // restarts: lane l of the 256 threads holds restart 64 rb + (l % RP) and slot
 // l / RP; a slot sums its units with stride NS = 256 / RP in order, then a
 // fixed tree over the slots.  Stage 2 sums the chunk partials the same way
-// with one 1024-thread block per restart block, and tracks the best.
+// with one 1024-thread block per restart block, and tracks the best.  When
+// the unit partials are few (n_chunks == 0), stage 2 sums them directly and
+// stage 1 is not launched.
 __device__ __forceinline__ int restart_lanes(int R) {
     int RP = 1;  // restarts side by side: the next power of two >= R, at most 64
     while (RP < 64 && RP < R) RP <<= 1;
@@ -813,11 +815,16 @@ __device__ __forceinline__ void reduce2_body(const ReduceArgs& A, const int bx, 
     const int r = bx * 64 + rloc;
     int64_t c = 0;
     double l = 0.0;
+    // with no stage-1 chunks the unit partials are few enough to sum here
+    const bool direct = A.n_chunks == 0;
+    const int nsrc = direct ? A.n_units : A.n_chunks;
+    const int64_t* __restrict__ cp = direct ? A.cnt_part : A.cnt_mid;
+    const double* __restrict__ lp = direct ? A.loss_part : A.loss_mid;
     if (r < A.R) {
 #pragma unroll 8
-        for (int u = slot; u < A.n_chunks; u += NS) {
-            c += A.cnt_mid[(size_t)u * A.R + r];
-            l = l + A.loss_mid[(size_t)u * A.R + r];
+        for (int u = slot; u < nsrc; u += NS) {
+            c += cp[(size_t)u * A.R + r];
+            l = l + lp[(size_t)u * A.R + r];
         }
     }
     sc[tid] = c;
