@@ -62,6 +62,10 @@ def lib():
         L.oracle_solve.argtypes = [P, I32, I32, I32, U64, I32, D, D, D, D, I32, P, I32,
                                    P, P, P, P, P, P]
         L.oracle_solve.restype = I64
+        L.oracle_run.argtypes = [P, I32, I32, I32, I32, D, D, D, D, I32, I32, P, P, P, P, P, P, P, P]
+        L.oracle_run.restype = C.c_int
+        L.oracle_init_state.argtypes = [P, I32, U64, P, P, P, P, P, P, P, P]
+        L.oracle_init_state.restype = None
         L.oracle_bruteforce.argtypes = [P, P, P, P]
         L.oracle_bruteforce.restype = C.c_int
         L.oracle_set_weights.argtypes = [P, P]
@@ -192,6 +196,49 @@ class OracleCNF:
         if want_x:
             out["x"] = xo
         return out
+
+    # --- the loop's state (x, moments, step, best so far) ---------------------
+    def init_state(self, restarts: int = 1, seed: int = 0, x0=None) -> dict:
+        """The state before the first iteration of Algorithm 1: x from x0
+        ([n][R] float32) or SplitMix64, zero moments, step 0, best = the total
+        weight, best_step = -1, best assignment = round(x).  x, m, v are
+        float64 [n][R], best_assignment uint8 [R][n]."""
+        R = int(restarts)
+        st = dict(x=np.zeros((self.n, R)), m=np.zeros((self.n, R)), v=np.zeros((self.n, R)),
+                  step=0, best=np.zeros(R, dtype=np.int64), best_step=np.zeros(R, dtype=np.int32),
+                  best_assignment=np.zeros((R, self.n), dtype=np.uint8))
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float32).reshape(self.n, R)
+        step = C.c_int32()
+        lib().oracle_init_state(self._h, R, int(seed) & (2**64 - 1), _ptr(x0a), _ptr(st["x"]), _ptr(st["m"]),
+                                _ptr(st["v"]), C.byref(step), _ptr(st["best"]), _ptr(st["best_step"]),
+                                _ptr(st["best_assignment"]))
+        st["step"] = step.value
+        return st
+
+    def run(self, state: dict, steps: int, eval_every: int = 1, optimizer: int = ADAM, lr: float = 1e-4,
+            beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, mode: int = UNSAT,
+            threads: int = 1) -> dict:
+        """Continue Algorithm 1 from ``state`` for ``steps`` more steps; returns
+        a new state (the argument is not changed) with ``final_loss`` [R], the
+        loss at its last iterate."""
+        st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in state.items()}
+        R = st["x"].shape[1]
+        for k, dt in (("x", np.float64), ("m", np.float64), ("v", np.float64)):
+            st[k] = np.ascontiguousarray(st[k], dtype=dt).reshape(self.n, R)
+        st["best"] = np.ascontiguousarray(st["best"], dtype=np.int64)
+        st["best_step"] = np.ascontiguousarray(st["best_step"], dtype=np.int32)
+        st["best_assignment"] = np.ascontiguousarray(st["best_assignment"], dtype=np.uint8).reshape(R, self.n)
+        fl = np.zeros(R)
+        step = C.c_int32(int(st["step"]))
+        rc = lib().oracle_run(self._h, int(steps), R, int(eval_every), int(optimizer), lr, beta1, beta2, eps,
+                              int(mode), int(threads), _ptr(st["x"]), _ptr(st["m"]), _ptr(st["v"]),
+                              C.byref(step), _ptr(st["best"]), _ptr(st["best_step"]),
+                              _ptr(st["best_assignment"]), _ptr(fl))
+        if rc != 0:
+            raise OracleError(rc)
+        st["step"] = step.value
+        st["final_loss"] = fl
+        return st
 
     def bruteforce(self):
         """(opt, number of optimal assignments, one optimal assignment)."""

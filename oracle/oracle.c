@@ -28,8 +28,12 @@
  *     4 e^{-2|x|} / (1 + e^{-2|x|})^2, which does not cancel).
  *   - optimizer (Section 5 Setup): Adam with PyTorch 1.10 semantics, or plain
  *     gradient descent as in the worked example.
- *   - Algorithm 1 loop: best_cost starts at m; at every evaluation step the
- *     rounded iterate is counted and kept when strictly better; then one step.
+ *   - Algorithm 1 loop: best_cost starts at m (the total weight) with the
+ *     rounded start as its assignment and step -1; at every evaluation step
+ *     (t a multiple of K, and the last iterate) the rounded iterate is
+ *     counted before the step and kept when strictly better; then one step.
+ *     The loop's state (x, moments, step, best so far) can be taken out and
+ *     the loop continued from it.
  *   - brute force (n <= 24): Gray-code enumeration of all assignments.
  *   - clause weights (weighted partial CNF, defined in Section 2 and left to
  *     future work in Section 6): with positive integer weights w_j the
@@ -272,43 +276,50 @@ void oracle_init_x(int32_t n, int32_t R, uint64_t seed, float *x) {
         }
 }
 
-/* Algorithm 1 for R independent restarts.
- *   opt: 0 = Adam, 1 = SGD.  mode: 0 = UNSAT, 1 = ALL.
- *   x0: [n][R] floats or NULL (SplitMix64 with `seed`).
- *   Outputs (any may be NULL): restart_best[R], restart_step[R],
- *   final_loss[R] (loss at x_T), best_assign[n] (of the best restart),
- *   x_out [n][R] doubles (x_T).  Returns the instance best cost.
- *   threads > 1 runs restarts in parallel (OpenMP), each restart unchanged. */
-int64_t oracle_solve(const ocnf *c, int32_t T, int32_t R, int32_t K, uint64_t seed,
-                     int32_t opt, double lr, double b1, double b2, double eps, int32_t mode,
-                     const float *x0, int32_t threads, int64_t *restart_best,
-                     int32_t *restart_step, double *final_loss, uint8_t *best_assign,
-                     int32_t *best_restart, double *x_out) {
+/* Algorithm 1 (Section 4, "The Solving Process") for R independent restarts,
+ * continued from a given state for T more steps.  The state is what the loop
+ * carries from one iteration to the next:
+ *   x, mm, vv   [n][R] doubles: relaxed values and Adam moments (in/out);
+ *   *step       iterations already taken (in), plus T (out);
+ *   best[R], best_step[R]: fewest unsatisfied clauses seen and the step of
+ *               that iterate, -1 for "not beaten since the start" (in/out);
+ *   best_a      [R][n] bytes: the rounded iterate that reached best (in/out).
+ * With t the global iteration index: whenever t % K == 0, and at the last
+ * iterate, the rounded iterate is counted and kept if strictly better; then
+ * the loss gradient at x_t (mask from the same rounding) takes Adam step
+ * number t + 1, or an SGD step.  final_loss[R] (may be NULL) receives the loss
+ * at the last iterate.  A solve of T1 + T2 steps equals this call with T1
+ * then with T2 on the state it left, bit for bit, when T1 is a multiple of K
+ * (otherwise the extra count of the T1-th iterate may only lower best).
+ *   opt: 0 = Adam, 1 = SGD.  mode: 0 = UNSAT, 1 = ALL.  threads > 1 runs the
+ *   restarts in parallel (OpenMP), each restart unchanged. */
+int oracle_run(const ocnf *c, int32_t T, int32_t R, int32_t K, int32_t opt, double lr, double b1,
+               double b2, double eps, int32_t mode, int32_t threads, double *x_s, double *m_s,
+               double *v_s, int32_t *step, int64_t *best_s, int32_t *best_step_s, uint8_t *best_a_s,
+               double *final_loss) {
     int32_t n = c->n;
-    if (R <= 0 || T < 0 || K <= 0) return -1;
-    float *xi = (float *)malloc(sizeof(float) * ((size_t)n * R + 1));
-    if (x0) memcpy(xi, x0, sizeof(float) * (size_t)n * R);
-    else oracle_init_x(n, R, seed, xi);
-    int64_t *rb = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
-    int32_t *rs = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
-    uint8_t *ra = (uint8_t *)malloc((size_t)n * R + 1);
+    if (R <= 0 || T < 0 || K <= 0 || !step || *step < 0 || *step > INT32_MAX - T) return OR_ERR_ARG;
+    const int32_t t0 = *step, t1 = *step + T;
 #ifdef _OPENMP
     int nt = threads > 0 ? threads : 1;
 #pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
 #endif
     for (int32_t r = 0; r < R; ++r) {
         double *x = (double *)malloc(sizeof(double) * ((size_t)n + 1));
-        double *mm = (double *)calloc((size_t)n + 1, sizeof(double));
-        double *vv = (double *)calloc((size_t)n + 1, sizeof(double));
+        double *mm = (double *)malloc(sizeof(double) * ((size_t)n + 1));
+        double *vv = (double *)malloc(sizeof(double) * ((size_t)n + 1));
         double *g = (double *)malloc(sizeof(double) * ((size_t)n + 1));
         uint8_t *a = (uint8_t *)malloc((size_t)n + 1);
-        uint8_t *best_a = ra + (size_t)r * n;
-        for (int32_t i = 0; i < n; ++i) x[i] = (double)xi[(int64_t)i * R + r];
-        int64_t best = c->wtot;  /* every clause unsatisfied */
-        int32_t best_step = -1;
-        for (int32_t i = 0; i < n; ++i) best_a[i] = (uint8_t)(x[i] > 0.0);
-        for (int32_t t = 0; t <= T; ++t) {
-            if (t % K == 0 || t == T) {
+        uint8_t *best_a = best_a_s + (size_t)r * n;
+        for (int32_t i = 0; i < n; ++i) {
+            x[i] = x_s[(int64_t)i * R + r];
+            mm[i] = m_s[(int64_t)i * R + r];
+            vv[i] = v_s[(int64_t)i * R + r];
+        }
+        int64_t best = best_s[r];
+        int32_t best_step = best_step_s[r];
+        for (int32_t t = t0; t <= t1; ++t) {
+            if (t % K == 0 || t == t1) {
                 for (int32_t i = 0; i < n; ++i) a[i] = (uint8_t)(x[i] > 0.0);
                 int64_t cnt = oracle_count(c, a);
                 if (cnt < best) {
@@ -316,7 +327,7 @@ int64_t oracle_solve(const ocnf *c, int32_t T, int32_t R, int32_t K, uint64_t se
                     memcpy(best_a, a, (size_t)n);
                 }
             }
-            if (t == T) {
+            if (t == t1) {
                 if (final_loss) final_loss[r] = oracle_loss_grad_d(c, x, mode, NULL, NULL, NULL, NULL);
                 break;
             }
@@ -324,20 +335,79 @@ int64_t oracle_solve(const ocnf *c, int32_t T, int32_t R, int32_t K, uint64_t se
             if (opt == 0) oracle_adam_step(n, x, mm, vv, g, t + 1, lr, b1, b2, eps);
             else oracle_sgd_step(n, x, g, lr);
         }
-        rb[r] = best; rs[r] = best_step;
-        if (x_out)
-            for (int32_t i = 0; i < n; ++i) x_out[(int64_t)i * R + r] = x[i];
+        best_s[r] = best; best_step_s[r] = best_step;
+        for (int32_t i = 0; i < n; ++i) {
+            x_s[(int64_t)i * R + r] = x[i];
+            m_s[(int64_t)i * R + r] = mm[i];
+            v_s[(int64_t)i * R + r] = vv[i];
+        }
         free(x); free(mm); free(vv); free(g); free(a);
     }
-    int32_t br = 0;
-    for (int32_t r = 1; r < R; ++r)
-        if (rb[r] < rb[br]) br = r;
-    if (restart_best) memcpy(restart_best, rb, sizeof(int64_t) * (size_t)R);
-    if (restart_step) memcpy(restart_step, rs, sizeof(int32_t) * (size_t)R);
-    if (best_assign) memcpy(best_assign, ra + (size_t)br * n, (size_t)n);
-    if (best_restart) *best_restart = br;
-    int64_t best = rb[br];
-    free(xi); free(rb); free(rs); free(ra);
+    *step = t1;
+    return OR_OK;
+}
+
+/* The state of Algorithm 1 before its first iteration: x^0 from x0 ([n][R]
+ * floats) or SplitMix64 with `seed`, zero moments, step 0, best = the total
+ * weight (every clause unsatisfied), best_step = -1, best_a = round(x^0). */
+void oracle_init_state(const ocnf *c, int32_t R, uint64_t seed, const float *x0, double *x_s, double *m_s,
+                       double *v_s, int32_t *step, int64_t *best_s, int32_t *best_step_s, uint8_t *best_a_s) {
+    int32_t n = c->n;
+    float *xi = (float *)malloc(sizeof(float) * ((size_t)n * R + 1));
+    if (x0) memcpy(xi, x0, sizeof(float) * (size_t)n * R);
+    else oracle_init_x(n, R, seed, xi);
+    for (int64_t e = 0; e < (int64_t)n * R; ++e) {
+        x_s[e] = (double)xi[e];
+        m_s[e] = 0.0;
+        v_s[e] = 0.0;
+    }
+    for (int32_t r = 0; r < R; ++r) {
+        best_s[r] = c->wtot;
+        best_step_s[r] = -1;
+        for (int32_t i = 0; i < n; ++i) best_a_s[(size_t)r * n + i] = (uint8_t)(x_s[(int64_t)i * R + r] > 0.0);
+    }
+    *step = 0;
+    free(xi);
+}
+
+/* Algorithm 1 for R independent restarts from the start.
+ *   opt: 0 = Adam, 1 = SGD.  mode: 0 = UNSAT, 1 = ALL.
+ *   x0: [n][R] floats or NULL (SplitMix64 with `seed`).
+ *   Outputs (any may be NULL): restart_best[R], restart_step[R],
+ *   final_loss[R] (loss at x_T), best_assign[n] (of the best restart; ties
+ *   go to the lowest restart), x_out [n][R] doubles (x_T).  Returns the
+ *   instance best cost (negative on an argument error). */
+int64_t oracle_solve(const ocnf *c, int32_t T, int32_t R, int32_t K, uint64_t seed,
+                     int32_t opt, double lr, double b1, double b2, double eps, int32_t mode,
+                     const float *x0, int32_t threads, int64_t *restart_best,
+                     int32_t *restart_step, double *final_loss, uint8_t *best_assign,
+                     int32_t *best_restart, double *x_out) {
+    int32_t n = c->n;
+    if (R <= 0 || T < 0 || K <= 0) return -1;
+    size_t nR = (size_t)n * R + 1;
+    double *xs = (double *)malloc(sizeof(double) * nR);
+    double *ms = (double *)malloc(sizeof(double) * nR);
+    double *vs = (double *)malloc(sizeof(double) * nR);
+    int64_t *rb = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    int32_t *rs = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    uint8_t *ra = (uint8_t *)malloc(nR);
+    int32_t step = 0;
+    oracle_init_state(c, R, seed, x0, xs, ms, vs, &step, rb, rs, ra);
+    int rc = oracle_run(c, T, R, K, opt, lr, b1, b2, eps, mode, threads, xs, ms, vs, &step, rb, rs, ra,
+                        final_loss);
+    int64_t best = -1;
+    if (rc == OR_OK) {
+        int32_t br = 0;
+        for (int32_t r = 1; r < R; ++r)
+            if (rb[r] < rb[br]) br = r;
+        if (restart_best) memcpy(restart_best, rb, sizeof(int64_t) * (size_t)R);
+        if (restart_step) memcpy(restart_step, rs, sizeof(int32_t) * (size_t)R);
+        if (best_assign) memcpy(best_assign, ra + (size_t)br * n, (size_t)n);
+        if (best_restart) *best_restart = br;
+        if (x_out) memcpy(x_out, xs, sizeof(double) * (size_t)n * R);
+        best = rb[br];
+    }
+    free(xs); free(ms); free(vs); free(rb); free(rs); free(ra);
     return best;
 }
 

@@ -288,6 +288,46 @@ def test_gradient_finite_differences(mode, seed):
 # Brute force
 # ----------------------------------------------------------------------------
 
+def _dense_w(n, clauses):
+    """Dense W of Section 4 from the clause lists: W[i][j] = +1 / -1 when x_i /
+    not x_i is a literal of c_j; a repeated literal counts once and a
+    complementary pair gives +1 - 1 = 0."""
+    W = np.zeros((n, len(clauses)))
+    for j, cl in enumerate(clauses):
+        for lit in set(cl):
+            W[abs(lit) - 1, j] += 1.0 if lit > 0 else -1.0
+    return W
+
+
+@pytest.mark.parametrize("mode", [O.UNSAT, O.ALL])
+def test_loss_and_gradient_match_dense_torch_autograd(mode):
+    """The paper's own formulation: the dense network tanh(x) W, the MSE
+    against zero over the unsatisfied clauses (mask held constant, from the
+    rounding) divided by m, differentiated by torch autograd in FP64."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(31 + mode)
+    n, clauses = 30, []
+    for _ in range(140):
+        k = int(rng.integers(0, 6))
+        clauses.append([int(v) * (1 if rng.random() < 0.5 else -1) for v in rng.integers(1, n + 1, size=k)])
+    clauses += [[3, -3, 5], [7, 7, -8], []]
+    m = len(clauses)
+    oc = O.OracleCNF(n, cnfgen.from_clauses(clauses))
+    W = torch.tensor(_dense_w(n, clauses), dtype=torch.float64)
+    for trial in range(4):
+        x_np = rng.uniform(-2.5, 2.5, size=n)
+        a = (x_np > 0).astype(np.uint8)
+        mask = oc.unsat_mask(a).astype(np.float64) if mode == O.UNSAT else np.ones(m)
+        x = torch.tensor(x_np, dtype=torch.float64, requires_grad=True)
+        f = torch.tanh(x) @ W
+        loss = ((torch.tensor(mask) * f) ** 2).sum() / m
+        loss.backward()
+        lo, go, uo = oc.loss_grad(x_np, mode)
+        np.testing.assert_allclose(lo[0], loss.item(), rtol=1e-12, atol=1e-300)
+        np.testing.assert_allclose(go, x.grad.numpy(), rtol=1e-10, atol=1e-14)
+        assert uo[0] == int(oc.unsat_mask(a).sum())
+
+
 def test_bruteforce_all_sign_patterns():
     # every one of the 2^k sign patterns over k variables: each assignment
     # falsifies exactly one clause
@@ -362,6 +402,27 @@ def test_splitmix64_published_outputs(golden):
     assert [O.splitmix64(g["seed1"], k) for k in (1, 2, 3)] == g["out1"]
 
 
+def test_init_x_values_from_published_outputs(golden):
+    """x of variables 0..2 from the top 24 bits of SplitMix64 outputs 1..3
+    (values derived by hand from the published generator's outputs): taking
+    the low bits, output i instead of i + 1, or seed * r instead of seed + r
+    each change them."""
+    g = golden("init_x.txt")
+    for top, x in zip(g["top24_seed0"], g["x_seed0"]):
+        assert top / 2.0 ** 23 - 1.0 == x
+    x0 = O.init_x(3, 1, seed=0)[:, 0]
+    assert x0.tolist() == g["x_seed0"]
+    # restart 1 of seed 1234566 is the stream seeded 1234567
+    x1 = O.init_x(3, 2, seed=1234566)[:, 1]
+    assert x1.tolist() == g["x_stream1234567"]
+    # the loop starts from them, rounded x > 0
+    oc = O.OracleCNF(3, cnfgen.from_clauses([[1], [2], [3]]))
+    st = oc.init_state(restarts=1, seed=0)
+    assert st["x"][:, 0].tolist() == g["x_seed0"]
+    assert st["best_assignment"][0].tolist() == [1, 0, 0]
+    assert st["best"].tolist() == [3] and st["best_step"].tolist() == [-1] and st["step"] == 0
+
+
 def test_init_x_range_exactness_and_restart_streams():
     n, R = 4000, 3
     x = O.init_x(n, R, seed=17)
@@ -421,6 +482,113 @@ def test_solve_x0_and_best_monotone():
         cur = c.solve(steps=T, restarts=1, eval_every=5, seed=7, lr=0.05)["best_cost"]
         assert cur <= prev
         prev = cur
+
+
+# ---- loop order pins (Algorithm 1: best starts at m, the iterate is counted
+# before its step whenever t is a multiple of K and at the last iterate, and is
+# kept only when strictly better).  Formula (x1); x0 = -0.5; plain gradient
+# descent with lr 10 on the ALL loss (m = 1): one step gives
+# x1 = -0.5 + 10 * 2 tanh(0.5) sech^2(0.5) = 6.7686..., which satisfies the
+# clause.  Values derived by hand.
+
+def _unit_clause():
+    return O.OracleCNF(1, cnfgen.from_clauses([[1]]))
+
+
+def _run_unit(T, K):
+    oc = _unit_clause()
+    x0 = np.array([[-0.5]], dtype=np.float32)
+    return oc.solve(steps=T, restarts=1, eval_every=K, optimizer=O.SGD, lr=10.0, mode=O.ALL, x0=x0,
+                    want_x=True)
+
+
+def test_loop_pin_no_step_keeps_initial_best():
+    r = _run_unit(0, 1)
+    # the start is counted (1 unsatisfied clause) but is not strictly below m = 1
+    assert r["best_cost"] == 1 and r["restart_step"][0] == -1
+    assert r["best_assignment"].tolist() == [0]
+
+
+def test_loop_pin_one_step_reaches_zero():
+    r = _run_unit(1, 1)
+    x1 = -0.5 + 10.0 * 2.0 * math.tanh(0.5) / math.cosh(0.5) ** 2
+    assert abs(r["x"][0, 0] - x1) < 1e-12 and abs(x1 - 6.7686) < 1e-4
+    assert r["best_cost"] == 0 and r["restart_step"][0] == 1
+    assert r["best_assignment"].tolist() == [1]
+
+
+@pytest.mark.parametrize("K,T,step", [(1, 3, 1), (2, 3, 2), (5, 3, 3), (5, 1, 1), (3, 6, 3)])
+def test_loop_pin_counts_multiples_of_k_and_the_last_iterate(K, T, step):
+    """The clause is satisfied from x_1 on: the first counted iterate after
+    t = 0 is the first multiple of K at or after 1, or x_T."""
+    r = _run_unit(T, K)
+    assert r["best_cost"] == 0 and r["restart_step"][0] == step
+
+
+def test_loop_pin_equal_counts_keep_the_earliest_step():
+    """(x1) and (not x1): every assignment leaves one clause unsatisfied, so
+    the best (1 < m = 2) is reached at t = 0 and never replaced."""
+    oc = O.OracleCNF(1, cnfgen.from_clauses([[1], [-1]]))
+    for x0 in (-0.5, 0.5):
+        r = oc.solve(steps=6, restarts=1, eval_every=1, optimizer=O.SGD, lr=0.5, mode=O.ALL,
+                     x0=np.array([[x0]], dtype=np.float32))
+        assert r["best_cost"] == 1 and r["restart_step"][0] == 0
+        assert r["best_assignment"].tolist() == [1 if x0 > 0 else 0]
+
+
+@pytest.mark.parametrize("opt,mode", [(O.ADAM, O.UNSAT), (O.SGD, O.ALL), (O.ADAM, O.ALL)])
+def test_resume_continues_the_loop_bitwise(opt, mode):
+    """The loop's state (x, moments, step, best so far) carries everything
+    one iteration passes to the next: 500 steps, then 500 more from the state
+    they left, equal 1000 steps bit for bit when the split is a multiple of
+    K."""
+    n, m, R, K = 40, 172, 3, 25
+    oc = O.OracleCNF(n, cnfgen.uniform_kcnf(n, m, 3, seed=21))
+    lr = 0.05 if opt == O.ADAM else 0.5
+    kw = dict(eval_every=K, optimizer=opt, lr=lr, mode=mode)
+    s0 = oc.init_state(restarts=R, seed=9)
+    full = oc.run(s0, 1000, **kw)
+    half = oc.run(oc.run(s0, 500, **kw), 500, **kw)
+    for k in ("x", "m", "v", "best", "best_step", "best_assignment", "final_loss"):
+        np.testing.assert_array_equal(full[k], half[k], err_msg=k)
+    assert full["step"] == half["step"] == 1000
+    # the state is what solve() reports
+    ref = oc.solve(steps=1000, restarts=R, seed=9, want_x=True, **{"eval_every": K, "optimizer": opt,
+                                                                      "lr": lr, "mode": mode})
+    np.testing.assert_array_equal(ref["x"], full["x"])
+    np.testing.assert_array_equal(ref["restart_best"], full["best"])
+    np.testing.assert_array_equal(ref["restart_step"], full["best_step"])
+    br = int(np.argmin(full["best"]))
+    np.testing.assert_array_equal(ref["best_assignment"], full["best_assignment"][br])
+    if opt == O.ADAM:
+        assert np.any(full["m"] != 0) and np.any(full["v"] != 0)
+
+
+def test_resume_off_period_counts_one_more_iterate():
+    """Split at a step that is not a multiple of K: the trajectory (x, m, v)
+    is unchanged, and the extra count of the split iterate can only lower
+    the best."""
+    n, m, R, K = 30, 129, 4, 50
+    oc = O.OracleCNF(n, cnfgen.uniform_kcnf(n, m, 3, seed=22))
+    s0 = oc.init_state(restarts=R, seed=3)
+    full = oc.run(s0, 400, eval_every=K, lr=0.05)
+    half = oc.run(oc.run(s0, 137, eval_every=K, lr=0.05), 263, eval_every=K, lr=0.05)
+    for k in ("x", "m", "v"):
+        np.testing.assert_array_equal(full[k], half[k])
+    assert np.all(half["best"] <= full["best"])
+
+
+def test_resume_from_a_caller_state():
+    """A state built by hand (moments and best given) is taken as is: one SGD
+    step from x = -0.5 on (x1) lowers the given best of 1 to 0 at step 8."""
+    oc = _unit_clause()
+    st = dict(x=np.array([[-0.5]]), m=np.zeros((1, 1)), v=np.zeros((1, 1)), step=7,
+              best=np.array([1]), best_step=np.array([4]), best_assignment=np.array([[0]], dtype=np.uint8))
+    out = oc.run(st, 1, eval_every=1, optimizer=O.SGD, lr=10.0, mode=O.ALL)
+    assert out["step"] == 8 and out["best"].tolist() == [0] and out["best_step"].tolist() == [8]
+    x1 = -0.5 + 10.0 * 2.0 * math.tanh(0.5) / math.cosh(0.5) ** 2
+    assert abs(out["x"][0, 0] - x1) < 1e-12
+    assert st["step"] == 7 and st["best"].tolist() == [1]  # the argument is not changed
 
 
 # ---- clause weights (weighted partial CNF of Section 2, future work in Section 6;
