@@ -211,11 +211,14 @@ double oracle_loss_grad_d(const ocnf *c, const double *x, int mode, double *f_ou
         int un = clause_unsat(c, j, a);
         double wj = (double)weight(c, j);
         u += weight(c, j) * un;
-        double mu = mode == 1 ? 1.0 : (double)un;
+        /* the loss is a sum over the clauses in the mask (all of them in mode
+         * ALL); a clause outside it is not in the sum, whatever its score */
+        int in_loss = mode == 1 || un;
         if (f_out) f_out[j] = fj;
-        if (mu_out) mu_out[j] = (uint8_t)(mu != 0.0);
-        loss += wj * mu * fj * fj;
-        double aj = m > 0 ? 2.0 / (double)m * mu * wj * fj : 0.0;
+        if (mu_out) mu_out[j] = (uint8_t)in_loss;
+        if (!in_loss) continue;
+        loss += wj * fj * fj;
+        double aj = m > 0 ? 2.0 / (double)m * wj * fj : 0.0;
         for (int64_t r = c->woff[j]; r < c->woff[j + 1]; ++r)
             G[c->wvar[r]] += (double)c->wcoef[r] * aj;
     }

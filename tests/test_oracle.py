@@ -233,6 +233,26 @@ def test_polarity_flip_symmetry():
         np.testing.assert_allclose(g1, g2, rtol=1e-13, atol=1e-18)
 
 
+def test_masked_loss_leaves_out_satisfied_clauses_whatever_their_score():
+    """The UNSAT loss sums over the unsatisfied clauses only: a NaN relaxed
+    value (which rounds to false, like -0.5) in clauses that are all
+    satisfied leaves the loss and the other gradient entries as they are with
+    -0.5 there; in mode ALL every clause is in the sum and the loss is NaN."""
+    # x1 = NaN occurs only in (x1 or x2) and (not x1 or x3), both satisfied
+    # by x2 = x3 = true (and not x1); (not x2 or not x3) is unsatisfied
+    lits = cnfgen.from_clauses([[1, 2], [-1, 3], [-2, -3], [4, 2]])
+    oc = O.OracleCNF(4, lits)
+    xa = np.array([np.nan, 0.7, 0.3, -0.2])
+    xb = np.array([-0.5, 0.7, 0.3, -0.2])
+    la, ga, ua = oc.loss_grad(xa, O.UNSAT)
+    lb, gb, ub = oc.loss_grad(xb, O.UNSAT)
+    assert ua[0] == ub[0] == 1
+    assert la[0] == lb[0] and np.isfinite(la[0])
+    np.testing.assert_array_equal(ga[1:], gb[1:])
+    assert np.isnan(ga[0])  # sech^2(NaN)
+    assert np.isnan(oc.loss_grad(xa, O.ALL)[0][0])
+
+
 def test_zero_loss_iff_zero_count():
     n, m = 40, 150
     lits, plant = cnfgen.planted_kcnf(n, m, 3, seed=3)
@@ -288,7 +308,7 @@ def test_gradient_finite_differences(mode, seed):
 # Brute force
 # ----------------------------------------------------------------------------
 
-def _dense_w(n, clauses):
+def _dense_w_of_clauses(n, clauses):
     """Dense W of Section 4 from the clause lists: W[i][j] = +1 / -1 when x_i /
     not x_i is a literal of c_j; a repeated literal counts once and a
     complementary pair gives +1 - 1 = 0."""
@@ -313,7 +333,7 @@ def test_loss_and_gradient_match_dense_torch_autograd(mode):
     clauses += [[3, -3, 5], [7, 7, -8], []]
     m = len(clauses)
     oc = O.OracleCNF(n, cnfgen.from_clauses(clauses))
-    W = torch.tensor(_dense_w(n, clauses), dtype=torch.float64)
+    W = torch.tensor(_dense_w_of_clauses(n, clauses), dtype=torch.float64)
     for trial in range(4):
         x_np = rng.uniform(-2.5, 2.5, size=n)
         a = (x_np > 0).astype(np.uint8)
