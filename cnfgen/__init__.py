@@ -157,19 +157,23 @@ def structured_cnf(n: int, m: int, seed: int, p_geom: float = 0.4, kmax: int = 1
 
 
 def random_x(n: int, R: int, seed: int, lo: float = -1.0, hi: float = 1.0,
-             specials: bool = False) -> np.ndarray:
+             specials: bool = False, nan: int = 0) -> np.ndarray:
     """Relaxed assignment ``[n][R]`` float32, U(lo, hi).
 
     With ``specials`` a few entries are replaced by rounding edge cases:
-    +0.0, -0.0, the smallest subnormal of either sign and large magnitudes.
+    +0.0, -0.0, the smallest subnormal of either sign, large magnitudes and
+    +-infinity.  ``nan`` entries (after those) are set to NaN.
     """
     rng = _rng(seed)
     x = rng.uniform(lo, hi, size=(n, R)).astype(np.float32)
     if specials and x.size:
-        vals = np.array([0.0, -0.0, 1e-45, -1e-45, 1e-30, -1e-30, 12.0, -12.0, 30.0, -30.0],
-                        dtype=np.float32)
+        vals = np.array([0.0, -0.0, 1e-45, -1e-45, 1e-30, -1e-30, 12.0, -12.0, 30.0, -30.0,
+                         np.inf, -np.inf], dtype=np.float32)
         idx = rng.choice(x.size, size=min(x.size, 2 * len(vals)), replace=False)
         x.reshape(-1)[idx] = np.resize(vals, idx.size)
+    if nan and x.size:
+        idx = rng.choice(x.size, size=min(x.size, int(nan)), replace=False)
+        x.reshape(-1)[idx] = np.float32(np.nan)
     return x
 
 

@@ -101,10 +101,19 @@ hms_status hms_load_cnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, voi
 hms_status hms_load_wcnf(int32_t n_vars, const int32_t* lits, int64_t n_lits, const int64_t* weights, void* stream,
                          hms_cnf** out);
 
-/* Same, from a DIMACS file ("c" comments): "p cnf n m" (unweighted); "p wcnf
- * n m top" (each clause led by its weight, kept as given); or no header with
- * each clause led by its weight or by "h" (hard: weight 1 + total soft
- * weight).  Clauses end with 0 and may span lines. */
+/*
+ * Same, from a DIMACS file (the CNF of Section 2, equation 1: a conjunction
+ * of clauses, each a disjunction of literals x_i or not x_i; weighted
+ * partial CNF as defined in Section 2).  "c" lines are comments.  Accepted
+ * forms: "p cnf n m" (unweighted); "p wcnf n m top" (each clause led by its
+ * weight, kept as given); no header, each clause led by its weight or by "h"
+ * (hard: weight 1 + the total soft weight).  Clauses end with 0 and may span
+ * lines.  `path` is a HOST string read once; nothing is kept after the call.
+ * Errors: HMS_ERR_IO (unreadable file), HMS_ERR_PARSE (bad token, header or
+ * an unterminated clause), HMS_ERR_LITERAL_RANGE, HMS_ERR_TOO_LARGE,
+ * HMS_ERR_ARG, HMS_ERR_DEVICE, HMS_ERR_NOMEM.  On success *out is as for
+ * hms_load_cnf.
+ */
 hms_status hms_load_cnf_dimacs(const char* path, void* stream, hms_cnf** out);
 
 /* Sizes of a loaded instance. */
@@ -112,6 +121,29 @@ hms_status hms_cnf_info_get(const hms_cnf* cnf, hms_cnf_info* out);
 
 /* Release a handle (NULL is allowed).  Not while a call on it is running. */
 void hms_free_cnf(hms_cnf* cnf);
+
+/*
+ * The state Algorithm 1 carries from one iteration to the next (Section 4,
+ * "The Solving Process"): the relaxed values, the Adam moments, the number of
+ * iterations taken, and the best rounded iterate so far with its cost and
+ * step (the "save and output" of each improvement).  A solve can start from
+ * one (hms_solve_params.resume) and hand one back (hms_solve_result.state), so
+ * a long solve can be cut into pieces: T1 steps, then T2 more from the state
+ * they left, equal T1 + T2 steps bit for bit when T1 is a multiple of
+ * eval_every (otherwise the extra count of the T1-th iterate can only lower
+ * the best).  All arrays are caller-owned; n and R are the instance's and the
+ * solve's.
+ */
+typedef struct {
+    float* x;                 /* DEVICE [n][R] relaxed values (caller variable order) */
+    float* m;                 /* DEVICE [n][R] Adam first moments (ignored with HMS_SGD) */
+    float* v;                 /* DEVICE [n][R] Adam second moments (ignored with HMS_SGD) */
+    uint8_t* best_assignment; /* DEVICE [R][n] each restart's best rounded iterate (0/1 bytes) */
+    int64_t* best;            /* HOST [R] each restart's best cost */
+    int32_t* best_step;       /* HOST [R] the iteration of that iterate (-1: the start, not beaten) */
+    int32_t step;             /* iterations taken (the Adam step count; >= 0) */
+    int32_t pad;
+} hms_solve_state;
 
 typedef struct {
     int32_t steps;       /* optimizer steps T (>= 0) */
@@ -135,6 +167,10 @@ typedef struct {
     const volatile int32_t* cancel; /* HOST flag or NULL: once nonzero (set by another thread), the
                             solve stops at the next K-step boundary, fills the result with the
                             best so far and returns HMS_ERR_CANCELLED */
+    const hms_solve_state* resume; /* NULL: start from x0 or the seed; else continue from this
+                            state (x0 must then be NULL): iteration numbers, the counting
+                            period and the Adam step count go on from resume->step, and the
+                            best so far is kept unless strictly beaten.  Read only. */
 } hms_solve_params;
 
 typedef struct {
@@ -150,6 +186,9 @@ typedef struct {
     double* restart_loss;     /* caller HOST [R] loss at x_T, or NULL */
     float* x_final;           /* caller DEVICE [n][R] receives x_T, or NULL */
     double device_ms;         /* device time of the step loop (HIP events) */
+    hms_solve_state* state;   /* NULL, or a state whose arrays receive the state after the last
+                                 step taken (also on HMS_ERR_CANCELLED and with a time limit), to
+                                 pass as a later solve's resume; m and v are written with Adam */
 } hms_solve_result;
 
 /* Fill *p with the defaults: T = 1000, R = 1, K = 1, Adam lr 1e-4, UNSAT loss,
@@ -166,8 +205,14 @@ void hms_solve_params_default(hms_solve_params* p);
  * is filled.  Results are bitwise reproducible for equal inputs and do not
  * depend on the schedule or on R (restart r of a solve with seed s equals the
  * single-restart solve with seed s + r), except `final_loss` rounding.
- * Errors: HMS_ERR_ARG, HMS_ERR_DEVICE, HMS_ERR_NOMEM; HMS_ERR_NONFINITE when
- * the final loss is not finite (the result is still filled).
+ * With params->resume the loop continues from that state instead: t runs
+ * from resume->step to resume->step + T, counting when t % K == 0 and at the
+ * last iterate, Adam step t + 1, best_step in that numbering.  With
+ * result->state the state after the last step taken is written there.
+ * Errors: HMS_ERR_ARG (also a null array of a given state, x0 beside
+ * resume, or resume->step + steps past 2^31 - 1), HMS_ERR_DEVICE,
+ * HMS_ERR_NOMEM; HMS_ERR_NONFINITE when the final loss is not finite (the
+ * result is still filled).
  */
 hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* params, hms_solve_result* result);
 
@@ -192,7 +237,8 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* params, 
  * steps, eval_every, optimizer, loss mode and requested schedule: each step of
  * a group is one launch per kernel over all its instances (a work queue of
  * (instance, work unit) items, replayed as a HIP graph), with the schedule of
- * its largest instance.  A group of one, or a solve with a time limit, runs as
+ * its largest instance.  A group of one, a solve with a time limit or a
+ * cancel flag, and a solve that resumes or returns its state run as
  * hms_solve.  All work goes on params[0].stream.  Each result is bitwise the
  * one hms_solve gives for that instance alone (restart_loss and final_loss may
  * differ in the last bits when the schedule does).  Returns the first error.
@@ -228,11 +274,23 @@ hms_status hms_tune_candidates(int32_t restarts, int32_t loss_mode, int32_t* cod
 hms_status hms_evaluate(const hms_cnf* cnf, const uint8_t* assignment, int64_t* unsat, void* stream);
 
 /*
- * One evaluation of the relaxed objective at R points (the parity entry point):
- * x (DEVICE [n][R]) -> loss[R] (HOST, may be NULL), gradient dL/dx into grad
- * (DEVICE [n][R], may be NULL), unsatisfied count of round(x) into unsat[R]
- * (HOST, may be NULL).  loss_mode as in hms_solve_params.  Synchronises
- * `stream` when a host output is requested.
+ * One evaluation of the relaxed objective at R points (the parity entry
+ * point): the forward pass, loss and backpropagation of one iteration of
+ * Algorithm 1, without the optimizer step.  For each restart r:
+ *   - scores f = tanh(x_r) W (Section 4, display equation for f);
+ *   - unsatisfied clauses of the rounding x_r > 0 (Section 4, "Unsatisfiable
+ *     Cores"; Algorithm 1 forward step), counted into unsat[r] (their total
+ *     weight for a weighted instance);
+ *   - loss[r] = (1/m) sum_j mu_j w_j f_j^2 with mu_j = 1 for the unsatisfied
+ *     clauses (HMS_LOSS_UNSAT, Algorithm 1 loss step) or for every clause
+ *     (HMS_LOSS_ALL, the Section 4 worked example's loss);
+ *   - grad = dL/dx with mu held constant (Algorithm 1 backpropagation step).
+ * x: DEVICE [n][R] FP32, caller order, read only.  loss: HOST [R] doubles,
+ * unsat: HOST [R] int64, grad: DEVICE [n][R] FP32 (caller-owned; each may be
+ * NULL).  The call allocates its own device workspace and releases it in
+ * stream order.  Synchronises `stream` when a host output is requested.
+ * Errors: HMS_ERR_ARG (null instance or x, R < 1, bad loss mode),
+ * HMS_ERR_DEVICE, HMS_ERR_NOMEM, HMS_ERR_TOO_LARGE.
  */
 hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t restarts, int32_t loss_mode,
                             double* loss, float* grad, int64_t* unsat, void* stream);

@@ -44,13 +44,18 @@ class CnfInfo(C.Structure):
                 ("state_bytes_r1", C.c_int64), ("weighted", C.c_int32), ("total_weight", C.c_int64)]
 
 
+class SolveState(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("best_assignment", C.c_void_p),
+                ("best", C.c_void_p), ("best_step", C.c_void_p), ("step", C.c_int32), ("pad", C.c_int32)]
+
+
 class SolveParams(C.Structure):
     _fields_ = [("steps", C.c_int32), ("restarts", C.c_int32), ("eval_every", C.c_int32),
                 ("optimizer", C.c_int32), ("seed", C.c_uint64), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("loss_mode", C.c_int32), ("schedule", C.c_int32), ("use_graph", C.c_int32),
                 ("autotune", C.c_int32), ("time_limit_s", C.c_double), ("x0", C.c_void_p),
-                ("stream", C.c_void_p), ("cancel", C.c_void_p)]
+                ("stream", C.c_void_p), ("cancel", C.c_void_p), ("resume", C.c_void_p)]
 
 
 class SolveResult(C.Structure):
@@ -58,7 +63,7 @@ class SolveResult(C.Structure):
                 ("steps_done", C.c_int32), ("schedule", C.c_int32), ("final_loss", C.c_double),
                 ("best_assignment", C.c_void_p), ("restart_best", C.c_void_p),
                 ("restart_step", C.c_void_p), ("restart_loss", C.c_void_p),
-                ("x_final", C.c_void_p), ("device_ms", C.c_double)]
+                ("x_final", C.c_void_p), ("device_ms", C.c_double), ("state", C.c_void_p)]
 
 
 class PlanView(C.Structure):
@@ -230,6 +235,42 @@ def load_cnf_dimacs(path: str, stream=None) -> Cnf:
 
 
 @dataclass
+class SolverState:
+    """The state Algorithm 1 carries between iterations (``hms_solve_state``):
+    relaxed values and Adam moments (device float32 [n][R]), each restart's
+    best rounded iterate (device uint8 [R][n]), its cost and step (host), and
+    the iterations taken.  ``solve(..., want_state=True)`` returns one;
+    ``solve(..., resume=state)`` continues from it."""
+    x: object
+    m: object
+    v: object
+    best_assignment: object
+    best: np.ndarray
+    best_step: np.ndarray
+    step: int
+
+    @classmethod
+    def empty(cls, n: int, restarts: int):
+        import torch
+        R = int(restarts)
+        f = lambda: torch.empty((n, R), dtype=torch.float32, device="cuda")  # noqa: E731
+        return cls(f(), f(), f(), torch.empty((R, n), dtype=torch.uint8, device="cuda"),
+                   np.zeros(R, dtype=np.int64), np.zeros(R, dtype=np.int32), 0)
+
+    def _struct(self) -> SolveState:
+        st = SolveState()
+        for k in ("x", "m", "v", "best_assignment"):
+            t = getattr(self, k)
+            setattr(st, k, None if t is None else t.data_ptr())
+        for k, dt in (("best", np.int64), ("best_step", np.int32)):
+            a = np.ascontiguousarray(getattr(self, k), dtype=dt)
+            setattr(self, k, a)
+            setattr(st, k, a.ctypes.data)
+        st.step = int(self.step)
+        return st
+
+
+@dataclass
 class SolveOutput:
     best_cost: int
     best_restart: int
@@ -243,6 +284,7 @@ class SolveOutput:
     restart_step: np.ndarray
     restart_loss: np.ndarray
     x_final: object = field(default=None)
+    state: object = field(default=None)
 
 
 def _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2, eps, loss_mode,
@@ -318,14 +360,40 @@ def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, s
           optimizer: int = ADAM, lr: float = 1e-4, beta1: float = 0.9, beta2: float = 0.999,
           eps: float = 1e-8, loss_mode: int = LOSS_UNSAT, schedule: int = 0, use_graph: bool = True,
           time_limit_s: float = 0.0, x0=None, want_x: bool = False, stream=None,
-          autotune: bool = True, cancel: CancelFlag | None = None) -> SolveOutput:
-    """Algorithm 1 over ``restarts`` relaxed points (see ``hms_solve``)."""
+          autotune: bool = True, cancel: CancelFlag | None = None, resume: SolverState | None = None,
+          want_state: bool = False) -> SolveOutput:
+    """Algorithm 1 over ``restarts`` relaxed points (see ``hms_solve``).
+    ``resume`` continues from a ``SolverState``; ``want_state`` returns the
+    state after the last step as ``output.state``."""
     R = int(restarts)
     p = _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2, eps, loss_mode,
                 schedule, use_graph, time_limit_s, x0, stream, autotune)
     if cancel is not None:
         p.cancel = cancel.address
+    keep = []  # structs and arrays the call reads, alive until it returns
+    if resume is not None:
+        for k in ("x", "m", "v"):
+            t = getattr(resume, k)
+            if t is not None:
+                _device_points(t, cnf, f"resume.{k}")
+                if t.view(cnf.n, -1).shape[1] != R:
+                    raise ValueError(f"resume.{k} has {t.view(cnf.n, -1).shape[1]} columns for {R} restarts")
+        ba = resume.best_assignment
+        if ba is not None and (not ba.is_cuda or ba.dtype.itemsize != 1 or not ba.is_contiguous()
+                               or ba.numel() != R * cnf.n):
+            raise ValueError(f"resume.best_assignment must be a contiguous byte tensor of {R} x {cnf.n} on the GPU")
+        rstruct = resume._struct()
+        keep.append(rstruct)
+        p.resume = C.addressof(rstruct)
     res = SolveResult()
+    out_state = None
+    if want_state:
+        out_state = SolverState.empty(cnf.n, R)
+        if optimizer != ADAM:
+            out_state.m = out_state.v = None
+        ostruct = out_state._struct()
+        keep.append(ostruct)
+        res.state = C.addressof(ostruct)
     ba = np.zeros(max(cnf.n, 1), dtype=np.uint8)
     rb = np.zeros(R, dtype=np.int64)
     rs = np.zeros(R, dtype=np.int32)
@@ -342,8 +410,10 @@ def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, s
     rc = lib().hms_solve(cnf.handle, C.byref(p), C.byref(res))
     if rc != HMS_OK and rc not in (-6, -7):
         _check(rc)
+    if out_state is not None:
+        out_state.step = int(ostruct.step)
     out = SolveOutput(res.best_cost, res.best_restart, res.best_step, res.steps_done, res.schedule,
-                      res.final_loss, res.device_ms, ba[:cnf.n].copy(), rb, rs, rl, xf)
+                      res.final_loss, res.device_ms, ba[:cnf.n].copy(), rb, rs, rl, xf, out_state)
     if rc in (-6, -7):  # non-finite loss or cancelled: the result holds the best so far
         err = HipMsatError(rc, lib().hms_last_error().decode())
         err.result = out
@@ -366,13 +436,14 @@ def solve_batch(cnfs, steps=1000, restarts=1, eval_every=1, seeds=0, optimizer: 
 
     steps, restarts, eval_every, seeds = per(steps), per(restarts), per(eval_every), per(seeds)
     optimizer, lr, loss_mode, schedule = per(optimizer), per(lr), per(loss_mode), per(schedule)
+    beta1, beta2, eps = per(beta1), per(beta2), per(eps)
     params = (SolveParams * N)()
     results = (SolveResult * N)()
     statuses = (C.c_int32 * N)()
     bufs = []
     for i, cnf in enumerate(cnfs):
-        p = _params(cnf, steps[i], restarts[i], eval_every[i], seeds[i], optimizer[i], lr[i], beta1,
-                    beta2, eps, loss_mode[i], schedule[i], True, 0.0, None, stream, False)
+        p = _params(cnf, steps[i], restarts[i], eval_every[i], seeds[i], optimizer[i], lr[i], beta1[i],
+                    beta2[i], eps[i], loss_mode[i], schedule[i], True, 0.0, None, stream, False)
         params[i] = p
         R = int(restarts[i])
         ba = np.zeros(max(cnf.n, 1), dtype=np.uint8)

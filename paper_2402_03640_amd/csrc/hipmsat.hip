@@ -563,7 +563,31 @@ struct SolveSetup {
     State S{};
     Shape sh{};
     Launch L{};
+    int32_t step0 = 0;  // iterations taken before this call (a resumed solve)
 };
+
+// A state a solve resumes from or hands back: every array it needs is given.
+hms_status check_state(const hms_cnf* cnf, const hms_solve_params* p, const hms_solve_state* st, const char* what) {
+    const bool has_n = cnf->plan.n > 0;
+    const bool adam = p->optimizer == HMS_ADAM;
+    if ((has_n && (!st->x || !st->best_assignment)) || !st->best || !st->best_step ||
+        (adam && has_n && (!st->m || !st->v)))
+        return fail(HMS_ERR_ARG, std::string(what) + ": a required state array is null");
+    return HMS_OK;
+}
+
+// Checks of hms_solve's resume input and state output.
+hms_status check_resume(const hms_cnf* cnf, const hms_solve_params* p, const hms_solve_result* res) {
+    if (p->resume) {
+        if (p->x0) return fail(HMS_ERR_ARG, "x0 and resume are both given");
+        hms_status rc = check_state(cnf, p, p->resume, "resume");
+        if (rc) return rc;
+        if (p->resume->step < 0 || p->steps < 0 || p->resume->step > INT32_MAX - p->steps)
+            return fail(HMS_ERR_ARG, "resume step out of range (0 <= step, step + steps < 2^31)");
+    }
+    if (res->state) return check_state(cnf, p, res->state, "state output");
+    return HMS_OK;
+}
 
 hms_status setup_solve(const hms_cnf* cnf, const hms_solve_params* p, SolveSetup& Z) {
     if (check_cnf(cnf) || !p) return fail(HMS_ERR_ARG, "null argument");
@@ -589,6 +613,20 @@ hms_status setup_solve(const hms_cnf* cnf, const hms_solve_params* p, SolveSetup
     hms::InitArgs ia = make_init(cnf, Z.sh, Z.S);
     ia.x0 = p->x0;
     ia.seed = p->seed;
+    if (const hms_solve_state* rs = p->resume) {
+        // continue from the caller's state: the best so far goes into the
+        // tracking arrays before the init kernel, which then keeps it
+        SyncOnExit up{s};  // the host arrays are read by queued copies
+        HIPTRY(hipMemcpyAsync(Z.S.best, rs->best, (size_t)R * 8, hipMemcpyHostToDevice, s));
+        HIPTRY(hipMemcpyAsync(Z.S.best_step, rs->best_step, (size_t)R * 4, hipMemcpyHostToDevice, s));
+        ia.x0 = rs->x;
+        ia.m0 = adam ? rs->m : nullptr;
+        ia.v0 = adam ? rs->v : nullptr;
+        ia.best_a0 = rs->best_assignment;
+        ia.step0 = rs->step;
+        ia.keep_best = 1;
+        Z.step0 = rs->step;
+    }
     HIPTRY(hms::launch_init(ia, s));
     Z.L = make_launch(cnf, Z.sh, Z.S, adam ? hms::kAdam : hms::kSgd, p->loss_mode, p->lr, p->beta1, p->beta2,
                       p->eps);
@@ -658,6 +696,7 @@ hms_status time_steps(const hms_cnf* cnf, const hms_solve_params* p0, int32_t co
     hms_solve_params p = *p0;
     p.schedule = code;
     p.x0 = nullptr;
+    p.resume = nullptr;
     SolveSetup Z;
     hms_status rc = setup_solve(cnf, &p, Z);
     if (rc) return rc;
@@ -726,6 +765,7 @@ hms_status time_split(const hms_cnf* cnf, const hms_solve_params* p0, int32_t co
     hms_solve_params p = *p0;
     p.schedule = code;
     p.x0 = nullptr;
+    p.resume = nullptr;
     SolveSetup Z;
     hms_status rc = setup_solve(cnf, &p, Z);
     if (rc) return rc;
@@ -822,7 +862,9 @@ hms_status resolve_schedule(const hms_cnf* cnf, const hms_solve_params* p, int32
     {
         std::lock_guard<std::mutex> lk(cnf->tune_mu);
         auto it = cnf->tuned.find(tune_key(p));
-        if (it != cnf->tuned.end()) {
+        // the resident solver cannot honour a time limit or a cancel flag:
+        // a solve that asks for one takes the tiled choice below instead
+        if (it != cnf->tuned.end() && (it->second != kResidentId || resident_ok(cnf, p))) {
             code = it->second;
             return HMS_OK;
         }
@@ -947,31 +989,54 @@ SmallOut layout_small_out(const hms::HostPlan& P, int32_t R, Layout& L) {
 hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_result* res) {
     const hms::HostPlan& P = cnf->plan;
     const int32_t R = p->restarts;
+    const bool adam = p->optimizer == HMS_ADAM;
     hipStream_t s = (hipStream_t)p->stream;
+    const hms_solve_state* rs = p->resume;
+    hms_solve_state* so = res->state;
+    // host destinations of the copies below: declared before the guard that
+    // waits for the stream, so an early return cannot free them under a copy
+    std::vector<int64_t> best(R);
+    std::vector<int32_t> bstep(R);
+    std::vector<double> closs(R);
     Layout lay;
     const size_t o_desc = lay.add(sizeof(hms::SmallDesc));
-    SmallOut so = layout_small_out(P, R, lay);
+    SmallOut so_l = layout_small_out(P, R, lay);
     Arena A;
     A.s = s;
     HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
     hms::SmallDesc D = make_desc(cnf, p);
     D.block0 = 0;
-    D.best_a = A.at<uint8_t>(so.o_best_a);
-    D.best = A.at<int64_t>(so.o_best);
-    D.best_step = A.at<int32_t>(so.o_step);
-    D.final_loss = A.at<double>(so.o_loss);
-    D.x_final = res->x_final;
+    D.best_a = A.at<uint8_t>(so_l.o_best_a);
+    D.best = A.at<int64_t>(so_l.o_best);
+    D.best_step = A.at<int32_t>(so_l.o_step);
+    D.final_loss = A.at<double>(so_l.o_loss);
+    D.x_final = res->x_final ? res->x_final : (so ? so->x : nullptr);
+    if (so && adam) {
+        D.m_final = so->m;
+        D.v_final = so->v;
+    }
+    if (rs) {
+        D.x0 = rs->x;
+        D.m0 = adam ? rs->m : nullptr;
+        D.v0 = adam ? rs->v : nullptr;
+        D.step0 = rs->step;
+        D.resume = 1;
+    }
     Events E;
     for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
-    HIPTRY(hipMemcpyAsync(A.base + o_desc, &D, sizeof(D), hipMemcpyHostToDevice, s));
     SyncOnExit d_done{s};
+    HIPTRY(hipMemcpyAsync(A.base + o_desc, &D, sizeof(D), hipMemcpyHostToDevice, s));
+    if (rs) {
+        // the resumed best enters through the output arrays the kernel updates
+        HIPTRY(hipMemcpyAsync(D.best, rs->best, (size_t)R * 8, hipMemcpyHostToDevice, s));
+        HIPTRY(hipMemcpyAsync(D.best_step, rs->best_step, (size_t)R * 4, hipMemcpyHostToDevice, s));
+        if (P.n > 0)
+            HIPTRY(hipMemcpyAsync(D.best_a, rs->best_assignment, (size_t)R * P.n, hipMemcpyDeviceToDevice, s));
+    }
     HIPTRY(hipEventRecord(E.e[0], s));
     HIPTRY(hms::launch_small(A.at<hms::SmallDesc>(o_desc), 1, R, resident_lds(cnf), lds_limit(cnf->device), D.stage,
                              resident_rows(cnf), hms::small_reg_ok(cnf->plan, resident_rows(cnf)), s));
     HIPTRY(hipEventRecord(E.e[1], s));
-    std::vector<int64_t> best(R);
-    std::vector<int32_t> bstep(R);
-    std::vector<double> closs(R);
     HIPTRY(hipMemcpyAsync(best.data(), D.best, R * 8, hipMemcpyDeviceToHost, s));
     HIPTRY(hipMemcpyAsync(bstep.data(), D.best_step, R * 4, hipMemcpyDeviceToHost, s));
     HIPTRY(hipMemcpyAsync(closs.data(), D.final_loss, R * 8, hipMemcpyDeviceToHost, s));
@@ -979,10 +1044,14 @@ hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_sol
     int32_t br = 0;
     for (int32_t r = 1; r < R; ++r)
         if (best[r] < best[br]) br = r;
-    if (res->best_assignment && P.n > 0) {
+    if (res->best_assignment && P.n > 0)
         HIPTRY(hipMemcpyAsync(res->best_assignment, D.best_a + (size_t)br * P.n, P.n, hipMemcpyDeviceToHost, s));
-        HIPTRY(hipStreamSynchronize(s));
+    if (so && P.n > 0) {
+        if (res->x_final && so->x != res->x_final)
+            HIPTRY(hipMemcpyAsync(so->x, res->x_final, (size_t)P.n * R * 4, hipMemcpyDeviceToDevice, s));
+        HIPTRY(hipMemcpyAsync(so->best_assignment, D.best_a, (size_t)R * P.n, hipMemcpyDeviceToDevice, s));
     }
+    HIPTRY(hipStreamSynchronize(s));
     float ms = 0;
     HIPTRY(hipEventElapsedTime(&ms, E.e[0], E.e[1]));
     res->best_cost = best[br];
@@ -995,6 +1064,11 @@ hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_sol
     if (res->restart_best) std::memcpy(res->restart_best, best.data(), R * 8);
     if (res->restart_step) std::memcpy(res->restart_step, bstep.data(), R * 4);
     if (res->restart_loss) std::memcpy(res->restart_loss, closs.data(), R * 8);
+    if (so) {
+        std::memcpy(so->best, best.data(), R * 8);
+        std::memcpy(so->best_step, bstep.data(), R * 4);
+        so->step = (rs ? rs->step : 0) + p->steps;
+    }
     for (int32_t r = 0; r < R; ++r)
         if (!std::isfinite(closs[r])) return fail(HMS_ERR_NONFINITE, "the loss at the final iterate is not finite");
     return HMS_OK;
@@ -1008,6 +1082,7 @@ hms_status time_resident(const hms_cnf* cnf, const hms_solve_params* p0, int32_t
     hms_solve_params p = *p0;
     p.eval_every = std::max(p0->eval_every, 1);
     p.x0 = nullptr;
+    p.resume = nullptr;
     const int32_t S = std::max(iters, 16) * 4;
     double t[3] = {0, 0, 0};
     for (int k = 0; k < 3; ++k) {  // the first solve only warms the device up
@@ -1030,16 +1105,21 @@ hipError_t count_final(const hms_cnf* cnf, const SolveSetup& Z, hipStream_t s) {
     return e;
 }
 
-// Read a finished solve's outcome into `res` (synchronises s).
+// Read a finished solve's outcome into `res` (synchronises s), and the state
+// after its last step into res->state when asked.
 hms_status read_result(const hms_cnf* cnf, const SolveSetup& Z, int32_t done, float ms, hipStream_t s,
                        hms_solve_result* res) {
     const hms::HostPlan& P = cnf->plan;
     const Shape& sh = Z.sh;
     const State& S = Z.S;
     const int32_t R = sh.B.R;
+    hms_solve_state* so = res->state;
+    // host destinations of the copies below, declared before the guard that
+    // waits for the stream: an early return cannot free them under a copy
     std::vector<int64_t> best(R);
     std::vector<int32_t> bstep(R);
     std::vector<double> closs(R);
+    SyncOnExit copies_done{s};
     HIPTRY(hipMemcpyAsync(best.data(), S.best, R * 8, hipMemcpyDeviceToHost, s));
     HIPTRY(hipMemcpyAsync(bstep.data(), S.best_step, R * 4, hipMemcpyDeviceToHost, s));
     HIPTRY(hipMemcpyAsync(closs.data(), S.cur_loss, R * 8, hipMemcpyDeviceToHost, s));
@@ -1052,6 +1132,14 @@ hms_status read_result(const hms_cnf* cnf, const SolveSetup& Z, int32_t done, fl
         HIPTRY(hipMemcpyAsync(res->best_assignment, S.out_assign, P.n, hipMemcpyDeviceToHost, s));
     }
     if (res->x_final) HIPTRY(hms::launch_scatter(P.n, P.n, sh.B, cnf->var_old, S.x, res->x_final, s));
+    if (so) {
+        HIPTRY(hms::launch_scatter(P.n, P.n, sh.B, cnf->var_old, S.x, so->x, s));
+        if (S.m) {
+            HIPTRY(hms::launch_scatter(P.n, P.n, sh.B, cnf->var_old, S.m, so->m, s));
+            HIPTRY(hms::launch_scatter(P.n, P.n, sh.B, cnf->var_old, S.v, so->v, s));
+        }
+        HIPTRY(hms::launch_scatter_bytes(P.n, sh.B, cnf->var_old, S.best_a, so->best_assignment, s));
+    }
     HIPTRY(hipStreamSynchronize(s));
     res->best_cost = best[br];
     res->best_restart = br;
@@ -1063,6 +1151,11 @@ hms_status read_result(const hms_cnf* cnf, const SolveSetup& Z, int32_t done, fl
     if (res->restart_best) std::memcpy(res->restart_best, best.data(), R * 8);
     if (res->restart_step) std::memcpy(res->restart_step, bstep.data(), R * 4);
     if (res->restart_loss) std::memcpy(res->restart_loss, closs.data(), R * 8);
+    if (so) {
+        std::memcpy(so->best, best.data(), R * 8);
+        std::memcpy(so->best_step, bstep.data(), R * 4);
+        so->step = Z.step0 + done;
+    }
     for (int32_t r = 0; r < R; ++r)
         if (!std::isfinite(closs[r])) return fail(HMS_ERR_NONFINITE, "the loss at the final iterate is not finite");
     return HMS_OK;
@@ -1214,6 +1307,7 @@ extern "C" {
 hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_result* res) {
     g_err.clear();
     if (check_cnf(cnf) || !p || !res) return fail(HMS_ERR_ARG, "null argument");
+    if (hms_status rc = check_resume(cnf, p, res)) return rc;
     DeviceGuard dg(cnf->device);
     hms_solve_params pr = *p;
     hms_status rc0 = resolve_schedule(cnf, p, pr.schedule);
@@ -1257,11 +1351,28 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     };
     const bool watch = p->time_limit_s > 0 || p->cancel != nullptr;  // poll at K-step boundaries
 
+    // iteration numbers go on from a resumed state: t = s0 + done
+    const int32_t s0 = Z.step0;
     int32_t done = 0;
-    bool stopped = false;  // the time limit ran out
+    bool stopped = false;  // the time limit ran out or the caller cancelled
+    // direct launches until `upto` steps are done; the watch is polled when
+    // t reaches a multiple of K
+    auto direct = [&](int32_t upto) -> hms_status {
+        while (done < upto && !stopped) {
+            HIPTRY(enqueue_step(L, (s0 + done) % K == 0, s));
+            ++done;
+            if (watch && (s0 + done) % K == 0) {
+                HIPTRY(hipStreamSynchronize(s));
+                stopped = over_time();
+            }
+        }
+        return HMS_OK;
+    };
+    // up to the first multiple of K, so the graph body starts on one
+    if (hms_status rc = direct(std::min(T, (K - s0 % K) % K))) return rc;
     // body of B steps (a multiple of K, starting at a multiple of K)
     const int32_t B = graph_body(K);
-    if (p->use_graph && T >= 2 * B) {
+    if (p->use_graph && T - done >= 2 * B && !stopped) {
         hipStream_t cs = nullptr;
         HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
@@ -1285,7 +1396,7 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
         if (ce != hipSuccess) return fail(HMS_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(ce));
         if (ee != hipSuccess) return fail(HMS_ERR_DEVICE, std::string("end capture: ") + hipGetErrorString(ee));
         HIPTRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        const int32_t reps = T / B;
+        const int32_t reps = (T - done) / B;
         for (int32_t r = 0; r < reps; ++r) {
             HIPTRY(hipGraphLaunch(exec, s));
             done += B;
@@ -1295,14 +1406,7 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
             }
         }
     }
-    while (done < T && !stopped) {
-        HIPTRY(enqueue_step(L, done % K == 0, s));
-        ++done;
-        if (watch && done % K == 0) {
-            HIPTRY(hipStreamSynchronize(s));
-            stopped = over_time();
-        }
-    }
+    if (hms_status rc = direct(T)) return rc;
     // x_T is always counted
     HIPTRY(count_final(cnf, Z, s));
     HIPTRY(hipEventRecord(ev1, s));
@@ -1320,6 +1424,7 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* p, int32
     if (check_cnf(cnf) || !p || iters < 1) return fail(HMS_ERR_ARG, "null argument or iters < 1");
     DeviceGuard dg(cnf->device);
     hms_solve_params pr = *p;
+    pr.resume = nullptr;  // timing starts from the seed or x0
     hms_status rc0 = resolve_schedule(cnf, p, pr.schedule);
     if (rc0) return rc0;
     p = &pr;
@@ -1385,8 +1490,13 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
             return fail(HMS_ERR_ARG, "invalid parameters for instance " + std::to_string(i));
     }
     DeviceGuard dg(dev);
-    std::vector<int32_t> res_idx, tiled_idx;
+    std::vector<int32_t> res_idx, tiled_idx, alone;
     for (int32_t i = 0; i < count; ++i) {
+        // a resumed solve, or one that hands its state back, runs as hms_solve
+        if (params[i].resume != nullptr || results[i].state != nullptr) {
+            alone.push_back(i);
+            continue;
+        }
         const bool want_res = params[i].schedule == kResidentId ||
                               (params[i].schedule == 0 && resident_preferred(cnfs[i], &params[i]));
         if (want_res && resident_ok(cnfs[i], &params[i])) res_idx.push_back(i);
@@ -1404,6 +1514,12 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
         std::vector<SmallOut> outs(res_idx.size());
         for (size_t k = 0; k < res_idx.size(); ++k)
             outs[k] = layout_small_out(cnfs[res_idx[k]]->plan, params[res_idx[k]].restarts, lay);
+        // host destinations of the read-back copies, declared before the
+        // guard that waits for the stream (an early return cannot free them
+        // under a copy)
+        std::vector<std::vector<int64_t>> best(res_idx.size());
+        std::vector<std::vector<int32_t>> step(res_idx.size());
+        std::vector<std::vector<double>> loss(res_idx.size());
         Arena A;
         A.s = s;
         HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
@@ -1434,8 +1550,8 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
                 blocks += params[res_idx[k]].restarts;
             }
         }
-        HIPTRY(hipMemcpyAsync(A.base + o_desc, D.data(), sizeof(hms::SmallDesc) * D.size(), hipMemcpyHostToDevice, s));
         SyncOnExit d_done{s};
+        HIPTRY(hipMemcpyAsync(A.base + o_desc, D.data(), sizeof(hms::SmallDesc) * D.size(), hipMemcpyHostToDevice, s));
         Events E;
         for (int i = 0; i < 2; ++i) HIPTRY(hipEventCreate(&E.e[i]));
         HIPTRY(hipEventRecord(E.e[0], s));
@@ -1455,9 +1571,6 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
         }
         HIPTRY(hipEventRecord(E.e[1], s));
         // read back every resident result
-        std::vector<std::vector<int64_t>> best(res_idx.size());
-        std::vector<std::vector<int32_t>> step(res_idx.size());
-        std::vector<std::vector<double>> loss(res_idx.size());
         for (size_t k = 0; k < res_idx.size(); ++k) {
             const int32_t R = params[res_idx[k]].restarts;
             best[k].resize(R);
@@ -1508,7 +1621,6 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
     // instance; a group of one, or a solve with a time limit, runs alone
     constexpr size_t kGroup = 64;
     std::map<std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>, std::vector<int32_t>> groups;
-    std::vector<int32_t> alone;
     for (int32_t i : tiled_idx) {
         const hms_solve_params& p = params[i];
         if (p.time_limit_s > 0 || p.cancel != nullptr) {
@@ -1609,6 +1721,8 @@ hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t R, int32
     Arena A;
     A.s = s;
     HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+    // the host outputs are written by queued copies: an early return waits
+    SyncOnExit outs_done{s};
     State S = bind_state(A, off, false, want_g, false);
     hms::InitArgs ia = make_init(cnf, sh, S);
     ia.x0 = x;

@@ -896,24 +896,27 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
         A.x[e] = x;
         A.t[e] = signed_tanh(x);
         if (A.mm != nullptr) {
-            A.mm[e] = 0.0f;
-            A.vv[e] = 0.0f;
+            A.mm[e] = A.m0 != nullptr ? A.m0[(size_t)o * B.R + r] : 0.0f;
+            A.vv[e] = A.v0 != nullptr ? A.v0[(size_t)o * B.R + r] : 0.0f;
         }
-        if (A.best_a != nullptr) A.best_a[e] = x > 0.0f ? 1 : 0;
+        if (A.best_a != nullptr)
+            A.best_a[e] = A.best_a0 != nullptr ? (A.best_a0[(size_t)r * A.n + o] != 0 ? 1 : 0) : (x > 0.0f ? 1 : 0);
     }
     if (idx < B.R) {
         const int r = (int)idx;
         A.t[boff(B, B.rows_x, A.n, r)] = -0.0f;
         if (A.a != nullptr) A.a[boff(B, B.rows_a, A.a_zero_row, r)] = 0.0f;
         if (A.best != nullptr) {
-            A.best[r] = A.best0;
-            A.best_step[r] = -1;
+            if (!A.keep_best) {
+                A.best[r] = A.best0;
+                A.best_step[r] = -1;
+            }
             A.improved[r] = 0;
         }
     }
     if (A.umask != nullptr && idx < A.umask_words) A.umask[idx] = 0u;
     if (idx == 0 && A.st != nullptr) {
-        A.st->t = 0;
+        A.st->t = A.step0;
         A.st->step_size = 0.0f;
         A.st->inv_sqrt_bc2 = 1.0f;
     }
@@ -936,6 +939,15 @@ __global__ __launch_bounds__(256) void k_extract(int32_t n, Blocking B, int32_t 
     const int32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     out[var_old[i]] = best_a[boff(B, B.rows_x, i, r)];
+}
+
+__global__ __launch_bounds__(256) void k_scatter_bytes(int32_t n, Blocking B, const int32_t* var_old,
+                                                       const uint8_t* src, uint8_t* dst) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n * B.R) return;
+    const int32_t i = (int32_t)(idx / B.R);
+    const int32_t r = (int32_t)(idx % B.R);
+    dst[(size_t)r * n + var_old[i]] = src[boff(B, B.rows_x, i, r)];
 }
 
 __global__ __launch_bounds__(256) void k_scatter(int32_t n, int32_t n_act, Blocking B, const int32_t* var_old,
@@ -1166,6 +1178,14 @@ hipError_t launch_extract(int32_t n, const Blocking& B, int32_t r, const int32_t
                           uint8_t* out, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_extract, dim3((n + 255) / 256), dim3(256), 0, s, n, B, r, var_old, best_a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_bytes(int32_t n, const Blocking& B, const int32_t* var_old, const uint8_t* src,
+                                uint8_t* dst, hipStream_t s) {
+    const int64_t total = (int64_t)n * B.R;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_bytes, dim3((int)((total + 255) / 256)), dim3(256), 0, s, n, B, var_old, src, dst);
     return hipGetLastError();
 }
 

@@ -114,6 +114,14 @@ struct InitArgs {
     const int32_t* var_old;
     const float* x0;          // caller order [n][R] or null
     const uint8_t* assign0;   // caller order [n] (evaluate) or null
+    // resuming a solve: moments in caller order [n][R] (null: zero), best
+    // rounded iterates in caller order [R][n] (null: round(x0)), the step count
+    // to continue from, and keep_best = 1 when best / best_step already hold
+    // the resumed values (uploaded before this kernel)
+    const float* m0;
+    const float* v0;
+    const uint8_t* best_a0;
+    int32_t step0, keep_best;
     uint64_t seed;
     float* x;
     float* t;
@@ -172,6 +180,10 @@ hipError_t launch_snapshot(int32_t n_act, const Blocking& B, const float* x, con
                            uint8_t* best_a, hipStream_t s);
 hipError_t launch_extract(int32_t n, const Blocking& B, int32_t r, const int32_t* var_old, const uint8_t* best_a,
                           uint8_t* out, hipStream_t s);
+// dst[r][var_old[i]] = src(i, r) for the blocked bytes src (a restart's
+// best rounded iterate in caller order, one row per restart).
+hipError_t launch_scatter_bytes(int32_t n, const Blocking& B, const int32_t* var_old, const uint8_t* src,
+                                uint8_t* dst, hipStream_t s);
 // dst[var_old[i]][r] = scale[r] * src(i, r) (scale may be null: 1), 0 for inactive variables.
 hipError_t launch_scatter(int32_t n, int32_t n_act, const Blocking& B, const int32_t* var_old, const float* src,
                           float* dst, hipStream_t s, const float* scale = nullptr);

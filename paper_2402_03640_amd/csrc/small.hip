@@ -152,22 +152,24 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
         }
         L.x[i] = x;
         L.t[i] = signed_tanh(x);
-        L.m[i] = 0.0f;
-        L.v[i] = 0.0f;
-        best_a[o] = x > 0.0f ? 1 : 0;
+        L.m[i] = D.m0 != nullptr ? D.m0[(size_t)o * D.R + r] : 0.0f;
+        L.v[i] = D.v0 != nullptr ? D.v0[(size_t)o * D.R + r] : 0.0f;
+        if (!D.resume) best_a[o] = x > 0.0f ? 1 : 0;
     }
     if (tid == 0) {
         L.t[n] = -0.0f;
         L.a[crows] = 0.0f;
     }
-    int64_t best = D.best0;  // every thread tracks it; thread 0's copy is stored
-    int best_step = -1;
+    // every thread tracks the best; thread 0's copy is stored at the end (a
+    // resumed solve reads its entry values here, before the barriers below)
+    int64_t best = D.resume ? D.best[r] : D.best0;
+    int best_step = D.resume ? D.best_step[r] : -1;
     // with no split rows and at most one variable per thread, thread i owns
     // variable i (row i of the variable side): it keeps that variable's best
     // bit in a register and stores it once at the end
     const bool own = D.n_heavy == 0 && n <= kThreads;
     const int own_o = (own && tid < n) ? D.var_old[tid] : 0;
-    bool own_bit = own && tid < n && L.x[tid] > 0.0f;
+    bool own_bit = own && tid < n && (D.resume ? best_a[own_o] != 0 : L.x[tid] > 0.0f);
 
     // this thread's clause rows and variable row, entries in registers (RF >
     // 0); entries past a row's end are the padding entries, which add nothing.
@@ -230,7 +232,8 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
                  "+s"(p_lrb), "+s"(p_we0), "+s"(p_we1));
     const float p_tom = __int_as_float(p_tomb), p_lr = __int_as_float(p_lrb);
     const int64_t p_wempty = (int64_t)(((uint64_t)(uint32_t)p_we1 << 32) | (uint32_t)p_we0);
-    int kc = 0;  // step modulo K, kept by counting
+    const int step0 = D.step0;  // iterations are numbered from here
+    int kc = step0 % D.K;       // iteration number modulo K, kept by counting
     for (int step = 0; step <= D.T; ++step) {
         const bool eval = kc == 0 || step == D.T;
         if (++kc == D.K) kc = 0;
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
             // ended with a barrier
             for (int k = tid; k < kScal && step + k < D.T; k += kThreads) {
                 float ss, ib2;
-                adam_scalars((double)(step + k) + 1.0, D.lr_d, D.b1_d, D.b2_d, ss, ib2);
+                adam_scalars((double)(step0 + step + k) + 1.0, D.lr_d, D.b1_d, D.b2_d, ss, ib2);
                 s_sc[k] = make_float2(ss, ib2);
             }
             __syncthreads();
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
                 D.final_loss[r] = l * D.inv_m;
             }
             if (improved) {
-                best_step = step;
+                best_step = step0 + step;
                 if (own) {
                     // only this thread writes x[tid] (in the transposed pass)
                     if (tid < n) own_bit = L.x[tid] > 0.0f;
@@ -449,6 +452,11 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
     }
     if (D.x_final != nullptr)
         for (int i = tid; i < n; i += kThreads) D.x_final[(size_t)D.var_old[i] * D.R + r] = L.x[i];
+    if (D.m_final != nullptr)
+        for (int i = tid; i < n; i += kThreads) {
+            D.m_final[(size_t)D.var_old[i] * D.R + r] = L.m[i];
+            D.v_final[(size_t)D.var_old[i] * D.R + r] = L.v[i];
+        }
 }
 
 }  // namespace

@@ -34,12 +34,20 @@ struct SmallDesc {
     double inv_m, lr_d, b1_d, b2_d;
     uint64_t seed;
     const float* x0;      // caller order [n][R] or null
+    // resuming a solve (resume = 1): moments in caller order [n][R] (null:
+    // zero); best_a, best and best_step below hold the resumed best on entry;
+    // iterations are numbered from step0
+    const float* m0;
+    const float* v0;
+    int32_t step0, resume;
     // outputs (device)
     uint8_t* best_a;      // [R][n] caller order: rounded iterate at each restart's best step
     int64_t* best;        // [R]
     int32_t* best_step;   // [R]
     double* final_loss;   // [R] loss at x_T
     float* x_final;       // caller order [n][R] or null
+    float* m_final;       // caller order [n][R] or null: Adam moments after the last step
+    float* v_final;
 };
 
 // LDS bytes the resident solver needs for an instance's state (per workgroup).

@@ -7,8 +7,9 @@ with it every queued request of the same kind that fits too; it builds and
 uploads their plans and solves them, so requests taken while others run overlap
 on the device.  Under light load a request is taken alone as soon as it arrives;
 as the queue grows, the requests taken together grow with it.  Requests of the
-same kind have the same step count, restart count, counting period, optimizer
-and loss mode: those small enough for the resident solver share one launch (one
+same kind have the same step count, restart count, counting period, optimizer,
+Adam constants, loss mode and schedule (learning rates and seeds may differ):
+those small enough for the resident solver share one launch (one
 workgroup per instance and restart), the others share one launch per kernel per
 step (a work queue over their units).
 Every instance's result is bitwise what a solo ``solve`` gives: the kernels'
@@ -70,7 +71,7 @@ class Server:
     """Admit by footprint, overlap on device, batch the small ones."""
 
     def __init__(self, workers: int = 8, hbm_budget: int | None = None, small_batch: int = 64,
-                 tiled_batch: int = 8, device: int = 0):
+                 tiled_batch: int = 8, device: int = 0, trace: bool = False):
         import torch
         self._torch = torch
         torch.cuda.set_device(device)
@@ -85,6 +86,13 @@ class Server:
         self.tiled_batch = int(tiled_batch)
         self._queue: collections.deque[Request] = collections.deque()
         self._cv = threading.Condition()
+        # admission statistics: the largest footprint admitted at once, the
+        # times a worker found the head of the queue over budget and waited,
+        # and (with trace) one (admitted, done, footprint, over budget alone)
+        # record per job
+        self.peak_in_use = 0
+        self.deferrals = 0
+        self.jobs: list | None = [] if trace else None
         self._closed = False
         self._ids = 0
         self._workers = []
@@ -137,8 +145,10 @@ class Server:
         while True:
             if self._queue:
                 head = self._queue[0]
+                # a request larger than the whole budget runs only on an idle device
                 if self.in_use + head.footprint <= self.budget or self.in_use == 0:
                     break
+                self.deferrals += 1
             elif self._closed:
                 return None
             self._cv.wait()
@@ -156,6 +166,7 @@ class Server:
                 keep.append(r)
         keep.extend(self._queue)
         self._queue = keep
+        self.peak_in_use = max(self.peak_in_use, self.in_use)
         now = time.perf_counter()
         for r in job:
             r.params["_admitted"] = now
@@ -179,41 +190,72 @@ class Server:
                         r.future.set_exception(e)
             finally:
                 with self._cv:
-                    for r in job:
-                        self.in_use -= r.footprint
+                    foot = sum(r.footprint for r in job)
+                    if self.jobs is not None:
+                        self.jobs.append((job[0].params["_admitted"], time.perf_counter(), foot,
+                                          foot > self.budget))
+                    self.in_use -= foot
                     self._cv.notify_all()
 
     def _run(self, job, stream):
-        cnfs = [_lib.load_cnf(r.n, r.lits, stream=stream, weights=r.weights) for r in job]
+        cnfs = []
         try:
-            clean = []
             for r in job:
-                p = {k: v for k, v in r.params.items() if not k.startswith("_")}
-                clean.append(p)
+                cnfs.append(_lib.load_cnf(r.n, r.lits, stream=stream, weights=r.weights))
+            clean = [{k: v for k, v in r.params.items() if not k.startswith("_")} for r in job]
             if len(job) == 1:
-                outs = [_lib.solve(cnfs[0], stream=stream, **clean[0])]
+                try:
+                    outs = [_lib.solve(cnfs[0], stream=stream, **clean[0])]
+                except _lib.HipMsatError as e:
+                    if getattr(e, "result", None) is None:
+                        raise
+                    outs = [e]  # non-finite loss or cancelled: the error carries the best so far
             else:
-                keys = ("steps", "restarts", "eval_every", "optimizer", "lr", "loss_mode")
-                kw = {k: [p.get(k, d) for p in clean] for k, d in
-                      zip(keys, (1000, 1, 1, _lib.ADAM, 1e-4, _lib.LOSS_UNSAT))}
-                outs = _lib.solve_batch(cnfs, seeds=[p.get("seed", 0) for p in clean], stream=stream,
-                                        **kw)
+                # a job holds requests of one kind (_group_key): every parameter
+                # that changes a solve goes through per instance
+                kw = {k: [p.get(k, d) for p in clean] for k, d in _BATCH_DEFAULTS.items()}
+                outs = _lib.solve_batch(cnfs, seeds=[p.get("seed", 0) for p in clean], stream=stream, **kw)
+                for i, o in enumerate(outs):
+                    if o.status != 0:
+                        # as the solo path reports it: an error with the partial result
+                        e = _lib.HipMsatError(o.status, f"instance {job[i].rid} of a batched job")
+                        e.result = o
+                        outs[i] = e
         finally:
             for c in cnfs:
                 c.free()
         done = time.perf_counter()
         for r, o in zip(job, outs):
-            r.future.set_result(ServeResult(r.rid, o, r.arrival, r.params["_admitted"], done))
+            if isinstance(o, Exception):
+                r.future.set_exception(o)
+            else:
+                r.future.set_result(ServeResult(r.rid, o, r.arrival, r.params["_admitted"], done))
+
+
+# solve parameters a batched job passes per instance, with their defaults
+# (use_graph and autotune change the speed only, never a result)
+_BATCH_DEFAULTS = {"steps": 1000, "restarts": 1, "eval_every": 1, "optimizer": _lib.ADAM, "lr": 1e-4,
+                   "beta1": 0.9, "beta2": 0.999, "eps": 1e-8, "loss_mode": _lib.LOSS_UNSAT, "schedule": 0}
+
+
+def _runs_alone(p: dict) -> bool:
+    """A time limit or cancel flag applies to one solve, and a start point,
+    a resumed state, x_T or the state handed back belong to one request."""
+    return ((p.get("time_limit_s") or 0.0) > 0 or any(p.get(k) is not None for k in ("x0", "cancel", "resume"))
+            or bool(p.get("want_x")) or bool(p.get("want_state")))
 
 
 def _group_key(r: Request):
-    """Requests that can share launches: same resident/tiled kind, steps,
-    restarts, counting period, optimizer and loss mode."""
+    """Requests that can share launches: same resident/tiled kind and the same
+    value of every solve parameter a batched job shares (steps, restarts,
+    counting period, optimizer, Adam constants, loss mode, schedule).  A
+    request with a time limit, a cancel flag, a start point, a resumed state,
+    or asking for x_T or its state is a job of its own (solved as alone)."""
     p = r.params
-    if p.get("time_limit_s", 0.0) > 0:
-        return ("alone", r.rid)  # a time limit applies to one solve
-    return (r.small, p.get("steps", 1000), p.get("restarts", 1), p.get("eval_every", 1),
-            p.get("optimizer", _lib.ADAM), p.get("loss_mode", _lib.LOSS_UNSAT))
+    if _runs_alone(p):
+        return ("alone", r.rid)
+    # lr and seed are per instance in a batch; the rest must match
+    return (r.small,) + tuple(p.get(k, d) for k, d in _BATCH_DEFAULTS.items() if k != "lr")
 
 
 def percentile(xs, q):

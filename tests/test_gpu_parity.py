@@ -86,6 +86,38 @@ def test_eval_random_formulas(seed):
 
 
 @pytest.mark.parametrize("mode", [hm.LOSS_UNSAT, hm.LOSS_ALL])
+def test_eval_nan_inputs(mode):
+    """NaN relaxed values round to false (a NaN is not > 0), so counts stay
+    exact; a NaN reaches the loss of a restart and the gradient entries of the
+    variables that share a loss clause with it, on both sides alike.  Finite
+    entries keep the parity tolerance."""
+    rng = np.random.default_rng(77 + mode)
+    n, m, R = 120, 500, 6
+    lits = _random_formula(rng, n, m)
+    x = _x(n, R, seed=78, lo=-2, hi=2, specials=True, nan=9)
+    x[:, 0] = np.where(np.isnan(x[:, 0]), np.float32(0.5), x[:, 0])  # restart 0 has no NaN
+    oc = O.OracleCNF(n, lits)
+    cnf = hm.load_cnf(n, lits)
+    loss, g, u = hm.eval_relaxed(cnf, torch.from_numpy(x).cuda(), loss_mode=mode)
+    torch.cuda.synchronize()
+    gn = g.cpu().numpy().astype(np.float64)
+    lo, go, uo = oc.loss_grad(x, mode)
+    np.testing.assert_array_equal(u, uo)
+    np.testing.assert_array_equal(np.isnan(loss), np.isnan(lo))
+    np.testing.assert_array_equal(np.isnan(gn), np.isnan(go))
+    assert not np.isnan(loss[0]) and np.isnan(loss).sum() >= 1
+    fin = ~np.isnan(lo)
+    W = w_abs_matrix(n, lits)
+    _, _, _, _, muo = oc.loss_grad(x[:, fin], mode, want_f=True)
+    lscale, S = tolerance_terms(W, x[:, fin], muo, oc.m)
+    assert np.all(np.abs(loss[fin] - lo[fin]) <= 1e-5 * lscale + 1e-300)
+    gf, gof = gn[:, fin], go[:, fin]
+    assert np.all(np.abs(gf - gof) <= 1e-5 * S + 1e-30)
+    _say(f"nan inputs: {int(np.isnan(loss).sum())} of {R} losses NaN, "
+         f"{int(np.isnan(gn).sum())} gradient entries NaN, counts {u.tolist()}")
+
+
+@pytest.mark.parametrize("mode", [hm.LOSS_UNSAT, hm.LOSS_ALL])
 def test_eval_worked_example(mode, golden):
     g = golden("worked_example.txt")
     lits = np.array(g["clauses"], np.int32)

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import cnfgen
+import oracle as O
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +32,29 @@ def _requests(count, seed, n_hi=6000):
                                 lr=1e-2)) for r in reqs]
 
 
+def _oracle_check(n, lits, out, weights=None):
+    """The method's own checks of a batched or served result: the oracle
+    counts the returned assignment at the reported cost, and no cost is below
+    the exact optimum (brute force for n <= 18)."""
+    oc = O.OracleCNF(n, lits, weights=weights)
+    assert oc.count(out.best_assignment) == out.best_cost
+    assert out.best_cost == int(np.min(out.restart_best))
+    if n <= 18:
+        opt, _, _ = oc.bruteforce()
+        assert np.all(out.restart_best >= opt)
+        return opt
+    return None
+
+
+def _tiny_requests(seed):
+    """Requests small enough to brute-force (n <= 18)."""
+    out = []
+    for i, n in enumerate((8, 12, 15, 18)):
+        out.append((n, cnfgen.uniform_kcnf(n, int(4.3 * n), 3, seed=seed * 100 + i),
+                    dict(steps=120, restarts=1 + i % 3, eval_every=10, seed=900 + i, lr=1e-2)))
+    return out
+
+
 def _same(a, b):
     np.testing.assert_array_equal(a.restart_best, b.restart_best)
     np.testing.assert_array_equal(a.restart_step, b.restart_step)
@@ -40,7 +64,7 @@ def _same(a, b):
 
 
 def test_solve_batch_equals_solo():
-    reqs = _requests(24, seed=1)
+    reqs = _requests(24, seed=1) + _tiny_requests(1)
     cnfs = [hm.load_cnf(n, lits) for n, lits, _ in reqs]
     solo = [hm.solve(c, **p) for c, (_, _, p) in zip(cnfs, reqs)]
     batch = hm.solve_batch(cnfs, steps=[p["steps"] for *_, p in reqs],
@@ -48,11 +72,12 @@ def test_solve_batch_equals_solo():
                            eval_every=[p["eval_every"] for *_, p in reqs],
                            seeds=[p["seed"] for *_, p in reqs], lr=[p["lr"] for *_, p in reqs])
     kinds = {}
-    for c, a, b in zip(cnfs, solo, batch):
+    for c, a, b, (n, lits, _) in zip(cnfs, solo, batch, reqs):
         assert b.status == 0
         _same(a, b)
         kinds[b.schedule == 255] = kinds.get(b.schedule == 255, 0) + 1
         assert hm.evaluate(c, b.best_assignment) == b.best_cost
+        _oracle_check(n, lits, b)
     _say(f"batch: resident {kinds.get(True, 0)}, tiled {kinds.get(False, 0)}")
     assert kinds.get(True, 0) > 0 and kinds.get(False, 0) > 0
 
@@ -66,10 +91,11 @@ def test_grouped_tiled_batch_equals_solo(opt, mode):
     # from the others', and the group runs them all with the largest's
     sizes = [(20000, 86000, "u"), (9000, 40000, "s"), (15000, 64000, "u"), (30000, 120000, "s"),
              (12000, 50000, "u"), (200000, 860000, "u")]
-    cnfs, lrs = [], []
+    cnfs, lrs, all_lits = [], [], []
     for i, (n, m, kind) in enumerate(sizes):
         lits = (cnfgen.uniform_kcnf(n, m, 3, seed=40 + i) if kind == "u"
                 else cnfgen.structured_cnf(n, m, seed=40 + i))
+        all_lits.append(lits)
         cnfs.append(hm.load_cnf(n, lits))
         lrs.append((1e-2 if opt == hm.ADAM else 0.5) * (1 + 0.1 * i))
     assert any(c.info["n_heavy"] > 0 for c in cnfs)
@@ -79,6 +105,7 @@ def test_grouped_tiled_batch_equals_solo(opt, mode):
     batch = hm.solve_batch(cnfs, seeds=list(range(len(cnfs))), lr=lrs, want_x=True, **kw)
     for i, (c, b) in enumerate(zip(cnfs, batch)):
         assert b.status == 0 and b.schedule != 255
+        _oracle_check(sizes[i][0], all_lits[i], b)
         a = hm.solve(c, seed=i, lr=lrs[i], want_x=True, autotune=False, **kw)
         _same(a, b)
         np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32),
@@ -109,8 +136,17 @@ def test_grouped_batch_multi_tile_schedules(sched):
 
 
 def test_served_equals_solo_and_overlaps():
+    """Requests of mixed kinds (default and other Adam constants, explicit
+    start points, instances small enough to brute-force) served together:
+    each equals its solo solve and passes the oracle's checks."""
     from paper_2402_03640_amd.serve import Server
-    reqs = _requests(40, seed=2)
+    reqs = _requests(40, seed=2) + _tiny_requests(2)
+    for i in range(0, 40, 5):  # other Adam constants: batched among themselves
+        reqs[i][2].update(beta1=0.8, beta2=0.99, eps=1e-7)
+    for i in range(3, 40, 9):  # a start point of its own: solved alone
+        n, p = reqs[i][0], reqs[i][2]
+        p["x0"] = torch.from_numpy(cnfgen.random_x(n, p["restarts"], seed=500 + i)).cuda()
+    torch.cuda.synchronize()  # the workers read x0 from their own streams
     solo = []
     for n, lits, p in reqs:
         c = hm.load_cnf(n, lits)
@@ -124,9 +160,10 @@ def test_served_equals_solo_and_overlaps():
             time.sleep(0.001 * (i % 3))
         res = [f.result(timeout=120) for f in futs]
     wall = time.perf_counter() - t0
-    for a, r in zip(solo, res):
+    for a, r, (n, lits, _) in zip(solo, res, reqs):
         _same(a, r.output)
         assert r.latency > 0 and r.done >= r.admitted >= r.arrival
+        _oracle_check(n, lits, r.output)
     # requests were in flight together: latencies overlap in time
     spans = sorted((r.admitted, r.done) for r in res)
     overlap = sum(1 for (a0, a1), (b0, b1) in zip(spans, spans[1:]) if b0 < a1)
@@ -135,16 +172,78 @@ def test_served_equals_solo_and_overlaps():
 
 
 def test_admission_respects_budget():
+    """Admission by footprint: with room for about two requests, the
+    footprint in flight never exceeds the budget, requests wait for room (at
+    least one deferral), and a request larger than the whole budget runs only
+    on an idle device, with nothing beside it.  Results equal the solo ones."""
     from paper_2402_03640_amd.serve import Server, footprint_bytes
-    reqs = _requests(10, seed=3, n_hi=3000)
-    budget = max(footprint_bytes(n, int(np.count_nonzero(l == 0)), l.size, p["restarts"])
-                 for n, l, p in reqs) + 1
-    with Server(workers=4, hbm_budget=budget) as srv:
+    reqs = _requests(16, seed=3, n_hi=3000)
+
+    def foot(n, l, p):
+        return footprint_bytes(n, int(np.count_nonzero(l == 0)), l.size - int(np.count_nonzero(l == 0)),
+                               p["restarts"])
+
+    budget = int(2.2 * max(foot(*r) for r in reqs))
+    nb, lb = 60000, cnfgen.uniform_kcnf(60000, 258000, 3, seed=33)
+    big = (nb, lb, dict(steps=60, restarts=2, eval_every=10, seed=77, lr=1e-2))
+    assert foot(*big) > budget
+    reqs = reqs[:8] + [big] + reqs[8:]
+    solo = []
+    for n, lits, p in reqs:
+        c = hm.load_cnf(n, lits)
+        solo.append(hm.solve(c, **p))
+        c.free()
+    with Server(workers=4, hbm_budget=budget, trace=True) as srv:
         futs = [srv.submit(n, lits, **p) for n, lits, p in reqs]
-        res = [f.result(timeout=120) for f in futs]
-    # with room for about one request at a time the admissions do not overlap much
-    assert all(r.output.best_cost >= 0 for r in res)
-    assert srv.in_use == 0
+        res = [f.result(timeout=300) for f in futs]
+    for a, r in zip(solo, res):
+        _same(a, r.output)
+    assert srv.in_use == 0 and srv.deferrals >= 1
+    # replay the admissions and completions (both stamped under the server's lock)
+    # (a completion sorts before an admission stamped at the same instant)
+    ev = sorted([(a, 1, f, over) for a, d, f, over in srv.jobs] + [(d, 0, -f, over) for a, d, f, over in srv.jobs])
+    in_use, running_over = 0, 0
+    for t, kind, df, over in ev:
+        if kind == 1 and over:
+            assert in_use == 0, "an over-budget request was admitted beside others"
+        if kind == 1 and not over:
+            assert running_over == 0, "a request was admitted beside an over-budget one"
+        in_use += df
+        running_over += (1 if df > 0 else -1) if over else 0
+        if not running_over:
+            assert in_use <= budget, (in_use, budget)
+    assert any(over for *_, over in srv.jobs)
+    _say(f"admission: budget {budget / 2**20:.1f} MiB, peak {srv.peak_in_use / 2**20:.1f} MiB, "
+         f"deferrals {srv.deferrals}, jobs {len(srv.jobs)}")
+
+
+def test_short_groups_match_the_oracle():
+    """Three Adam steps (lr 1e-4, counting every step) of a batched group and
+    of a served mix: each instance's per-restart best costs and steps equal
+    the oracle's from the same seeds, and the batched x_T is within the step
+    tolerance of the oracle's x_T (FP32 rounding of three updates)."""
+    from paper_2402_03640_amd.serve import Server
+    T, lr = 3, 1e-4
+    inst = []
+    for i, n in enumerate((12, 90, 700, 3000, 9000, 24000)):
+        inst.append((n, cnfgen.uniform_kcnf(n, int(4.3 * n), 3, seed=300 + i), 1 + i % 3, 40 + 7 * i))
+    cnfs = [hm.load_cnf(n, lits) for n, lits, _, _ in inst]
+    kw = dict(steps=T, eval_every=1, lr=lr)
+    batch = hm.solve_batch(cnfs, restarts=[R for *_, R, _ in inst], seeds=[s for *_, s in inst], want_x=True, **kw)
+    with Server(workers=3) as srv:
+        futs = [srv.submit(n, lits, restarts=R, seed=s, **kw) for n, lits, R, s in inst]
+        served = [f.result(timeout=120).output for f in futs]
+    for (n, lits, R, s), b, v in zip(inst, batch, served):
+        oc = O.OracleCNF(n, lits)
+        o = oc.solve(steps=T, restarts=R, eval_every=1, seed=s, lr=lr, want_x=True)
+        for out in (b, v):
+            np.testing.assert_array_equal(out.restart_best, o["restart_best"])
+            np.testing.assert_array_equal(out.restart_step, o["restart_step"])
+            assert oc.count(out.best_assignment) == out.best_cost
+        xg = b.x_final.cpu().numpy().astype(np.float64)
+        tol = T * (2.0 ** -23 * (np.abs(o["x"]) + 4 * lr * T) + 1e-5 * 4 * lr)
+        assert np.all(np.abs(xg - o["x"]) <= tol), np.max(np.abs(xg - o["x"]) / tol)
+    _say(f"short groups: {len(inst)} instances, batched schedules {[b.schedule for b in batch]}")
 
 
 def test_large_tiled_group_equals_solo():
@@ -152,20 +251,22 @@ def test_large_tiled_group_equals_solo():
     one grouped launch: each result is bitwise its solo result, the group
     running the schedule of its largest instance."""
     rng = np.random.default_rng(77)
-    cnfs, seeds = [], []
+    cnfs, seeds, inst = [], [], []
     for i in range(16):
         k = int(rng.integers(3, 6))
         n = int(rng.integers(2000, 40000))
         m = int(n * (3.5 + 1.5 * rng.random()) * 2 ** k / 8)
-        cnfs.append(hm.load_cnf(n, cnfgen.uniform_kcnf(n, m, k, seed=100 + i)))
+        inst.append((n, cnfgen.uniform_kcnf(n, m, k, seed=100 + i)))
+        cnfs.append(hm.load_cnf(*inst[-1]))
         seeds.append(1000 + i)
     kw = dict(steps=80, restarts=1, eval_every=10, lr=1e-2)
     batch = hm.solve_batch(cnfs, seeds=seeds, want_x=True, **kw)
     tiled = 0
-    for c, s, b in zip(cnfs, seeds, batch):
+    for c, s, b, (n, lits) in zip(cnfs, seeds, batch, inst):
         a = hm.solve(c, seed=s, autotune=False, want_x=True, **kw)
         assert b.status == 0
         _same(a, b)
+        _oracle_check(n, lits, b)
         np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32),
                                       b.x_final.cpu().numpy().view(np.uint32))
         tiled += b.schedule != 255

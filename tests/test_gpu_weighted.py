@@ -164,9 +164,19 @@ def test_wcnf_files(tmp_path):
         hm.load_cnf(3, cnfgen.from_clauses([[1, 2], [-3]]), weights=[1, 0])
 
 
+def _weighted_oracle_check(n, lits, w, out):
+    """The oracle weighs the returned assignment at the reported cost, and
+    (n <= 18) no restart reports less than the exact weighted optimum."""
+    oc = O.OracleCNF(n, lits, weights=w)
+    assert oc.count(out.best_assignment) == out.best_cost == int(np.min(out.restart_best))
+    if n <= 18:
+        assert np.all(out.restart_best >= oc.bruteforce()[0])
+
+
 def test_weighted_batch_equals_solo():
     reqs = []
-    for i, (n, m) in enumerate([(50, 215), (3000, 12900), (20000, 86000), (40, 170), (15000, 64000)]):
+    for i, (n, m) in enumerate([(50, 215), (3000, 12900), (20000, 86000), (40, 170), (15000, 64000), (14, 60),
+                                (18, 77)]):
         lits = cnfgen.uniform_kcnf(n, m, 3, seed=60 + i)
         reqs.append((n, lits, _weights(m, seed=i)))
     cnfs = [hm.load_cnf(n, lits, weights=w) for n, lits, w in reqs]
@@ -177,12 +187,13 @@ def test_weighted_batch_equals_solo():
         np.testing.assert_array_equal(a.restart_best, b.restart_best)
         np.testing.assert_array_equal(a.best_assignment, b.best_assignment)
         assert hm.evaluate(c, b.best_assignment) == b.best_cost
+        _weighted_oracle_check(reqs[i][0], reqs[i][1], reqs[i][2], b)
 
 
 def test_weighted_served_equals_solo():
     from paper_2402_03640_amd.serve import Server
     reqs = []
-    for i, (n, m) in enumerate([(50, 215), (3000, 12900), (8000, 34400), (60, 250)]):
+    for i, (n, m) in enumerate([(50, 215), (3000, 12900), (8000, 34400), (60, 250), (16, 68)]):
         lits = cnfgen.uniform_kcnf(n, m, 3, seed=80 + i)
         reqs.append((n, lits, _weights(m, seed=80 + i)))
     kw = dict(steps=60, restarts=1, eval_every=6, lr=1e-2)
@@ -190,6 +201,7 @@ def test_weighted_served_equals_solo():
     with Server(workers=2) as srv:
         futs = [srv.submit(n, l, weights=w, seed=i, **kw) for i, (n, l, w) in enumerate(reqs)]
         res = [f.result(timeout=120) for f in futs]
-    for a, r in zip(solo, res):
+    for a, r, (n, l, w) in zip(solo, res, reqs):
         np.testing.assert_array_equal(a.restart_best, r.output.restart_best)
         np.testing.assert_array_equal(a.best_assignment, r.output.best_assignment)
+        _weighted_oracle_check(n, l, w, r.output)
