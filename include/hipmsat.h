@@ -296,6 +296,24 @@ hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t restarts
                             double* loss, float* grad, int64_t* unsat, void* stream);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, hosts that forbid allocation.  The same
+ * evaluation as hms_eval_relaxed (bitwise the same loss, gradient and
+ * counts), with no allocation and no wait: its workspace is a fixed array of
+ * 64 MiB inside the library, one per GPU, which each GPU the library runs on
+ * holds until the process ends; loss (DEVICE [R] doubles) and unsat (DEVICE
+ * [R] int64) are device outputs like grad (DEVICE [n][R]); each may be NULL.
+ * All work is enqueued on `stream`; the outputs are ready when it reaches
+ * them.  Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (nothing in it needs clearing: each call writes what it
+ * reads): calls that overlap on one GPU race, so order them (one stream, or
+ * events).  Errors: HMS_ERR_TOO_LARGE when the instance and R need more than
+ * the 64 MiB (hms_eval_relaxed has no such limit), and as hms_eval_relaxed.
+ */
+hms_status hms_eval_relaxed_noalloc(const hms_cnf* cnf, const float* x, int32_t restarts, int32_t loss_mode,
+                                    double* loss, float* grad, int64_t* unsat, void* stream);
+
+/*
  * Differentiable pieces of the loss, for autograd frameworks (Section 4: the
  * loss is differentiated through the network by backpropagation).
  * hms_forward: loss[R] (DEVICE doubles) at x (DEVICE [n][R]) and optionally the

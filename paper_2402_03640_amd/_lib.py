@@ -81,7 +81,7 @@ EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_
            "hms_solve_params_default", "hms_solve", "hms_evaluate", "hms_eval_relaxed",
            "hms_last_error", "hms_version", "hms_plan_view_build", "hms_plan_view_free",
            "hms_time_kernels", "hms_tune", "hms_adjoint_bytes", "hms_forward", "hms_backward",
-           "hms_solve_batch", "hms_tune_candidates", "hms_load_wcnf"]
+           "hms_solve_batch", "hms_tune_candidates", "hms_load_wcnf", "hms_eval_relaxed_noalloc"]
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -123,6 +123,7 @@ def _load():
     L.hms_forward.argtypes = [P, P, I32, I32, P, P, P, P]
     L.hms_backward.argtypes = [P, P, I32, I32, P, P, P, P]
     L.hms_eval_relaxed.argtypes = [P, P, I32, I32, P, P, P, P]
+    L.hms_eval_relaxed_noalloc.argtypes = [P, P, I32, I32, P, P, P, P]
     L.hms_last_error.argtypes = []
     L.hms_last_error.restype = C.c_char_p
     L.hms_version.argtypes = []
@@ -132,7 +133,7 @@ def _load():
     L.hms_plan_view_free.restype = None
     L.hms_tune_candidates.argtypes = [I32, I32, P, I32, P]
     for name in ("hms_load_cnf", "hms_load_wcnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_solve",
-                 "hms_evaluate", "hms_eval_relaxed", "hms_plan_view_build", "hms_time_kernels", "hms_tune", "hms_adjoint_bytes",
+                 "hms_evaluate", "hms_eval_relaxed", "hms_eval_relaxed_noalloc", "hms_plan_view_build", "hms_time_kernels", "hms_tune", "hms_adjoint_bytes",
                  "hms_forward", "hms_backward", "hms_solve_batch", "hms_tune_candidates"):
         getattr(L, name).restype = I32
     _lib = L
@@ -506,6 +507,29 @@ def eval_relaxed(cnf: Cnf, x, loss_mode: int = LOSS_UNSAT, want_grad: bool = Tru
                                   C.c_void_p(g.data_ptr()) if g is not None else None,
                                   unsat.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
     return loss, g, unsat
+
+
+def eval_relaxed_noalloc(cnf: Cnf, x, loss_out=None, grad_out=None, unsat_out=None, loss_mode: int = LOSS_UNSAT,
+                         stream=None):
+    """``hms_eval_relaxed_noalloc``: the evaluation of ``eval_relaxed`` into
+    caller device tensors (loss float64 [R], grad float32 [n][R], unsat int64
+    [R]; each may be None), with no allocation and no wait in the library."""
+    import torch
+    X = _device_points(x, cnf, "x")
+    R = X.shape[1]
+
+    def dev(t, dtype, shape, name):
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous() \
+                or tuple(t.shape) != shape or t.device.index != cnf.device:
+            raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {shape} on the instance's GPU")
+        return C.c_void_p(t.data_ptr())
+
+    _check(lib().hms_eval_relaxed_noalloc(cnf.handle, C.c_void_p(X.data_ptr()), R, int(loss_mode),
+                                          dev(loss_out, torch.float64, (R,), "loss_out"),
+                                          dev(grad_out, torch.float32, tuple(X.shape), "grad_out"),
+                                          dev(unsat_out, torch.int64, (R,), "unsat_out"), _stream_ptr(stream)))
 
 
 def version() -> str:

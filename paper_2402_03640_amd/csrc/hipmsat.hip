@@ -88,12 +88,14 @@ struct DeviceGuard {
     }
 };
 
-// Stream-ordered scratch arena, released on scope exit.
+// Stream-ordered scratch arena, released on scope exit (owns = false: a
+// view of memory the arena does not own, never freed).
 struct Arena {
     char* base = nullptr;
     hipStream_t s = nullptr;
+    bool owns = true;
     ~Arena() {
-        if (base) (void)hipFreeAsync(base, s);
+        if (base && owns) (void)hipFreeAsync(base, s);
     }
     template <typename T>
     T* at(size_t off) const {
@@ -106,7 +108,10 @@ struct Arena {
 // freeing that buffer while the copy may still read it.
 struct SyncOnExit {
     hipStream_t s;
-    ~SyncOnExit() { (void)hipStreamSynchronize(s); }
+    bool on = true;  // false: nothing to wait for
+    ~SyncOnExit() {
+        if (on) (void)hipStreamSynchronize(s);
+    }
 };
 
 // Default kernel schedule for R restarts (table index into hms::kSchedules).
@@ -1702,14 +1707,47 @@ hms_status hms_tune(const hms_cnf* cnf, const hms_solve_params* params, int32_t 
     return HMS_OK;
 }
 
-hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t R, int32_t loss_mode, double* loss,
-                            float* grad, int64_t* unsat, void* stream) {
-    g_err.clear();
+}  // extern "C"
+
+namespace {
+
+// Workspace of hms_eval_relaxed_noalloc: a fixed device array, one copy per
+// GPU (each GPU holds it until the process ends).  Host code must never use
+// the array's name as an address: its device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};  // device address of `scratch` on each GPU, once known
+
+// Device address of the workspace on `dev` (the current device).
+hms_status scratch_on(int dev, char*& ptr) {
+    if (dev < 0 || dev >= 64) return fail(HMS_ERR_DEVICE, "device index out of range for the fixed workspace");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(HMS_ERR_DEVICE, std::string("hipGetSymbolAddress of the fixed workspace: ") +
+                                            hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    ptr = static_cast<char*>(g_scratch_ptr[dev]);
+    return HMS_OK;
+}
+
+// One evaluation of the relaxed objective (hms_eval_relaxed).  With `fixed`
+// the workspace is that device memory (cap bytes) and loss / unsat are
+// DEVICE outputs, so nothing is allocated and nothing waits; otherwise the
+// workspace is a stream-ordered allocation of this call and loss / unsat are
+// HOST outputs.
+hms_status eval_relaxed_impl(const hms_cnf* cnf, const float* x, int32_t R, int32_t loss_mode, double* loss,
+                             float* grad, int64_t* unsat, void* stream, char* fixed, size_t cap) {
     if (check_cnf(cnf) || (!x && cnf->plan.n > 0)) return fail(HMS_ERR_ARG, "null argument");
     if (R < 1) return fail(HMS_ERR_ARG, "restarts >= 1 required");
     if (loss_mode != HMS_LOSS_UNSAT && loss_mode != HMS_LOSS_ALL) return fail(HMS_ERR_ARG, "unknown loss mode");
     const hms::HostPlan& P = cnf->plan;
-    DeviceGuard dg(cnf->device);
     hipStream_t s = (hipStream_t)stream;
     Shape sh;
     hms_status rc = make_shape(P, R, 0, loss_mode, sh);
@@ -1720,9 +1758,21 @@ hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t R, int32
     layout_state(P, sh, false, want_g, false, lay, off);
     Arena A;
     A.s = s;
-    HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
-    // the host outputs are written by queued copies: an early return waits
-    SyncOnExit outs_done{s};
+    if (fixed) {
+        if (lay.off > cap)
+            return fail(HMS_ERR_TOO_LARGE, "this evaluation needs " + std::to_string(lay.off) +
+                                               " bytes of workspace, more than the " + std::to_string(cap) +
+                                               " of the allocation-free variant");
+        A.base = fixed;
+        A.owns = false;
+    } else {
+        HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
+    }
+    // host outputs are written by queued copies: an early return waits (the
+    // allocation-free variant has device outputs only and never waits)
+    SyncOnExit outs_done{s, fixed == nullptr};
+    // every piece the kernels read is written first (init kernel, forward
+    // pass), so a reused workspace needs no clearing
     State S = bind_state(A, off, false, want_g, false);
     hms::InitArgs ia = make_init(cnf, sh, S);
     ia.x0 = x;
@@ -1736,10 +1786,34 @@ hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t R, int32
         HIPTRY(hms::launch_combine(hms::kGrad, L.ba, s));
         HIPTRY(hms::launch_scatter(P.n, P.n_act, sh.B, cnf->var_old, S.g, grad, s));
     }
-    if (loss) HIPTRY(hipMemcpyAsync(loss, S.cur_loss, R * 8, hipMemcpyDeviceToHost, s));
-    if (unsat) HIPTRY(hipMemcpyAsync(unsat, S.cur_count, R * 8, hipMemcpyDeviceToHost, s));
-    if (loss || unsat) HIPTRY(hipStreamSynchronize(s));
+    const hipMemcpyKind kind = fixed ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (loss) HIPTRY(hipMemcpyAsync(loss, S.cur_loss, (size_t)R * 8, kind, s));
+    if (unsat) HIPTRY(hipMemcpyAsync(unsat, S.cur_count, (size_t)R * 8, kind, s));
+    if (!fixed && (loss || unsat)) HIPTRY(hipStreamSynchronize(s));
     return HMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hms_status hms_eval_relaxed(const hms_cnf* cnf, const float* x, int32_t R, int32_t loss_mode, double* loss,
+                            float* grad, int64_t* unsat, void* stream) {
+    g_err.clear();
+    if (check_cnf(cnf)) return fail(HMS_ERR_ARG, "null instance handle");
+    DeviceGuard dg(cnf->device);
+    return eval_relaxed_impl(cnf, x, R, loss_mode, loss, grad, unsat, stream, nullptr, 0);
+}
+
+hms_status hms_eval_relaxed_noalloc(const hms_cnf* cnf, const float* x, int32_t R, int32_t loss_mode, double* loss,
+                                    float* grad, int64_t* unsat, void* stream) {
+    g_err.clear();
+    if (check_cnf(cnf)) return fail(HMS_ERR_ARG, "null instance handle");
+    DeviceGuard dg(cnf->device);
+    char* ws = nullptr;
+    hms_status rc = scratch_on(cnf->device, ws);
+    if (rc) return rc;
+    return eval_relaxed_impl(cnf, x, R, loss_mode, loss, grad, unsat, stream, ws, kScratchBytes);
 }
 
 // ---- differentiable forward / backward ---------------------------------------
