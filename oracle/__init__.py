@@ -14,21 +14,27 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# HIPMSAT_ORACLE_LIB names another build (the sanitized one of build(sanitize=True))
+_LIB = os.environ.get("HIPMSAT_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 UNSAT, ALL = 0, 1
 ADAM, SGD = 0, 1
 
 
-def build(force: bool = True) -> str:
-    """Compile ``oracle.c`` with gcc (plain IEEE FP64, no contraction)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+def build(force: bool = True, sanitize: bool = False, out: str | None = None) -> str:
+    """Compile ``oracle.c`` with gcc (plain IEEE FP64, no contraction); with
+    ``sanitize`` under ASan and UBSan (load it through HIPMSAT_ORACLE_LIB with
+    gcc's libasan and libubsan preloaded)."""
+    lib_path = out or _LIB
+    if force or not os.path.exists(lib_path):
+        tmp = lib_path + ".tmp"
+        san = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined",
+               "-g"] if sanitize else []
         subprocess.check_call([
             "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-            "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+            "-fno-fast-math", "-Wall"] + san + ["-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 _lib = None

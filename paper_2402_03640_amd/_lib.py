@@ -14,7 +14,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libhipmsat.so")
+# HIPMSAT_LIB names another build of the same library (the sanitized host build)
+LIB_PATH = os.environ.get("HIPMSAT_LIB") or os.path.join(_PKG, "libhipmsat.so")
 
 HMS_OK = 0
 ERRORS = {

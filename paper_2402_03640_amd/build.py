@@ -35,11 +35,28 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose: bool = False) -> str:
+SAN_DIR = os.path.join(BUILD, "san")
+# gcc's AddressSanitizer and UndefinedBehaviorSanitizer for the host-only plan
+# builder (the HIP sources stay as they are: one sanitizer runtime per process)
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"]
+
+
+def _gcc_runtime_dir() -> str:
+    return os.path.dirname(subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip())
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Build libhipmsat.so in the package; with ``sanitize`` a copy whose
+    host plan code carries ASan/UBSan, in _build/san/ (load it through the
+    HIPMSAT_LIB variable, with gcc's libasan and libubsan preloaded)."""
     os.makedirs(BUILD, exist_ok=True)
+    bdir = SAN_DIR if sanitize else BUILD
+    os.makedirs(bdir, exist_ok=True)
+    out = os.path.join(SAN_DIR, "libhipmsat.so") if sanitize else OUT
+    plan_flags = SAN_FLAGS if sanitize else []
     jobs = [
-        ["g++"] + COMMON + ["-ffp-contract=off", "-c", os.path.join(CSRC, "plan.cpp"), "-o",
-                            os.path.join(BUILD, "plan.o")],
+        ["g++"] + COMMON + plan_flags + ["-ffp-contract=off", "-c", os.path.join(CSRC, "plan.cpp"), "-o",
+                                         os.path.join(bdir, "plan.o")],
         [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "kernels.hip"), "-o",
                                os.path.join(BUILD, "kernels.o")],
         [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "hipmsat.hip"), "-o",
@@ -49,17 +66,21 @@ def build(verbose: bool = False) -> str:
     ]
     with ThreadPoolExecutor(4) as ex:
         outs = list(ex.map(_run, jobs))
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
+    san_link = []
+    if sanitize:
+        rt = _gcc_runtime_dir()
+        san_link = ["-L" + rt, "-Wl,-rpath," + rt, "-lasan", "-lubsan"]
     outs.append(_run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
-                      os.path.join(BUILD, "plan.o"), os.path.join(BUILD, "kernels.o"),
-                      os.path.join(BUILD, "hipmsat.o"), os.path.join(BUILD, "small.o")]))
-    os.replace(tmp, OUT)
+                      os.path.join(bdir, "plan.o"), os.path.join(BUILD, "kernels.o"),
+                      os.path.join(BUILD, "hipmsat.o"), os.path.join(BUILD, "small.o")] + san_link))
+    os.replace(tmp, out)
     if verbose:
         for o in outs:
             if o.strip():
                 print(o)
-    return OUT
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))
