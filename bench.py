@@ -90,18 +90,20 @@ def counters_summary(dirs):
         if not files:
             continue
         rows = list(csv.DictReader(open(files[0])))
-        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        copies = [float(r["Counter_Value"]) for r in rows if "k_copy" in r["Kernel_Name"]]
+        gathers = [float(r["Counter_Value"]) for r in rows if "k_gather" in r["Kernel_Name"]]
         per = {}
         for r in rows:
             name = r["Kernel_Name"]
             key = "fwd" if ("k_fwd<" in name or "k_fwd_nt<" in name) else ("bwd" if "k_bwd<" in name else None)
             if key:
                 per.setdefault(key, [name, []])[1].append(float(r["Counter_Value"]))
-        runs.setdefault((config, sched), {})[counter] = (max(copies) if copies else None, per)
+        runs.setdefault((config, sched), {})[counter] = (max(copies) if copies else None, per,
+                                                         max(gathers) if gathers else None)
     out = {"kernels_sha": kernels_sha(),
            "method": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --kernel-trace, KiB per dispatch averaged "
-                     "over launches, each scaled by (256 MiB / the counter's reading for the 256 MiB device "
-                     "copy made in the same run)",
+                     "over launches, each scaled by (256 MiB / the counter's reading for the project's 256 MiB "
+                     "streaming copy made in the same run); a cold 128-byte gather checks the FETCH factor",
            "configs": {}}
     base = os.path.dirname(os.path.normpath(dirs[0])) if dirs else "."
     lines = ["# HBM traffic per launch from rocprofv3 counters (calibrated)",
@@ -119,11 +121,18 @@ def counters_summary(dirs):
         wl = make_workload(config)
         L = int(hm.Plan(wl["n"], wl["lits"]).nnz)  # canonical literal count (host-only plan)
         fb, bb = kernel_bytes(wl["n"], wl["m"], L, wl["R"], wl["weights"] is not None)
-        fcopy, fper = ctr["FETCH_SIZE"]
-        wcopy, wper = ctr["WRITE_SIZE"]
+        fcopy, fper, fgat = ctr["FETCH_SIZE"]
+        wcopy, wper, _ = ctr["WRITE_SIZE"]
         ff = copy_bytes / (fcopy * 1024) if fcopy else None
         wf = copy_bytes / (wcopy * 1024) if wcopy else None
-        rec = {"fetch_factor": ff, "write_factor": wf, "kernels": {}}
+        # second point: the cold gather fetches about 94% of its 512 MiB of
+        # rows as distinct lines (16 MiB of indices on top): its scaled reading
+        # should come out near 0.94 * 512 + 16 MiB
+        gat = fgat * 1024 * ff / 2 ** 20 if (fgat and ff) else None
+        rec = {"fetch_factor": ff, "write_factor": wf, "gather_check_mib": gat, "kernels": {}}
+        if gat is not None:
+            lines.append(f"# {config} {sched}: cold 128-byte gather, FETCH scaled by the copy factor: {gat:.0f} MiB "
+                         f"(expected about {0.94 * 512 + 16:.0f} MiB of distinct lines)")
         for key, alg in (("fwd", fb), ("bwd", bb)):
             if key not in fper or key not in wper or ff is None or wf is None:
                 continue
@@ -163,24 +172,90 @@ def sweep(cnf, wl, iters):
     print("# fastest: " + ", ".join(f"{c} ({t * 1e3:.2f} us)" for t, c in res[:5]), flush=True)
 
 
-def copy_bandwidth(nbytes=1 << 30, reps=5):
-    """Achievable HBM bandwidth: best of `reps` device-to-device copies of
-    `nbytes` (bytes read + bytes written per second), HIP events."""
+def copy_bandwidth(nbytes=1 << 30, iters=20):
+    """Achievable HBM bandwidth: the project's streaming-copy kernel (probe
+    library) over `nbytes`, bytes read + bytes written per second, HIP events."""
     import torch
-    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+
+    from paper_2402_03640_amd import probe
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    best = None
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        dst.copy_(src)
-        e1.record()
-        e1.synchronize()
-        t = e0.elapsed_time(e1) * 1e-3
-        best = t if best is None else min(best, t)
+    ms = probe.copy_ms(src, dst, iters)
     del src, dst
-    return 2.0 * nbytes / best / 1e9
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+# gather probe points: (row bytes, footprint bytes); rows of 4 B are the
+# one-restart gathers, 32 B eight restarts, 128 B the 32-restart groups of the
+# headline; 2 MiB sits in an XCD's L2, 22 MiB is the headline's adjoint array
+# (in the 256 MB Infinity Cache), 4 GiB is beyond every cache
+GATHER_POINTS = [(rb, fp) for rb in (4, 32, 128) for fp in (2 << 20, 22 << 20, 64 << 20, 4 << 30)]
+
+
+def gather_bandwidth(row_bytes, footprint, iters=10, seed=0):
+    """The project's gather-sum probe: random rows of `row_bytes` from a
+    `footprint`-byte array, the best of its lane and rows-per-output shapes.
+    Returns (gathered GB/s, total GB/s with the index and output bytes, ms
+    per launch, the best shape)."""
+    import torch
+
+    from paper_2402_03640_amd import probe
+    W = row_bytes // 4
+    rows = footprint // row_bytes
+    gathered = (512 << 20) if row_bytes >= 32 else (128 << 20)  # gathered bytes per launch
+    n_idx = gathered // row_bytes
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    src = torch.ones((rows, W), dtype=torch.float32, device="cuda")
+    idx = torch.randint(0, rows, (n_idx,), dtype=torch.int32, device="cuda", generator=g)
+    out = torch.empty((n_idx // 8, W), dtype=torch.float32, device="cuda")
+    best = None
+    for vec, deg in probe.GATHER_SHAPES:
+        if vec > W:
+            continue
+        ms = probe.gather_ms(src, idx, out, deg=deg, vec=vec, iters=iters)
+        if best is None or ms < best[0]:
+            best = (ms, vec, deg)
+    ms, vec, deg = best
+    total = gathered + n_idx * 4 + (n_idx // deg) * W * 4
+    del src, idx, out
+    return gathered / (ms * 1e-3) / 1e9, total / (ms * 1e-3) / 1e9, ms, f"{vec} floats per lane, {deg} rows per output"
+
+
+def pattern_floors(n, m, L, R, copy_gbps):
+    """Floors of the two sparse passes from the probes: each pass's gathered
+    bytes (L R 4: one row of the gathered array per literal, all restarts) at
+    the gather probe's rate for that array's row size and footprint, plus its
+    streamed bytes at the copy rate.  Rows are 4 min(R, 32) bytes (a restart
+    group of up to 32 restarts; 4 bytes at one restart)."""
+    rp = 1
+    while rp < R and rp < 32:
+        rp *= 2
+    rb = 4 * rp
+    gathered = 4.0 * L * R
+    out = {}
+    # forward: gathers t ([n + 1][R]); streams the literal entries and writes the adjoint
+    # backward: gathers the adjoint ([m][R]); streams the occurrence entries, x, m, v (read and
+    # write) and writes t
+    for name, foot, streamed in (("fwd", 4 * (n + 1) * R, 4 * L + 4 * (m + 1) + 4 * m * R),
+                                 ("bwd", 4 * m * R, 4 * L + 4 * (n + 1) + 28 * n * R)):
+        gg, _, _, shape = gather_bandwidth(rb, max(foot // rb * rb, rb * 16), iters=10)
+        out[name] = {"gather_row_bytes": rb, "gather_footprint_bytes": foot, "gather_GBps": round(gg, 1),
+                     "gather_shape": shape,
+                     "floor_us": round((gathered / (gg * 1e9) + streamed / (copy_gbps * 1e9)) * 1e6, 3)}
+    return out
+
+
+def probe_table():
+    """Print the copy and gather ceilings (``--probe``)."""
+    print("# bandwidth probes on this GPU (libhipmsat_probe.so, HIP events)\n"
+          "# command: python -u bench.py --probe\n"
+          f"copy 1 GiB: {copy_bandwidth():.0f} GB/s (read + write)\n"
+          "# gather-sum of random rows, best of the probe's shapes: row bytes, footprint MiB, gathered GB/s, "
+          "total GB/s (+ indices and outputs), us per launch, shape", flush=True)
+    for rb, fp in GATHER_POINTS:
+        gg, tt, ms, shape = gather_bandwidth(rb, fp)
+        print(f"gather {rb:4d} {fp >> 20:6d} {gg:8.0f} {tt:8.0f} {ms * 1e3:9.1f}  {shape}", flush=True)
 
 
 def make_workload(name):
@@ -224,7 +299,41 @@ def make_workload(name):
     weights = None
     if name.endswith("-weighted"):
         weights = np.random.default_rng(20).integers(1, 101, size=m).astype(np.int64)
-    return dict(name=name, n=n, m=m, R=R, T=T, K=K, lits=lits, desc=desc, weights=weights)
+    # uniform random clauses: the probes' uniform random rows model their gathers
+    uniform = name.startswith("cfg2") or name in ("cfg1", "cfg4")
+    return dict(name=name, n=n, m=m, R=R, T=T, K=K, lits=lits, desc=desc, weights=weights, uniform=uniform)
+
+
+# the structured workload's schedule: table entry 37 (one lane per row, the
+# unsat bitset, two clause tiles per forward wavefront), 64 rows per unit,
+# which the tuner picks for it (the sweep under profiles/sweeps)
+STRUCTURED_SCHEDULE = 37 | (64 << 8)
+
+
+def structured_record(kernel_iters=100, solves=3):
+    """The largest workload (structured n=500000, m=2.5M, one restart, 200
+    Adam steps, count every 50) timed as the headline is: µs per gradient step
+    over whole solves (HIP events), and the forward and backward (with the
+    heavy-row combine) kernels against the HBM roofline."""
+    import numpy as np
+
+    import paper_2402_03640_amd as hm
+    wl = make_workload("cfg3")
+    cnf = hm.load_cnf(wl["n"], wl["lits"])
+    L = cnf.info["nnz"]
+    kw = dict(steps=wl["T"], restarts=1, eval_every=wl["K"], seed=0, lr=1e-4, schedule=STRUCTURED_SCHEDULE)
+    hm.solve(cnf, **kw)  # warm
+    dev = [hm.solve(cnf, **kw).device_ms for _ in range(solves)]
+    f, b, st = hm.time_kernels(cnf, restarts=1, iters=kernel_iters, lr=1e-4, schedule=STRUCTURED_SCHEDULE)
+    fb, bb = kernel_bytes(wl["n"], wl["m"], L, 1)
+    us = 1e3 * float(np.median(dev)) / wl["T"]
+    cnf.free()
+    return {"workload": wl["desc"], "nnz": int(L), "schedule": STRUCTURED_SCHEDULE,
+            "us_per_grad_step": round(us, 3), "nnz_per_s": 2.0 * L * wl["T"] / (float(np.median(dev)) * 1e-3),
+            "fwd_us": round(f * 1e3, 3), "bwd_with_combine_us": round(b * 1e3, 3),
+            "fwd_frac": round(fb / (f * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "bwd_frac": round(bb / (b * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "algorithmic_bytes": {"fwd": fb, "bwd": bb}}
 
 
 def cpu_baseline(wl, L, max_threads=16, sample_steps=None, min_wall=2.0):
@@ -268,7 +377,9 @@ def host_cpu_model():
 
 def serve_bench(args):
     """Serving workload: Poisson arrivals replayed in real time into the
-    continuous-batching server, then the same instances one at a time."""
+    continuous-batching server (at the workload's 200 req/s and again at 80
+    req/s, below capacity), then the same instances one at a time in arrival
+    order, with the host plan build and the solve timed apart."""
     import numpy as np
     import torch
 
@@ -292,56 +403,80 @@ def serve_bench(args):
     hm.solve(c, **params[0])
     c.free()
     torch.cuda.synchronize()
-    log("[serve] served run ...")
-    srv = Server(workers=args.serve_workers)
-    t0 = time.perf_counter()
-    futs = []
-    for r, lits, p in zip(reqs, data, params):
-        target = t0 + r.arrival_s
-        while True:
-            now = time.perf_counter()
-            if now >= target:
-                break
-            time.sleep(min(target - now, 0.002))
-        futs.append(srv.submit(r.n, lits, arrival=target, **p))
-    res = [f.result() for f in futs]
-    srv.close()
-    first = t0 + reqs[0].arrival_s
-    span = max(x.done for x in res) - first
-    lat = [x.latency for x in res]
+
+    def served(scale):
+        """Replay the arrivals with their times multiplied by `scale`."""
+        srv = Server(workers=args.serve_workers)
+        t0 = time.perf_counter()
+        futs = []
+        for r, lits, p in zip(reqs, data, params):
+            target = t0 + scale * r.arrival_s
+            while True:
+                now = time.perf_counter()
+                if now >= target:
+                    break
+                time.sleep(min(target - now, 0.002))
+            futs.append(srv.submit(r.n, lits, arrival=target, **p))
+        res = [f.result() for f in futs]
+        srv.close()
+        span = max(x.done for x in res) - (t0 + scale * reqs[0].arrival_s)
+        lat = [x.latency for x in res]
+        return res, span, lat
+
+    rate = len(reqs) / reqs[-1].arrival_s
+    log(f"[serve] served run at {rate:.0f} req/s ...")
+    res, span, lat = served(1.0)
     served_ips = len(res) / span
     log(f"[serve] served {len(res)} in {span:.3f} s, p50 {percentile(lat, 50)*1e3:.1f} ms, "
         f"p99 {percentile(lat, 99)*1e3:.1f} ms")
-    log("[serve] plain run (one at a time, arrival order) ...")
+    low = 80.0
+    log(f"[serve] served run at {low:.0f} req/s (arrival times scaled by {rate / low:.2f}) ...")
+    res_lo, span_lo, lat_lo = served(rate / low)
+    log(f"[serve] at {low:.0f} req/s: {len(res_lo) / span_lo:.1f} inst/s, p50 {percentile(lat_lo, 50)*1e3:.1f} ms, "
+        f"p99 {percentile(lat_lo, 99)*1e3:.1f} ms")
+    log("[serve] plain run (one at a time, arrival order; plan build and solve timed apart) ...")
     t1 = time.perf_counter()
     plain = []
-    plain_lat = []
+    build_s, solve_s, threads = [], [], 1
     for r, lits, p in zip(reqs, data, params):
         a = time.perf_counter()
         c = hm.load_cnf(r.n, lits)
+        b = time.perf_counter()
+        threads = max(threads, c.info["plan_threads"])
         plain.append(hm.solve(c, **p))
+        e = time.perf_counter()
         c.free()
-        plain_lat.append(time.perf_counter() - a)
+        build_s.append(b - a)
+        solve_s.append(e - b)
     plain_span = time.perf_counter() - t1
     plain_ips = len(plain) / plain_span
+    dev_ips = len(plain) / sum(solve_s)
     same = all(int(a.best_cost) == int(b.output.best_cost) and
                np.array_equal(a.best_assignment, b.output.best_assignment) for a, b in zip(plain, res))
-    log(f"[serve] plain {plain_span:.3f} s ({plain_ips:.1f} inst/s); results identical: {same}")
+    same_lo = all(int(a.best_cost) == int(b.output.best_cost) and
+                  np.array_equal(a.best_assignment, b.output.best_assignment) for a, b in zip(plain, res_lo))
+    log(f"[serve] plain {plain_span:.3f} s ({plain_ips:.1f} inst/s): plan builds {sum(build_s):.3f} s, "
+        f"solves {sum(solve_s):.3f} s ({dev_ips:.1f} inst/s without the builds); results identical: {same}, {same_lo}")
     out = {
         "metric": "instances/s (served, continuous batching)",
         "value": served_ips, "unit": "instances/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": 1e3 * span, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{len(reqs)} random k-CNF requests (k in 3..5, n log-uniform "
-                               f"100..200000, m = n U(3.5,5) 2^k/8), Poisson 200/s, {T} Adam steps, "
+                               f"100..200000, m = n U(3.5,5) 2^k/8), Poisson {rate:.0f}/s, {T} Adam steps, "
                                f"eval every 50", "total_literals": L_tot,
-                   "workers": args.serve_workers},
+                   "workers": args.serve_workers, "plain_plan_threads": threads},
         "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99),
                        "max": 1e3 * max(lat)},
-        "plain": {"instances_per_s": plain_ips, "p50_solve_ms": 1e3 * percentile(plain_lat, 50),
-                  "total_s": plain_span},
+        "below_capacity": {"offered_req_per_s": low, "instances_per_s": len(res_lo) / span_lo,
+                           "latency_ms": {"p50": 1e3 * percentile(lat_lo, 50), "p99": 1e3 * percentile(lat_lo, 99),
+                                          "max": 1e3 * max(lat_lo)}},
+        "plain": {"instances_per_s": plain_ips, "p50_solve_ms": 1e3 * percentile(solve_s, 50),
+                  "total_s": plain_span, "plan_build_s": sum(build_s), "solve_s": sum(solve_s),
+                  "device_only_instances_per_s": dev_ips},
         "speedup_vs_plain": served_ips / plain_ips,
-        "equal_cost": bool(same),
+        "speedup_vs_plain_device_only": served_ips / dev_ips,
+        "equal_cost": bool(same and same_lo),
         "fwd_bwd_nnz_per_s_served": 2.0 * L_tot * T / span,
     }
     print(json.dumps(out), flush=True)
@@ -355,6 +490,8 @@ def main():
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-structured", action="store_true",
+                    help="leave out the structured-workload record of the default line")
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -366,6 +503,7 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only time the forward/backward kernels (for counter runs), after a "
                          "256 MiB device copy used to calibrate the byte counters")
+    ap.add_argument("--probe", action="store_true", help="print the copy and gather bandwidth ceilings and exit")
     args = ap.parse_args()
     if args.counters_summary is not None:
         counters_summary(args.counters_summary)
@@ -382,6 +520,9 @@ def main():
     import paper_2402_03640_amd as hm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.probe:
+        probe_table()
+        return
     if args.config == "serve":
         serve_bench(args)
         return
@@ -405,17 +546,21 @@ def main():
         log(f"[bench] tuned schedule {code} ({tms * 1e3:.2f} us per step)")
     kw = dict(steps=T, restarts=R, eval_every=K, seed=0, lr=1e-4, schedule=code)
     if args.kernels_only:
-        src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device="cuda")
+        from paper_2402_03640_amd import probe
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        src.fill_(1.0)
         torch.cuda.synchronize()
-        dst.copy_(src)  # calibration: 256 MiB read, 256 MiB written
+        probe.copy_ms(src, dst, 1)  # calibration: each launch reads 256 MiB and writes 256 MiB
+        # a second point: 512 MiB of random 128-byte rows from a 4 GiB array
+        # (about 94% of them distinct lines), plus 16 MiB of indices, per launch
+        gather_bandwidth(128, 4 << 30, iters=1)
         torch.cuda.synchronize()
         f, b, st = hm.time_kernels(cnf, restarts=R, iters=args.kernel_iters, lr=1e-4, schedule=code)
         fb, bb = kernel_bytes(n, m, L, R, wl['weights'] is not None)
         print(json.dumps({"config": wl["name"], "schedule": code, "fwd_us": f * 1e3, "bwd_us": b * 1e3,
                           "step_us": st * 1e3, "fwd_bytes": fb, "bwd_bytes": bb,
-                          "kernel_iters": args.kernel_iters, "calibration_copy_bytes": 2 * 4 * src.numel()}),
+                          "kernel_iters": args.kernel_iters,
+                          "calibration_copy_bytes": 2 * 4 * src.numel()}),
               flush=True)
         return
     for i in range(args.warmup):
@@ -462,9 +607,15 @@ def main():
                                  "achieved_GBps": round(obytes / (oms * 1e-3) / 1e9, 1)}}
     step_bytes = fb + bb
     copy_gbps = copy_bandwidth()
-    log(f"[bench] device copy: {copy_gbps:.0f} GB/s (read + write)")
+    log(f"[bench] device copy (project kernel): {copy_gbps:.0f} GB/s (read + write)")
+    floors = None
     if roof is not None:
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbps, 4)
+        if wl["uniform"]:
+            floors = pattern_floors(n, m, L, R, copy_gbps)
+            roof["pattern_floor_us"] = floors[key]["floor_us"]
+            roof["frac_of_pattern_floor"] = round(floors[key]["floor_us"] / roof["avg_launch_us"], 4)
+            log(f"[bench] pattern floors: {floors}")
     out = {
         "metric": "fwd+bwd literal nnz/s",
         "value": value,
@@ -483,11 +634,17 @@ def main():
         "roofline": roof,
         "effective_GBps_per_step": round(step_bytes / (step_ms * 1e-3) / 1e9, 1),
         "copy_GBps": round(copy_gbps, 1),
+        "ceilings": {"copy_GBps": round(copy_gbps, 1), "copy_kernel": "project streaming copy (probe library)",
+                     "pattern_floors": floors},
         "device_ms_per_solve": round(float(np.median(dev_ms)), 3),
         "us_per_grad_step": round(1e3 * float(np.median(dev_ms)) / max(T, 1), 3),
         "best_cost": int(min(best)),
         "load_s": round(load_s, 4),
     }
+    if args.config == "cfg2" and not args.no_structured:
+        log("[bench] the structured workload (n=500000, m=2.5M) ...")
+        out["structured"] = structured_record()
+        log(f"[bench] structured: {out['structured']}")
     if not args.no_cpu:
         log("[bench] timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(wl, L)

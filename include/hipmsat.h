@@ -70,6 +70,10 @@ typedef struct {
     int64_t state_bytes_r1; /* device bytes of solver state per restart */
     int32_t weighted;       /* 1 if the clauses carry weights */
     int64_t total_weight;   /* total clause weight (n_clauses without weights) */
+    int32_t plan_threads;   /* host threads the plan build used: the host's hardware threads (at most
+                               16) shared by the loads running at once, at most one per 2^16 literals,
+                               or the count the HIPMSAT_PLAN_THREADS variable sets (shared the same
+                               way); the plan does not depend on it */
 } hms_cnf_info;
 
 /*

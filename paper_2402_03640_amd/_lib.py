@@ -42,7 +42,8 @@ class CnfInfo(C.Structure):
     _fields_ = [("n_vars", C.c_int32), ("n_clauses", C.c_int32), ("n_lits", C.c_int64),
                 ("nnz", C.c_int64), ("n_empty", C.c_int32), ("n_taut", C.c_int32),
                 ("n_active", C.c_int32), ("n_heavy", C.c_int32), ("struct_bytes", C.c_int64),
-                ("state_bytes_r1", C.c_int64), ("weighted", C.c_int32), ("total_weight", C.c_int64)]
+                ("state_bytes_r1", C.c_int64), ("weighted", C.c_int32), ("total_weight", C.c_int64),
+                ("plan_threads", C.c_int32)]
 
 
 class SolveState(C.Structure):

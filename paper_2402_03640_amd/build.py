@@ -1,4 +1,5 @@
-"""Build the HIP library ``libhipmsat.so`` in-tree for gfx950.
+"""Build the HIP library ``libhipmsat.so`` (and the bandwidth probes,
+``libhipmsat_probe.so``) in-tree for gfx950.
 
 Host plan code is compiled with g++, the kernels and the C ABI with hipcc
 (cross-compiles without a GPU).  ``python -m paper_2402_03640_amd.build``.
@@ -15,6 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INC = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libhipmsat.so")
+PROBE_OUT = os.path.join(PKG, "libhipmsat_probe.so")
 BUILD = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -64,6 +66,8 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
         [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "small.hip"), "-o",
                                os.path.join(BUILD, "small.o")],
     ]
+    if not sanitize:
+        jobs.append([HIPCC] + HIP_FLAGS + ["-shared", os.path.join(CSRC, "probe.hip"), "-o", PROBE_OUT + ".tmp"])
     with ThreadPoolExecutor(4) as ex:
         outs = list(ex.map(_run, jobs))
     tmp = out + ".tmp"
@@ -75,6 +79,8 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
                       os.path.join(bdir, "plan.o"), os.path.join(BUILD, "kernels.o"),
                       os.path.join(BUILD, "hipmsat.o"), os.path.join(BUILD, "small.o")] + san_link))
     os.replace(tmp, out)
+    if not sanitize:
+        os.replace(PROBE_OUT + ".tmp", PROBE_OUT)
     if verbose:
         for o in outs:
             if o.strip():

@@ -533,6 +533,7 @@ hms_status hms_cnf_info_get(const hms_cnf* cnf, hms_cnf_info* out) {
     out->state_bytes_r1 = (int64_t)(P.n + 1) * 16 + P.n + (int64_t)P.a_rows() * 4 + (int64_t)P.seg_rows * 8;
     out->weighted = P.weighted ? 1 : 0;
     out->total_weight = P.w_total;
+    out->plan_threads = P.build_threads;
     return HMS_OK;
 }
 

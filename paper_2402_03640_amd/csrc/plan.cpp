@@ -26,11 +26,16 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cerrno>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <numeric>
+#include <thread>
+#include <utility>
 
 namespace hms {
 
@@ -44,51 +49,188 @@ struct Row {
     bool taut;
 };
 
-// Lay out rows (already ordered) into 64-row column-major tiles.
+// ---- host threads ---------------------------------------------------------
+// A build uses the host's hardware threads (at most 16), shared by the builds
+// running at once, and one thread per 2^16 literals at most; the variable
+// HIPMSAT_PLAN_THREADS sets the count instead (shared the same way, with no
+// size rule).  Every phase gives the same plan whatever the thread count:
+// each is a fixed function of the instance.
+std::atomic<int> g_active_builds{0};
+
+struct BuildSlot {
+    int threads;
+    explicit BuildSlot(int64_t nlits) {
+        const int active = g_active_builds.fetch_add(1) + 1;
+        const char* e = std::getenv("HIPMSAT_PLAN_THREADS");
+        const int set = (e && *e) ? std::min(std::atoi(e), 64) : 0;
+        if (set > 0) {
+            threads = std::max(1, set / active);
+        } else {
+            const int cap = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+            const int64_t by_size = std::max<int64_t>(1, nlits >> 16);
+            threads = (int)std::max<int64_t>(1, std::min<int64_t>(cap / active, by_size));
+        }
+    }
+    ~BuildSlot() { g_active_builds.fetch_sub(1); }
+};
+
+// Runs fn(t) for t = 0..T-1, thread 0 on the caller; an exception in any
+// part is rethrown here after all have joined.
+template <typename F>
+void par(int T, const F& fn) {
+    if (T <= 1) {
+        fn(0);
+        return;
+    }
+    std::vector<std::exception_ptr> ex((size_t)T);
+    auto run = [&](int t) {
+        try {
+            fn(t);
+        } catch (...) {
+            ex[(size_t)t] = std::current_exception();
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve((size_t)T - 1);
+    try {
+        for (int t = 1; t < T; ++t) th.emplace_back(run, t);
+    } catch (...) {
+        // could not start every thread: run the rest here
+        for (int t = (int)th.size() + 1; t < T; ++t) run(t);
+    }
+    run(0);
+    for (auto& x : th) x.join();
+    for (auto& e : ex)
+        if (e) std::rethrow_exception(e);
+}
+
+// Part t of T of [0, n): [lo, hi).
+inline int64_t part_lo(int64_t n, int t, int T) { return (int64_t)((__int128)n * t / T); }
+
+// Lay out rows (already ordered) into 64-row column-major tiles appended to
+// tiles / ent; tiles fill in parallel at bases fixed beforehand.
 template <typename LenFn, typename EntFn>
-int32_t tile_rows(int32_t nrows, LenFn len_of, EntFn ent_of,
-                  uint32_t pad, uint32_t flags, std::vector<TileDesc>& tiles,
-                  std::vector<uint32_t>& ent, std::string& err) {
-    {
-        // room for every tile up front (no regrowth)
-        uint64_t total = ent.size();
-        for (int32_t t0 = 0; t0 < nrows; t0 += kTile) {
+int32_t tile_rows(int T, int32_t nrows, LenFn len_of, EntFn ent_of, uint32_t pad, uint32_t flags,
+                  std::vector<TileDesc>& tiles, std::vector<uint32_t>& ent, std::string& err) {
+    const int32_t nt = (nrows + kTile - 1) / kTile;
+    std::vector<uint32_t> tlen((size_t)nt, 0);
+    par(T, [&](int t) {
+        for (int64_t k = part_lo(nt, t, T); k < part_lo(nt, t + 1, T); ++k) {
             uint32_t len = 0;
-            for (int32_t q = t0; q < std::min<int32_t>(nrows, t0 + kTile); ++q)
-                len = std::max<uint32_t>(len, (uint32_t)len_of(q));
-            total += (uint64_t)len * kTile;
+            const int32_t r1 = std::min<int32_t>(nrows, (int32_t)k * kTile + kTile);
+            for (int32_t r = (int32_t)k * kTile; r < r1; ++r) len = std::max<uint32_t>(len, (uint32_t)len_of(r));
+            tlen[(size_t)k] = len;
         }
-        if (total > 0xffffffffull) {
+    });
+    const size_t t0 = tiles.size();
+    uint64_t base = ent.size();
+    tiles.reserve(t0 + (size_t)nt);
+    for (int32_t k = 0; k < nt; ++k) {
+        if (base + (uint64_t)tlen[(size_t)k] * kTile > 0xffffffffull) {
             err = "instance too large: more than 2^32 padded entries";
             return kErrTooLarge;
         }
-        ent.reserve(total);
-        tiles.reserve(tiles.size() + (nrows + kTile - 1) / kTile);
+        tiles.push_back(TileDesc{(uint32_t)base, tlen[(size_t)k],
+                                 (uint32_t)std::min<int32_t>(kTile, nrows - k * kTile), flags});
+        base += (uint64_t)tlen[(size_t)k] * kTile;
     }
-    for (int32_t t0 = 0; t0 < nrows; t0 += kTile) {
-        int32_t nreal = std::min<int32_t>(kTile, nrows - t0);
-        uint32_t len = 0;
-        for (int32_t q = 0; q < nreal; ++q) len = std::max<uint32_t>(len, (uint32_t)len_of(t0 + q));
-        uint64_t base = ent.size();
-        if (base + (uint64_t)len * kTile > 0xffffffffull) {
-            err = "instance too large: more than 2^32 padded entries";
-            return kErrTooLarge;
+    ent.resize((size_t)base, pad);
+    par(T, [&](int t) {
+        for (int64_t k = part_lo(nt, t, T); k < part_lo(nt, t + 1, T); ++k) {
+            const TileDesc& d = tiles[t0 + (size_t)k];
+            for (uint32_t q = 0; q < d.nreal; ++q) {
+                const int32_t r = (int32_t)k * kTile + (int32_t)q;
+                const int32_t L = len_of(r);
+                for (int32_t c = 0; c < L; ++c) ent[d.base + (size_t)c * kTile + q] = ent_of(r, c);
+            }
         }
-        TileDesc d{(uint32_t)base, len, (uint32_t)nreal, flags};
-        tiles.push_back(d);
-        ent.resize(base + (size_t)len * kTile, pad);
-        for (int32_t q = 0; q < nreal; ++q) {
-            int32_t L = len_of(t0 + q);
-            for (int32_t c = 0; c < L; ++c) ent[base + (size_t)c * kTile + q] = ent_of(t0 + q, c);
-        }
-    }
+    });
     return kOk;
 }
 
-}  // namespace
+// Canonical entries of the clauses in lits[b0, b1) (whole clauses), numbered
+// from j0: a variable is emitted at its first appearance with its sign,
+// unless it also appears negated (then the clause is a tautology).
+struct Chunk {
+    std::vector<uint32_t> flat;  // original variable | sign
+    std::vector<Row> rows;       // off into this chunk's flat
+    int32_t m_empty = 0, m_taut = 0, m_taut_dropped = 0;
+    int64_t w_empty = 0;
+};
 
-int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t* weights, HostPlan& P,
-                   std::string& err) {
+void canonical_chunk(const int32_t* lits, int64_t b0, int64_t b1, int32_t j0, const int64_t* weights, Chunk& C) {
+    constexpr int kShort = 16;  // clauses up to this length are deduplicated in registers
+    std::vector<uint64_t> key;  // longer ones: (variable, position) sorted
+    std::vector<uint64_t> emit; // (position, entry) of the emitted literals
+    int64_t start = b0;
+    int32_t j = j0;
+    for (int64_t p = b0; p < b1; ++p) {
+        if (lits[p] != 0) continue;
+        const int k64 = (int)std::min<int64_t>(p - start, INT32_MAX);
+        const int64_t off = (int64_t)C.flat.size();
+        bool taut = false;
+        if (p - start <= kShort) {
+            // pairwise comparison
+            const int k = k64;
+            int32_t v[kShort];
+            uint8_t sg[kShort];
+            for (int q = 0; q < k; ++q) {
+                v[q] = std::abs(lits[start + q]) - 1;
+                sg[q] = lits[start + q] > 0 ? 1 : 2;
+            }
+            for (int q = 0; q < k; ++q) {
+                bool first = true;
+                uint8_t both = sg[q];
+                for (int u = 0; u < k; ++u) {
+                    if (v[u] != v[q]) continue;
+                    if (u < q) first = false;
+                    both |= sg[u];
+                }
+                if (!first) continue;
+                if (both == 3) {
+                    taut = true;
+                    continue;
+                }
+                C.flat.push_back((uint32_t)v[q] | ((both & 2) ? kSign : 0u));
+            }
+        } else {
+            // the same rule through a sort by (variable, position)
+            const int64_t k = p - start;
+            key.resize((size_t)k);
+            for (int64_t q = 0; q < k; ++q) key[(size_t)q] = ((uint64_t)(std::abs(lits[start + q]) - 1) << 32) | (uint64_t)q;
+            std::sort(key.begin(), key.end());
+            emit.clear();
+            for (int64_t g = 0; g < k;) {
+                const uint32_t v = (uint32_t)(key[(size_t)g] >> 32);
+                int64_t h = g;
+                uint8_t both = 0;
+                while (h < k && (uint32_t)(key[(size_t)h] >> 32) == v) {
+                    both |= lits[start + (int64_t)(uint32_t)key[(size_t)h]] > 0 ? 1 : 2;
+                    ++h;
+                }
+                if (both == 3) taut = true;
+                else emit.push_back((key[(size_t)g] << 32) | (v | ((both & 2) ? kSign : 0u)));  // first position
+                g = h;
+            }
+            std::sort(emit.begin(), emit.end());  // by position
+            for (uint64_t e : emit) C.flat.push_back((uint32_t)e);
+        }
+        const int32_t len = (int32_t)((int64_t)C.flat.size() - off);
+        if (p == start) {
+            C.m_empty++;
+            C.w_empty += weights ? weights[j] : 1;
+        } else if (taut) {
+            C.m_taut++;
+            if (len == 0) C.m_taut_dropped++;
+        }
+        if (len > 0) C.rows.push_back(Row{off, len, j, 0, taut});
+        ++j;
+        start = p + 1;
+    }
+}
+
+int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int64_t* weights, HostPlan& P,
+                        std::string& err) {
     P = HostPlan{};
     if (n < 0 || nlits < 0 || (nlits > 0 && lits == nullptr)) {
         err = "bad arguments: n_vars < 0, n_lits < 0 or null literal array";
@@ -102,20 +244,47 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
         err = "last clause is not terminated by 0";
         return kErrParse;
     }
-    int64_t m = 0;
-    for (int64_t p = 0; p < nlits; ++p) {
-        int32_t l = lits[p];
-        if (l == 0) {
-            ++m;
-            continue;
+    BuildSlot slot(nlits);
+    const int T = slot.threads;
+
+    // ---- chunks of whole clauses; checks and counts per chunk ---------------
+    std::vector<int64_t> cb((size_t)T + 1, nlits);
+    cb[0] = 0;
+    for (int t = 1; t < T; ++t) {
+        int64_t q = std::max(cb[(size_t)t - 1], part_lo(nlits, t, T));
+        while (q < nlits && q > 0 && lits[q - 1] != 0) ++q;  // the next clause start
+        cb[(size_t)t] = q;
+    }
+    std::vector<int64_t> zeros((size_t)T, 0), nonzero((size_t)T, 0), bad((size_t)T, -1);
+    par(T, [&](int t) {
+        for (int64_t p = cb[(size_t)t]; p < cb[(size_t)t + 1]; ++p) {
+            const int32_t l = lits[p];
+            if (l == 0) {
+                zeros[(size_t)t]++;
+                continue;
+            }
+            if (l == INT32_MIN || std::abs(l) > n) {
+                bad[(size_t)t] = p;  // the first one of the chunk
+                return;
+            }
+            nonzero[(size_t)t]++;
         }
-        if (l == INT32_MIN || std::abs(l) > n) {
+    });
+    for (int t = 0; t < T; ++t)
+        if (bad[(size_t)t] >= 0) {
+            const int64_t p = bad[(size_t)t];
             char buf[128];
-            snprintf(buf, sizeof buf, "literal %d at position %lld is outside 1..%d", l, (long long)p, n);
+            snprintf(buf, sizeof buf, "literal %d at position %lld is outside 1..%d", lits[p], (long long)p, n);
             err = buf;
             return kErrRange;
         }
-        P.lits_in++;
+    int64_t m = 0;
+    std::vector<int32_t> j0((size_t)T, 0);
+    for (int t = 0; t < T; ++t) {
+        if (m >= (int64_t)kIdx) break;
+        j0[(size_t)t] = (int32_t)m;
+        m += zeros[(size_t)t];
+        P.lits_in += nonzero[(size_t)t];
     }
     if (m >= (int64_t)kIdx) {
         err = "too many clauses";
@@ -138,93 +307,55 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
     }
 
     // ---- canonical clauses: W entries in order of first appearance --------
-    std::vector<uint32_t> flat;          // original variable | sign
-    flat.reserve((size_t)P.lits_in);
+    std::vector<uint32_t> flat;  // original variable | sign, then new variable | sign
     std::vector<Row> rows;
-    rows.reserve((size_t)m);
-    std::vector<int64_t> stamp((size_t)n + 1, -1);
-    std::vector<uint8_t> seen((size_t)n + 1, 0);   // bit0 positive, bit1 negative, bit2 emitted
-    int64_t start = 0;
-    int32_t j = 0;
-    constexpr int kShort = 16;  // clauses up to this length are deduplicated in registers
-    for (int64_t p = 0; p < nlits; ++p) {
-        if (lits[p] != 0) continue;
-        bool taut = false;
-        if (p - start <= kShort) {
-            // the same rule by pairwise comparison: a variable is emitted at its
-            // first appearance with its sign, unless it also appears negated
-            const int k = (int)(p - start);
-            int32_t v[kShort];
-            uint8_t sg[kShort];
-            for (int q = 0; q < k; ++q) {
-                v[q] = std::abs(lits[start + q]) - 1;
-                sg[q] = lits[start + q] > 0 ? 1 : 2;
-            }
-            const int64_t off = (int64_t)flat.size();
-            for (int q = 0; q < k; ++q) {
-                bool first = true;
-                uint8_t both = sg[q];
-                for (int u = 0; u < k; ++u) {
-                    if (v[u] != v[q]) continue;
-                    if (u < q) first = false;
-                    both |= sg[u];
-                }
-                if (!first) continue;
-                if (both == 3) {
-                    taut = true;
-                    continue;
-                }
-                flat.push_back((uint32_t)v[q] | ((both & 2) ? kSign : 0u));
-            }
-            const int32_t len = (int32_t)((int64_t)flat.size() - off);
-            if (p == start) {
-                P.m_empty++;
-                P.w_empty += weights ? weights[j] : 1;
-            } else if (taut) {
-                P.m_taut++;
-                if (len == 0) P.m_taut_dropped++;
-            }
-            if (len > 0) rows.push_back(Row{off, len, j, 0, taut});
-            ++j;
-            start = p + 1;
-            continue;
+    {
+        std::vector<Chunk> ch((size_t)T);
+        par(T, [&](int t) { canonical_chunk(lits, cb[(size_t)t], cb[(size_t)t + 1], j0[(size_t)t], weights, ch[(size_t)t]); });
+        std::vector<int64_t> foff((size_t)T + 1, 0), roff((size_t)T + 1, 0);
+        for (int t = 0; t < T; ++t) {
+            const Chunk& c = ch[(size_t)t];
+            foff[(size_t)t + 1] = foff[(size_t)t] + (int64_t)c.flat.size();
+            roff[(size_t)t + 1] = roff[(size_t)t] + (int64_t)c.rows.size();
+            P.m_empty += c.m_empty;
+            P.m_taut += c.m_taut;
+            P.m_taut_dropped += c.m_taut_dropped;
+            P.w_empty += c.w_empty;
         }
-        for (int64_t q = start; q < p; ++q) {
-            int32_t v = std::abs(lits[q]) - 1;
-            if (stamp[v] != j) {
-                stamp[v] = j;
-                seen[v] = 0;
+        flat.resize((size_t)foff[(size_t)T]);
+        rows.resize((size_t)roff[(size_t)T]);
+        par(T, [&](int t) {
+            Chunk& c = ch[(size_t)t];
+            if (!c.flat.empty()) std::memcpy(&flat[(size_t)foff[(size_t)t]], c.flat.data(), c.flat.size() * 4);
+            for (size_t i = 0; i < c.rows.size(); ++i) {
+                Row r = c.rows[i];
+                r.off += foff[(size_t)t];
+                rows[(size_t)roff[(size_t)t] + i] = r;
             }
-            seen[v] |= lits[q] > 0 ? 1 : 2;
-        }
-        int64_t off = (int64_t)flat.size();
-        for (int64_t q = start; q < p; ++q) {
-            int32_t v = std::abs(lits[q]) - 1;
-            if (seen[v] & 4) continue;
-            seen[v] |= 4;
-            if ((seen[v] & 3) == 3) {
-                taut = true;
-                continue;
-            }
-            flat.push_back((uint32_t)v | ((seen[v] & 2) ? kSign : 0u));
-        }
-        int32_t len = (int32_t)((int64_t)flat.size() - off);
-        if (p == start) {
-            P.m_empty++;
-            P.w_empty += weights ? weights[j] : 1;
-        } else if (taut) {
-            P.m_taut++;
-            if (len == 0) P.m_taut_dropped++;
-        }
-        if (len > 0) rows.push_back(Row{off, len, j, 0, taut});
-        ++j;
-        start = p + 1;
+            std::vector<uint32_t>().swap(c.flat);
+        });
     }
     P.nnz = (int64_t)flat.size();
 
     // ---- variable order: degree descending, ties by original index -------
     std::vector<int32_t> deg_orig((size_t)n, 0);
-    for (uint32_t e : flat) deg_orig[e & kIdx]++;
+    if ((int64_t)T * n <= ((int64_t)1 << 26) && T > 1) {
+        // per-thread histograms, then a sum over variable ranges
+        std::vector<std::vector<int32_t>> h((size_t)T);
+        par(T, [&](int t) {
+            h[(size_t)t].assign((size_t)n, 0);
+            for (int64_t e = part_lo(P.nnz, t, T); e < part_lo(P.nnz, t + 1, T); ++e) h[(size_t)t][flat[(size_t)e] & kIdx]++;
+        });
+        par(T, [&](int t) {
+            for (int64_t i = part_lo(n, t, T); i < part_lo(n, t + 1, T); ++i) {
+                int32_t d = 0;
+                for (int u = 0; u < T; ++u) d += h[(size_t)u][(size_t)i];
+                deg_orig[(size_t)i] = d;
+            }
+        });
+    } else {
+        for (uint32_t e : flat) deg_orig[e & kIdx]++;
+    }
     // counting sort: degree descending, ties by original index (stable)
     {
         int32_t maxd = 0;
@@ -251,57 +382,84 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
     const int32_t maxd = n > 0 ? P.degree[0] : 0;
     P.split_len = ((int64_t)n_long * 4 >= (int64_t)P.n_act && n_long > 0 && maxd <= kSplitDense) ? maxd : kSeg;
     while (P.n_heavy < n && P.degree[P.n_heavy] > P.split_len) ++P.n_heavy;
-    // from here on the flat entries hold the new variable index
-    for (uint32_t& e : flat) e = (uint32_t)P.var_new[e & kIdx] | (e & kSign);
+    // from here on the flat entries hold the new variable index, and each row
+    // knows its smallest one
+    const int64_t nr = (int64_t)rows.size();
+    par(T, [&](int t) {
+        for (int64_t e = part_lo(P.nnz, t, T); e < part_lo(P.nnz, t + 1, T); ++e)
+            flat[(size_t)e] = (uint32_t)P.var_new[flat[(size_t)e] & kIdx] | (flat[(size_t)e] & kSign);
+    });
+    par(T, [&](int t) {
+        for (int64_t i = part_lo(nr, t, T); i < part_lo(nr, t + 1, T); ++i) {
+            Row& r = rows[(size_t)i];
+            int32_t mv = INT32_MAX;
+            for (int32_t c = 0; c < r.len; ++c) mv = std::min(mv, (int32_t)(flat[(size_t)r.off + c] & kIdx));
+            r.minvar = mv;
+        }
+    });
 
     // ---- clause rows: plain rows by length desc, then tautological rows; ---
     // within a length, by the smallest (hottest) new variable index, so that
     // the clauses of a frequent variable sit together and its transposed row
-    // reads neighbouring adjoint entries.
-    for (Row& r : rows) {
-        int32_t mv = INT32_MAX;
-        for (int32_t c = 0; c < r.len; ++c) mv = std::min(mv, (int32_t)(flat[r.off + c] & kIdx));
-        r.minvar = mv;
-    }
-    // stable two-pass counting sort of row indices: by smallest variable,
-    // then by (tautology flag, length descending); then the rows and their
-    // entries are gathered into that order once, so every later pass reads
-    // them sequentially
+    // reads neighbouring adjoint entries; ties keep the clause order.  A
+    // stable sort on (length class, smallest variable), in sorted runs per
+    // thread merged pairwise (each merge stable), then the rows and their
+    // entries are gathered into that order once.
     {
-        const size_t nr = rows.size();
         int32_t maxl = 0;
         for (const Row& r : rows) maxl = std::max(maxl, r.len);
-        // bucket b: plain rows of length maxl - b for b <= maxl, then tautologies likewise
-        const size_t nb = 2 * ((size_t)maxl + 1);
-        std::vector<uint32_t> bucket_of(nr);
-        std::vector<int64_t> cnt((size_t)n + 2, 0), c2(nb + 1, 0);
-        for (size_t i = 0; i < nr; ++i) {
-            const Row& r = rows[i];
-            bucket_of[i] = (uint32_t)((r.taut ? maxl + 1 : 0) + (maxl - r.len));
-            cnt[(size_t)r.minvar + 1]++;
-            c2[bucket_of[i] + 1]++;
-        }
-        for (int32_t v = 0; v <= n; ++v) cnt[v + 1] += cnt[v];
-        for (size_t b = 0; b < nb; ++b) c2[b + 1] += c2[b];
-        std::vector<int32_t> tmp(nr), ord(nr);
-        for (size_t i = 0; i < nr; ++i) tmp[cnt[rows[i].minvar]++] = (int32_t)i;
-        for (int32_t i : tmp) ord[c2[bucket_of[i]]++] = i;
-        std::vector<Row> sorted(nr);
-        std::vector<uint32_t> flat2(flat.size());
-        int64_t o = 0;
-        constexpr size_t kAhead = 16;  // rows fetched ahead of the copy
-        for (size_t r = 0; r < nr; ++r) {
-            if (r + kAhead < nr) {
-                const Row& f = rows[ord[r + kAhead]];
-                __builtin_prefetch(&f);
-                __builtin_prefetch(&flat[f.off]);
+        std::vector<uint64_t> key((size_t)nr);
+        par(T, [&](int t) {
+            for (int64_t i = part_lo(nr, t, T); i < part_lo(nr, t + 1, T); ++i) {
+                const Row& r = rows[(size_t)i];
+                // class: plain rows of length maxl - c for c <= maxl, then tautologies likewise
+                const uint64_t cls = (uint64_t)((r.taut ? maxl + 1 : 0) + (maxl - r.len));
+                key[(size_t)i] = (cls << 31) | (uint64_t)r.minvar;
             }
-            Row R = rows[ord[r]];
-            std::memcpy(&flat2[o], &flat[R.off], (size_t)R.len * 4);
-            R.off = o;
-            o += R.len;
-            sorted[r] = R;
+        });
+        std::vector<int32_t> ord((size_t)nr), tmp((size_t)nr);
+        std::iota(ord.begin(), ord.end(), 0);
+        auto less = [&](int32_t a, int32_t b) { return key[(size_t)a] < key[(size_t)b]; };
+        par(T, [&](int t) {
+            std::stable_sort(ord.begin() + part_lo(nr, t, T), ord.begin() + part_lo(nr, t + 1, T), less);
+        });
+        for (int w = 1; w < T; w *= 2) {
+            const int pairs = (T + 2 * w - 1) / (2 * w);
+            par(std::min(pairs, T), [&](int q) {
+                for (int g = q; g < pairs; g += std::min(pairs, T)) {
+                    const int64_t a = part_lo(nr, 2 * w * g, T), b = part_lo(nr, std::min(T, 2 * w * g + w), T),
+                                  c = part_lo(nr, std::min(T, 2 * w * g + 2 * w), T);
+                    std::merge(ord.begin() + a, ord.begin() + b, ord.begin() + b, ord.begin() + c, tmp.begin() + a, less);
+                    std::copy(tmp.begin() + a, tmp.begin() + c, ord.begin() + a);
+                }
+            });
         }
+        std::vector<int64_t> psum((size_t)T + 1, 0);
+        par(T, [&](int t) {
+            int64_t s = 0;
+            for (int64_t r = part_lo(nr, t, T); r < part_lo(nr, t + 1, T); ++r) s += rows[(size_t)ord[(size_t)r]].len;
+            psum[(size_t)t + 1] = s;
+        });
+        for (int t = 0; t < T; ++t) psum[(size_t)t + 1] += psum[(size_t)t];
+        std::vector<Row> sorted((size_t)nr);
+        std::vector<uint32_t> flat2(flat.size());
+        par(T, [&](int t) {
+            int64_t o = psum[(size_t)t];
+            constexpr int64_t kAhead = 16;  // rows fetched ahead of the copy
+            const int64_t r1 = part_lo(nr, t + 1, T);
+            for (int64_t r = part_lo(nr, t, T); r < r1; ++r) {
+                if (r + kAhead < r1) {
+                    const Row& f = rows[(size_t)ord[(size_t)(r + kAhead)]];
+                    __builtin_prefetch(&f);
+                    __builtin_prefetch(&flat[(size_t)f.off]);
+                }
+                Row R = rows[(size_t)ord[(size_t)r]];
+                std::memcpy(&flat2[(size_t)o], &flat[(size_t)R.off], (size_t)R.len * 4);
+                R.off = o;
+                o += R.len;
+                sorted[(size_t)r] = R;
+            }
+        });
         rows.swap(sorted);
         flat.swap(flat2);
     }
@@ -310,10 +468,10 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
     int32_t n_tr = (int32_t)rows.size() - n_plain;
     const uint32_t cpad = (uint32_t)n;  // dummy variable whose relaxed value stays -0.0
     int32_t rc;
-    rc = tile_rows(n_plain, [&](int32_t r) { return rows[r].len; },
+    rc = tile_rows(T, n_plain, [&](int32_t r) { return rows[r].len; },
                    [&](int32_t r, int32_t c) { return flat[rows[r].off + c]; }, cpad, 0u, P.c_tile, P.c_ent, err);
     if (rc) return rc;
-    rc = tile_rows(n_tr, [&](int32_t r) { return rows[n_plain + r].len; },
+    rc = tile_rows(T, n_tr, [&](int32_t r) { return rows[n_plain + r].len; },
                    [&](int32_t r, int32_t c) { return flat[rows[n_plain + r].off + c]; }, cpad, 1u, P.c_tile,
                    P.c_ent, err);
     if (rc) return rc;
@@ -327,14 +485,16 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
     std::vector<int32_t> krow(rows.size());
     P.c_row_orig.assign((size_t)P.c_tiles * kTile, -1);
     {
-        int32_t tp = (n_plain + kTile - 1) / kTile;
-        for (int32_t r = 0; r < n_plain; ++r) krow[r] = r;
-        for (int32_t r = 0; r < n_tr; ++r) krow[n_plain + r] = tp * kTile + r;
-        for (size_t r = 0; r < rows.size(); ++r) P.c_row_orig[krow[r]] = rows[r].orig;
-        if (weights) {
-            P.c_w.assign((size_t)P.c_tiles * kTile, 0);
-            for (size_t r = 0; r < rows.size(); ++r) P.c_w[krow[r]] = weights[rows[r].orig];
-        }
+        const int32_t tp = (n_plain + kTile - 1) / kTile;
+        if (weights) P.c_w.assign((size_t)P.c_tiles * kTile, 0);
+        par(T, [&](int t) {
+            for (int64_t r = part_lo(nr, t, T); r < part_lo(nr, t + 1, T); ++r) {
+                const int32_t k = r < n_plain ? (int32_t)r : tp * kTile + (int32_t)(r - n_plain);
+                krow[(size_t)r] = k;
+                P.c_row_orig[(size_t)k] = rows[(size_t)r].orig;
+                if (weights) P.c_w[(size_t)k] = weights[rows[(size_t)r].orig];
+            }
+        });
     }
 
     // ---- variable-major occurrence lists (clause rows ascending) ----------
@@ -342,28 +502,56 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
     for (int32_t i = 0; i < n; ++i) voff[i + 1] = voff[i] + P.degree[i];
     std::vector<uint32_t> occ((size_t)P.nnz);
     {
-        // Two passes, each with few write streams: (1) scatter (variable,
-        // kernel row) pairs into blocks of 1024 consecutive variables, (2)
-        // scatter each block into its variables' lists.  Rows are visited in
-        // increasing kernel-row order and both passes are stable, so every
-        // list ends in increasing kernel-row order.
+        // Two stable scatters with few write streams each: (1) (variable,
+        // kernel row) pairs into blocks of 1024 consecutive variables, each
+        // thread taking a range of rows and writing after the threads before
+        // it, (2) each block into its variables' lists.  Rows are visited in
+        // increasing kernel-row order, so every list ends in increasing
+        // kernel-row order.
         constexpr int kShift = 10;
         const int32_t nblk = (n >> kShift) + 1;
         std::vector<int64_t> bstart((size_t)nblk + 1, 0);
         for (int32_t b = 0; b < nblk; ++b)
             bstart[b + 1] = voff[std::min<int64_t>((int64_t)(b + 1) << kShift, n)];
         std::vector<uint64_t> pairs((size_t)P.nnz);  // variable << 32 | (row | sign)
-        std::vector<int64_t> bfill(bstart.begin(), bstart.end() - 1);
-        for (size_t r = 0; r < rows.size(); ++r) {
-            const Row& R = rows[r];
-            for (int32_t c = 0; c < R.len; ++c) {
-                const uint32_t e = flat[R.off + c];
-                const uint32_t v = e & kIdx;
-                pairs[bfill[v >> kShift]++] = ((uint64_t)v << 32) | (uint32_t)krow[r] | (e & kSign);
+        std::vector<std::vector<int64_t>> cnt((size_t)T);
+        par(T, [&](int t) {
+            cnt[(size_t)t].assign((size_t)nblk, 0);
+            for (int64_t r = part_lo(nr, t, T); r < part_lo(nr, t + 1, T); ++r) {
+                const Row& R = rows[(size_t)r];
+                for (int32_t c = 0; c < R.len; ++c) cnt[(size_t)t][(flat[(size_t)R.off + c] & kIdx) >> kShift]++;
+            }
+        });
+        for (int32_t b = 0; b < nblk; ++b) {
+            int64_t o = bstart[b];
+            for (int t = 0; t < T; ++t) {
+                const int64_t c = cnt[(size_t)t][b];
+                cnt[(size_t)t][b] = o;  // this thread's first slot in block b
+                o += c;
             }
         }
-        std::vector<int64_t> fill(voff.begin(), voff.end() - 1);
-        for (const uint64_t q : pairs) occ[fill[q >> 32]++] = (uint32_t)q;
+        par(T, [&](int t) {
+            std::vector<int64_t>& fill = cnt[(size_t)t];
+            for (int64_t r = part_lo(nr, t, T); r < part_lo(nr, t + 1, T); ++r) {
+                const Row& R = rows[(size_t)r];
+                for (int32_t c = 0; c < R.len; ++c) {
+                    const uint32_t e = flat[(size_t)R.off + c];
+                    const uint32_t v = e & kIdx;
+                    pairs[(size_t)fill[v >> kShift]++] = ((uint64_t)v << 32) | (uint32_t)krow[(size_t)r] | (e & kSign);
+                }
+            }
+        });
+        par(T, [&](int t) {
+            std::vector<int64_t> fill;
+            for (int64_t b = part_lo(nblk, t, T); b < part_lo(nblk, t + 1, T); ++b) {
+                const int64_t v0 = b << kShift, v1 = std::min<int64_t>((b + 1) << kShift, n);
+                fill.assign(voff.begin() + v0, voff.begin() + std::max(v0, v1));
+                for (int64_t p = bstart[(size_t)b]; p < bstart[(size_t)b + 1]; ++p) {
+                    const uint64_t q = pairs[(size_t)p];
+                    occ[(size_t)fill[(size_t)((int64_t)(q >> 32) - v0)]++] = (uint32_t)q;
+                }
+            }
+        });
     }
 
     // ---- segments of heavy variables ---------------------------------------
@@ -387,18 +575,36 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
     P.seg_row.resize((size_t)P.seg_rows);
     std::iota(P.seg_row.begin(), P.seg_row.end(), 0);
     const uint32_t vpad = (uint32_t)P.a_zero_row();
-    rc = tile_rows(P.seg_rows, [&](int32_t r) { return segs[r].len; },
-                   [&](int32_t r, int32_t c) { return occ[segs[r].off + (int64_t)c * segs[r].stride]; }, vpad, 0u, P.v_tile,
-                   P.v_ent, err);
+    rc = tile_rows(T, P.seg_rows, [&](int32_t r) { return segs[r].len; },
+                   [&](int32_t r, int32_t c) { return occ[segs[r].off + (int64_t)c * segs[r].stride]; }, vpad, 0u,
+                   P.v_tile, P.v_ent, err);
     if (rc) return rc;
     P.seg_tiles = (int32_t)P.v_tile.size();
     int32_t n_light = P.n_act - P.n_heavy;
-    rc = tile_rows(n_light, [&](int32_t r) { return P.degree[P.n_heavy + r]; },
+    rc = tile_rows(T, n_light, [&](int32_t r) { return P.degree[P.n_heavy + r]; },
                    [&](int32_t r, int32_t c) { return occ[voff[P.n_heavy + r] + c]; }, vpad, 0u,
                    P.v_tile, P.v_ent, err);
     if (rc) return rc;
     P.v_tiles = (int32_t)P.v_tile.size();
+    P.build_threads = T;
     return kOk;
+}
+
+}  // namespace
+
+int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t* weights, HostPlan& P,
+                   std::string& err) {
+    try {
+        return build_plan_impl(n, lits, nlits, weights, P, err);
+    } catch (const std::bad_alloc&) {
+        P = HostPlan{};
+        err = "host allocation failed while building the plan";
+        return kErrNoMem;
+    } catch (const std::exception& e) {
+        P = HostPlan{};
+        err = std::string("plan build failed: ") + e.what();
+        return kErrNoMem;
+    }
 }
 
 int32_t read_dimacs(const char* path, int32_t& n, std::vector<int32_t>& lits, std::vector<int64_t>& weights,

@@ -61,6 +61,8 @@ struct HostPlan {
     int32_t max_segs = 0;            // most segments of one variable
     int32_t n_heavy_wide = 0;        // heavy variables with more than kWideSegs segments (come first)
 
+    int32_t build_threads = 1;       // host threads the build used (the plan is the same for any count)
+
     std::vector<int32_t> var_old;    // new index -> original (0-based)
     std::vector<int32_t> var_new;    // original -> new index
     std::vector<int32_t> degree;     // by new index

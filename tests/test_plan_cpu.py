@@ -26,6 +26,17 @@ def test_library_exports_every_declared_symbol():
     assert hm.version().startswith("hipmsat")
 
 
+def test_probe_library_exports_every_declared_symbol():
+    from paper_2402_03640_amd import probe
+    header = open(os.path.join(ROOT, "include", "hipmsat_probe.h")).read()
+    declared = set(re.findall(r"\b(hmsp_[a-z_]+)\s*\(", header))
+    assert declared
+    L = probe.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), f"{name} is declared but not exported"
+    assert set(probe.EXPORTS) == declared
+
+
 def _canonical(clauses):
     """Canonical W entries per clause: (var0, sign) in first-appearance order."""
     out, taut = [], []
@@ -174,6 +185,55 @@ def test_plan_random_formulas_property():
         _check_plan(n, cnfgen.from_clauses(clauses))
 
     run()
+
+
+def _plan_arrays(n, lits, threads):
+    os.environ["HIPMSAT_PLAN_THREADS"] = str(threads)
+    try:
+        P = hm.Plan(n, lits)
+    finally:
+        del os.environ["HIPMSAT_PLAN_THREADS"]
+    return {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in vars(P).items()}
+
+
+@pytest.mark.parametrize("threads", [2, 3, 7, 16])
+def test_plan_is_the_same_for_any_thread_count(threads):
+    """The host plan build splits its phases over threads; the plan (every
+    array and counter) is bitwise the one-thread plan, on formulas with
+    tautologies, repeats, empty clauses, clauses past the 16-literal fast path,
+    heavy segmented rows and dense unsplit rows, and with a tiny formula that
+    leaves most threads an empty share."""
+    rng = np.random.default_rng(threads)
+    cases = [(1, cnfgen.from_clauses([[1], [-1, 1]])),
+             (24, cnfgen.from_clauses([[1, -2, 3], [2, 2, -3], [], [1, -1, 4], [-4, 4], [5], [-5, 1, 1, 2],
+                                       list(range(1, 21)) + [-7, 7, 3], [-20, 21, -22], []]))]
+    clauses = []
+    for _ in range(3000):
+        k = int(rng.choice([0, 1, 2, 3, 5, 17, 30], p=[.02, .05, .2, .5, .15, .05, .03]))
+        clauses.append([int(v) * (1 if rng.random() < 0.5 else -1) for v in rng.integers(1, 400, k)])
+    cases.append((400, cnfgen.from_clauses(clauses)))
+    cases.append((3000, cnfgen.structured_cnf(3000, 15000, seed=4)))
+    cases.append((2000, cnfgen.uniform_kcnf(2000, 34000, 5, seed=7)))
+    for n, lits in cases:
+        a, b = _plan_arrays(n, lits, 1), _plan_arrays(n, lits, threads)
+        assert a.keys() == b.keys()
+        for k in a:
+            if isinstance(a[k], np.ndarray):
+                np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+            else:
+                assert a[k] == b[k], k
+    # parse errors name the same first bad literal
+    bad = cnfgen.from_clauses([[1, 2]] * 500 + [[3, 99]] + [[1]] * 500 + [[-98]])
+    msgs = []
+    for th in (1, threads):
+        os.environ["HIPMSAT_PLAN_THREADS"] = str(th)
+        try:
+            with pytest.raises(hm.HipMsatError) as e:
+                hm.Plan(50, bad)
+            msgs.append(str(e.value))
+        finally:
+            del os.environ["HIPMSAT_PLAN_THREADS"]
+    assert msgs[0] == msgs[1] and "literal 99 at position 1501" in msgs[0]
 
 
 def test_tune_candidates():
