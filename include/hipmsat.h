@@ -177,6 +177,14 @@ typedef struct {
                             best so far is kept unless strictly beaten.  Read only. */
 } hms_solve_params;
 
+/* One counted iterate of one restart (the trajectory of hms_solve_result). */
+typedef struct {
+    int32_t step;             /* iteration t of the iterate */
+    int32_t pad;
+    int64_t cost;             /* unsatisfied clauses (their total weight) of its rounding */
+    double loss;              /* the loss at it */
+} hms_trace_point;
+
 typedef struct {
     int64_t best_cost;        /* fewest unsatisfied clauses seen over all restarts */
     int32_t best_restart;     /* restart that found it (lowest index on ties) */
@@ -193,6 +201,12 @@ typedef struct {
     hms_solve_state* state;   /* NULL, or a state whose arrays receive the state after the last
                                  step taken (also on HMS_ERR_CANCELLED and with a time limit), to
                                  pass as a later solve's resume; m and v are written with Adam */
+    hms_trace_point* trace;   /* NULL, or a caller HOST [trace_cap][R] array: the trajectory of the
+                                 solve, one row of R points per counted iterate (t a multiple of K,
+                                 and the last), kept on the device in a ring of trace_cap rows and
+                                 read at the end; it receives the last trace_cap rows, oldest first */
+    int32_t trace_cap;        /* rows of trace (>= 1 when trace is given) */
+    int32_t trace_len;        /* out: rows written (the counts taken, at most trace_cap) */
 } hms_solve_result;
 
 /* Fill *p with the defaults: T = 1000, R = 1, K = 1, Adam lr 1e-4, UNSAT loss,
@@ -212,7 +226,8 @@ void hms_solve_params_default(hms_solve_params* p);
  * With params->resume the loop continues from that state instead: t runs
  * from resume->step to resume->step + T, counting when t % K == 0 and at the
  * last iterate, Adam step t + 1, best_step in that numbering.  With
- * result->state the state after the last step taken is written there.
+ * result->state the state after the last step taken is written there; with
+ * result->trace the (step, cost, loss) of every counted iterate.
  * Errors: HMS_ERR_ARG (also a null array of a given state, x0 beside
  * resume, or resume->step + steps past 2^31 - 1), HMS_ERR_DEVICE,
  * HMS_ERR_NOMEM; HMS_ERR_NONFINITE when the final loss is not finite (the
@@ -242,8 +257,8 @@ hms_status hms_time_kernels(const hms_cnf* cnf, const hms_solve_params* params, 
  * a group is one launch per kernel over all its instances (a work queue of
  * (instance, work unit) items, replayed as a HIP graph), with the schedule of
  * its largest instance.  A group of one, a solve with a time limit or a
- * cancel flag, and a solve that resumes or returns its state run as
- * hms_solve.  All work goes on params[0].stream.  Each result is bitwise the
+ * cancel flag, and a solve that resumes, returns its state or records its
+ * trajectory run as hms_solve.  All work goes on params[0].stream.  Each result is bitwise the
  * one hms_solve gives for that instance alone (restart_loss and final_loss may
  * differ in the last bits when the schedule does).  Returns the first error.
  */

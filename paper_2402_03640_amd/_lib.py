@@ -65,7 +65,12 @@ class SolveResult(C.Structure):
                 ("steps_done", C.c_int32), ("schedule", C.c_int32), ("final_loss", C.c_double),
                 ("best_assignment", C.c_void_p), ("restart_best", C.c_void_p),
                 ("restart_step", C.c_void_p), ("restart_loss", C.c_void_p),
-                ("x_final", C.c_void_p), ("device_ms", C.c_double), ("state", C.c_void_p)]
+                ("x_final", C.c_void_p), ("device_ms", C.c_double), ("state", C.c_void_p),
+                ("trace", C.c_void_p), ("trace_cap", C.c_int32), ("trace_len", C.c_int32)]
+
+
+# hms_trace_point: one counted iterate of one restart
+TRACE_DTYPE = np.dtype([("step", np.int32), ("pad", np.int32), ("cost", np.int64), ("loss", np.float64)])
 
 
 class PlanView(C.Structure):
@@ -288,6 +293,7 @@ class SolveOutput:
     restart_loss: np.ndarray
     x_final: object = field(default=None)
     state: object = field(default=None)
+    trace: object = field(default=None)  # [counts][R] TRACE_DTYPE records, oldest first
 
 
 def _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2, eps, loss_mode,
@@ -364,10 +370,12 @@ def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, s
           eps: float = 1e-8, loss_mode: int = LOSS_UNSAT, schedule: int = 0, use_graph: bool = True,
           time_limit_s: float = 0.0, x0=None, want_x: bool = False, stream=None,
           autotune: bool = True, cancel: CancelFlag | None = None, resume: SolverState | None = None,
-          want_state: bool = False) -> SolveOutput:
+          want_state: bool = False, trace_cap: int = 0) -> SolveOutput:
     """Algorithm 1 over ``restarts`` relaxed points (see ``hms_solve``).
     ``resume`` continues from a ``SolverState``; ``want_state`` returns the
-    state after the last step as ``output.state``."""
+    state after the last step as ``output.state``; ``trace_cap`` > 0 returns
+    the (step, cost, loss) of the last ``trace_cap`` counted iterates of each
+    restart as ``output.trace`` ([counts][R] records of TRACE_DTYPE)."""
     R = int(restarts)
     p = _params(cnf, steps, restarts, eval_every, seed, optimizer, lr, beta1, beta2, eps, loss_mode,
                 schedule, use_graph, time_limit_s, x0, stream, autotune)
@@ -389,6 +397,11 @@ def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, s
         keep.append(rstruct)
         p.resume = C.addressof(rstruct)
     res = SolveResult()
+    trace = None
+    if trace_cap:
+        trace = np.zeros((int(trace_cap), R), dtype=TRACE_DTYPE)
+        res.trace = trace.ctypes.data
+        res.trace_cap = int(trace_cap)
     out_state = None
     if want_state:
         out_state = SolverState.empty(cnf.n, R)
@@ -416,7 +429,8 @@ def solve(cnf: Cnf, steps: int = 1000, restarts: int = 1, eval_every: int = 1, s
     if out_state is not None:
         out_state.step = int(ostruct.step)
     out = SolveOutput(res.best_cost, res.best_restart, res.best_step, res.steps_done, res.schedule,
-                      res.final_loss, res.device_ms, ba[:cnf.n].copy(), rb, rs, rl, xf, out_state)
+                      res.final_loss, res.device_ms, ba[:cnf.n].copy(), rb, rs, rl, xf, out_state,
+                      None if trace is None else trace[:res.trace_len].copy())
     if rc in (-6, -7):  # non-finite loss or cancelled: the result holds the best so far
         err = HipMsatError(rc, lib().hms_last_error().decode())
         err.result = out

@@ -582,8 +582,37 @@ hms_status check_state(const hms_cnf* cnf, const hms_solve_params* p, const hms_
     return HMS_OK;
 }
 
+static_assert(sizeof(hms::TracePoint) == sizeof(hms_trace_point), "trace record layout");
+
+// Rows of a solve's trajectory: one per count, at t % K == 0 for t in
+// [s0, t_end) and at t_end, the count at t in row ceil(t / K) - ceil(s0 / K).
+int64_t trace_rows(int32_t s0, int32_t t_end, int32_t K) {
+    return ((int64_t)t_end + K - 1) / K - ((int64_t)s0 + K - 1) / K + 1;
+}
+
+// Copy a device trajectory ring into res->trace, oldest row first
+// (synchronises s).
+hms_status read_trace(const hms::TracePoint* ring, int32_t R, int32_t K, int32_t s0, int32_t t_end, hipStream_t s,
+                      hms_solve_result* res) {
+    const int64_t total = trace_rows(s0, t_end, K);
+    const int64_t cap = res->trace_cap;
+    const int64_t stored = std::min(total, cap);
+    std::vector<hms::TracePoint> h((size_t)(cap * R));  // before the guard: a queued copy writes it
+    SyncOnExit copy_done{s};
+    HIPTRY(hipMemcpyAsync(h.data(), ring, h.size() * sizeof(hms::TracePoint), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    for (int64_t j = 0; j < stored; ++j) {
+        const int64_t row = (total - stored + j) % cap;
+        std::memcpy(res->trace + j * R, h.data() + row * R, (size_t)R * sizeof(hms::TracePoint));
+    }
+    res->trace_len = (int32_t)stored;
+    return HMS_OK;
+}
+
 // Checks of hms_solve's resume input and state output.
 hms_status check_resume(const hms_cnf* cnf, const hms_solve_params* p, const hms_solve_result* res) {
+    if (res->trace && (res->trace_cap < 1 || (int64_t)res->trace_cap * std::max(p->restarts, 1) > (1 << 26)))
+        return fail(HMS_ERR_ARG, "trace needs 1 <= trace_cap and trace_cap * restarts <= 2^26");
     if (p->resume) {
         if (p->x0) return fail(HMS_ERR_ARG, "x0 and resume are both given");
         hms_status rc = check_state(cnf, p, p->resume, "resume");
@@ -1007,10 +1036,15 @@ hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_sol
     Layout lay;
     const size_t o_desc = lay.add(sizeof(hms::SmallDesc));
     SmallOut so_l = layout_small_out(P, R, lay);
+    const size_t o_trace = res->trace ? lay.add((size_t)res->trace_cap * R * sizeof(hms::TracePoint)) : 0;
     Arena A;
     A.s = s;
     HIPTRY(hipMallocAsync((void**)&A.base, lay.off, s));
     hms::SmallDesc D = make_desc(cnf, p);
+    if (res->trace) {
+        D.trace = A.at<hms::TracePoint>(o_trace);
+        D.trace_cap = res->trace_cap;
+    }
     D.block0 = 0;
     D.best_a = A.at<uint8_t>(so_l.o_best_a);
     D.best = A.at<int64_t>(so_l.o_best);
@@ -1074,6 +1108,10 @@ hms_status solve_resident(const hms_cnf* cnf, const hms_solve_params* p, hms_sol
         std::memcpy(so->best, best.data(), R * 8);
         std::memcpy(so->best_step, bstep.data(), R * 4);
         so->step = (rs ? rs->step : 0) + p->steps;
+    }
+    if (res->trace) {
+        const int32_t s0 = rs ? rs->step : 0;
+        if (hms_status rt = read_trace(D.trace, R, p->eval_every, s0, s0 + p->steps, s, res)) return rt;
     }
     for (int32_t r = 0; r < R; ++r)
         if (!std::isfinite(closs[r])) return fail(HMS_ERR_NONFINITE, "the loss at the final iterate is not finite");
@@ -1330,6 +1368,15 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     if (rc0) return rc0;
     const int32_t T = p->steps, K = p->eval_every;
     hipStream_t s = (hipStream_t)p->stream;
+    Arena ring;  // trajectory ring, written by the count reduction
+    if (res->trace) {
+        ring.s = s;
+        HIPTRY(hipMallocAsync((void**)&ring.base, (size_t)res->trace_cap * p->restarts * sizeof(hms::TracePoint), s));
+        Z.L.ra.trace = ring.at<hms::TracePoint>(0);
+        Z.L.ra.trace_cap = res->trace_cap;
+        Z.L.ra.trace_k = K;
+        Z.L.ra.trace_base = (int32_t)(((int64_t)Z.step0 + K - 1) / K);
+    }
     const Launch& L = Z.L;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1420,6 +1467,10 @@ hms_status hms_solve(const hms_cnf* cnf, const hms_solve_params* p, hms_solve_re
     float ms = 0.0f;
     HIPTRY(hipEventElapsedTime(&ms, ev0, ev1));
     const hms_status rr = read_result(cnf, Z, done, ms, s, res);
+    if (res->trace) {
+        const hms_status rt = read_trace(Z.L.ra.trace, p->restarts, K, Z.step0, Z.step0 + done, s, res);
+        if (rt) return rt;
+    }
     if (cancelled && rr == HMS_OK) return fail(HMS_ERR_CANCELLED, "cancelled by the caller; the best so far is filled");
     return rr;
 }
@@ -1498,8 +1549,8 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
     DeviceGuard dg(dev);
     std::vector<int32_t> res_idx, tiled_idx, alone;
     for (int32_t i = 0; i < count; ++i) {
-        // a resumed solve, or one that hands its state back, runs as hms_solve
-        if (params[i].resume != nullptr || results[i].state != nullptr) {
+        // a resumed solve, or one that hands back its state or its trajectory, runs as hms_solve
+        if (params[i].resume != nullptr || results[i].state != nullptr || results[i].trace != nullptr) {
             alone.push_back(i);
             continue;
         }

@@ -841,6 +841,11 @@ __device__ __forceinline__ void reduce2_body(const ReduceArgs& A, const int bx, 
         const int64_t count = sc[tid] + A.n_empty;
         A.cur_count[r] = count;
         A.cur_loss[r] = sl[tid] * A.inv_m;
+        if (A.trace != nullptr) {
+            const int32_t t = A.st->t;
+            const int32_t row = (int32_t)((((int64_t)t + A.trace_k - 1) / A.trace_k - A.trace_base) % A.trace_cap);
+            A.trace[(size_t)row * A.R + r] = TracePoint{t, 0, count, sl[tid] * A.inv_m};
+        }
         if (A.track) {
             if (count < A.best[r]) {
                 A.best[r] = count;

@@ -91,6 +91,13 @@ struct BwdArgs {
     const int32_t* seg_first;
 };
 
+// One counted iterate of one restart: the trajectory record of a solve.
+struct TracePoint {
+    int32_t step, pad;
+    int64_t cost;
+    double loss;
+};
+
 struct ReduceArgs {
     const int64_t* cnt_part;
     const double* loss_part;
@@ -105,6 +112,10 @@ struct ReduceArgs {
     int32_t* best_step;
     int32_t* improved;
     const StepState* st;
+    // trajectory ring (or null): the count at iteration t goes to row
+    // (ceil(t / trace_k) - trace_base) % trace_cap of [trace_cap][R]
+    TracePoint* trace;
+    int32_t trace_cap, trace_k, trace_base;
 };
 
 struct InitArgs {

@@ -257,18 +257,21 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
     }
     std::vector<int64_t> zeros((size_t)T, 0), nonzero((size_t)T, 0), bad((size_t)T, -1);
     par(T, [&](int t) {
+        int64_t z = 0, nz = 0;  // counted in registers, stored once (no shared cache lines in the loop)
         for (int64_t p = cb[(size_t)t]; p < cb[(size_t)t + 1]; ++p) {
             const int32_t l = lits[p];
             if (l == 0) {
-                zeros[(size_t)t]++;
+                ++z;
                 continue;
             }
             if (l == INT32_MIN || std::abs(l) > n) {
                 bad[(size_t)t] = p;  // the first one of the chunk
                 return;
             }
-            nonzero[(size_t)t]++;
+            ++nz;
         }
+        zeros[(size_t)t] = z;
+        nonzero[(size_t)t] = nz;
     });
     for (int t = 0; t < T; ++t)
         if (bad[(size_t)t] >= 0) {
@@ -402,38 +405,58 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
     // within a length, by the smallest (hottest) new variable index, so that
     // the clauses of a frequent variable sit together and its transposed row
     // reads neighbouring adjoint entries; ties keep the clause order.  A
-    // stable sort on (length class, smallest variable), in sorted runs per
-    // thread merged pairwise (each merge stable), then the rows and their
-    // entries are gathered into that order once.
+    // least-significant-digit radix sort on (length class, smallest
+    // variable), 11 bits a pass, each pass a stable scatter with per-thread
+    // counts; then the rows and their entries are gathered into that order
+    // once.
     {
         int32_t maxl = 0;
         for (const Row& r : rows) maxl = std::max(maxl, r.len);
-        std::vector<uint64_t> key((size_t)nr);
+        int vbits = 1;
+        while (vbits < 31 && ((int64_t)1 << vbits) < (int64_t)n) ++vbits;
+        std::vector<uint64_t> key((size_t)nr), key2((size_t)nr);
+        std::vector<int32_t> ord((size_t)nr), ord2((size_t)nr);
+        uint64_t kmax = 0;
         par(T, [&](int t) {
             for (int64_t i = part_lo(nr, t, T); i < part_lo(nr, t + 1, T); ++i) {
                 const Row& r = rows[(size_t)i];
                 // class: plain rows of length maxl - c for c <= maxl, then tautologies likewise
                 const uint64_t cls = (uint64_t)((r.taut ? maxl + 1 : 0) + (maxl - r.len));
-                key[(size_t)i] = (cls << 31) | (uint64_t)r.minvar;
+                key[(size_t)i] = (cls << vbits) | (uint64_t)r.minvar;
+                ord[(size_t)i] = (int32_t)i;
             }
         });
-        std::vector<int32_t> ord((size_t)nr), tmp((size_t)nr);
-        std::iota(ord.begin(), ord.end(), 0);
-        auto less = [&](int32_t a, int32_t b) { return key[(size_t)a] < key[(size_t)b]; };
-        par(T, [&](int t) {
-            std::stable_sort(ord.begin() + part_lo(nr, t, T), ord.begin() + part_lo(nr, t + 1, T), less);
-        });
-        for (int w = 1; w < T; w *= 2) {
-            const int pairs = (T + 2 * w - 1) / (2 * w);
-            par(std::min(pairs, T), [&](int q) {
-                for (int g = q; g < pairs; g += std::min(pairs, T)) {
-                    const int64_t a = part_lo(nr, 2 * w * g, T), b = part_lo(nr, std::min(T, 2 * w * g + w), T),
-                                  c = part_lo(nr, std::min(T, 2 * w * g + 2 * w), T);
-                    std::merge(ord.begin() + a, ord.begin() + b, ord.begin() + b, ord.begin() + c, tmp.begin() + a, less);
-                    std::copy(tmp.begin() + a, tmp.begin() + c, ord.begin() + a);
+        kmax = ((uint64_t)(2 * (maxl + 1)) << vbits);
+        constexpr int kDigit = 11;
+        constexpr int kBins = 1 << kDigit;
+        std::vector<std::vector<int64_t>> cnt((size_t)T);
+        for (int shift = 0; shift < 64 && (kmax >> shift) != 0; shift += kDigit) {
+            par(T, [&](int t) {
+                std::vector<int64_t>& c = cnt[(size_t)t];
+                c.assign(kBins, 0);
+                for (int64_t i = part_lo(nr, t, T); i < part_lo(nr, t + 1, T); ++i)
+                    c[(key[(size_t)i] >> shift) & (kBins - 1)]++;
+            });
+            int64_t o = 0;
+            for (int d = 0; d < kBins; ++d)
+                for (int t = 0; t < T; ++t) {
+                    const int64_t c = cnt[(size_t)t][d];
+                    cnt[(size_t)t][d] = o;  // this thread's first slot for digit d
+                    o += c;
+                }
+            par(T, [&](int t) {
+                std::vector<int64_t>& c = cnt[(size_t)t];
+                for (int64_t i = part_lo(nr, t, T); i < part_lo(nr, t + 1, T); ++i) {
+                    const int64_t q = c[(key[(size_t)i] >> shift) & (kBins - 1)]++;
+                    key2[(size_t)q] = key[(size_t)i];
+                    ord2[(size_t)q] = ord[(size_t)i];
                 }
             });
+            key.swap(key2);
+            ord.swap(ord2);
         }
+        std::vector<uint64_t>().swap(key);
+        std::vector<uint64_t>().swap(key2);
         std::vector<int64_t> psum((size_t)T + 1, 0);
         par(T, [&](int t) {
             int64_t s = 0;

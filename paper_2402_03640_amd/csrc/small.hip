@@ -237,7 +237,8 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
     for (int step = 0; step <= D.T; ++step) {
         const bool eval = kc == 0 || step == D.T;
         if (++kc == D.K) kc = 0;
-        const bool want_loss = step == D.T;  // the loss is reported at x_T only
+        // the loss is reported at x_T, and at every count when the trajectory is recorded
+        const bool want_loss = step == D.T || (eval && D.trace != nullptr);
         if (p_opt != kSgd && step % kScal == 0 && step < D.T) {
             // the previous block of scalars is no longer read: the last step
             // ended with a barrier
@@ -351,7 +352,12 @@ __global__ __launch_bounds__(NW * 64) void k_small(const SmallDesc* __restrict__
             if (want_loss && tid == 0) {
                 double l = 0.0;
                 for (int w = 0; w < kWaves; ++w) l = l + red_l[w];
-                D.final_loss[r] = l * D.inv_m;
+                if (step == D.T) D.final_loss[r] = l * D.inv_m;
+                if (D.trace != nullptr) {
+                    const int64_t gs = (int64_t)step0 + step;
+                    const int64_t row = ((gs + D.K - 1) / D.K - ((int64_t)step0 + D.K - 1) / D.K) % D.trace_cap;
+                    D.trace[(size_t)row * D.R + r] = TracePoint{(int32_t)gs, 0, c, l * D.inv_m};
+                }
             }
             if (improved) {
                 best_step = step0 + step;

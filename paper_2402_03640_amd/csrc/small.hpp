@@ -8,6 +8,7 @@
 
 #include <cstdint>
 
+#include "kernels.hpp"
 #include "plan.hpp"
 
 namespace hms {
@@ -48,6 +49,8 @@ struct SmallDesc {
     float* x_final;       // caller order [n][R] or null
     float* m_final;       // caller order [n][R] or null: Adam moments after the last step
     float* v_final;
+    TracePoint* trace;    // trajectory ring [trace_cap][R] or null (rows as in ReduceArgs)
+    int32_t trace_cap;
 };
 
 // LDS bytes the resident solver needs for an instance's state (per workgroup).
