@@ -256,6 +256,18 @@ def probe_table():
     for rb, fp in GATHER_POINTS:
         gg, tt, ms, shape = gather_bandwidth(rb, fp)
         print(f"gather {rb:4d} {fp >> 20:6d} {gg:8.0f} {tt:8.0f} {ms * 1e3:9.1f}  {shape}", flush=True)
+    from paper_2402_03640_amd import probe
+    print("# synchronisation between two passes: a grid barrier inside one cooperative launch (agent-scope\n"
+          "# release/acquire on one counter) vs one more dependent launch; blocks of 256 threads, us each",
+          flush=True)
+    for blocks in (8, 64, 256, 512, 1024):
+        us, gave = probe.grid_barrier_us(blocks)
+        print(f"grid barrier {blocks:5d} blocks {us:8.2f} us" + ("  (a bounded wait gave up)" if gave else ""),
+              flush=True)
+    for blocks in (256, 1024):
+        for graph in (False, True):
+            print(f"launch gap   {blocks:5d} blocks {probe.launch_gap_us(blocks, graph=graph):8.2f} us  "
+                  f"({'graph replay' if graph else 'stream launches'})", flush=True)
 
 
 def make_workload(name):

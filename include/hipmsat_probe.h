@@ -43,6 +43,28 @@ int32_t hmsp_copy(const void* src, void* dst, int64_t bytes, int32_t iters, void
 int32_t hmsp_gather(const float* src, int64_t rows, int32_t row_floats, const uint32_t* idx, int64_t n_idx,
                     int32_t deg, int32_t vec, float* out, int32_t iters, void* stream, double* ms);
 
+/*
+ * Grid barrier: one cooperative launch of `blocks` 256-thread workgroups (all
+ * resident at once) running `rounds` barrier rounds; in each, every
+ * workgroup adds one to a device counter (agent-scope release) and polls it
+ * (agent-scope acquire) until all have arrived, as a persistent kernel must
+ * between passes whose data cross the XCDs.  *us receives the average
+ * microseconds per round.  Every wait is bounded: a workgroup that polls
+ * 2^20 times, or sees that another gave up, sets an abort flag and leaves
+ * (*gave_up = 1; the time is then not a barrier's).  Uses 256 bytes of
+ * stream-ordered device memory.
+ */
+int32_t hmsp_grid_barrier(int32_t blocks, int32_t rounds, void* stream, double* us, int32_t* gave_up);
+
+/*
+ * Launch gap: `kernels` launches, one after the other on `stream`, of a
+ * kernel of `blocks` 256-thread workgroups that does nothing, enqueued
+ * directly (graph = 0) or replayed from a captured graph (graph = 1); *us
+ * receives the average microseconds per launch (each waits for the one
+ * before, as the passes of a step do).
+ */
+int32_t hmsp_launch_gap(int32_t blocks, int32_t kernels, int32_t graph, void* stream, double* us);
+
 /* Message of the last failed probe call on this thread ("" if none). */
 const char* hmsp_last_error(void);
 

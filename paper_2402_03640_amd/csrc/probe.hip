@@ -97,6 +97,39 @@ hipError_t launch_gather(const float* src, int32_t W, const uint32_t* idx, int64
     return hipGetLastError();
 }
 
+// Grid barrier: `rounds` rounds in which every block adds one to a counter
+// and its first thread polls it until every block has arrived (agent-scope
+// release and acquire: what a persistent kernel needs between two passes
+// whose data cross the XCDs).  Every wait is bounded: after `limit` polls, or
+// once any block has given up, a block sets the abort flag and leaves.
+__global__ __launch_bounds__(256) void k_barrier(unsigned* cnt, int* flag, int rounds, int limit) {
+    __shared__ int give_up;
+    for (int r = 0; r < rounds; ++r) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            give_up = 0;
+            __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned target = (unsigned)(r + 1) * gridDim.x;
+            int k = 0;
+            while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (++k > limit || __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    give_up = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        if (give_up) return;
+    }
+}
+
+// A kernel that does nothing observable (its one load decides nothing).
+__global__ __launch_bounds__(256) void k_empty(int* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && p[0] == 0x2545f491) p[1] = 1;
+}
+
 // Times `iters` launches of `launch` on s (after one warm launch).
 template <typename F>
 int32_t timed(F launch, int32_t iters, hipStream_t s, double* ms) {
@@ -191,6 +224,121 @@ int32_t hmsp_gather(const float* src, int64_t rows, int32_t row_floats, const ui
         }
     };
     return timed(launch, iters, s, ms);
+}
+
+int32_t hmsp_grid_barrier(int32_t blocks, int32_t rounds, void* stream, double* us, int32_t* gave_up) {
+    g_err.clear();
+    if (blocks < 1 || rounds < 1 || rounds > (1 << 20) || !us || !gave_up) {
+        g_err = "blocks >= 1, 1 <= rounds <= 2^20 and output pointers required";
+        return -1;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, cus = 0, per_cu = 0, coop = 0;
+    PTRY(hipGetDevice(&dev), "hipGetDevice");
+    PTRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev), "hipDeviceGetAttribute");
+    PTRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    PTRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_barrier, 256, 0), "occupancy");
+    if (!coop || blocks > per_cu * cus) {
+        g_err = "cooperative launch unsupported, or more blocks than can be resident at once";
+        return -1;
+    }
+    unsigned* cnt = nullptr;
+    PTRY(hipMallocAsync((void**)&cnt, 256, s), "hipMallocAsync");
+    struct Free {
+        unsigned* p;
+        hipStream_t s;
+        ~Free() {
+            (void)hipStreamSynchronize(s);
+            (void)hipFreeAsync(p, s);
+        }
+    } fr{cnt, s};
+    int* flag = reinterpret_cast<int*>(cnt + 32);
+    PTRY(hipMemsetAsync(cnt, 0, 256, s), "hipMemsetAsync");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PTRY(hipEventCreate(&e0), "hipEventCreate");
+    PTRY(hipEventCreate(&e1), "hipEventCreate");
+    struct FreeEv {
+        hipEvent_t a, b;
+        ~FreeEv() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } fe{e0, e1};
+    int limit = 1 << 20;
+    void* args[] = {&cnt, &flag, &rounds, &limit};
+    PTRY(hipEventRecord(e0, s), "hipEventRecord");
+    PTRY(hipLaunchCooperativeKernel((const void*)k_barrier, dim3(blocks), dim3(256), args, 0, s), "cooperative launch");
+    PTRY(hipEventRecord(e1, s), "hipEventRecord");
+    PTRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    float t = 0.0f;
+    PTRY(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+    int f = 0;
+    PTRY(hipMemcpy(&f, flag, 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    *us = (double)t * 1e3 / rounds;
+    *gave_up = f;
+    return 0;
+}
+
+int32_t hmsp_launch_gap(int32_t blocks, int32_t kernels, int32_t graph, void* stream, double* us) {
+    g_err.clear();
+    if (blocks < 1 || kernels < 1 || kernels > 100000 || !us) {
+        g_err = "blocks >= 1, 1 <= kernels <= 100000 and an output pointer required";
+        return -1;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int* p = nullptr;
+    PTRY(hipMallocAsync((void**)&p, 64, s), "hipMallocAsync");
+    struct Free {
+        int* p;
+        hipStream_t s;
+        ~Free() {
+            (void)hipStreamSynchronize(s);
+            (void)hipFreeAsync(p, s);
+        }
+    } fr{p, s};
+    PTRY(hipMemsetAsync(p, 0, 64, s), "hipMemsetAsync");
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    hipStream_t cs = nullptr;
+    struct FreeG {
+        hipGraph_t& g;
+        hipGraphExec_t& x;
+        hipStream_t& cs;
+        hipStream_t s;
+        ~FreeG() {
+            (void)hipStreamSynchronize(s);
+            if (x) (void)hipGraphExecDestroy(x);
+            if (g) (void)hipGraphDestroy(g);
+            if (cs) (void)hipStreamDestroy(cs);
+        }
+    } fg{g, x, cs, s};
+    if (graph) {
+        PTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+        PTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "begin capture");
+        hipError_t ce = hipSuccess;
+        for (int i = 0; i < kernels && ce == hipSuccess; ++i) {
+            hipLaunchKernelGGL(k_empty, dim3(blocks), dim3(256), 0, cs, p);
+            ce = hipGetLastError();
+        }
+        hipError_t ee = hipStreamEndCapture(cs, &g);
+        PTRY(ce, "capture");
+        PTRY(ee, "end capture");
+        PTRY(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    }
+    auto launch = [&]() -> hipError_t {
+        if (graph) return hipGraphLaunch(x, s);
+        for (int i = 0; i < kernels; ++i) {
+            hipLaunchKernelGGL(k_empty, dim3(blocks), dim3(256), 0, s, p);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    double ms = 0.0;
+    const int32_t rc = timed(launch, 4, s, &ms);
+    if (rc) return rc;
+    *us = ms * 1e3 / kernels;
+    return 0;
 }
 
 }  // extern "C"

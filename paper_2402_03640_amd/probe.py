@@ -8,7 +8,7 @@ import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhipmsat_probe.so")
-EXPORTS = ["hmsp_copy", "hmsp_gather", "hmsp_last_error"]
+EXPORTS = ["hmsp_copy", "hmsp_gather", "hmsp_grid_barrier", "hmsp_launch_gap", "hmsp_last_error"]
 # (floats per lane, rows per output) shapes of the gather probe; a ceiling is
 # the best of them
 GATHER_SHAPES = [(1, 16), (2, 8), (2, 16), (4, 8), (4, 16)]
@@ -28,6 +28,10 @@ def lib():
         L.hmsp_copy.restype = I32
         L.hmsp_gather.argtypes = [P, I64, I32, P, I64, I32, I32, P, I32, P, P]
         L.hmsp_gather.restype = I32
+        L.hmsp_grid_barrier.argtypes = [I32, I32, P, P, P]
+        L.hmsp_grid_barrier.restype = I32
+        L.hmsp_launch_gap.argtypes = [I32, I32, I32, P, P]
+        L.hmsp_launch_gap.restype = I32
         L.hmsp_last_error.argtypes = []
         L.hmsp_last_error.restype = C.c_char_p
         _lib = L
@@ -62,3 +66,17 @@ def gather_ms(src, idx, out, deg: int = 16, vec: int = 2, iters: int = 20) -> fl
     _check(lib().hmsp_gather(C.c_void_p(src.data_ptr()), rows, W, C.c_void_p(idx.data_ptr()), idx.numel(),
                              int(deg), int(vec), C.c_void_p(out.data_ptr()), int(iters), _stream(), C.byref(ms)))
     return ms.value
+
+
+def grid_barrier_us(blocks: int, rounds: int = 2000):
+    """(average microseconds per grid-barrier round, whether a bounded wait gave up)."""
+    us, gave = C.c_double(), C.c_int32()
+    _check(lib().hmsp_grid_barrier(int(blocks), int(rounds), _stream(), C.byref(us), C.byref(gave)))
+    return us.value, bool(gave.value)
+
+
+def launch_gap_us(blocks: int, kernels: int = 2000, graph: bool = True) -> float:
+    """Average microseconds per launch of dependent do-nothing kernels."""
+    us = C.c_double()
+    _check(lib().hmsp_launch_gap(int(blocks), int(kernels), int(bool(graph)), _stream(), C.byref(us)))
+    return us.value
