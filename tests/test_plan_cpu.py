@@ -187,12 +187,21 @@ def test_plan_random_formulas_property():
     run()
 
 
-def _plan_arrays(n, lits, threads):
+def _with_plan_threads(threads, fn):
+    """fn() with HIPMSAT_PLAN_THREADS set to `threads` (the setting before is restored)."""
+    old = os.environ.get("HIPMSAT_PLAN_THREADS")
     os.environ["HIPMSAT_PLAN_THREADS"] = str(threads)
     try:
-        P = hm.Plan(n, lits)
+        return fn()
     finally:
-        del os.environ["HIPMSAT_PLAN_THREADS"]
+        if old is None:
+            del os.environ["HIPMSAT_PLAN_THREADS"]
+        else:
+            os.environ["HIPMSAT_PLAN_THREADS"] = old
+
+
+def _plan_arrays(n, lits, threads):
+    P = _with_plan_threads(threads, lambda: hm.Plan(n, lits))
     return {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in vars(P).items()}
 
 
@@ -226,13 +235,9 @@ def test_plan_is_the_same_for_any_thread_count(threads):
     bad = cnfgen.from_clauses([[1, 2]] * 500 + [[3, 99]] + [[1]] * 500 + [[-98]])
     msgs = []
     for th in (1, threads):
-        os.environ["HIPMSAT_PLAN_THREADS"] = str(th)
-        try:
-            with pytest.raises(hm.HipMsatError) as e:
-                hm.Plan(50, bad)
-            msgs.append(str(e.value))
-        finally:
-            del os.environ["HIPMSAT_PLAN_THREADS"]
+        with pytest.raises(hm.HipMsatError) as e:
+            _with_plan_threads(th, lambda: hm.Plan(50, bad))
+        msgs.append(str(e.value))
     assert msgs[0] == msgs[1] and "literal 99 at position 1501" in msgs[0]
 
 
