@@ -286,6 +286,15 @@ hms_status hms_tune(const hms_cnf* cnf, const hms_solve_params* params, int32_t 
 hms_status hms_tune_candidates(int32_t restarts, int32_t loss_mode, int32_t* codes, int32_t cap, int32_t* count);
 
 /*
+ * Number of kernel table entries (host only): schedule table indices run
+ * from 1 to this count.  Every entry computes the same values; they differ
+ * in how lanes, restarts and rows map onto wavefronts and, for the
+ * unsat-masked loss, in whether a bitset lets the backward pass skip the
+ * adjoints of satisfied clauses.
+ */
+int32_t hms_schedule_count(void);
+
+/*
  * Count the clauses an assignment leaves unsatisfied (Section 4 "Unsatisfiable
  * Cores", with the rounding a_i in {0,1}).  `assignment`: HOST n bytes, nonzero
  * = true.  *unsat receives the count.  Synchronises `stream`.

@@ -6,8 +6,8 @@ The Python names mirror the C entry points of ``include/hipmsat.h``:
 """
 from ._lib import (ADAM, LOSS_ALL, LOSS_UNSAT, RESIDENT, SGD, CancelFlag, Cnf, HipMsatError, Plan,
                    SolveOutput, SolverState, eval_relaxed, eval_relaxed_noalloc, evaluate, lib, load_cnf, load_cnf_dimacs, solve,
-                   solve_batch, time_kernels, tune, tune_candidates, version)
+                   schedule_count, solve_batch, time_kernels, tune, tune_candidates, version)
 
 __all__ = ["ADAM", "SGD", "LOSS_UNSAT", "LOSS_ALL", "RESIDENT", "CancelFlag", "Cnf", "HipMsatError", "Plan",
            "SolveOutput", "SolverState", "eval_relaxed", "eval_relaxed_noalloc", "evaluate", "lib", "load_cnf", "load_cnf_dimacs",
-           "solve", "solve_batch", "time_kernels", "tune", "tune_candidates", "version"]
+           "schedule_count", "solve", "solve_batch", "time_kernels", "tune", "tune_candidates", "version"]

@@ -88,7 +88,8 @@ EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_
            "hms_solve_params_default", "hms_solve", "hms_evaluate", "hms_eval_relaxed",
            "hms_last_error", "hms_version", "hms_plan_view_build", "hms_plan_view_free",
            "hms_time_kernels", "hms_tune", "hms_adjoint_bytes", "hms_forward", "hms_backward",
-           "hms_solve_batch", "hms_tune_candidates", "hms_load_wcnf", "hms_eval_relaxed_noalloc"]
+           "hms_solve_batch", "hms_tune_candidates", "hms_load_wcnf", "hms_eval_relaxed_noalloc",
+           "hms_schedule_count"]
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -139,6 +140,8 @@ def _load():
     L.hms_plan_view_free.argtypes = [C.POINTER(PlanView)]
     L.hms_plan_view_free.restype = None
     L.hms_tune_candidates.argtypes = [I32, I32, P, I32, P]
+    L.hms_schedule_count.argtypes = []
+    L.hms_schedule_count.restype = I32
     for name in ("hms_load_cnf", "hms_load_wcnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_solve",
                  "hms_evaluate", "hms_eval_relaxed", "hms_eval_relaxed_noalloc", "hms_plan_view_build", "hms_time_kernels", "hms_tune", "hms_adjoint_bytes",
                  "hms_forward", "hms_backward", "hms_solve_batch", "hms_tune_candidates"):
@@ -347,6 +350,11 @@ def tune_candidates(restarts: int = 1, loss_mode: int = LOSS_UNSAT) -> list[int]
     _check(lib().hms_tune_candidates(int(restarts), int(loss_mode), C.cast(buf, C.c_void_p), cnt.value,
                                      C.byref(cnt)))
     return [int(buf[i]) for i in range(cnt.value)]
+
+
+def schedule_count() -> int:
+    """Number of kernel table entries: schedule table indices are 1..count."""
+    return int(lib().hms_schedule_count())
 
 
 class CancelFlag:

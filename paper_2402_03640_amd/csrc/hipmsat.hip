@@ -1745,6 +1745,8 @@ hms_status hms_tune_candidates(int32_t restarts, int32_t loss_mode, int32_t* cod
     return HMS_OK;
 }
 
+int32_t hms_schedule_count(void) { return hms::kNumSchedules; }
+
 hms_status hms_tune(const hms_cnf* cnf, const hms_solve_params* params, int32_t iters, int32_t* schedule,
                     double* step_ms) {
     g_err.clear();

@@ -145,7 +145,7 @@ def test_eval_cfg4_all_schedules():
     cnf = hm.load_cnf(n, lits)
     xt = torch.from_numpy(x).cuda()
     ref = None
-    codes = list(range(1, 38)) + [34 | (32 << 8) | (8 << 16), 26 | (32 << 8) | (64 << 16),
+    codes = list(range(1, hm.schedule_count() + 1)) + [34 | (32 << 8) | (8 << 16), 26 | (32 << 8) | (64 << 16),
                                   25 | (32 << 8) | (16 << 16), 14 | (16 << 8), 14 | (64 << 8), 11 | (1 << 8), 16 | (32 << 8),
                                   7 | (64 << 8), 1 | (64 << 8), 255]
     for sched in codes:
@@ -185,7 +185,8 @@ def test_single_restart_schedules_bitwise():
 def test_schedule_id_errors():
     n, lits = 200, cnfgen.uniform_kcnf(200, 860, 3, seed=1)
     cnf = hm.load_cnf(n, lits)
-    for bad in (26 | (32 << 8) | (3 << 16), 26 | (3 << 8), 1 << 24, 38, 26 | (128 << 8), 36 | (32 << 8)):
+    for bad in (26 | (32 << 8) | (3 << 16), 26 | (3 << 8), 1 << 24, hm.schedule_count() + 1, 26 | (128 << 8),
+                36 | (32 << 8)):
         with pytest.raises(hm.HipMsatError):
             hm.solve(cnf, steps=2, restarts=8, schedule=bad)
     code, ms = hm.tune(cnf, restarts=8, iters=3)

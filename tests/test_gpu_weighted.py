@@ -82,7 +82,7 @@ def test_weighted_schedules_bitwise():
     cnf = hm.load_cnf(n, lits, weights=_weights(m, seed=9))
     xt = torch.from_numpy(cnfgen.random_x(n, R, seed=44, lo=-2, hi=2)).cuda()
     ref = None
-    for sched in list(range(1, 38)) + [34 | (32 << 8) | (8 << 16), 255]:
+    for sched in list(range(1, hm.schedule_count() + 1)) + [34 | (32 << 8) | (8 << 16), 255]:
         res = hm.solve(cnf, steps=5, restarts=R, eval_every=1, x0=xt, schedule=sched, want_x=True)
         cur = (res.restart_best.copy(), res.restart_step.copy(), res.x_final.cpu().numpy().view(np.uint32))
         if ref is None:

@@ -244,12 +244,14 @@ def test_plan_is_the_same_for_any_thread_count(threads):
 def test_tune_candidates():
     """The autotuner's candidate list (host only): valid table entries and
     rows per unit, bitset variants only with the unsat-masked loss."""
+    nsched = hm.schedule_count()
+    assert nsched == 37
     for R, mode in ((1, hm.LOSS_UNSAT), (1, hm.LOSS_ALL), (3, hm.LOSS_UNSAT), (64, hm.LOSS_UNSAT)):
         codes = hm.tune_candidates(R, mode)
         assert codes and len(set(codes)) == len(codes)
         for c in codes:
             idx, U = c & 0xFF, c >> 8
-            assert 1 <= idx <= 37 and U >= 1 and 64 % U == 0
+            assert 1 <= idx <= nsched and U >= 1 and 64 % U == 0
         has_mask = any((c & 0xFF) in (23, 24, 25, 29, 30, 31, 32) for c in codes)
         assert has_mask == (mode == hm.LOSS_UNSAT)
     assert (26 | (32 << 8)) in hm.tune_candidates(64)
