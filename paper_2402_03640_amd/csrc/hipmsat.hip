@@ -115,8 +115,17 @@ struct SyncOnExit {
 };
 
 // Default kernel schedule for R restarts (table index into hms::kSchedules).
-int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0) {
-    if (R <= 1) return loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 21) ? 37 : 2;
+// One restart: above 2^20 nonzeros (unsat-masked loss) one row per lane with
+// the unsat bitset and two clause tiles per forward wavefront (entry 37);
+// below, when variable rows average 24 entries or more, four lanes per row
+// (entry 3: one of them works, so a wavefront takes 16 rows and the long
+// rows' scattered reads spread over four times the wavefronts); else two.
+int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0, int32_t n_act = 0) {
+    if (R <= 1) {
+        if (loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 20)) return 37;
+        if (n_act > 0 && nnz >= 24 * (int64_t)n_act) return 3;
+        return 2;
+    }
     if (R <= 2) return 2;
     if (R <= 4) return 3;
     if (R <= 8) return 5;
@@ -146,7 +155,7 @@ hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_m
     int U = (req >> 8) & 0xff;
     int Ub = (req >> 16) & 0xff;
     if (req < 0 || (req >> 24) != 0 || idx > hms::kNumSchedules) return fail(HMS_ERR_ARG, "unknown schedule id");
-    sh.sched = idx == 0 ? auto_schedule(R, loss_mode, P.nnz) : idx;
+    sh.sched = idx == 0 ? auto_schedule(R, loss_mode, P.nnz, P.n_act) : idx;
     if (hms::kSchedules[sh.sched].mask && (loss_mode != HMS_LOSS_UNSAT || !allow_mask))
         sh.sched = hms::kSchedules[sh.sched].twin;
     const hms::Schedule& c = hms::kSchedules[sh.sched];
@@ -713,7 +722,7 @@ std::vector<int32_t> tune_candidates(int32_t R, int loss_mode) {
         const hms::Schedule& c = hms::kSchedules[idx];
         if (R % c.V) continue;
         if (c.mask && loss_mode != HMS_LOSS_UNSAT) continue;
-        if (c.P * c.V > 2 * std::max(R, 1) && c.P * c.V > 2) continue;  // mostly idle lanes
+        if (c.P * c.V > 4 * std::max(R, 1)) continue;  // mostly idle lanes
         if (c.nt > 1 && R > 4) continue;  // many restarts already give every wavefront enough reads
         const int per = (64 / c.P) * c.UR;
         for (int U = per; U <= 64; U *= 2) {

@@ -337,6 +337,24 @@ def test_untimed_choice_of_resident():
     assert out[0].schedule == RESIDENT and out[1].schedule != RESIDENT
 
 
+def test_untimed_tiled_schedule_at_one_restart():
+    """Without timing, one-restart tiled solves take: above 2^20 nonzeros the
+    one-row-per-lane bitset schedule (table entry 37); below, four lanes per
+    variable row (entry 3) when rows average 24 entries or more, else entry 2.
+    Every choice gives the same result bit for bit."""
+    kw = dict(steps=12, restarts=1, eval_every=4, seed=0, autotune=False, want_x=True)
+    for n, m, k, want in ((40000, 340000, 4, 37), (3000, 51000, 5, 3), (20000, 86000, 3, 2)):
+        lits = cnfgen.uniform_kcnf(n, m, k, seed=n)
+        cnf = hm.load_cnf(n, lits)
+        a = hm.solve(cnf, **kw)
+        _say(f"n={n} m={m} k={k} nnz={cnf.info['nnz']}: untimed schedule {a.schedule}")
+        assert a.schedule & 0xFF == want
+        b = hm.solve(cnf, schedule=1, **kw)
+        np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32), b.x_final.cpu().numpy().view(np.uint32))
+        np.testing.assert_array_equal(a.restart_best, b.restart_best)
+        cnf.free()
+
+
 def test_resident_concurrent_threads():
     """Resident solves of different LDS sizes on several threads at once (the
     kernel's dynamic-LDS attribute is shared by all of them): every result
