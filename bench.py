@@ -8,7 +8,10 @@ that batch (inputs resident in HBM; loading the instance is timed apart).
 Printed: one JSON line with fwd+bwd literal nonzeros per second (2 L R T per
 solve), the roofline of the dominant kernel (algorithmic bytes per launch /
 average launch time from HIP events), and the FP64 CPU oracle timed on a
-bounded sample of the same workload on this host.
+bounded sample of the same workload on this host.  The default line also
+carries the structured workload (n = 500000, m = 2.5M, one restart) and the
+serving workload (512 Poisson requests through the continuous-batching
+server: instances/s, p50/p99 latency, against the plain one-at-a-time loop).
 """
 from __future__ import annotations
 
@@ -388,6 +391,11 @@ def host_cpu_model():
 
 
 def serve_bench(args):
+    """Serving workload as its own bench line."""
+    print(json.dumps(serve_record(args)), flush=True)
+
+
+def serve_record(args):
     """Serving workload: Poisson arrivals replayed in real time into the
     continuous-batching server (at the workload's 200 req/s and again at 80
     req/s, below capacity), then the same instances one at a time in arrival
@@ -491,7 +499,7 @@ def serve_bench(args):
         "equal_cost": bool(same and same_lo),
         "fwd_bwd_nnz_per_s_served": 2.0 * L_tot * T / span,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -504,6 +512,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-structured", action="store_true",
                     help="leave out the structured-workload record of the default line")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave out the serving record (512 Poisson requests) of the default line")
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -657,6 +667,14 @@ def main():
         log("[bench] the structured workload (n=500000, m=2.5M) ...")
         out["structured"] = structured_record()
         log(f"[bench] structured: {out['structured']}")
+    if args.config == "cfg2" and not args.no_serving:
+        log("[bench] the serving workload (512 Poisson requests) ...")
+        sv = serve_record(args)
+        out["serving"] = {k: sv[k] for k in ("metric", "value", "unit", "latency_ms", "below_capacity", "plain",
+                                             "speedup_vs_plain", "speedup_vs_plain_device_only", "equal_cost",
+                                             "fwd_bwd_nnz_per_s_served")}
+        out["serving"]["workload"] = sv["config"]["workload"]
+        log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu:
         log("[bench] timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(wl, L)
