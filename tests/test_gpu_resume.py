@@ -87,6 +87,32 @@ def test_resume_equals_uninterrupted(case, opt):
     _say(f"  best {full.best_cost} at step {full.best_step} (schedule {full.schedule})")
 
 
+@pytest.mark.parametrize("sched", [37, 255], ids=["tiled-bitset", "resident"])
+def test_weighted_resume_equals_uninterrupted(sched):
+    """Weighted MaxSAT with hard clauses: the best so far is a total weight
+    (int64, past 2^31) and enters a resumed solve as one; 200 + 200 steps
+    equal 400 bit for bit, and the oracle weighs the returned assignment at
+    the reported cost."""
+    if sched == 37:
+        n, R, lits = 20000, 1, cnfgen.structured_cnf(20000, 100000, seed=9)
+    else:
+        n, R, lits = 60, 3, cnfgen.uniform_kcnf(60, 300, 3, seed=9)
+    m = int(np.count_nonzero(lits == 0))
+    rng = np.random.default_rng(9)
+    w = rng.integers(1, 1000, size=m).astype(np.int64)
+    w[rng.choice(m, size=max(m // 50, 1), replace=False)] = 10 ** 12  # hard clauses
+    cnf = hm.load_cnf(n, lits, weights=w)
+    kw = dict(restarts=R, eval_every=10, seed=2, lr=1e-2, schedule=sched, autotune=False)
+    full = hm.solve(cnf, steps=400, want_state=True, **kw)
+    a = hm.solve(cnf, steps=200, want_state=True, **kw)
+    b = hm.solve(cnf, steps=200, resume=a.state, want_state=True, **kw)
+    assert b.schedule == full.schedule == (sched if sched == 255 else b.schedule)
+    _same_out(full, b)
+    _same_state(full.state, b.state)
+    assert O.OracleCNF(n, lits, weights=w).count(b.best_assignment) == b.best_cost
+    _say(f"weighted resume {sched}: best {b.best_cost} at step {b.best_step}")
+
+
 def test_resume_across_solvers():
     """500 steps on the tiled kernels, then 500 on the resident solver from
     the state they left (and the other way round): the same as 1000 on

@@ -54,6 +54,28 @@ def test_trace_records_every_count(sched):
     _say(f"trace ({'resident' if sched == 255 else 'tiled'}): costs of restart 0 {tr['cost'][:, 0].tolist()}")
 
 
+@pytest.mark.parametrize("sched", [1, 255], ids=["tiled", "resident"])
+def test_trace_of_a_weighted_solve(sched):
+    """Weighted MaxSAT: each recorded cost is the total weight of the
+    unsatisfied clauses (int64, hard clauses past 2^31), the best is the
+    lowest one, and the oracle weighs the returned assignment at it."""
+    n, m, R, T, K = 200, 860, 2, 120, 10
+    lits = cnfgen.uniform_kcnf(n, m, 3, seed=13)
+    rng = np.random.default_rng(13)
+    w = rng.integers(1, 500, size=m).astype(np.int64)
+    w[rng.choice(m, size=20, replace=False)] = 3 * 10 ** 11
+    cnf = hm.load_cnf(n, lits, weights=w)
+    out = hm.solve(cnf, steps=T, restarts=R, eval_every=K, seed=6, lr=1e-2, schedule=sched, autotune=False,
+                   trace_cap=64)
+    tr = out.trace
+    assert tr.shape == (len(_counted(0, T, K)), R)
+    for r in range(R):
+        costs = tr["cost"][:, r]
+        assert out.restart_best[r] == min(int(costs.min()), int(w.sum()))
+    assert O.OracleCNF(n, lits, weights=w).count(out.best_assignment) == out.best_cost
+    _say(f"weighted trace ({'resident' if sched == 255 else 'tiled'}): restart 0 {tr['cost'][:, 0].tolist()[:6]}")
+
+
 def test_trace_tiled_equals_resident():
     n, m, R, T, K = 60, 258, 2, 150, 7
     cnf = hm.load_cnf(n, cnfgen.uniform_kcnf(n, m, 3, seed=5))
