@@ -434,9 +434,9 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     const hms::HostPlan& P = C->plan;
     Layout L;
     size_t o_ct = L.add(P.c_tile.size() * sizeof(hms::TileDesc));
-    size_t o_ce = L.add((P.c_ent.size() + hms::kEntrySlack) * 4);
+    size_t o_ce = L.add(P.c_ent.size() * 4);
     size_t o_vt = L.add(P.v_tile.size() * sizeof(hms::TileDesc));
-    size_t o_ve = L.add((P.v_ent.size() + hms::kEntrySlack) * 4);
+    size_t o_ve = L.add(P.v_ent.size() * 4);
     size_t o_sf = L.add(P.seg_first.size() * 4);
     size_t o_vo = L.add(P.var_old.size() * 4);
     size_t o_w = L.add(P.c_w.size() * 8);

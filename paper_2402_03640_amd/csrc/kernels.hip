@@ -41,10 +41,16 @@ int default_rows_per_unit(int sched) {
 namespace {
 
 // Columns per load batch in the tiled kernels: clauses are short, variable
-// rows longer (the entry arrays carry kEntrySlack entries of slack at their
-// end, so a batch may read past a row's end).
+// rows longer.  A row's last batch takes only the columns left, so no batch
+// reads a padding column past the tile's length.
 constexpr int kChunkF = 4;
 constexpr int kChunkB = 8;
+
+// Column count of a load batch, as a type (one instantiation per batch size).
+template <int N>
+struct Cols {
+    static constexpr int value = N;
+};
 
 template <int V>
 struct VecF {
@@ -168,26 +174,24 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& A, const int bx) {
             }
         if (ract) {
             if (d.len <= 16) {
-                // chunks of kChunkF columns: all entry loads, then all gathers,
-                // then the sums in column order; columns past the row's end
-                // read the padding entry (inert: adds -0.0, stays "false")
-                for (uint32_t c0 = 0; c0 < d.len; c0 += kChunkF) {
-                    uint32_t en[kChunkF][UR];
+                // batches of kChunkF columns, then one batch of the last
+                // d.len % kChunkF: all entry loads, then all gathers, then the
+                // sums in column order (no padding column is read)
+                auto batch = [&](auto nc, const uint32_t c0) {
+                    constexpr int NC = decltype(nc)::value;
+                    uint32_t en[NC][UR];
 #pragma unroll
-                    for (int cc = 0; cc < kChunkF; ++cc)
+                    for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
-                        for (int j = 0; j < UR; ++j) {
-                            const uint32_t v = ldc(e + (size_t)(c0 + cc) * kTile + j);
-                            en[cc][j] = c0 + cc < d.len ? v : A.pad_entry;
-                        }
-                    VecF<V> tv[kChunkF][UR];
+                        for (int j = 0; j < UR; ++j) en[cc][j] = ldc(e + (size_t)(c0 + cc) * kTile + j);
+                    VecF<V> tv[NC][UR];
 #pragma unroll
-                    for (int cc = 0; cc < kChunkF; ++cc)
+                    for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
                         for (int j = 0; j < UR; ++j)
                             tv[cc][j] = ldv<V>(tg + (size_t)(en[cc][j] & kIdx) * B.G + rl);
 #pragma unroll
-                    for (int cc = 0; cc < kChunkF; ++cc)
+                    for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
                         for (int j = 0; j < UR; ++j)
 #pragma unroll
@@ -196,6 +200,15 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& A, const int bx) {
                                 f[j][k] = f[j][k] + __uint_as_float(b);
                                 allf[j][k] &= b;
                             }
+                };
+                uint32_t c0 = 0;
+                for (; c0 + kChunkF <= d.len; c0 += kChunkF) batch(Cols<kChunkF>{}, c0);
+                static_assert(kChunkF == 4, "one case per remainder");
+                switch (d.len - c0) {
+                    case 1: batch(Cols<1>{}, c0); break;
+                    case 2: batch(Cols<2>{}, c0); break;
+                    case 3: batch(Cols<3>{}, c0); break;
+                    default: break;
                 }
             } else {
                 // long clauses: FP64 accumulation, one row at a time
@@ -363,26 +376,36 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
         f[u] = 0.0f;
         allf[u] = ~0u;
     }
-    for (uint32_t c0 = 0; c0 < lmax; c0 += kChunkF) {
-        uint32_t en[kChunkF][NT];
+    // batches of kChunkF columns, then one batch of the last lmax % kChunkF
+    auto batch = [&](auto nc, const uint32_t c0) {
+        constexpr int NC = decltype(nc)::value;
+        uint32_t en[NC][NT];
 #pragma unroll
-        for (int cc = 0; cc < kChunkF; ++cc)
+        for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
             for (int u = 0; u < NT; ++u)
                 en[cc][u] = unit_entry(A.ent, d[u], c0 + cc, d[u].len <= 16, lane, A.pad_entry);
-        float tv[kChunkF][NT];
+        float tv[NC][NT];
 #pragma unroll
-        for (int cc = 0; cc < kChunkF; ++cc)
+        for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
             for (int u = 0; u < NT; ++u) tv[cc][u] = tg[en[cc][u] & kIdx];
 #pragma unroll
-        for (int cc = 0; cc < kChunkF; ++cc)
+        for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
             for (int u = 0; u < NT; ++u) {
                 const uint32_t b = __float_as_uint(tv[cc][u]) ^ (en[cc][u] & kSign);
                 f[u] = f[u] + __uint_as_float(b);
                 allf[u] &= b;
             }
+    };
+    uint32_t c0 = 0;
+    for (; c0 + kChunkF <= lmax; c0 += kChunkF) batch(Cols<kChunkF>{}, c0);
+    switch (lmax - c0) {
+        case 1: batch(Cols<1>{}, c0); break;
+        case 2: batch(Cols<2>{}, c0); break;
+        case 3: batch(Cols<3>{}, c0); break;
+        default: break;
     }
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
@@ -580,29 +603,27 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
                     st[j] = var_load<V, OPT>(
                         A, xbase + (size_t)(A.n_heavy + (tile * kTile + rowin0 + j - A.seg_tiles * kTile)) * B.G + rl);
         }
-        for (uint32_t c0 = 0; c0 < d.len; c0 += CB) {
-            // all entry loads of the chunk, then all gathers, then the sums in
-            // column order; columns past the row's end read the padding entry
-            // (the always-zero adjoint row)
-            uint32_t en[CB][UR];
+        // batches of CB columns, then one batch of the last d.len % CB: all
+        // entry loads, then all gathers, then the sums in column order (no
+        // padding column is read)
+        auto batch = [&](auto nc, const uint32_t c0) {
+            constexpr int NC = decltype(nc)::value;
+            uint32_t en[NC][UR];
 #pragma unroll
-            for (int cc = 0; cc < CB; ++cc)
+            for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
-                for (int j = 0; j < UR; ++j) {
-                    const uint32_t v = ldc(e + (size_t)(c0 + cc) * kTile + j);
-                    en[cc][j] = c0 + cc < d.len ? v : A.pad_entry;
-                }
-            VecF<V> av[CB][UR];
+                for (int j = 0; j < UR; ++j) en[cc][j] = ldc(e + (size_t)(c0 + cc) * kTile + j);
+            VecF<V> av[NC][UR];
             if constexpr (MASK) {
-                uint32_t w[CB][UR];
+                uint32_t w[NC][UR];
 #pragma unroll
-                for (int cc = 0; cc < CB; ++cc)
+                for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
                     for (int j = 0; j < UR; ++j) w[cc][j] = um[(en[cc][j] & kIdx) >> 5];
                 // a satisfied clause's adjoint is 0: read the always-zero row
                 // instead (one cached line), so every gather issues at once
 #pragma unroll
-                for (int cc = 0; cc < CB; ++cc)
+                for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
                     for (int j = 0; j < UR; ++j) {
                         const uint32_t row = en[cc][j] & kIdx;
@@ -611,18 +632,31 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
                     }
             } else {
 #pragma unroll
-                for (int cc = 0; cc < CB; ++cc)
+                for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
                     for (int j = 0; j < UR; ++j)
                         av[cc][j] = ldv<V>(ag + (size_t)(en[cc][j] & kIdx) * B.G + rl);
             }
 #pragma unroll
-            for (int cc = 0; cc < CB; ++cc)
+            for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
                 for (int j = 0; j < UR; ++j)
 #pragma unroll
                     for (int k = 0; k < V; ++k)
                         G[j][k] = G[j][k] + (double)__uint_as_float(__float_as_uint(av[cc][j].v[k]) ^ (en[cc][j] & kSign));
+        };
+        uint32_t c0 = 0;
+        for (; c0 + CB <= d.len; c0 += CB) batch(Cols<CB>{}, c0);
+        static_assert(CB == 8, "one case per remainder");
+        switch (d.len - c0) {
+            case 1: batch(Cols<1>{}, c0); break;
+            case 2: batch(Cols<2>{}, c0); break;
+            case 3: batch(Cols<3>{}, c0); break;
+            case 4: batch(Cols<4>{}, c0); break;
+            case 5: batch(Cols<5>{}, c0); break;
+            case 6: batch(Cols<6>{}, c0); break;
+            case 7: batch(Cols<7>{}, c0); break;
+            default: break;
         }
 #pragma unroll
         for (int j = 0; j < UR; ++j) {

@@ -147,10 +147,6 @@ struct InitArgs {
     StepState* st;
 };
 
-// Slack at the end of the entry arrays, in entries (tile columns read past a
-// row's end by the batched loads of the tiled kernels).
-constexpr int kEntrySlack = 16 * kTile;
-
 // Kernel schedules: P lanes per restart group (64 / P rows side by side),
 // V restarts per lane (vector width), UR rows per lane handled together.
 // A work unit is U rows of one tile (U a multiple of (64 / P) * UR dividing 64).
