@@ -117,14 +117,16 @@ struct SyncOnExit {
 // Default kernel schedule for R restarts (table index into hms::kSchedules).
 // One restart: above 2^20 nonzeros (unsat-masked loss) one row per lane with
 // the unsat bitset and two clause tiles per forward wavefront (entry 37);
-// below, when variable rows average 24 entries or more, four lanes per row
-// (entry 3: one of them works, so a wavefront takes 16 rows and the long
-// rows' scattered reads spread over four times the wavefronts); else two.
+// below, 16-column backward batches (half the round trips of a long row),
+// with four lanes per row up to 2^14 active variables (entry 39: one of them
+// works, so a wavefront takes 16 rows and a small instance's rows spread over
+// four times the wavefronts), else two (entry 38).
 int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0, int32_t n_act = 0) {
     if (R <= 1) {
         if (loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 20)) return 37;
-        if (n_act > 0 && nnz >= 24 * (int64_t)n_act) return 3;
-        return 2;
+        // long backward batches; four lanes per variable row (more wavefronts)
+        // while the rows are few, two beyond
+        return n_act <= (1 << 14) ? 39 : 38;
     }
     if (R <= 2) return 2;
     if (R <= 4) return 3;

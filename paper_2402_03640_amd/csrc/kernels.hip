@@ -28,6 +28,7 @@ const Schedule kSchedules[kNumSchedules + 1] = {
     {1, 2, 1, 1, 27}, {1, 4, 1, 1, 26}, {2, 4, 1, 1, 26}, {4, 2, 1, 1, 27},                  // 29..32
     {4, 4, 1, 0, 0},  {8, 4, 1, 0, 0},  {8, 2, 1, 0, 0},                                      // 33..35
     {1, 1, 1, 0, 0, 2}, {1, 1, 1, 1, 36, 2},                                                  // 36..37
+    {2, 1, 1, 0, 0, 1, 16}, {4, 1, 1, 0, 0, 1, 16}, {1, 1, 1, 0, 0, 2, 16},                    // 38..40
 };
 
 int default_rows_per_unit(int sched) {
@@ -41,8 +42,10 @@ int default_rows_per_unit(int sched) {
 namespace {
 
 // Columns per load batch in the tiled kernels: clauses are short, variable
-// rows longer.  A row's last batch takes only the columns left, so no batch
-// reads a padding column past the tile's length.
+// rows longer (schedules with one value per lane may take 16: a batch's
+// loads then fit the registers twice over).  A row's last batch takes only
+// the columns left, so no batch reads a padding column past the tile's
+// length, and the batch length never changes the order of a sum.
 constexpr int kChunkF = 4;
 constexpr int kChunkB = 8;
 
@@ -558,10 +561,10 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int 
 // adjoint of a clause is read only when its unsat bit is set (it is 0
 // otherwise).
 // ---------------------------------------------------------------------------
-template <int P, int V, int UR, int OPT, bool MASK>
+template <int P, int V, int UR, int OPT, bool MASK, int CB>
 __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
+    static_assert(CB == kChunkB || (CB == 2 * kChunkB && V * UR == 1), "long batches take one value per lane");
     constexpr int W = 64 / P;
-    constexpr int CB = kChunkB;
     const int lane = threadIdx.x & 63;
     const int s = lane / P;
     const int q = lane % P;
@@ -647,15 +650,23 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
         };
         uint32_t c0 = 0;
         for (; c0 + CB <= d.len; c0 += CB) batch(Cols<CB>{}, c0);
-        static_assert(CB == 8, "one case per remainder");
+        static_assert(CB <= 16, "one case per remainder");
         switch (d.len - c0) {
-            case 1: batch(Cols<1>{}, c0); break;
-            case 2: batch(Cols<2>{}, c0); break;
-            case 3: batch(Cols<3>{}, c0); break;
-            case 4: batch(Cols<4>{}, c0); break;
-            case 5: batch(Cols<5>{}, c0); break;
-            case 6: batch(Cols<6>{}, c0); break;
-            case 7: batch(Cols<7>{}, c0); break;
+            case 1: if constexpr (CB > 1) batch(Cols<1>{}, c0); break;
+            case 2: if constexpr (CB > 2) batch(Cols<2>{}, c0); break;
+            case 3: if constexpr (CB > 3) batch(Cols<3>{}, c0); break;
+            case 4: if constexpr (CB > 4) batch(Cols<4>{}, c0); break;
+            case 5: if constexpr (CB > 5) batch(Cols<5>{}, c0); break;
+            case 6: if constexpr (CB > 6) batch(Cols<6>{}, c0); break;
+            case 7: if constexpr (CB > 7) batch(Cols<7>{}, c0); break;
+            case 8: if constexpr (CB > 8) batch(Cols<8>{}, c0); break;
+            case 9: if constexpr (CB > 9) batch(Cols<9>{}, c0); break;
+            case 10: if constexpr (CB > 10) batch(Cols<10>{}, c0); break;
+            case 11: if constexpr (CB > 11) batch(Cols<11>{}, c0); break;
+            case 12: if constexpr (CB > 12) batch(Cols<12>{}, c0); break;
+            case 13: if constexpr (CB > 13) batch(Cols<13>{}, c0); break;
+            case 14: if constexpr (CB > 14) batch(Cols<14>{}, c0); break;
+            case 15: if constexpr (CB > 15) batch(Cols<15>{}, c0); break;
             default: break;
         }
 #pragma unroll
@@ -676,16 +687,16 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
     }
 }
 
-template <int P, int V, int UR, int OPT, bool MASK>
+template <int P, int V, int UR, int OPT, bool MASK, int CB = kChunkB>
 __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
-    bwd_body<P, V, UR, OPT, MASK>(A, blockIdx.x);
+    bwd_body<P, V, UR, OPT, MASK, CB>(A, blockIdx.x);
 }
 
-template <int P, int V, int UR, int OPT, bool MASK>
+template <int P, int V, int UR, int OPT, bool MASK, int CB = kChunkB>
 __global__ __launch_bounds__(256) void k_bwd_multi(const BwdArgs* __restrict__ As, const int32_t* __restrict__ b0,
                                                    int32_t n) {
     const int i = owner(b0, n, blockIdx.x);
-    bwd_body<P, V, UR, OPT, MASK>(As[i], blockIdx.x - b0[i]);
+    bwd_body<P, V, UR, OPT, MASK, CB>(As[i], blockIdx.x - b0[i]);
 }
 
 // Heavy variables: combine segment partials in a fixed order that depends on
@@ -1000,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t n, int32_t n_act, Block
     dst[(size_t)var_old[i] * B.R + r] = v;
 }
 
-template <int P, int V, int UR, int MASK>
+template <int P, int V, int UR, int MASK, int CB = kChunkB>
 hipError_t fwd_for(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
     if (eval)
         hipLaunchKernelGGL((k_fwd<P, V, UR, true, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
@@ -1009,7 +1020,7 @@ hipError_t fwd_for(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int P, int V, int UR, int MASK>
+template <int P, int V, int UR, int MASK, int CB = kChunkB>
 hipError_t fwd_multi_for(bool eval, const MultiLaunch& M, hipStream_t s) {
     if (eval)
         hipLaunchKernelGGL((k_fwd_multi<P, V, UR, true, MASK != 0>), dim3(M.blocks), dim3(256), 0, s,
@@ -1020,17 +1031,19 @@ hipError_t fwd_multi_for(bool eval, const MultiLaunch& M, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int P, int V, int UR, int MASK>
+template <int P, int V, int UR, int MASK, int CB = kChunkB>
 hipError_t bwd_multi_for(int opt, const MultiLaunch& M, hipStream_t s) {
     const BwdArgs* a = static_cast<const BwdArgs*>(M.args);
     if (opt == kAdam)
-        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kAdam, MASK != 0>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
+        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kAdam, MASK != 0, CB>), dim3(M.blocks), dim3(256), 0, s, a, M.b0,
+                           M.n);
     else
-        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kSgd, MASK != 0>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
+        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kSgd, MASK != 0, CB>), dim3(M.blocks), dim3(256), 0, s, a, M.b0,
+                           M.n);
     return hipGetLastError();
 }
 
-template <int NT, int MASK>
+template <int NT, int MASK, int CB = kChunkB>
 hipError_t fwd_for_nt(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
     if (eval)
         hipLaunchKernelGGL((k_fwd_nt<NT, true, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
@@ -1039,7 +1052,7 @@ hipError_t fwd_for_nt(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int NT, int MASK>
+template <int NT, int MASK, int CB = kChunkB>
 hipError_t fwd_multi_for_nt(bool eval, const MultiLaunch& M, hipStream_t s) {
     const FwdArgs* a = static_cast<const FwdArgs*>(M.args);
     if (eval)
@@ -1049,27 +1062,27 @@ hipError_t fwd_multi_for_nt(bool eval, const MultiLaunch& M, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int P, int V, int UR, int MASK>
+template <int P, int V, int UR, int MASK, int CB = kChunkB>
 hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
     if (opt == kAdam)
-        hipLaunchKernelGGL((k_bwd<P, V, UR, kAdam, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kAdam, MASK != 0, CB>), dim3(blocks), dim3(256), 0, s, A);
     else if (opt == kSgd)
-        hipLaunchKernelGGL((k_bwd<P, V, UR, kSgd, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kSgd, MASK != 0, CB>), dim3(blocks), dim3(256), 0, s, A);
     else
-        hipLaunchKernelGGL((k_bwd<P, V, UR, kGrad, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kGrad, MASK != 0, CB>), dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
 // The multi-tile entries differ in the forward only: their backward is the
 // one-row-per-lane kernel.
-template <int NT, int MASK>
+template <int NT, int MASK, int CB = kChunkB>
 hipError_t bwd_for_nt(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
-    return bwd_for<1, 1, 1, MASK>(opt, A, blocks, s);
+    return bwd_for<1, 1, 1, MASK, CB>(opt, A, blocks, s);
 }
 
-template <int NT, int MASK>
+template <int NT, int MASK, int CB = kChunkB>
 hipError_t bwd_multi_for_nt(int opt, const MultiLaunch& M, hipStream_t s) {
-    return bwd_multi_for<1, 1, 1, MASK>(opt, M, s);
+    return bwd_multi_for<1, 1, 1, MASK, CB>(opt, M, s);
 }
 
 }  // namespace
@@ -1113,6 +1126,9 @@ hipError_t bwd_multi_for_nt(int opt, const MultiLaunch& M, hipStream_t s) {
         case 35: return FN<8, 2, 1, 0>(__VA_ARGS__);       \
         case 36: return FN##_nt<2, 0>(__VA_ARGS__);        \
         case 37: return FN##_nt<2, 1>(__VA_ARGS__);        \
+        case 38: return FN<2, 1, 1, 0, 16>(__VA_ARGS__);   \
+        case 39: return FN<4, 1, 1, 0, 16>(__VA_ARGS__);   \
+        case 40: return FN##_nt<2, 0, 16>(__VA_ARGS__);    \
         default: return hipErrorInvalidValue;              \
     }
 

@@ -157,8 +157,9 @@ struct InitArgs {
 struct Schedule {
     int P, V, UR, mask, twin;
     int nt = 1;  // whole clause tiles per forward wavefront (more than 1 only with P = V = UR = 1)
+    int cb = 8;  // columns per backward load batch (16 only with V = UR = 1)
 };
-constexpr int kNumSchedules = 37;
+constexpr int kNumSchedules = 40;
 extern const Schedule kSchedules[kNumSchedules + 1];
 
 int default_rows_per_unit(int sched);

@@ -169,7 +169,7 @@ def test_single_restart_schedules_bitwise():
     cnf = hm.load_cnf(n, lits)
     assert cnf.info["n_heavy"] > 0
     ref = None
-    for sched in [1, 2, 3, 4, 11, 23, 24, 25, 24 | (32 << 8), 25 | (64 << 8), 2 | (32 << 8), 36, 37]:
+    for sched in [1, 2, 3, 4, 11, 23, 24, 25, 24 | (32 << 8), 25 | (64 << 8), 2 | (32 << 8), 36, 37, 38, 39, 40]:
         res = hm.solve(cnf, steps=60, restarts=1, eval_every=7, seed=5, lr=1e-2, schedule=sched,
                        want_x=True)
         cur = (res.restart_best.copy(), res.restart_step.copy(),
@@ -339,11 +339,12 @@ def test_untimed_choice_of_resident():
 
 def test_untimed_tiled_schedule_at_one_restart():
     """Without timing, one-restart tiled solves take: above 2^20 nonzeros the
-    one-row-per-lane bitset schedule (table entry 37); below, four lanes per
-    variable row (entry 3) when rows average 24 entries or more, else entry 2.
-    Every choice gives the same result bit for bit."""
+    one-row-per-lane bitset schedule (table entry 37); below, 16-column
+    backward batches with four lanes per variable row (entry 39) up to 2^14
+    active variables, else two (entry 38).  Every choice gives the same result
+    bit for bit."""
     kw = dict(steps=12, restarts=1, eval_every=4, seed=0, autotune=False, want_x=True)
-    for n, m, k, want in ((40000, 340000, 4, 37), (3000, 51000, 5, 3), (20000, 86000, 3, 2)):
+    for n, m, k, want in ((40000, 340000, 4, 37), (3000, 51000, 5, 39), (20000, 86000, 3, 38)):
         lits = cnfgen.uniform_kcnf(n, m, k, seed=n)
         cnf = hm.load_cnf(n, lits)
         a = hm.solve(cnf, **kw)

@@ -245,7 +245,7 @@ def test_tune_candidates():
     """The autotuner's candidate list (host only): valid table entries and
     rows per unit, bitset variants only with the unsat-masked loss."""
     nsched = hm.schedule_count()
-    assert nsched == 37
+    assert nsched == 40
     for R, mode in ((1, hm.LOSS_UNSAT), (1, hm.LOSS_ALL), (3, hm.LOSS_UNSAT), (64, hm.LOSS_UNSAT)):
         codes = hm.tune_candidates(R, mode)
         assert codes and len(set(codes)) == len(codes)
