@@ -42,8 +42,8 @@ int default_rows_per_unit(int sched) {
 namespace {
 
 // Columns per load batch in the tiled kernels: clauses are short, variable
-// rows longer (schedules with one value per lane may take 16: a batch's
-// loads then fit the registers twice over).  A row's last batch takes only
+// rows longer.  With one value per lane the registers hold twice the batch:
+// the forward then takes 8 columns and schedules may take 16 backward.  A row's last batch takes only
 // the columns left, so no batch reads a padding column past the tile's
 // length, and the batch length never changes the order of a sum.
 constexpr int kChunkF = 4;
@@ -177,9 +177,9 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& A, const int bx) {
             }
         if (ract) {
             if (d.len <= 16) {
-                // batches of kChunkF columns, then one batch of the last
-                // d.len % kChunkF: all entry loads, then all gathers, then the
-                // sums in column order (no padding column is read)
+                // batches of CF columns, then one batch of the last d.len % CF:
+                // all entry loads, then all gathers, then the sums in column
+                // order (no padding column is read)
                 auto batch = [&](auto nc, const uint32_t c0) {
                     constexpr int NC = decltype(nc)::value;
                     uint32_t en[NC][UR];
@@ -204,13 +204,17 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& A, const int bx) {
                                 allf[j][k] &= b;
                             }
                 };
+                constexpr int CF = V * UR == 1 ? 2 * kChunkF : kChunkF;
                 uint32_t c0 = 0;
-                for (; c0 + kChunkF <= d.len; c0 += kChunkF) batch(Cols<kChunkF>{}, c0);
-                static_assert(kChunkF == 4, "one case per remainder");
+                for (; c0 + CF <= d.len; c0 += CF) batch(Cols<CF>{}, c0);
                 switch (d.len - c0) {
                     case 1: batch(Cols<1>{}, c0); break;
                     case 2: batch(Cols<2>{}, c0); break;
                     case 3: batch(Cols<3>{}, c0); break;
+                    case 4: if constexpr (CF > 4) batch(Cols<4>{}, c0); break;
+                    case 5: if constexpr (CF > 5) batch(Cols<5>{}, c0); break;
+                    case 6: if constexpr (CF > 6) batch(Cols<6>{}, c0); break;
+                    case 7: if constexpr (CF > 7) batch(Cols<7>{}, c0); break;
                     default: break;
                 }
             } else {
@@ -379,7 +383,7 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
         f[u] = 0.0f;
         allf[u] = ~0u;
     }
-    // batches of kChunkF columns, then one batch of the last lmax % kChunkF
+    // batches of CF columns, then one batch of the last lmax % CF
     auto batch = [&](auto nc, const uint32_t c0) {
         constexpr int NC = decltype(nc)::value;
         uint32_t en[NC][NT];
@@ -402,12 +406,17 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
                 allf[u] &= b;
             }
     };
+    constexpr int CF = 2 * kChunkF;  // one value per lane
     uint32_t c0 = 0;
-    for (; c0 + kChunkF <= lmax; c0 += kChunkF) batch(Cols<kChunkF>{}, c0);
+    for (; c0 + CF <= lmax; c0 += CF) batch(Cols<CF>{}, c0);
     switch (lmax - c0) {
         case 1: batch(Cols<1>{}, c0); break;
         case 2: batch(Cols<2>{}, c0); break;
         case 3: batch(Cols<3>{}, c0); break;
+        case 4: batch(Cols<4>{}, c0); break;
+        case 5: batch(Cols<5>{}, c0); break;
+        case 6: batch(Cols<6>{}, c0); break;
+        case 7: batch(Cols<7>{}, c0); break;
         default: break;
     }
 #pragma unroll
