@@ -288,9 +288,9 @@ hms_status hms_tune_candidates(int32_t restarts, int32_t loss_mode, int32_t* cod
 /*
  * Number of kernel table entries (host only): schedule table indices run
  * from 1 to this count.  Every entry computes the same values; they differ
- * in how lanes, restarts and rows map onto wavefronts and, for the
- * unsat-masked loss, in whether a bitset lets the backward pass skip the
- * adjoints of satisfied clauses.
+ * in how lanes, restarts and rows map onto wavefronts, in how many columns
+ * of a row one load batch takes and, for the unsat-masked loss, in whether
+ * a bitset lets the backward pass skip the adjoints of satisfied clauses.
  */
 int32_t hms_schedule_count(void);
 
