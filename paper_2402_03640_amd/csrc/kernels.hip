@@ -166,6 +166,13 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& A, const int bx) {
     for (int pass = 0; pass < passes; ++pass) {
         const int rowin0 = chunk * A.U + pass * (W * UR) + s * UR;
         const uint32_t* e = A.ent + d.base + rowin0;
+        // clause weights go out with the entry loads: every row of a tile,
+        // padding included, has one, so the load needs no guard
+        int64_t wrow[UR];
+        if (A.w != nullptr) {
+#pragma unroll
+            for (int j = 0; j < UR; ++j) wrow[j] = A.w[(size_t)tile * kTile + rowin0 + j];
+        }
         float f[UR][V];
         uint32_t allf[UR][V];
 #pragma unroll
@@ -246,7 +253,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& A, const int bx) {
             // clause weight: a_j = (2/m) mu_j w_j f_j, cost and loss weighted
             // (w = 1 leaves every value bitwise unchanged)
             int64_t wj = 1;
-            if (A.w != nullptr && real) wj = A.w[(size_t)tile * kTile + rowin0 + j];
+            if (A.w != nullptr && real) wj = wrow[j];
             const float wf = (float)wj;
             VecF<V> av;
             bool any_mu = false;
@@ -376,6 +383,16 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
 #pragma unroll
     for (int u = 0; u < NT; ++u)
         if (d[u].len <= 16) lmax = d[u].len > lmax ? d[u].len : lmax;
+    // clause weights go out before the gathers (rows of tiles past the end
+    // read tile 0's, unused)
+    int64_t wrow[NT];
+    if (A.w != nullptr) {
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int tile = tc * NT + u;
+            wrow[u] = A.w[(size_t)(tile < A.ntiles ? tile : 0) * kTile + lane];
+        }
+    }
     float f[NT];
     uint32_t allf[NT];
 #pragma unroll
@@ -442,7 +459,7 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
         const bool taut = (d[u].flags & 1u) != 0;
         const size_t row = (size_t)tile * kTile + lane;
         int64_t wj = 1;
-        if (A.w != nullptr && real) wj = A.w[row];
+        if (A.w != nullptr && real) wj = wrow[u];
         const float wf = (float)wj;
         const bool unsat = real && !taut && (allf[u] >> 31) != 0;
         const bool mu = real && (A.all_mode ? true : unsat);
