@@ -319,10 +319,11 @@ def make_workload(name):
     return dict(name=name, n=n, m=m, R=R, T=T, K=K, lits=lits, desc=desc, weights=weights, uniform=uniform)
 
 
-# the structured workload's schedule: table entry 37 (one lane per row, the
-# unsat bitset, two clause tiles per forward wavefront), 64 rows per unit,
-# which the tuner picks for it (the sweep under profiles/sweeps)
-STRUCTURED_SCHEDULE = 37 | (64 << 8)
+# the structured workload's schedule: table entry 41 (one lane per row, two
+# clause tiles per forward wavefront, occurrence slots: the forward leaves each
+# occurrence's adjoint where the backward reads it in entry order), 64 rows per
+# unit, which the untimed rule takes for it (the sweep under profiles/sweeps)
+STRUCTURED_SCHEDULE = 41 | (64 << 8)
 
 
 def structured_record(kernel_iters=100, solves=3):

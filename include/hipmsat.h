@@ -387,6 +387,8 @@ typedef struct {
     const int32_t* seg_row;          /* [seg_rows] row of each segment; the identity, since a heavy
                                         variable's segments are consecutive rows in segment order */
     const int32_t* var_old;          /* [n] new -> original */
+    const uint32_t* c_slot;          /* [c_ent_len] v_ent index of the same occurrence | sign << 31, or
+                                        0xffffffff for padding; NULL when v_ent_len >= 2^31 */
     void* priv;
 } hms_plan_view;
 

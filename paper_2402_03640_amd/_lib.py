@@ -81,7 +81,8 @@ class PlanView(C.Structure):
                 ("nnz", C.c_int64), ("c_ent_len", C.c_int64), ("v_ent_len", C.c_int64),
                 ("c_tile", C.c_void_p), ("c_ent", C.c_void_p), ("c_row_orig", C.c_void_p),
                 ("v_tile", C.c_void_p), ("v_ent", C.c_void_p), ("seg_first", C.c_void_p),
-                ("seg_row", C.c_void_p), ("var_old", C.c_void_p), ("priv", C.c_void_p)]
+                ("seg_row", C.c_void_p), ("var_old", C.c_void_p), ("c_slot", C.c_void_p),
+                ("priv", C.c_void_p)]
 
 
 EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_cnf",
@@ -571,7 +572,7 @@ class Plan:
         try:
             for k, _ in PlanView._fields_:
                 if k not in ("c_tile", "c_ent", "c_row_orig", "v_tile", "v_ent", "seg_first",
-                             "seg_row", "var_old", "priv"):
+                             "seg_row", "var_old", "c_slot", "priv"):
                     setattr(self, k, getattr(v, k))
 
             def arr(ptr, count, dt):
@@ -588,5 +589,6 @@ class Plan:
             self.seg_first = arr(v.seg_first, v.n_heavy + 1 if v.n_heavy else 0, np.int32)
             self.seg_row = arr(v.seg_row, v.seg_rows, np.int32)
             self.var_old = arr(v.var_old, v.n, np.int32)
+            self.c_slot = arr(v.c_slot, v.c_ent_len, np.uint32)
         finally:
             lib().hms_plan_view_free(C.byref(v))

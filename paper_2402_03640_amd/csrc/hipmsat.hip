@@ -25,6 +25,7 @@ struct hms_cnf {
     void* arena = nullptr;
     hms::TileDesc* c_tile = nullptr;
     uint32_t* c_ent = nullptr;
+    uint32_t* c_slot = nullptr;  // variable-side entry of each clause-side entry (slot schedules)
     hms::TileDesc* v_tile = nullptr;
     uint32_t* v_ent = nullptr;
     int32_t* seg_first = nullptr;
@@ -123,7 +124,11 @@ struct SyncOnExit {
 // four times the wavefronts), else two (entry 38).
 int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0, int32_t n_act = 0) {
     if (R <= 1) {
-        if (loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 20)) return 37;
+        // the slot schedules from 2^17 nonzeros with the unsat-masked loss:
+        // two clause tiles per forward wavefront past 2^22, one below
+        if (loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 22)) return 41;
+        if (loss_mode == HMS_LOSS_UNSAT && nnz > (1 << 17)) return 42;
+        if (loss_mode != HMS_LOSS_UNSAT && nnz > (1 << 20)) return 36;
         // long backward batches; four lanes per variable row (more wavefronts)
         // while the rows are few, two beyond
         return n_act <= (1 << 14) ? 39 : 38;
@@ -138,7 +143,7 @@ int auto_schedule(int32_t R, int loss_mode, int64_t nnz = 0, int32_t n_act = 0) 
 }
 
 struct Shape {
-    int sched, P, V, UR, U, chunks, mask, nt;
+    int sched, P, V, UR, U, chunks, mask, nt, slot;
     int Ub, chunks_b;  // rows per work unit and units per tile of the backward pass
     hms::Blocking B;
     int64_t n_tc, fwd_blocks64, bwd_blocks64;
@@ -160,11 +165,16 @@ hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_m
     sh.sched = idx == 0 ? auto_schedule(R, loss_mode, P.nnz, P.n_act) : idx;
     if (hms::kSchedules[sh.sched].mask && (loss_mode != HMS_LOSS_UNSAT || !allow_mask))
         sh.sched = hms::kSchedules[sh.sched].twin;
+    // slot schedules: one restart, the unsat-masked loss, and a plan with the
+    // occurrence map; elsewhere their twin
+    if (hms::kSchedules[sh.sched].slot && (R != 1 || loss_mode != HMS_LOSS_UNSAT || !allow_mask || !P.slot_ok))
+        sh.sched = hms::kSchedules[sh.sched].twin;
     const hms::Schedule& c = hms::kSchedules[sh.sched];
     sh.P = c.P;
     sh.V = c.V;
     sh.UR = c.UR;
     sh.mask = c.mask;
+    sh.slot = c.slot;
     if (R % sh.V != 0) return fail(HMS_ERR_ARG, "schedule vector width does not divide the restart count");
     if (U == 0) U = hms::default_rows_per_unit(sh.sched);
     if (Ub == 0) Ub = U;
@@ -213,10 +223,12 @@ struct State {
     double* loss_mid;
     hms::StepState* st;
     uint8_t* out_assign;
+    float* contrib;  // slot schedules
 };
 
 enum { kOffX, kOffM, kOffV, kOffT, kOffA, kOffG, kOffSeg, kOffCnt, kOffLoss, kOffBest, kOffMask, kOffBestC,
-       kOffCurC, kOffBestS, kOffImp, kOffCurL, kOffCntMid, kOffLossMid, kOffSt, kOffN };
+       kOffCurC, kOffBestS, kOffImp, kOffCurL, kOffCntMid, kOffLossMid, kOffSt, kOffContrib, kOffN };
+constexpr size_t kNoOff = ~size_t(0);  // a piece the solve does not have
 
 // Units per stage-1 reduce chunk: a fixed function of the unit count.
 int32_t reduce_chunk(int64_t n_units) { return (int32_t)std::max<int64_t>(64, (n_units + 1023) / 1024); }
@@ -256,6 +268,7 @@ void layout_state(const hms::HostPlan& P, const Shape& sh, bool moments, bool gr
     off[kOffCntMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc, R), 1) * R * 8);
     off[kOffLossMid] = L.add((size_t)std::max(reduce_chunks(sh.n_tc, R), 1) * R * 8);
     off[kOffSt] = L.add(256 + (size_t)std::max(P.n, 1));  // step state, then out_assign at +256
+    off[kOffContrib] = sh.slot ? L.add(P.v_ent.size() * 4) : kNoOff;
 }
 
 State bind_state(const Arena& A, const size_t off[kOffN], bool moments, bool grad, bool best) {
@@ -280,6 +293,7 @@ State bind_state(const Arena& A, const size_t off[kOffN], bool moments, bool gra
     S.loss_mid = A.at<double>(off[kOffLossMid]);
     S.st = A.at<hms::StepState>(off[kOffSt]);
     S.out_assign = A.at<uint8_t>(off[kOffSt] + 256);
+    S.contrib = off[kOffContrib] != kNoOff ? A.at<float>(off[kOffContrib]) : nullptr;
     return S;
 }
 
@@ -299,6 +313,8 @@ hms::InitArgs make_init(const hms_cnf* C, const Shape& sh, const State& S) {
     ia.vv = S.v;
     ia.a = S.a;
     ia.umask = S.umask;
+    ia.contrib = S.contrib;
+    ia.contrib_n = S.contrib ? (int64_t)P.v_ent.size() : 0;
     ia.best_a = S.best_a;
     ia.st = S.st;
     if (S.best_a) {
@@ -337,6 +353,8 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     f.umask = S.umask;
     f.umask_words = umask_words(P);
     f.w = C->c_w;
+    f.slot = C->c_slot;
+    f.contrib = S.contrib;
     f.two_over_m = P.m > 0 ? (float)(2.0 / (double)P.m) : 0.0f;
     f.cnt_part = S.cnt_part;
     f.loss_part = S.loss_part;
@@ -360,6 +378,7 @@ Launch make_launch(const hms_cnf* C, const Shape& sh, const State& S, int opt, i
     b.a = S.a;
     b.umask = S.umask;
     b.umask_words = umask_words(P);
+    b.contrib = S.contrib;
     b.seg_part = S.seg_part;
     b.x = S.x;
     b.m = S.m;
@@ -442,6 +461,7 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     size_t o_sf = L.add(P.seg_first.size() * 4);
     size_t o_vo = L.add(P.var_old.size() * 4);
     size_t o_w = L.add(P.c_w.size() * 8);
+    size_t o_cs = L.add(P.c_slot.size() * 4);
     void* base = nullptr;
     hipError_t e = hipMalloc(&base, std::max<size_t>(L.off, 256));
     if (e != hipSuccess) {
@@ -458,6 +478,7 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     C->seg_first = (int32_t*)(b + o_sf);
     C->var_old = (int32_t*)(b + o_vo);
     C->c_w = P.c_w.empty() ? nullptr : (int64_t*)(b + o_w);
+    C->c_slot = P.c_slot.empty() ? nullptr : (uint32_t*)(b + o_cs);
     C->struct_bytes = (int64_t)L.off;
     hms_status r = HMS_OK;
     if (!r) r = upload(P.c_tile, C->c_tile, s);
@@ -467,6 +488,7 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     if (!r) r = upload(P.seg_first, C->seg_first, s);
     if (!r) r = upload(P.var_old, C->var_old, s);
     if (!r) r = upload(P.c_w, C->c_w, s);
+    if (!r) r = upload(P.c_slot, C->c_slot, s);
     if (!r) {
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) r = fail(HMS_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
@@ -724,6 +746,7 @@ std::vector<int32_t> tune_candidates(int32_t R, int loss_mode) {
         const hms::Schedule& c = hms::kSchedules[idx];
         if (R % c.V) continue;
         if (c.mask && loss_mode != HMS_LOSS_UNSAT) continue;
+        if (c.slot && (R != 1 || loss_mode != HMS_LOSS_UNSAT)) continue;
         if (c.P * c.V > 4 * std::max(R, 1)) continue;  // mostly idle lanes
         if (c.nt > 1 && R > 4) continue;  // many restarts already give every wavefront enough reads
         const int per = (64 / c.P) * c.UR;
@@ -2031,6 +2054,7 @@ hms_status hms_plan_view_build(int32_t n_vars, const int32_t* lits, int64_t n_li
     out->seg_first = P->seg_first.data();
     out->seg_row = P->seg_row.data();
     out->var_old = P->var_old.data();
+    out->c_slot = P->c_slot.empty() ? nullptr : P->c_slot.data();
     out->priv = P;
     return HMS_OK;
 }

@@ -29,6 +29,7 @@ const Schedule kSchedules[kNumSchedules + 1] = {
     {4, 4, 1, 0, 0},  {8, 4, 1, 0, 0},  {8, 2, 1, 0, 0},                                      // 33..35
     {1, 1, 1, 0, 0, 2}, {1, 1, 1, 1, 36, 2},                                                  // 36..37
     {2, 1, 1, 0, 0, 1, 16}, {4, 1, 1, 0, 0, 1, 16}, {1, 1, 1, 0, 0, 2, 16},                    // 38..40
+    {1, 1, 1, 0, 40, 2, 16, 1}, {1, 1, 1, 0, 40, 1, 16, 1},                                  // 41..42
 };
 
 int default_rows_per_unit(int sched) {
@@ -366,7 +367,7 @@ __device__ __forceinline__ uint32_t unit_entry(const uint32_t* ent, const TileDe
 // Every row is computed exactly as the one-tile kernel computes it (FP32 sum
 // in column order up to 16 columns, FP64 beyond).
 // ---------------------------------------------------------------------------
-template <int NT, bool EVAL, bool MASK>
+template <int NT, bool EVAL, int MASK>
 __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
     const int lane = threadIdx.x & 63;
     if (bx == 0 && threadIdx.x == 0 && A.st != nullptr)
@@ -451,6 +452,13 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
     }
     int64_t cnt = 0;
     double los = 0.0;
+    bool put[NT];       // slot mode: row's occurrences get a value this step
+    uint32_t pval[NT];  // slot mode: the row's adjoint bits (0 outside the loss)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        put[u] = false;
+        pval[u] = 0u;
+    }
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
         const int tile = tc * NT + u;
@@ -468,7 +476,7 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
             cnt += unsat ? wj : 0;
             los += mu ? ((double)f[u] * (double)f[u]) * (double)wj : 0.0;
         }
-        if constexpr (MASK) {
+        if constexpr (MASK == 1) {
             const uint64_t bits = __ballot(mu ? 1 : 0);
             if (mu) ag[row] = av;
             if (lane == 0) {
@@ -476,8 +484,45 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
                 w[0] = (uint32_t)bits;
                 w[1] = (uint32_t)(bits >> 32);
             }
+        } else if constexpr (MASK == 2) {
+            // the tile's bits of the step before say which rows still hold
+            // their adjoint in the occurrence slots; this step's replace them
+            const uint64_t bits = __ballot(mu ? 1 : 0);
+            uint32_t* w = A.umask + (size_t)rg * A.umask_words + (size_t)tile * 2;
+            const uint64_t was = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+            put[u] = mu || ((was >> lane) & 1u) != 0;
+            pval[u] = __float_as_uint(av);
+            if (lane == 0) {
+                w[0] = (uint32_t)bits;
+                w[1] = (uint32_t)(bits >> 32);
+            }
         } else {
             ag[row] = av;
+        }
+    }
+    if constexpr (MASK == 2) {
+        // every occurrence of a row in the loss, or that was in it one step
+        // ago, gets the row's adjoint (signed by its literal) or 0 in its
+        // variable-side slot; slots of other rows already hold 0.  The slot
+        // loads of a batch go out together.
+        uint32_t smax = 0;
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+            if (__ballot(put[u] ? 1 : 0) != 0) smax = d[u].len > smax ? d[u].len : smax;
+        for (uint32_t c0 = 0; c0 < smax; c0 += 8) {
+            uint32_t sl[8][NT];
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+                for (int u = 0; u < NT; ++u)
+                    sl[cc][u] = (put[u] && c0 + cc < d[u].len)
+                                    ? A.slot[(size_t)d[u].base + (size_t)(c0 + cc) * kTile + lane]
+                                    : kNoSlot;
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+                for (int u = 0; u < NT; ++u)
+                    if (sl[cc][u] != kNoSlot) A.contrib[sl[cc][u] & kIdx] = __uint_as_float(pval[u] ^ (sl[cc][u] & kSign));
         }
     }
     if (EVAL) {
@@ -493,12 +538,12 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
     }
 }
 
-template <int NT, bool EVAL, bool MASK>
+template <int NT, bool EVAL, int MASK>
 __global__ __launch_bounds__(256) void k_fwd_nt(FwdArgs A) {
     fwd_nt_body<NT, EVAL, MASK>(A, blockIdx.x);
 }
 
-template <int NT, bool EVAL, bool MASK>
+template <int NT, bool EVAL, int MASK>
 __global__ __launch_bounds__(256) void k_fwd_nt_multi(const FwdArgs* __restrict__ As,
                                                       const int32_t* __restrict__ b0, int32_t n) {
     const int i = owner(b0, n, blockIdx.x);
@@ -587,9 +632,10 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int 
 // adjoint of a clause is read only when its unsat bit is set (it is 0
 // otherwise).
 // ---------------------------------------------------------------------------
-template <int P, int V, int UR, int OPT, bool MASK, int CB>
+template <int P, int V, int UR, int OPT, int MASK, int CB>
 __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
     static_assert(CB == kChunkB || (CB == 2 * kChunkB && V * UR == 1), "long batches take one value per lane");
+    static_assert(MASK != 2 || (P == 1 && V == 1 && UR == 1), "slot mode takes one restart and one row per lane");
     constexpr int W = 64 / P;
     const int lane = threadIdx.x & 63;
     const int s = lane / P;
@@ -615,6 +661,7 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
         const int rowin0 = chunk * A.U + pass * (W * UR) + s * UR;
         if (rowin0 >= (int)d.nreal) break;
         const uint32_t* e = A.ent + d.base + rowin0;
+        const float* cs = MASK == 2 ? A.contrib + d.base + rowin0 : nullptr;
         double G[UR][V];
 #pragma unroll
         for (int j = 0; j < UR; ++j)
@@ -637,13 +684,23 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
         // padding column is read)
         auto batch = [&](auto nc, const uint32_t c0) {
             constexpr int NC = decltype(nc)::value;
+            if constexpr (MASK == 2) {
+                // slot mode: the forward left each occurrence's signed
+                // adjoint (or 0) in the slot parallel to its entry
+                float cv[NC];
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) cv[cc] = cs[(size_t)(c0 + cc) * kTile];
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc) G[0][0] = G[0][0] + (double)cv[cc];
+                return;
+            }
             uint32_t en[NC][UR];
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc)
 #pragma unroll
                 for (int j = 0; j < UR; ++j) en[cc][j] = ldc(e + (size_t)(c0 + cc) * kTile + j);
             VecF<V> av[NC][UR];
-            if constexpr (MASK) {
+            if constexpr (MASK == 1) {
                 uint32_t w[NC][UR];
 #pragma unroll
                 for (int cc = 0; cc < NC; ++cc)
@@ -713,12 +770,12 @@ __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
     }
 }
 
-template <int P, int V, int UR, int OPT, bool MASK, int CB = kChunkB>
+template <int P, int V, int UR, int OPT, int MASK, int CB = kChunkB>
 __global__ __launch_bounds__(256) void k_bwd(BwdArgs A) {
     bwd_body<P, V, UR, OPT, MASK, CB>(A, blockIdx.x);
 }
 
-template <int P, int V, int UR, int OPT, bool MASK, int CB = kChunkB>
+template <int P, int V, int UR, int OPT, int MASK, int CB = kChunkB>
 __global__ __launch_bounds__(256) void k_bwd_multi(const BwdArgs* __restrict__ As, const int32_t* __restrict__ b0,
                                                    int32_t n) {
     const int i = owner(b0, n, blockIdx.x);
@@ -991,6 +1048,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
         }
     }
     if (A.umask != nullptr && idx < A.umask_words) A.umask[idx] = 0u;
+    if (A.contrib != nullptr && idx < A.contrib_n) A.contrib[idx] = 0.0f;
     if (idx == 0 && A.st != nullptr) {
         A.st->t = A.step0;
         A.st->step_size = 0.0f;
@@ -1061,10 +1119,10 @@ template <int P, int V, int UR, int MASK, int CB = kChunkB>
 hipError_t bwd_multi_for(int opt, const MultiLaunch& M, hipStream_t s) {
     const BwdArgs* a = static_cast<const BwdArgs*>(M.args);
     if (opt == kAdam)
-        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kAdam, MASK != 0, CB>), dim3(M.blocks), dim3(256), 0, s, a, M.b0,
+        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kAdam, MASK, CB>), dim3(M.blocks), dim3(256), 0, s, a, M.b0,
                            M.n);
     else
-        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kSgd, MASK != 0, CB>), dim3(M.blocks), dim3(256), 0, s, a, M.b0,
+        hipLaunchKernelGGL((k_bwd_multi<P, V, UR, kSgd, MASK, CB>), dim3(M.blocks), dim3(256), 0, s, a, M.b0,
                            M.n);
     return hipGetLastError();
 }
@@ -1072,9 +1130,9 @@ hipError_t bwd_multi_for(int opt, const MultiLaunch& M, hipStream_t s) {
 template <int NT, int MASK, int CB = kChunkB>
 hipError_t fwd_for_nt(bool eval, const FwdArgs& A, int blocks, hipStream_t s) {
     if (eval)
-        hipLaunchKernelGGL((k_fwd_nt<NT, true, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_fwd_nt<NT, true, MASK>), dim3(blocks), dim3(256), 0, s, A);
     else
-        hipLaunchKernelGGL((k_fwd_nt<NT, false, MASK != 0>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_fwd_nt<NT, false, MASK>), dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
@@ -1082,20 +1140,20 @@ template <int NT, int MASK, int CB = kChunkB>
 hipError_t fwd_multi_for_nt(bool eval, const MultiLaunch& M, hipStream_t s) {
     const FwdArgs* a = static_cast<const FwdArgs*>(M.args);
     if (eval)
-        hipLaunchKernelGGL((k_fwd_nt_multi<NT, true, MASK != 0>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
+        hipLaunchKernelGGL((k_fwd_nt_multi<NT, true, MASK>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
     else
-        hipLaunchKernelGGL((k_fwd_nt_multi<NT, false, MASK != 0>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
+        hipLaunchKernelGGL((k_fwd_nt_multi<NT, false, MASK>), dim3(M.blocks), dim3(256), 0, s, a, M.b0, M.n);
     return hipGetLastError();
 }
 
 template <int P, int V, int UR, int MASK, int CB = kChunkB>
 hipError_t bwd_for(int opt, const BwdArgs& A, int blocks, hipStream_t s) {
     if (opt == kAdam)
-        hipLaunchKernelGGL((k_bwd<P, V, UR, kAdam, MASK != 0, CB>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kAdam, MASK, CB>), dim3(blocks), dim3(256), 0, s, A);
     else if (opt == kSgd)
-        hipLaunchKernelGGL((k_bwd<P, V, UR, kSgd, MASK != 0, CB>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kSgd, MASK, CB>), dim3(blocks), dim3(256), 0, s, A);
     else
-        hipLaunchKernelGGL((k_bwd<P, V, UR, kGrad, MASK != 0, CB>), dim3(blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((k_bwd<P, V, UR, kGrad, MASK, CB>), dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
@@ -1155,6 +1213,8 @@ hipError_t bwd_multi_for_nt(int opt, const MultiLaunch& M, hipStream_t s) {
         case 38: return FN<2, 1, 1, 0, 16>(__VA_ARGS__);   \
         case 39: return FN<4, 1, 1, 0, 16>(__VA_ARGS__);   \
         case 40: return FN##_nt<2, 0, 16>(__VA_ARGS__);    \
+        case 41: return FN##_nt<2, 2, 16>(__VA_ARGS__);    \
+        case 42: return FN##_nt<1, 2, 16>(__VA_ARGS__);    \
         default: return hipErrorInvalidValue;              \
     }
 
@@ -1167,7 +1227,7 @@ hipError_t launch_bwd(int sched, int opt, const BwdArgs& A, int blocks, hipStrea
     if (blocks <= 0) {
         // still advance the step counter
         if (opt != kGrad) {
-            hipLaunchKernelGGL((k_bwd<1, 1, 1, kAdam, false>), dim3(1), dim3(256), 0, s, A);
+            hipLaunchKernelGGL((k_bwd<1, 1, 1, kAdam, 0>), dim3(1), dim3(256), 0, s, A);
             return hipGetLastError();
         }
         return hipSuccess;
@@ -1240,6 +1300,7 @@ hipError_t launch_init(const InitArgs& A, hipStream_t s) {
     int64_t total = (int64_t)A.n * A.B.R;
     if (total < A.B.R) total = A.B.R;
     if (total < A.umask_words) total = A.umask_words;
+    if (A.contrib != nullptr && total < A.contrib_n) total = A.contrib_n;
     if (total < 1) total = 1;
     const int blocks = (int)((total + 255) / 256);
     hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, A);

@@ -16,6 +16,9 @@
 //   cnt_part, loss_part : [units][R]     per-unit unsatisfied weight (int64) / loss partials
 //   umask      : [RG][c_tiles * 2 + 1] bitset words over clause rows: bit j of group g =
 //                clause j unsatisfied for some restart of group g (unsat-masked loss)
+//   contrib    : [v_ent entries] FP32, slot schedules only (one restart, unsat-masked
+//                loss): the signed adjoint of each occurrence, at the index of its
+//                variable-side entry, 0 for clauses outside the loss
 //
 // t stores tanh(x) with its sign bit forced to "x does not round to true":
 // sign(t) = 1 iff !(x > 0).  A literal entry holds the variable index and the
@@ -61,6 +64,8 @@ struct FwdArgs {
     float* a;
     uint32_t* umask;     // written when the schedule keeps the unsat bitset
     const int64_t* w;    // weight of each clause row (weighted MaxSAT), or null: weight 1
+    const uint32_t* slot; // slot schedules: variable-side entry of each clause-side entry | sign
+    float* contrib;       // slot schedules: occurrence adjoints (written where they change)
     float two_over_m;
     int64_t* cnt_part;   // unsatisfied weight per unit
     double* loss_part;
@@ -78,6 +83,7 @@ struct BwdArgs {
     int32_t umask_words; // bitset words per restart group
     const float* a;
     const uint32_t* umask;
+    const float* contrib; // slot schedules: occurrence adjoints, parallel to ent
     double* seg_part;
     float* x;
     float* m;
@@ -140,6 +146,8 @@ struct InitArgs {
     float* vv;
     float* a;
     uint32_t* umask;
+    float* contrib;           // slot schedules: zeroed (contrib_n floats), else null
+    int64_t contrib_n;
     uint8_t* best_a;
     int64_t* best;
     int32_t* best_step;
@@ -154,12 +162,19 @@ struct InitArgs {
 // adjoint gathers of clauses satisfied in every restart of the group; they
 // need U >= 32 and UR = 1.  `twin` is the schedule with the same arithmetic
 // and no bitset that runs in their place when the loss is not masked.
+// Slot schedules (one restart, unsat-masked loss) have the forward write each
+// occurrence's signed adjoint into the slot parallel to its variable-side
+// entry, for the clauses in the loss and those that just left it, so the
+// backward reads its terms in entry order with no gather; they fall back to
+// `twin` elsewhere.  The terms and their order are those of every schedule.
 struct Schedule {
     int P, V, UR, mask, twin;
-    int nt = 1;  // whole clause tiles per forward wavefront (more than 1 only with P = V = UR = 1)
-    int cb = 8;  // columns per backward load batch (16 only with V = UR = 1)
+    int nt = 1;    // whole clause tiles per forward wavefront (more than 1 only with P = V = UR = 1;
+                   // slot schedules always take whole tiles)
+    int cb = 8;    // columns per backward load batch (16 only with V = UR = 1)
+    int slot = 0;  // slot schedule
 };
-constexpr int kNumSchedules = 40;
+constexpr int kNumSchedules = 42;
 extern const Schedule kSchedules[kNumSchedules + 1];
 
 int default_rows_per_unit(int sched);

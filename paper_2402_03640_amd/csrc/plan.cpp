@@ -524,6 +524,8 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
     std::vector<int64_t> voff((size_t)n + 1, 0);
     for (int32_t i = 0; i < n; ++i) voff[i + 1] = voff[i] + P.degree[i];
     std::vector<uint32_t> occ((size_t)P.nnz);
+    // clause-side entry of each occurrence, carried through both scatters
+    std::vector<uint32_t> occ_src((size_t)P.nnz);
     {
         // Two stable scatters with few write streams each: (1) (variable,
         // kernel row) pairs into blocks of 1024 consecutive variables, each
@@ -537,6 +539,7 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
         for (int32_t b = 0; b < nblk; ++b)
             bstart[b + 1] = voff[std::min<int64_t>((int64_t)(b + 1) << kShift, n)];
         std::vector<uint64_t> pairs((size_t)P.nnz);  // variable << 32 | (row | sign)
+        std::vector<uint32_t> psrc((size_t)P.nnz);   // clause-side entry of each pair
         std::vector<std::vector<int64_t>> cnt((size_t)T);
         par(T, [&](int t) {
             cnt[(size_t)t].assign((size_t)nblk, 0);
@@ -557,10 +560,14 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
             std::vector<int64_t>& fill = cnt[(size_t)t];
             for (int64_t r = part_lo(nr, t, T); r < part_lo(nr, t + 1, T); ++r) {
                 const Row& R = rows[(size_t)r];
+                const int32_t k = krow[(size_t)r];
+                const uint32_t cb = P.c_tile[(size_t)(k / kTile)].base + (uint32_t)(k % kTile);
                 for (int32_t c = 0; c < R.len; ++c) {
                     const uint32_t e = flat[(size_t)R.off + c];
                     const uint32_t v = e & kIdx;
-                    pairs[(size_t)fill[v >> kShift]++] = ((uint64_t)v << 32) | (uint32_t)krow[(size_t)r] | (e & kSign);
+                    const int64_t q = fill[v >> kShift]++;
+                    pairs[(size_t)q] = ((uint64_t)v << 32) | (uint32_t)k | (e & kSign);
+                    psrc[(size_t)q] = cb + (uint32_t)c * kTile;
                 }
             }
         });
@@ -571,7 +578,9 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
                 fill.assign(voff.begin() + v0, voff.begin() + std::max(v0, v1));
                 for (int64_t p = bstart[(size_t)b]; p < bstart[(size_t)b + 1]; ++p) {
                     const uint64_t q = pairs[(size_t)p];
-                    occ[(size_t)fill[(size_t)((int64_t)(q >> 32) - v0)]++] = (uint32_t)q;
+                    const int64_t o = fill[(size_t)((int64_t)(q >> 32) - v0)]++;
+                    occ[(size_t)o] = (uint32_t)q;
+                    occ_src[(size_t)o] = psrc[(size_t)p];
                 }
             }
         });
@@ -609,6 +618,28 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
                    P.v_tile, P.v_ent, err);
     if (rc) return rc;
     P.v_tiles = (int32_t)P.v_tile.size();
+    // the inverse map, clause-side entry -> variable-side entry of the same
+    // occurrence (each variable-side entry is written by one thread)
+    P.slot_ok = P.v_ent.size() < (size_t)kIdx;
+    if (P.slot_ok) {
+        P.c_slot.assign(P.c_ent.size(), kNoSlot);
+        auto put = [&](int32_t tile, int32_t q, int32_t c, int64_t o) {
+            const uint32_t vpos = P.v_tile[(size_t)tile].base + (uint32_t)c * kTile + (uint32_t)q;
+            P.c_slot[occ_src[(size_t)o]] = vpos | (occ[(size_t)o] & kSign);
+        };
+        par(T, [&](int t) {
+            for (int64_t r = part_lo(P.seg_rows, t, T); r < part_lo(P.seg_rows, t + 1, T); ++r) {
+                const Seg& g = segs[(size_t)r];
+                for (int32_t c = 0; c < g.len; ++c)
+                    put((int32_t)(r / kTile), (int32_t)(r % kTile), c, g.off + (int64_t)c * g.stride);
+            }
+            for (int64_t r = part_lo(n_light, t, T); r < part_lo(n_light, t + 1, T); ++r) {
+                const int32_t d = P.degree[P.n_heavy + r];
+                for (int32_t c = 0; c < d; ++c)
+                    put(P.seg_tiles + (int32_t)(r / kTile), (int32_t)(r % kTile), c, voff[P.n_heavy + r] + c);
+            }
+        });
+    }
     P.build_threads = T;
     return kOk;
 }

@@ -15,6 +15,7 @@ constexpr int kSplitDense = 256;   // longest row kept whole when most rows exce
 constexpr int kWideSegs = 1024;    // variables with more segments combine over 1024 slots (else 64)
 constexpr uint32_t kSign = 0x80000000u;
 constexpr uint32_t kIdx = 0x7fffffffu;
+constexpr uint32_t kNoSlot = 0xffffffffu;  // clause-side entry with no occurrence (padding)
 
 // Per-tile descriptor (16 bytes).  Entry (c, rowin) of the tile sits at
 // ent[base + c * kTile + rowin]; rows rowin >= nreal are padding.
@@ -45,6 +46,11 @@ struct HostPlan {
     std::vector<TileDesc> c_tile;
     std::vector<uint32_t> c_ent;     // new variable index | sign bit (negated literal)
     std::vector<int32_t> c_row_orig; // [c_tiles * kTile] original clause of a row, -1 = padding
+    // [c_ent.size()] where each clause-side entry sits on the variable side:
+    // the index into v_ent of the same occurrence | its sign bit, or kNoSlot
+    // for padding; empty when the variable side has 2^31 entries or more
+    std::vector<uint32_t> c_slot;
+    bool slot_ok = false;            // c_slot was built (the slot schedules can run)
 
     // variable side (transposed sums); rows are whole light variables or
     // fixed-length segments of heavy variables

@@ -36,8 +36,11 @@ def footprint_bytes(n: int, m: int, n_lits: int, restarts: int = 1, weighted: bo
     clause weights) plus per-restart state (x, m, v, t, adjoint, best bytes,
     heavy partials)."""
     L = max(n_lits, 0)
-    struct = 4 * (2 * L + m + n + 2) + 16 * (m + n) // 64 + 4 * n + 8 * L // 64 + (8 * (m + 64) if weighted else 0)
+    # clause-side and variable-side entries and the map between them
+    struct = 4 * (3 * L + m + n + 2) + 16 * (m + n) // 64 + 4 * n + 8 * L // 64 + (8 * (m + 64) if weighted else 0)
     state = restarts * (16 * (n + 1) + 4 * (m + 64) + (n + 1) + 8 * L // 64) + 4096
+    if restarts == 1:
+        state += 4 * L + 4 * L // 8  # occurrence slots of the slot schedule
     return int(1.25 * (struct + state)) + (1 << 16)
 
 

@@ -169,7 +169,7 @@ def test_single_restart_schedules_bitwise():
     cnf = hm.load_cnf(n, lits)
     assert cnf.info["n_heavy"] > 0
     ref = None
-    for sched in [1, 2, 3, 4, 11, 23, 24, 25, 24 | (32 << 8), 25 | (64 << 8), 2 | (32 << 8), 36, 37, 38, 39, 40]:
+    for sched in [1, 2, 3, 4, 11, 23, 24, 25, 24 | (32 << 8), 25 | (64 << 8), 2 | (32 << 8), 36, 37, 38, 39, 40, 41, 42]:
         res = hm.solve(cnf, steps=60, restarts=1, eval_every=7, seed=5, lr=1e-2, schedule=sched,
                        want_x=True)
         cur = (res.restart_best.copy(), res.restart_step.copy(),
@@ -180,6 +180,74 @@ def test_single_restart_schedules_bitwise():
         else:
             for a, b in zip(cur, ref):
                 np.testing.assert_array_equal(a, b)
+
+
+def _slot_instances(rng):
+    """One-restart instances for the slot schedule: uniform, skewed (heavy
+    rows in segments), mixed, dense 5-CNF (rows kept whole), and one with
+    long clauses, repeats, tautologies and empty clauses."""
+    out = [(3000, cnfgen.uniform_kcnf(3000, 12900, 3, seed=1)),
+           (20000, cnfgen.structured_cnf(20000, 90000, seed=2)),
+           (2000, cnfgen.mixed_kcnf(2000, 8400, seed=3)),
+           (1200, cnfgen.uniform_kcnf(1200, 20400, 5, seed=4))]
+    n = 500
+    cl = cnfgen.to_clauses(cnfgen.uniform_kcnf(n, 2000, 3, seed=5))
+    for _ in range(12):  # long clauses (FP64 scores past 16 columns)
+        vs = rng.choice(n, size=int(rng.integers(17, 40)), replace=False) + 1
+        cl.append([int(v) if rng.random() < 0.5 else -int(v) for v in vs])
+    cl += [[], [7, -7, 9], [4, 4, -5], [-11, 12, 12, -11], [], [300, -300]]
+    out.append((n, cnfgen.from_clauses(cl)))
+    return out
+
+
+def test_slot_schedule_bitwise():
+    """The slot schedule (the forward leaves each occurrence's adjoint in
+    the slot of its variable-side entry, the backward reads them in entry
+    order) gives the trajectory of its twin and of the bitset schedule bit
+    for bit, while clauses enter and leave the loss every step (large steps,
+    both optimizers, weights, hard clauses), in solo and grouped solves; with
+    several restarts or the unmasked loss it falls back to its twin."""
+    rng = np.random.default_rng(77)
+    for idx, (n, lits) in enumerate(_slot_instances(rng)):
+        m = int(np.count_nonzero(lits == 0))
+        for weighted in (False, True):
+            w = None
+            if weighted:
+                w = rng.integers(1, 30, size=m).astype(np.int64)
+                w[rng.random(m) < 0.02] = 10 ** 6  # hard clauses
+            cnf = hm.load_cnf(n, lits, weights=w)
+            for opt, lr, K in ((hm.SGD, 0.3, 3), (hm.ADAM, 5e-2, 1)):
+                kw = dict(steps=40, restarts=1, eval_every=K, optimizer=opt, lr=lr, seed=idx, want_x=True)
+                runs = {s: hm.solve(cnf, schedule=s, **kw) for s in (40, 37, 41, 42)}
+                ref = runs[40]
+                for s, o in runs.items():
+                    np.testing.assert_array_equal(o.restart_best, ref.restart_best, err_msg=str(s))
+                    np.testing.assert_array_equal(o.restart_step, ref.restart_step)
+                    np.testing.assert_array_equal(o.best_assignment, ref.best_assignment)
+                    np.testing.assert_array_equal(o.x_final.cpu().numpy().view(np.uint32),
+                                                  ref.x_final.cpu().numpy().view(np.uint32))
+                _say(f"slot schedule, instance {idx} weighted={weighted} opt={opt}: best {ref.best_cost}")
+            cnf.free()
+    # grouped one-restart solves under the slot schedule equal their solo solves
+    inst = _slot_instances(rng)[:3]
+    cnfs = [hm.load_cnf(n, lits) for n, lits in inst]
+    outs = hm.solve_batch(cnfs, steps=30, restarts=1, eval_every=5, seeds=[3, 4, 5], lr=5e-2, schedule=41,
+                          want_x=True)
+    for c, o, sd in zip(cnfs, outs, (3, 4, 5)):
+        a = hm.solve(c, steps=30, restarts=1, eval_every=5, seed=sd, lr=5e-2, schedule=40, want_x=True)
+        assert o.best_cost == a.best_cost and o.best_step == a.best_step
+        np.testing.assert_array_equal(o.x_final.cpu().numpy().view(np.uint32),
+                                      a.x_final.cpu().numpy().view(np.uint32))
+    # several restarts and the unmasked loss: the twin runs
+    c = cnfs[0]
+    for kw in (dict(restarts=4), dict(restarts=1, loss_mode=hm.LOSS_ALL)):
+        a = hm.solve(c, steps=20, eval_every=4, seed=9, lr=5e-2, schedule=41, want_x=True, **kw)
+        b = hm.solve(c, steps=20, eval_every=4, seed=9, lr=5e-2, schedule=40, want_x=True, **kw)
+        assert a.schedule == b.schedule
+        np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32),
+                                      b.x_final.cpu().numpy().view(np.uint32))
+    for c in cnfs:
+        c.free()
 
 
 def test_schedule_id_errors():
@@ -338,19 +406,24 @@ def test_untimed_choice_of_resident():
 
 
 def test_untimed_tiled_schedule_at_one_restart():
-    """Without timing, one-restart tiled solves take: above 2^20 nonzeros the
-    one-row-per-lane bitset schedule (table entry 37); below, 16-column
-    backward batches with four lanes per variable row (entry 39) up to 2^14
-    active variables, else two (entry 38).  Every choice gives the same result
-    bit for bit."""
+    """Without timing, one-restart tiled solves with the unsat-masked loss
+    take: above 2^22 nonzeros the slot schedule with two clause tiles per
+    forward wavefront (table entry 41), above 2^17 the one with one tile
+    (entry 42); below, 16-column backward batches with four lanes per
+    variable row (entry 39) up to 2^14 active variables, else two (entry
+    38).  With the unmasked loss above 2^20 nonzeros: two tiles per forward
+    wavefront, no slots (entry 36).  Every choice gives the same result bit
+    for bit."""
     kw = dict(steps=12, restarts=1, eval_every=4, seed=0, autotune=False, want_x=True)
-    for n, m, k, want in ((40000, 340000, 4, 37), (3000, 51000, 5, 39), (20000, 86000, 3, 38)):
+    for n, m, k, mode, want in ((400000, 1720000, 3, hm.LOSS_UNSAT, 41), (40000, 340000, 4, hm.LOSS_UNSAT, 42),
+                                (20000, 86000, 3, hm.LOSS_UNSAT, 42), (8000, 34400, 3, hm.LOSS_UNSAT, 39),
+                                (30000, 40000, 3, hm.LOSS_UNSAT, 38), (40000, 340000, 4, hm.LOSS_ALL, 36)):
         lits = cnfgen.uniform_kcnf(n, m, k, seed=n)
         cnf = hm.load_cnf(n, lits)
-        a = hm.solve(cnf, **kw)
-        _say(f"n={n} m={m} k={k} nnz={cnf.info['nnz']}: untimed schedule {a.schedule}")
+        a = hm.solve(cnf, loss_mode=mode, **kw)
+        _say(f"n={n} m={m} k={k} nnz={cnf.info['nnz']} mode {mode}: untimed schedule {a.schedule}")
         assert a.schedule & 0xFF == want
-        b = hm.solve(cnf, schedule=1, **kw)
+        b = hm.solve(cnf, schedule=1, loss_mode=mode, **kw)
         np.testing.assert_array_equal(a.x_final.cpu().numpy().view(np.uint32), b.x_final.cpu().numpy().view(np.uint32))
         np.testing.assert_array_equal(a.restart_best, b.restart_best)
         cnf.free()
@@ -496,7 +569,7 @@ def test_step_parity_adam():
 def test_bench_schedule_full_size_step(kind):
     """At the benchmark sizes and in the schedules the benchmark times (64
     restarts: table entry 34 with 32/8 rows per unit; one restart on the
-    structured instance: entry 37), one Adam step from x0 with |x| >= 0.05:
+    structured instance: entry 41, occurrence slots), one Adam step from x0 with |x| >= 0.05:
     bitwise equal to another schedule's step, counts equal to the
     oracle's, and the step within tolerance of the oracle's wherever the
     gradient's sign is well determined (|g| > 1e-3 S_i)."""
@@ -504,7 +577,7 @@ def test_bench_schedule_full_size_step(kind):
         n, m, R, sched, other = 20000, 86000, 64, 34 | (32 << 8) | (8 << 16), 15
         lits = cnfgen.uniform_kcnf(n, m, 3, seed=21)
     else:
-        n, m, R, sched, other = 500000, 2500000, 1, 37, 23
+        n, m, R, sched, other = 500000, 2500000, 1, 41, 37
         lits = cnfgen.structured_cnf(n, m, seed=3)
     rng = np.random.default_rng(77)
     x0 = (rng.uniform(0.05, 1.0, (n, R)) * np.where(rng.random((n, R)) < 0.5, -1, 1)).astype(np.float32)

@@ -87,13 +87,13 @@ def test_resume_equals_uninterrupted(case, opt):
     _say(f"  best {full.best_cost} at step {full.best_step} (schedule {full.schedule})")
 
 
-@pytest.mark.parametrize("sched", [37, 255], ids=["tiled-bitset", "resident"])
+@pytest.mark.parametrize("sched", [37, 42, 255], ids=["tiled-bitset", "tiled-slot", "resident"])
 def test_weighted_resume_equals_uninterrupted(sched):
     """Weighted MaxSAT with hard clauses: the best so far is a total weight
     (int64, past 2^31) and enters a resumed solve as one; 200 + 200 steps
     equal 400 bit for bit, and the oracle weighs the returned assignment at
     the reported cost."""
-    if sched == 37:
+    if sched in (37, 42):
         n, R, lits = 20000, 1, cnfgen.structured_cnf(20000, 100000, seed=9)
     else:
         n, R, lits = 60, 3, cnfgen.uniform_kcnf(60, 300, 3, seed=9)

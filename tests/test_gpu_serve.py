@@ -114,11 +114,11 @@ def test_grouped_tiled_batch_equals_solo(opt, mode):
     _say(f"grouped batch of {len(cnfs)}: device {batch[0].device_ms:.2f} ms, schedule {batch[0].schedule}")
 
 
-@pytest.mark.parametrize("sched", [36, 37])
+@pytest.mark.parametrize("sched", [36, 37, 41, 42])
 def test_grouped_batch_multi_tile_schedules(sched):
-    """Grouped launches under the schedules that give each wavefront several
-    whole tiles: each result is bitwise the solo result under the default
-    schedule."""
+    """Grouped launches under the schedules that give each forward wavefront
+    whole tiles (several tiles, or one with occurrence slots): each result is
+    bitwise the solo result under the default schedule."""
     sizes = [(9000, 40000, "s"), (20000, 86000, "u"), (30000, 120000, "s"), (3000, 12000, "u")]
     cnfs = []
     for i, (n, m, kind) in enumerate(sizes):

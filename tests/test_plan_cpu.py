@@ -128,7 +128,43 @@ def _check_plan(n, lits):
         got = [e for e in vrows[r] if e != azero]
         assert got == occ[i]
         assert all(e == azero for e in vrows[r][len(got):])
+    _check_slots(P, n)
     return P
+
+
+def _check_slots(P, n):
+    """The clause-side -> variable-side occurrence map: every real clause
+    entry names the variable-side entry of the same (variable, clause row,
+    sign), each variable-side entry is named once, padding names none."""
+    assert P.c_slot.size == P.c_ent.size
+    # variable and row of every variable-side entry
+    v_var = np.full(P.v_ent.size, -1, dtype=np.int64)
+    v_real = np.zeros(P.v_ent.size, dtype=bool)
+    for t, (base, ln, nreal, _) in enumerate(P.v_tile.tolist()):
+        for q in range(nreal):
+            row = t * 64 + q
+            if row < P.seg_rows:
+                var = int(np.searchsorted(P.seg_first, row, side="right")) - 1
+            else:
+                var = P.n_heavy + row - P.seg_tiles * 64
+            pos = base + q + 64 * np.arange(ln)
+            v_var[pos] = var
+            v_real[pos] = P.v_ent[pos] != P.c_tiles * 64
+    hits = np.zeros(P.v_ent.size, dtype=np.int64)
+    for t, (base, ln, nreal, _) in enumerate(P.c_tile.tolist()):
+        for q in range(64):
+            for c in range(ln):
+                p = base + 64 * c + q
+                e, sl = int(P.c_ent[p]), int(P.c_slot[p])
+                if e == n:
+                    assert sl == 0xFFFFFFFF
+                    continue
+                vp = sl & 0x7FFFFFFF
+                assert sl & 0x80000000 == e & 0x80000000
+                assert int(P.v_ent[vp]) == (t * 64 + q) | (e & 0x80000000)
+                assert v_var[vp] == e & 0x7FFFFFFF
+                hits[vp] += 1
+    assert np.array_equal(hits, v_real.astype(np.int64))
 
 
 def test_plan_small_edge_cases():
@@ -245,7 +281,7 @@ def test_tune_candidates():
     """The autotuner's candidate list (host only): valid table entries and
     rows per unit, bitset variants only with the unsat-masked loss."""
     nsched = hm.schedule_count()
-    assert nsched == 40
+    assert nsched == 42
     for R, mode in ((1, hm.LOSS_UNSAT), (1, hm.LOSS_ALL), (3, hm.LOSS_UNSAT), (64, hm.LOSS_UNSAT)):
         codes = hm.tune_candidates(R, mode)
         assert codes and len(set(codes)) == len(codes)
@@ -254,6 +290,8 @@ def test_tune_candidates():
             assert 1 <= idx <= nsched and U >= 1 and 64 % U == 0
         has_mask = any((c & 0xFF) in (23, 24, 25, 29, 30, 31, 32) for c in codes)
         assert has_mask == (mode == hm.LOSS_UNSAT)
+        # the slot schedule: one restart and the unsat-masked loss only
+        assert any((c & 0xFF) in (41, 42) for c in codes) == (R == 1 and mode == hm.LOSS_UNSAT)
     assert (26 | (32 << 8)) in hm.tune_candidates(64)
     with pytest.raises(hm.HipMsatError):
         hm.tune_candidates(0)
