@@ -153,6 +153,36 @@ def counters_summary(dirs):
     print("\n".join(lines))
 
 
+# one-restart schedules compared over instance sizes: the uniform bitset
+# entry, the 16-column one-row and multi-lane entries, the slot entries
+SIZE_SWEEP_SCHEDULES = (37, 38, 39, 41, 42)
+
+
+def size_sweep(iters):
+    """Step time of the one-restart schedules (their default rows per unit)
+    on uniform 3- and 5-CNF and skewed instances of growing size, best of
+    three hms_time_kernels runs each."""
+    import cnfgen
+    import paper_2402_03640_amd as hm
+    insts = [(f"3-CNF n={n} m={int(4.3 * n)}", n, cnfgen.uniform_kcnf(n, int(4.3 * n), 3, seed=n))
+             for n in (2000, 5000, 20000, 60000, 200000)]
+    insts += [(f"5-CNF n={n} m={17 * n}", n, cnfgen.uniform_kcnf(n, 17 * n, 5, seed=n)) for n in (4000, 30000)]
+    insts += [(f"structured n={n} m={5 * n}", n, cnfgen.structured_cnf(n, 5 * n, seed=3)) for n in (100000, 500000)]
+    print(f"# one-restart schedules over instance sizes: hms_time_kernels, {iters} launches, best of three\n"
+          f"# command: python -u bench.py --size-sweep --kernel-iters {iters}\n"
+          f"# columns: instance, nonzeros, then per table entry: step us (forward us / backward with combine us)",
+          flush=True)
+    for name, n, lits in insts:
+        cnf = hm.load_cnf(n, lits)
+        cols = []
+        for sc in SIZE_SWEEP_SCHEDULES:
+            best = min((hm.time_kernels(cnf, restarts=1, iters=iters, schedule=sc) for _ in range(3)),
+                       key=lambda t: t[2])
+            cols.append(f"{sc}: {best[2] * 1e3:6.2f} ({best[0] * 1e3:5.2f}/{best[1] * 1e3:5.2f})")
+        print(f"{name:28s} {cnf.info['nnz']:9d}  " + "  ".join(cols), flush=True)
+        cnf.free()
+
+
 def sweep(cnf, wl, iters):
     """Time every schedule the autotuner considers (hms_time_kernels, HIP events)."""
     import paper_2402_03640_amd as hm
@@ -520,6 +550,8 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=1000)
     ap.add_argument("--serve-workers", type=int, default=16)
     ap.add_argument("--sweep", action="store_true", help="time every candidate schedule and exit")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="time the one-restart schedules over instance sizes and exit")
     ap.add_argument("--tune-iters", type=int, default=20)
     ap.add_argument("--counters-summary", nargs="*", default=None, metavar="DIR",
                     help="summarise rocprofv3 counter runs of --kernels-only into profiles/traffic.json")
@@ -545,6 +577,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.probe:
         probe_table()
+        return
+    if args.size_sweep:
+        size_sweep(args.kernel_iters)
         return
     if args.config == "serve":
         serve_bench(args)

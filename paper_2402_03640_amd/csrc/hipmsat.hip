@@ -461,7 +461,8 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     size_t o_sf = L.add(P.seg_first.size() * 4);
     size_t o_vo = L.add(P.var_old.size() * 4);
     size_t o_w = L.add(P.c_w.size() * 8);
-    size_t o_cs = L.add(P.c_slot.size() * 4);
+    const bool slots = P.slot_ok && !P.c_ent.empty();
+    size_t o_cs = L.add(slots ? P.c_ent.size() * 4 : 0);
     void* base = nullptr;
     hipError_t e = hipMalloc(&base, std::max<size_t>(L.off, 256));
     if (e != hipSuccess) {
@@ -478,7 +479,7 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     C->seg_first = (int32_t*)(b + o_sf);
     C->var_old = (int32_t*)(b + o_vo);
     C->c_w = P.c_w.empty() ? nullptr : (int64_t*)(b + o_w);
-    C->c_slot = P.c_slot.empty() ? nullptr : (uint32_t*)(b + o_cs);
+    C->c_slot = slots ? (uint32_t*)(b + o_cs) : nullptr;
     C->struct_bytes = (int64_t)L.off;
     hms_status r = HMS_OK;
     if (!r) r = upload(P.c_tile, C->c_tile, s);
@@ -488,7 +489,24 @@ hms_status load_plan(hms::HostPlan&& plan, void* stream, hms_cnf** out) {
     if (!r) r = upload(P.seg_first, C->seg_first, s);
     if (!r) r = upload(P.var_old, C->var_old, s);
     if (!r) r = upload(P.c_w, C->c_w, s);
-    if (!r) r = upload(P.c_slot, C->c_slot, s);
+    if (!r && slots) {
+        // the occurrence map of the slot schedules, built from the uploaded sides
+        hms::SlotArgs sa{};
+        sa.c_tile = C->c_tile;
+        sa.c_ent = C->c_ent;
+        sa.v_tile = C->v_tile;
+        sa.v_ent = C->v_ent;
+        sa.seg_first = C->seg_first;
+        sa.n_heavy = P.n_heavy;
+        sa.seg_rows = P.seg_rows;
+        sa.seg_tiles = P.seg_tiles;
+        sa.v_tiles = P.v_tiles;
+        sa.vpad = (uint32_t)P.a_zero_row();
+        sa.c_slot = C->c_slot;
+        sa.c_ent_n = (int64_t)P.c_ent.size();
+        e = hms::launch_build_slots(sa, s);
+        if (e != hipSuccess) r = fail(HMS_ERR_DEVICE, std::string("occurrence map: ") + hipGetErrorString(e));
+    }
     if (!r) {
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) r = fail(HMS_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
@@ -2029,6 +2047,7 @@ hms_status hms_plan_view_build(int32_t n_vars, const int32_t* lits, int64_t n_li
         delete P;
         return fail(rc, err);
     }
+    hms::build_slots(*P);
     out->n = P->n;
     out->m = P->m;
     out->mk = P->mk;

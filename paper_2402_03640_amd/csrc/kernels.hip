@@ -11,6 +11,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device_common.hpp"
@@ -1056,6 +1057,49 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_slot_fill(uint32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = kNoSlot;
+}
+
+// One thread per variable-side row: for each of the row's entries, the entry
+// of its clause row that holds the row's variable (each variable appears at
+// most once in a canonical clause) gets this entry's index and sign.
+__global__ __launch_bounds__(256) void k_slots(SlotArgs A) {
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (int64_t)A.v_tiles * kTile) return;
+    const int32_t tile = (int32_t)(gid / kTile), q = (int32_t)(gid % kTile);
+    const TileDesc d = A.v_tile[tile];
+    if (q >= (int32_t)d.nreal) return;
+    const int32_t row = tile * kTile + q;
+    int32_t v;
+    if (row < A.seg_rows) {
+        // the heavy variable whose segments hold this row: the last h with
+        // seg_first[h] <= row
+        int32_t lo = 0, hi = A.n_heavy;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) / 2;
+            if (A.seg_first[mid] <= row) lo = mid; else hi = mid;
+        }
+        v = lo;
+    } else {
+        v = A.n_heavy + (row - A.seg_tiles * kTile);
+    }
+    for (uint32_t c = 0; c < d.len; ++c) {
+        const uint32_t vpos = d.base + c * kTile + (uint32_t)q;
+        const uint32_t e = A.v_ent[vpos];
+        if (e == A.vpad) continue;
+        const uint32_t j = e & kIdx;
+        const TileDesc cd = A.c_tile[j / kTile];
+        for (uint32_t cc = 0; cc < cd.len; ++cc) {
+            const uint32_t cpos = cd.base + cc * kTile + j % kTile;
+            if ((A.c_ent[cpos] & kIdx) == (uint32_t)v) {
+                A.c_slot[cpos] = vpos | (e & kSign);
+                break;
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_snapshot(int32_t n_act, Blocking B, const float* x,
                                                    const int32_t* improved, uint8_t* best_a) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1295,6 +1339,17 @@ hipError_t launch_reduce(const ReduceArgs& A, hipStream_t s) {
     return hipGetLastError();
 }
 
+
+hipError_t launch_build_slots(const SlotArgs& A, hipStream_t s) {
+    if (A.c_ent_n <= 0) return hipSuccess;
+    const int64_t fb = std::min<int64_t>((A.c_ent_n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_slot_fill, dim3((int)fb), dim3(256), 0, s, A.c_slot, A.c_ent_n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || A.v_tiles == 0) return e;
+    const int64_t rows = (int64_t)A.v_tiles * kTile;
+    hipLaunchKernelGGL(k_slots, dim3((int)((rows + 255) / 256)), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
 
 hipError_t launch_init(const InitArgs& A, hipStream_t s) {
     int64_t total = (int64_t)A.n * A.B.R;

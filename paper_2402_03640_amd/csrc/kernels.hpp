@@ -198,6 +198,22 @@ hipError_t launch_bwd_multi(int sched, int opt, const MultiLaunch& M, hipStream_
 hipError_t launch_combine_multi(int opt, const MultiLaunch& M, hipStream_t s);
 // Stage 1 (grids ceil(R/64) x n_chunks, flattened) then stage 2 (ceil(R/64)).
 hipError_t launch_reduce_multi(const MultiLaunch& stage1, const MultiLaunch& stage2, hipStream_t s);
+// The clause-side -> variable-side occurrence map of the slot schedules,
+// built on the device at load: c_slot[clause-side entry] = variable-side
+// entry of the same occurrence | its sign bit, kNoSlot for padding.
+struct SlotArgs {
+    const TileDesc* c_tile;
+    const uint32_t* c_ent;
+    const TileDesc* v_tile;
+    const uint32_t* v_ent;
+    const int32_t* seg_first;  // [n_heavy + 1] first segment row of each heavy variable
+    int32_t n_heavy, seg_rows, seg_tiles, v_tiles;
+    uint32_t vpad;             // variable-side padding entry
+    uint32_t* c_slot;
+    int64_t c_ent_n;
+};
+hipError_t launch_build_slots(const SlotArgs& A, hipStream_t s);
+
 hipError_t launch_init(const InitArgs& A, hipStream_t s);
 hipError_t launch_snapshot(int32_t n_act, const Blocking& B, const float* x, const int32_t* improved,
                            uint8_t* best_a, hipStream_t s);

@@ -524,8 +524,6 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
     std::vector<int64_t> voff((size_t)n + 1, 0);
     for (int32_t i = 0; i < n; ++i) voff[i + 1] = voff[i] + P.degree[i];
     std::vector<uint32_t> occ((size_t)P.nnz);
-    // clause-side entry of each occurrence, carried through both scatters
-    std::vector<uint32_t> occ_src((size_t)P.nnz);
     {
         // Two stable scatters with few write streams each: (1) (variable,
         // kernel row) pairs into blocks of 1024 consecutive variables, each
@@ -539,7 +537,6 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
         for (int32_t b = 0; b < nblk; ++b)
             bstart[b + 1] = voff[std::min<int64_t>((int64_t)(b + 1) << kShift, n)];
         std::vector<uint64_t> pairs((size_t)P.nnz);  // variable << 32 | (row | sign)
-        std::vector<uint32_t> psrc((size_t)P.nnz);   // clause-side entry of each pair
         std::vector<std::vector<int64_t>> cnt((size_t)T);
         par(T, [&](int t) {
             cnt[(size_t)t].assign((size_t)nblk, 0);
@@ -560,14 +557,10 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
             std::vector<int64_t>& fill = cnt[(size_t)t];
             for (int64_t r = part_lo(nr, t, T); r < part_lo(nr, t + 1, T); ++r) {
                 const Row& R = rows[(size_t)r];
-                const int32_t k = krow[(size_t)r];
-                const uint32_t cb = P.c_tile[(size_t)(k / kTile)].base + (uint32_t)(k % kTile);
                 for (int32_t c = 0; c < R.len; ++c) {
                     const uint32_t e = flat[(size_t)R.off + c];
                     const uint32_t v = e & kIdx;
-                    const int64_t q = fill[v >> kShift]++;
-                    pairs[(size_t)q] = ((uint64_t)v << 32) | (uint32_t)k | (e & kSign);
-                    psrc[(size_t)q] = cb + (uint32_t)c * kTile;
+                    pairs[(size_t)fill[v >> kShift]++] = ((uint64_t)v << 32) | (uint32_t)krow[(size_t)r] | (e & kSign);
                 }
             }
         });
@@ -578,9 +571,7 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
                 fill.assign(voff.begin() + v0, voff.begin() + std::max(v0, v1));
                 for (int64_t p = bstart[(size_t)b]; p < bstart[(size_t)b + 1]; ++p) {
                     const uint64_t q = pairs[(size_t)p];
-                    const int64_t o = fill[(size_t)((int64_t)(q >> 32) - v0)]++;
-                    occ[(size_t)o] = (uint32_t)q;
-                    occ_src[(size_t)o] = psrc[(size_t)p];
+                    occ[(size_t)fill[(size_t)((int64_t)(q >> 32) - v0)]++] = (uint32_t)q;
                 }
             }
         });
@@ -618,33 +609,46 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
                    P.v_tile, P.v_ent, err);
     if (rc) return rc;
     P.v_tiles = (int32_t)P.v_tile.size();
-    // the inverse map, clause-side entry -> variable-side entry of the same
-    // occurrence (each variable-side entry is written by one thread)
+    // the slot schedules index the variable side with 31 bits
     P.slot_ok = P.v_ent.size() < (size_t)kIdx;
-    if (P.slot_ok) {
-        P.c_slot.assign(P.c_ent.size(), kNoSlot);
-        auto put = [&](int32_t tile, int32_t q, int32_t c, int64_t o) {
-            const uint32_t vpos = P.v_tile[(size_t)tile].base + (uint32_t)c * kTile + (uint32_t)q;
-            P.c_slot[occ_src[(size_t)o]] = vpos | (occ[(size_t)o] & kSign);
-        };
-        par(T, [&](int t) {
-            for (int64_t r = part_lo(P.seg_rows, t, T); r < part_lo(P.seg_rows, t + 1, T); ++r) {
-                const Seg& g = segs[(size_t)r];
-                for (int32_t c = 0; c < g.len; ++c)
-                    put((int32_t)(r / kTile), (int32_t)(r % kTile), c, g.off + (int64_t)c * g.stride);
-            }
-            for (int64_t r = part_lo(n_light, t, T); r < part_lo(n_light, t + 1, T); ++r) {
-                const int32_t d = P.degree[P.n_heavy + r];
-                for (int32_t c = 0; c < d; ++c)
-                    put(P.seg_tiles + (int32_t)(r / kTile), (int32_t)(r % kTile), c, voff[P.n_heavy + r] + c);
-            }
-        });
-    }
     P.build_threads = T;
     return kOk;
 }
 
 }  // namespace
+
+void build_slots(HostPlan& P) {
+    P.c_slot.clear();
+    if (!P.slot_ok) return;
+    P.c_slot.assign(P.c_ent.size(), kNoSlot);
+    const uint32_t vpad = (uint32_t)P.a_zero_row();
+    for (int32_t t = 0; t < P.v_tiles; ++t) {
+        const TileDesc& d = P.v_tile[(size_t)t];
+        for (uint32_t q = 0; q < d.nreal; ++q) {
+            const int32_t row = t * kTile + (int32_t)q;
+            // variable of the row: a heavy variable's segments, or a light row
+            int32_t v;
+            if (row < P.seg_rows)
+                v = (int32_t)(std::upper_bound(P.seg_first.begin(), P.seg_first.end(), row) - P.seg_first.begin()) - 1;
+            else
+                v = P.n_heavy + (row - P.seg_tiles * kTile);
+            for (uint32_t c = 0; c < d.len; ++c) {
+                const uint32_t vpos = d.base + c * kTile + q;
+                const uint32_t e = P.v_ent[vpos];
+                if (e == vpad) continue;
+                const uint32_t j = e & kIdx;
+                const TileDesc& cd = P.c_tile[j / kTile];
+                for (uint32_t cc = 0; cc < cd.len; ++cc) {
+                    const uint32_t cpos = cd.base + cc * kTile + j % kTile;
+                    if ((P.c_ent[cpos] & kIdx) == (uint32_t)v) {
+                        P.c_slot[cpos] = vpos | (e & kSign);
+                        break;
+                    }
+                }
+            }
+        }
+    }
+}
 
 int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t* weights, HostPlan& P,
                    std::string& err) {

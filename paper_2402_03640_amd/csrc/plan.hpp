@@ -48,9 +48,10 @@ struct HostPlan {
     std::vector<int32_t> c_row_orig; // [c_tiles * kTile] original clause of a row, -1 = padding
     // [c_ent.size()] where each clause-side entry sits on the variable side:
     // the index into v_ent of the same occurrence | its sign bit, or kNoSlot
-    // for padding; empty when the variable side has 2^31 entries or more
+    // for padding.  The library builds this map on the device at load; the
+    // host copy is filled only by build_slots (the host plan view).
     std::vector<uint32_t> c_slot;
-    bool slot_ok = false;            // c_slot was built (the slot schedules can run)
+    bool slot_ok = false;            // the variable side has fewer than 2^31 entries (slot schedules can run)
 
     // variable side (transposed sums); rows are whole light variables or
     // fixed-length segments of heavy variables
@@ -99,6 +100,10 @@ int32_t build_plan(int32_t n, const int32_t* lits, int64_t nlits, const int64_t*
 // or the header-less weighted form whose clauses are led by a weight or by
 // "h" (hard: weight 1 + the total soft weight).  weights is left empty for
 // plain CNF.
+// The clause-side -> variable-side occurrence map on the host, by scanning
+// each occurrence's clause row for its variable (the same rule as the
+// device build); leaves c_slot empty when !slot_ok.
+void build_slots(HostPlan& P);
 int32_t read_dimacs(const char* path, int32_t& n, std::vector<int32_t>& lits, std::vector<int64_t>& weights,
                     std::string& err);
 
