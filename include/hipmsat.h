@@ -290,7 +290,10 @@ hms_status hms_tune_candidates(int32_t restarts, int32_t loss_mode, int32_t* cod
  * from 1 to this count.  Every entry computes the same values; they differ
  * in how lanes, restarts and rows map onto wavefronts, in how many columns
  * of a row one load batch takes and, for the unsat-masked loss, in whether
- * a bitset lets the backward pass skip the adjoints of satisfied clauses.
+ * a bitset lets the backward pass skip the adjoints of satisfied clauses or,
+ * at one restart, whether the forward pass stores each occurrence's adjoint
+ * where the backward pass reads its terms in order (the slot entries, which
+ * run their unmasked twin with several restarts or the unmasked loss).
  */
 int32_t hms_schedule_count(void);
 
