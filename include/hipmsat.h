@@ -398,6 +398,18 @@ typedef struct {
 hms_status hms_plan_view_build(int32_t n_vars, const int32_t* lits, int64_t n_lits, hms_plan_view* out);
 void hms_plan_view_free(hms_plan_view* view);
 
+/*
+ * The occurrence map a loaded instance holds on its device (built there at
+ * load, for the slot schedules), copied to `out`: a caller-owned HOST array
+ * of `cap` >= c_ent_len entries laid out as hms_plan_view.c_slot (the
+ * variable-side entry of each clause-side entry | sign << 31, 0xffffffff for
+ * padding), for tests of the layouts.  *len receives c_ent_len, or 0 when the
+ * instance has no map (no entries, or 2^31 variable-side entries or more);
+ * with out = NULL only *len is set.  Synchronises the instance's device.
+ * Errors: HMS_ERR_ARG (null instance or len, cap too small), HMS_ERR_DEVICE.
+ */
+hms_status hms_cnf_slot_map(const hms_cnf* cnf, uint32_t* out, int64_t cap, int64_t* len);
+
 #ifdef __cplusplus
 }
 #endif

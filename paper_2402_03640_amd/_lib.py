@@ -90,7 +90,7 @@ EXPORTS = ["hms_load_cnf", "hms_load_cnf_dimacs", "hms_cnf_info_get", "hms_free_
            "hms_last_error", "hms_version", "hms_plan_view_build", "hms_plan_view_free",
            "hms_time_kernels", "hms_tune", "hms_adjoint_bytes", "hms_forward", "hms_backward",
            "hms_solve_batch", "hms_tune_candidates", "hms_load_wcnf", "hms_eval_relaxed_noalloc",
-           "hms_schedule_count"]
+           "hms_schedule_count", "hms_cnf_slot_map"]
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -139,6 +139,8 @@ def _load():
     L.hms_version.restype = C.c_char_p
     L.hms_plan_view_build.argtypes = [I32, P, I64, C.POINTER(PlanView)]
     L.hms_plan_view_free.argtypes = [C.POINTER(PlanView)]
+    L.hms_cnf_slot_map.argtypes = [P, P, I64, P]
+    L.hms_cnf_slot_map.restype = I32
     L.hms_plan_view_free.restype = None
     L.hms_tune_candidates.argtypes = [I32, I32, P, I32, P]
     L.hms_schedule_count.argtypes = []
@@ -202,6 +204,16 @@ class Cnf:
     @property
     def handle(self):
         return self._h
+
+    def slot_map(self) -> np.ndarray:
+        """The occurrence map built on the device (layout tests; see
+        ``hms_cnf_slot_map``); empty when the instance has none."""
+        n = C.c_int64()
+        _check(lib().hms_cnf_slot_map(self._h, None, 0, C.byref(n)))
+        out = np.zeros(n.value, dtype=np.uint32)
+        if n.value:
+            _check(lib().hms_cnf_slot_map(self._h, out.ctypes.data_as(C.c_void_p), out.size, C.byref(n)))
+        return out
 
     def free(self):
         if self._h is not None and self._h.value:

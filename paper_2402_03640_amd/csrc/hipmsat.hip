@@ -2084,4 +2084,22 @@ void hms_plan_view_free(hms_plan_view* view) {
     std::memset(view, 0, sizeof(*view));
 }
 
+hms_status hms_cnf_slot_map(const hms_cnf* cnf, uint32_t* out, int64_t cap, int64_t* len) {
+    g_err.clear();
+    if (check_cnf(cnf) || !len) return fail(HMS_ERR_ARG, "null argument");
+    *len = 0;
+    if (!cnf->c_slot) return HMS_OK;
+    const int64_t n = (int64_t)cnf->plan.c_ent.size();
+    if (!out) {  // size query
+        *len = n;
+        return HMS_OK;
+    }
+    if (cap < n) return fail(HMS_ERR_ARG, "output array shorter than the clause side");
+    DeviceGuard dg(cnf->device);
+    HIPTRY(hipDeviceSynchronize());
+    HIPTRY(hipMemcpy(out, cnf->c_slot, (size_t)n * 4, hipMemcpyDeviceToHost));
+    *len = n;
+    return HMS_OK;
+}
+
 }  // extern "C"

@@ -200,6 +200,24 @@ def _slot_instances(rng):
     return out
 
 
+def test_device_slot_map_equals_host_scan():
+    """The occurrence map the library builds on the device at load equals
+    the host scan of the plan view (checked against the layouts on the CPU),
+    on instances with heavy rows in segments, dense rows kept whole, long
+    clauses, repeats, tautologies and empty clauses."""
+    rng = np.random.default_rng(5)
+    for n, lits in _slot_instances(rng):
+        cnf = hm.load_cnf(n, lits)
+        dev = cnf.slot_map()
+        host = hm.Plan(n, lits).c_slot
+        assert dev.size == host.size > 0
+        np.testing.assert_array_equal(dev, host)
+        _say(f"slot map n={n}: {dev.size} entries, {int(np.count_nonzero(dev != 0xFFFFFFFF))} real")
+        cnf.free()
+    empty = hm.load_cnf(5, np.zeros(0, dtype=np.int32))
+    assert empty.slot_map().size == 0
+
+
 def test_slot_schedule_bitwise():
     """The slot schedule (the forward leaves each occurrence's adjoint in
     the slot of its variable-side entry, the backward reads them in entry
