@@ -366,7 +366,10 @@ __device__ __forceinline__ uint32_t unit_entry(const uint32_t* ent, const TileDe
 // is mostly the wait on its dependent loads: large instances, one restart).
 // Work unit u covers tiles [u NT, u NT + NT) and owns one count/loss partial.
 // Every row is computed exactly as the one-tile kernel computes it (FP32 sum
-// in column order up to 16 columns, FP64 beyond).
+// in column order up to 16 columns, FP64 beyond).  MASK = 0 writes every
+// row's adjoint; 1 writes the rows in the loss and the tile's unsat bits; 2
+// (slot mode) writes the unsat bits and, for the rows in the loss now or one
+// step ago, the signed adjoint (or 0) into each occurrence's variable-side slot.
 // ---------------------------------------------------------------------------
 template <int NT, bool EVAL, int MASK>
 __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
@@ -629,9 +632,10 @@ __device__ __forceinline__ void var_epilogue(const BwdArgs& A, size_t base, int 
 // ---------------------------------------------------------------------------
 // Backward: transposed sums G = sum_j W_ij a_j over variable rows (atomic-free;
 // each (row, restart) summed by one lane in FP64 in entry order), fused
-// epilogue for whole rows, partials for heavy-row segments.  With MASK the
-// adjoint of a clause is read only when its unsat bit is set (it is 0
-// otherwise).
+// epilogue for whole rows, partials for heavy-row segments.  MASK = 0 gathers
+// every entry's clause adjoint; 1 gathers it only when the clause's unsat bit
+// is set (it is 0 otherwise); 2 (slot mode) reads the occurrence slots that
+// the forward filled, parallel to the entries, with no index load or gather.
 // ---------------------------------------------------------------------------
 template <int P, int V, int UR, int OPT, int MASK, int CB>
 __device__ __forceinline__ void bwd_body(const BwdArgs& A, const int bx) {
