@@ -74,6 +74,8 @@ typedef struct {
                                16) shared by the loads running at once, at most one per 2^16 literals,
                                or the count the HIPMSAT_PLAN_THREADS variable sets (shared the same
                                way); the plan does not depend on it */
+    int64_t slot_bytes;     /* device bytes a one-restart solve under a slot schedule holds beside
+                               its state (one FP32 per variable-side entry; 0: no slot schedule) */
 } hms_cnf_info;
 
 /*

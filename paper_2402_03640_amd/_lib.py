@@ -43,7 +43,7 @@ class CnfInfo(C.Structure):
                 ("nnz", C.c_int64), ("n_empty", C.c_int32), ("n_taut", C.c_int32),
                 ("n_active", C.c_int32), ("n_heavy", C.c_int32), ("struct_bytes", C.c_int64),
                 ("state_bytes_r1", C.c_int64), ("weighted", C.c_int32), ("total_weight", C.c_int64),
-                ("plan_threads", C.c_int32)]
+                ("plan_threads", C.c_int32), ("slot_bytes", C.c_int64)]
 
 
 class SolveState(C.Structure):

@@ -585,6 +585,7 @@ hms_status hms_cnf_info_get(const hms_cnf* cnf, hms_cnf_info* out) {
     out->weighted = P.weighted ? 1 : 0;
     out->total_weight = P.w_total;
     out->plan_threads = P.build_threads;
+    out->slot_bytes = cnf->c_slot ? (int64_t)P.v_ent.size() * 4 : 0;
     return HMS_OK;
 }
 

@@ -209,13 +209,15 @@ def test_device_slot_map_equals_host_scan():
     for n, lits in _slot_instances(rng):
         cnf = hm.load_cnf(n, lits)
         dev = cnf.slot_map()
-        host = hm.Plan(n, lits).c_slot
+        plan = hm.Plan(n, lits)
+        host = plan.c_slot
         assert dev.size == host.size > 0
         np.testing.assert_array_equal(dev, host)
+        assert cnf.info["slot_bytes"] == 4 * plan.v_ent.size
         _say(f"slot map n={n}: {dev.size} entries, {int(np.count_nonzero(dev != 0xFFFFFFFF))} real")
         cnf.free()
     empty = hm.load_cnf(5, np.zeros(0, dtype=np.int32))
-    assert empty.slot_map().size == 0
+    assert empty.slot_map().size == 0 and empty.info["slot_bytes"] == 0
 
 
 def test_slot_schedule_bitwise():
