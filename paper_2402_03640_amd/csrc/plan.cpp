@@ -51,16 +51,21 @@ struct Row {
 
 // ---- host threads ---------------------------------------------------------
 // A build uses the host's hardware threads (at most 16), shared by the builds
-// running at once, and one thread per 2^16 literals at most; the variable
-// HIPMSAT_PLAN_THREADS sets the count instead (shared the same way, with no
-// size rule).  Every phase gives the same plan whatever the thread count:
-// each is a fixed function of the instance.
+// running at once in proportion to their literal counts (a large build next
+// to small ones takes most of them: its latency is the longest), at least one
+// each and one per 2^16 literals at most; the variable HIPMSAT_PLAN_THREADS
+// sets the count instead (shared equally, with no size rule).  Every phase
+// gives the same plan whatever the thread count: each is a fixed function of
+// the instance.
 std::atomic<int> g_active_builds{0};
+std::atomic<int64_t> g_active_lits{0};
 
 struct BuildSlot {
     int threads;
-    explicit BuildSlot(int64_t nlits) {
+    int64_t lits;
+    explicit BuildSlot(int64_t nlits) : lits(std::max<int64_t>(nlits, 1)) {
         const int active = g_active_builds.fetch_add(1) + 1;
+        const int64_t all = g_active_lits.fetch_add(lits) + lits;
         const char* e = std::getenv("HIPMSAT_PLAN_THREADS");
         const int set = (e && *e) ? std::min(std::atoi(e), 64) : 0;
         if (set > 0) {
@@ -68,10 +73,14 @@ struct BuildSlot {
         } else {
             const int cap = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
             const int64_t by_size = std::max<int64_t>(1, nlits >> 16);
-            threads = (int)std::max<int64_t>(1, std::min<int64_t>(cap / active, by_size));
+            const int64_t share = (int64_t)((double)cap * (double)lits / (double)std::max<int64_t>(all, lits) + 0.5);
+            threads = (int)std::max<int64_t>(1, std::min<int64_t>(share, by_size));
         }
     }
-    ~BuildSlot() { g_active_builds.fetch_sub(1); }
+    ~BuildSlot() {
+        g_active_lits.fetch_sub(lits);
+        g_active_builds.fetch_sub(1);
+    }
 };
 
 // Runs fn(t) for t = 0..T-1, thread 0 on the caller; an exception in any

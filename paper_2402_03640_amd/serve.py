@@ -29,6 +29,10 @@ from . import _lib
 
 # instances at most this large (n + m) are grouped for the resident solver
 SMALL_ROWS = 12000
+# instances with more literals run as jobs of their own: one of them keeps the
+# device busy alone, and a job's plans are built one after the other, so a
+# request grouped with a large one would wait for its build and its solve
+GROUP_MAX_LITS = 1 << 21
 
 
 def footprint_bytes(n: int, m: int, n_lits: int, restarts: int = 1, weighted: bool = False) -> int:
@@ -52,6 +56,7 @@ class Request:
     arrival: float = 0.0
     future: Future = field(default_factory=Future)
     footprint: int = 0
+    n_lits: int = 0
     small: bool = False
     rid: int = 0
     weights: object = None  # clause weights (weighted MaxSAT) or None
@@ -117,6 +122,7 @@ class Server:
         if req.weights is not None and req.weights.size != m:
             raise ValueError(f"{req.weights.size} clause weights for {m} clauses")
         req.footprint = footprint_bytes(n, m, lits.size - m, R, req.weights is not None)
+        req.n_lits = lits.size - m
         req.small = (n + m) <= SMALL_ROWS
         with self._cv:
             if self._closed:
@@ -159,10 +165,13 @@ class Server:
         self.in_use += job[0].footprint
         key = _group_key(job[0])
         cap = self.small_batch if job[0].small else self.tiled_batch
+        if job[0].n_lits > GROUP_MAX_LITS:
+            cap = 1
         keep = collections.deque()
         while self._queue and len(job) < cap:
             r = self._queue.popleft()
-            if _group_key(r) == key and self.in_use + r.footprint <= self.budget:
+            if (_group_key(r) == key and r.n_lits <= GROUP_MAX_LITS
+                    and self.in_use + r.footprint <= self.budget):
                 job.append(r)
                 self.in_use += r.footprint
             else:
