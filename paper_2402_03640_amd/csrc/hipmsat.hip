@@ -437,7 +437,7 @@ hms_status check_cnf(const hms_cnf* C) {
 }
 
 template <typename T>
-hms_status upload(const std::vector<T>& h, T* d, hipStream_t s) {
+hms_status upload(const hms::PVec<T>& h, T* d, hipStream_t s) {
     if (h.empty()) return HMS_OK;
     HIPTRY(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return HMS_OK;

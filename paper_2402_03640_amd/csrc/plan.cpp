@@ -25,6 +25,8 @@
 //    way; the entries of a row follow increasing clause-row index.
 #include "plan.hpp"
 
+#include <sys/mman.h>
+
 #include <algorithm>
 #include <atomic>
 #include <cerrno>
@@ -38,6 +40,27 @@
 #include <utility>
 
 namespace hms {
+
+// ---- host buffers ---------------------------------------------------------
+constexpr std::size_t kHuge = std::size_t(2) << 20;
+
+void* build_alloc(std::size_t bytes) {
+    if (bytes < kHuge) return ::operator new(bytes);
+    const std::size_t len = (bytes + kHuge - 1) & ~(kHuge - 1);
+    void* p = mmap(nullptr, len, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+    if (p == MAP_FAILED) throw std::bad_alloc();
+    (void)madvise(p, len, MADV_HUGEPAGE);  // a hint: without it the pages are 4 KiB
+    return p;
+}
+
+void build_free(void* p, std::size_t bytes) noexcept {
+    if (!p) return;
+    if (bytes < kHuge) {
+        ::operator delete(p);
+        return;
+    }
+    (void)munmap(p, (bytes + kHuge - 1) & ~(kHuge - 1));
+}
 
 namespace {
 
@@ -120,9 +143,9 @@ inline int64_t part_lo(int64_t n, int t, int T) { return (int64_t)((__int128)n *
 // tiles / ent; tiles fill in parallel at bases fixed beforehand.
 template <typename LenFn, typename EntFn>
 int32_t tile_rows(int T, int32_t nrows, LenFn len_of, EntFn ent_of, uint32_t pad, uint32_t flags,
-                  std::vector<TileDesc>& tiles, std::vector<uint32_t>& ent, std::string& err) {
+                  PVec<TileDesc>& tiles, PVec<uint32_t>& ent, std::string& err) {
     const int32_t nt = (nrows + kTile - 1) / kTile;
-    std::vector<uint32_t> tlen((size_t)nt, 0);
+    PVec<uint32_t> tlen((size_t)nt, 0);
     par(T, [&](int t) {
         for (int64_t k = part_lo(nt, t, T); k < part_lo(nt, t + 1, T); ++k) {
             uint32_t len = 0;
@@ -161,16 +184,16 @@ int32_t tile_rows(int T, int32_t nrows, LenFn len_of, EntFn ent_of, uint32_t pad
 // from j0: a variable is emitted at its first appearance with its sign,
 // unless it also appears negated (then the clause is a tautology).
 struct Chunk {
-    std::vector<uint32_t> flat;  // original variable | sign
-    std::vector<Row> rows;       // off into this chunk's flat
+    PVec<uint32_t> flat;  // original variable | sign
+    PVec<Row> rows;       // off into this chunk's flat
     int32_t m_empty = 0, m_taut = 0, m_taut_dropped = 0;
     int64_t w_empty = 0;
 };
 
 void canonical_chunk(const int32_t* lits, int64_t b0, int64_t b1, int32_t j0, const int64_t* weights, Chunk& C) {
     constexpr int kShort = 16;  // clauses up to this length are deduplicated in registers
-    std::vector<uint64_t> key;  // longer ones: (variable, position) sorted
-    std::vector<uint64_t> emit; // (position, entry) of the emitted literals
+    PVec<uint64_t> key;  // longer ones: (variable, position) sorted
+    PVec<uint64_t> emit; // (position, entry) of the emitted literals
     int64_t start = b0;
     int32_t j = j0;
     for (int64_t p = b0; p < b1; ++p) {
@@ -257,14 +280,14 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
     const int T = slot.threads;
 
     // ---- chunks of whole clauses; checks and counts per chunk ---------------
-    std::vector<int64_t> cb((size_t)T + 1, nlits);
+    PVec<int64_t> cb((size_t)T + 1, nlits);
     cb[0] = 0;
     for (int t = 1; t < T; ++t) {
         int64_t q = std::max(cb[(size_t)t - 1], part_lo(nlits, t, T));
         while (q < nlits && q > 0 && lits[q - 1] != 0) ++q;  // the next clause start
         cb[(size_t)t] = q;
     }
-    std::vector<int64_t> zeros((size_t)T, 0), nonzero((size_t)T, 0), bad((size_t)T, -1);
+    PVec<int64_t> zeros((size_t)T, 0), nonzero((size_t)T, 0), bad((size_t)T, -1);
     par(T, [&](int t) {
         int64_t z = 0, nz = 0;  // counted in registers, stored once (no shared cache lines in the loop)
         for (int64_t p = cb[(size_t)t]; p < cb[(size_t)t + 1]; ++p) {
@@ -291,7 +314,7 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
             return kErrRange;
         }
     int64_t m = 0;
-    std::vector<int32_t> j0((size_t)T, 0);
+    PVec<int32_t> j0((size_t)T, 0);
     for (int t = 0; t < T; ++t) {
         if (m >= (int64_t)kIdx) break;
         j0[(size_t)t] = (int32_t)m;
@@ -319,12 +342,12 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
     }
 
     // ---- canonical clauses: W entries in order of first appearance --------
-    std::vector<uint32_t> flat;  // original variable | sign, then new variable | sign
-    std::vector<Row> rows;
+    PVec<uint32_t> flat;  // original variable | sign, then new variable | sign
+    PVec<Row> rows;
     {
-        std::vector<Chunk> ch((size_t)T);
+        PVec<Chunk> ch((size_t)T);
         par(T, [&](int t) { canonical_chunk(lits, cb[(size_t)t], cb[(size_t)t + 1], j0[(size_t)t], weights, ch[(size_t)t]); });
-        std::vector<int64_t> foff((size_t)T + 1, 0), roff((size_t)T + 1, 0);
+        PVec<int64_t> foff((size_t)T + 1, 0), roff((size_t)T + 1, 0);
         for (int t = 0; t < T; ++t) {
             const Chunk& c = ch[(size_t)t];
             foff[(size_t)t + 1] = foff[(size_t)t] + (int64_t)c.flat.size();
@@ -344,13 +367,13 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
                 r.off += foff[(size_t)t];
                 rows[(size_t)roff[(size_t)t] + i] = r;
             }
-            std::vector<uint32_t>().swap(c.flat);
+            PVec<uint32_t>().swap(c.flat);
         });
     }
     P.nnz = (int64_t)flat.size();
 
     // ---- variable order: degree descending, ties by original index -------
-    std::vector<int32_t> deg_orig((size_t)n, 0);
+    PVec<int32_t> deg_orig((size_t)n, 0);
     if ((int64_t)T * n <= ((int64_t)1 << 26) && T > 1) {
         // per-thread histograms, then a sum over variable ranges
         std::vector<std::vector<int32_t>> h((size_t)T);
@@ -372,7 +395,7 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
     {
         int32_t maxd = 0;
         for (int32_t i = 0; i < n; ++i) maxd = std::max(maxd, deg_orig[i]);
-        std::vector<int64_t> start((size_t)maxd + 2, 0);
+        PVec<int64_t> start((size_t)maxd + 2, 0);
         for (int32_t i = 0; i < n; ++i) start[(size_t)(maxd - deg_orig[i]) + 1]++;
         for (int32_t d = 0; d <= maxd; ++d) start[d + 1] += start[d];
         P.var_old.resize((size_t)n);
@@ -423,8 +446,8 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
         for (const Row& r : rows) maxl = std::max(maxl, r.len);
         int vbits = 1;
         while (vbits < 31 && ((int64_t)1 << vbits) < (int64_t)n) ++vbits;
-        std::vector<uint64_t> key((size_t)nr), key2((size_t)nr);
-        std::vector<int32_t> ord((size_t)nr), ord2((size_t)nr);
+        PVec<uint64_t> key((size_t)nr), key2((size_t)nr);
+        PVec<int32_t> ord((size_t)nr), ord2((size_t)nr);
         uint64_t kmax = 0;
         par(T, [&](int t) {
             for (int64_t i = part_lo(nr, t, T); i < part_lo(nr, t + 1, T); ++i) {
@@ -464,17 +487,17 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
             key.swap(key2);
             ord.swap(ord2);
         }
-        std::vector<uint64_t>().swap(key);
-        std::vector<uint64_t>().swap(key2);
-        std::vector<int64_t> psum((size_t)T + 1, 0);
+        PVec<uint64_t>().swap(key);
+        PVec<uint64_t>().swap(key2);
+        PVec<int64_t> psum((size_t)T + 1, 0);
         par(T, [&](int t) {
             int64_t s = 0;
             for (int64_t r = part_lo(nr, t, T); r < part_lo(nr, t + 1, T); ++r) s += rows[(size_t)ord[(size_t)r]].len;
             psum[(size_t)t + 1] = s;
         });
         for (int t = 0; t < T; ++t) psum[(size_t)t + 1] += psum[(size_t)t];
-        std::vector<Row> sorted((size_t)nr);
-        std::vector<uint32_t> flat2(flat.size());
+        PVec<Row> sorted((size_t)nr);
+        PVec<uint32_t> flat2(flat.size());
         par(T, [&](int t) {
             int64_t o = psum[(size_t)t];
             constexpr int64_t kAhead = 16;  // rows fetched ahead of the copy
@@ -514,7 +537,7 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
     }
     P.mk = (int32_t)rows.size();
     // kernel row index of each canonical row
-    std::vector<int32_t> krow(rows.size());
+    PVec<int32_t> krow(rows.size());
     P.c_row_orig.assign((size_t)P.c_tiles * kTile, -1);
     {
         const int32_t tp = (n_plain + kTile - 1) / kTile;
@@ -530,9 +553,9 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
     }
 
     // ---- variable-major occurrence lists (clause rows ascending) ----------
-    std::vector<int64_t> voff((size_t)n + 1, 0);
+    PVec<int64_t> voff((size_t)n + 1, 0);
     for (int32_t i = 0; i < n; ++i) voff[i + 1] = voff[i] + P.degree[i];
-    std::vector<uint32_t> occ((size_t)P.nnz);
+    PVec<uint32_t> occ((size_t)P.nnz);
     {
         // Two stable scatters with few write streams each: (1) (variable,
         // kernel row) pairs into blocks of 1024 consecutive variables, each
@@ -542,10 +565,10 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
         // kernel-row order.
         constexpr int kShift = 10;
         const int32_t nblk = (n >> kShift) + 1;
-        std::vector<int64_t> bstart((size_t)nblk + 1, 0);
+        PVec<int64_t> bstart((size_t)nblk + 1, 0);
         for (int32_t b = 0; b < nblk; ++b)
             bstart[b + 1] = voff[std::min<int64_t>((int64_t)(b + 1) << kShift, n)];
-        std::vector<uint64_t> pairs((size_t)P.nnz);  // variable << 32 | (row | sign)
+        PVec<uint64_t> pairs((size_t)P.nnz);  // variable << 32 | (row | sign)
         std::vector<std::vector<int64_t>> cnt((size_t)T);
         par(T, [&](int t) {
             cnt[(size_t)t].assign((size_t)nblk, 0);
@@ -574,7 +597,7 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
             }
         });
         par(T, [&](int t) {
-            std::vector<int64_t> fill;
+            PVec<int64_t> fill;
             for (int64_t b = part_lo(nblk, t, T); b < part_lo(nblk, t + 1, T); ++b) {
                 const int64_t v0 = b << kShift, v1 = std::min<int64_t>((b + 1) << kShift, n);
                 fill.assign(voff.begin() + v0, voff.begin() + std::max(v0, v1));
@@ -591,7 +614,7 @@ int32_t build_plan_impl(int32_t n, const int32_t* lits, int64_t nlits, const int
         int32_t var, idx, len, stride;
         int64_t off;
     };
-    std::vector<Seg> segs;
+    PVec<Seg> segs;
     P.seg_first.assign((size_t)P.n_heavy + 1, 0);
     for (int32_t h = 0; h < P.n_heavy; ++h) {
         int32_t d = P.degree[h];

@@ -3,11 +3,35 @@
 // column-major form the kernels read.  No HIP in here.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
 
 namespace hms {
+
+// Host buffers of the plan build.  Blocks of 2 MiB or more are mapped apart
+// with transparent huge pages requested: the build is bound by the first-touch
+// page faults of its fresh buffers, and a 2 MiB page faults once where 4 KiB
+// pages fault 512 times.  Smaller blocks come from operator new.
+void* build_alloc(std::size_t bytes);
+void build_free(void* p, std::size_t bytes) noexcept;
+
+template <class T>
+struct BuildAlloc {
+    using value_type = T;
+    BuildAlloc() = default;
+    template <class U>
+    BuildAlloc(const BuildAlloc<U>&) {}
+    T* allocate(std::size_t n) { return static_cast<T*>(build_alloc(n * sizeof(T))); }
+    void deallocate(T* p, std::size_t n) noexcept { build_free(p, n * sizeof(T)); }
+    template <class U>
+    bool operator==(const BuildAlloc<U>&) const { return true; }
+    template <class U>
+    bool operator!=(const BuildAlloc<U>&) const { return false; }
+};
+template <class T>
+using PVec = std::vector<T, BuildAlloc<T>>;
 
 constexpr int kTile = 64;          // rows per tile; one wavefront lane per row at R = 1
 constexpr int kSeg = 64;           // entries per segment of a split variable row; rows up to kSeg stay whole
@@ -38,19 +62,19 @@ struct HostPlan {
     bool weighted = false;
     int64_t w_total = 0;        // total weight (m without weights): the cost of "all unsatisfied"
     int64_t w_empty = 0;        // total weight of the empty clauses (always unsatisfied)
-    std::vector<int64_t> c_w;   // [c_tiles * kTile] weight of each kernel row (0 = padding); empty if unweighted
+    PVec<int64_t> c_w;   // [c_tiles * kTile] weight of each kernel row (0 = padding); empty if unweighted
 
     // clause side (scores / mask / adjoint)
     int32_t mk = 0;             // kernel clause rows
     int32_t c_tiles = 0;
-    std::vector<TileDesc> c_tile;
-    std::vector<uint32_t> c_ent;     // new variable index | sign bit (negated literal)
-    std::vector<int32_t> c_row_orig; // [c_tiles * kTile] original clause of a row, -1 = padding
+    PVec<TileDesc> c_tile;
+    PVec<uint32_t> c_ent;     // new variable index | sign bit (negated literal)
+    PVec<int32_t> c_row_orig; // [c_tiles * kTile] original clause of a row, -1 = padding
     // [c_ent.size()] where each clause-side entry sits on the variable side:
     // the index into v_ent of the same occurrence | its sign bit, or kNoSlot
     // for padding.  The library builds this map on the device at load; the
     // host copy is filled only by build_slots (the host plan view).
-    std::vector<uint32_t> c_slot;
+    PVec<uint32_t> c_slot;
     bool slot_ok = false;            // the variable side has fewer than 2^31 entries (slot schedules can run)
 
     // variable side (transposed sums); rows are whole light variables or
@@ -61,18 +85,18 @@ struct HostPlan {
     int32_t seg_rows = 0;       // real segment rows
     int32_t seg_tiles = 0;      // tiles holding segment rows (come first)
     int32_t v_tiles = 0;        // all variable-side tiles
-    std::vector<TileDesc> v_tile;
-    std::vector<uint32_t> v_ent;     // clause row index | sign bit
-    std::vector<int32_t> seg_first;  // [n_heavy + 1] into seg_row
-    std::vector<int32_t> seg_row;    // segment row of each segment: the identity (rows are in segment order)
+    PVec<TileDesc> v_tile;
+    PVec<uint32_t> v_ent;     // clause row index | sign bit
+    PVec<int32_t> seg_first;  // [n_heavy + 1] into seg_row
+    PVec<int32_t> seg_row;    // segment row of each segment: the identity (rows are in segment order)
     int32_t max_segs = 0;            // most segments of one variable
     int32_t n_heavy_wide = 0;        // heavy variables with more than kWideSegs segments (come first)
 
     int32_t build_threads = 1;       // host threads the build used (the plan is the same for any count)
 
-    std::vector<int32_t> var_old;    // new index -> original (0-based)
-    std::vector<int32_t> var_new;    // original -> new index
-    std::vector<int32_t> degree;     // by new index
+    PVec<int32_t> var_old;    // new index -> original (0-based)
+    PVec<int32_t> var_new;    // original -> new index
+    PVec<int32_t> degree;     // by new index
 
     int32_t a_rows() const { return c_tiles * kTile + 1; }  // last row stays zero
     int32_t a_zero_row() const { return c_tiles * kTile; }
