@@ -101,6 +101,7 @@ class Server:
         self.peak_in_use = 0
         self.deferrals = 0
         self.jobs: list | None = [] if trace else None
+        self.job_rids: list | None = [] if trace else None  # with trace: the request ids of each job
         self._closed = False
         self._ids = 0
         self._workers = []
@@ -204,6 +205,7 @@ class Server:
                 with self._cv:
                     foot = sum(r.footprint for r in job)
                     if self.jobs is not None:
+                        self.job_rids.append(tuple(r.rid for r in job))
                         self.jobs.append((job[0].params["_admitted"], time.perf_counter(), foot,
                                           foot > self.budget))
                     self.in_use -= foot

@@ -274,6 +274,36 @@ def test_large_tiled_group_equals_solo():
     assert tiled >= 9
 
 
+def test_large_requests_run_alone():
+    """Requests of more than 2^21 literals form jobs of their own, while the
+    smaller requests of the same kind queued with them are still grouped; every
+    result equals its solo solve."""
+    from paper_2402_03640_amd.serve import GROUP_MAX_LITS, Server
+    kw = dict(steps=20, restarts=1, eval_every=10, lr=1e-2)
+    reqs = []
+    for i in range(8):
+        n = 250000 if i % 4 == 0 else 3000
+        lits = cnfgen.uniform_kcnf(n, int(4.3 * n), 3, seed=300 + i)
+        reqs.append((n, lits, dict(seed=i, **kw)))
+    big = {i for i, (n, lits, p) in enumerate(reqs) if lits.size - np.count_nonzero(lits == 0) > GROUP_MAX_LITS}
+    assert len(big) == 2
+    solo = []
+    for n, lits, p in reqs:
+        c = hm.load_cnf(n, lits)
+        solo.append(hm.solve(c, **p))
+        c.free()
+    with Server(workers=1, trace=True) as srv:
+        futs = [srv.submit(n, lits, **p) for n, lits, p in reqs]
+        res = [f.result(timeout=300) for f in futs]
+    for a, r in zip(solo, res):
+        _same(a, r.output)
+    for rids in srv.job_rids:
+        if any(r in big for r in rids):
+            assert len(rids) == 1, srv.job_rids
+    assert any(len(rids) > 1 for rids in srv.job_rids), srv.job_rids
+    _say(f"jobs: {srv.job_rids}")
+
+
 def test_queued_requests_are_taken_together():
     """With its one worker busy, requests of one kind that queue up are taken
     together when the worker frees (one job, shared launches), and each
