@@ -157,7 +157,7 @@ struct Shape {
 // the unsat-masked loss; elsewhere they fall back to their unmasked twin (same
 // arithmetic).
 hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_mode, Shape& sh,
-                      bool allow_mask = true) {
+                      bool allow_mask = true, bool allow_slot = true) {
     const int idx = req & 0xff;
     int U = (req >> 8) & 0xff;
     int Ub = (req >> 16) & 0xff;
@@ -167,7 +167,8 @@ hms_status make_shape(const hms::HostPlan& P, int32_t R, int32_t req, int loss_m
         sh.sched = hms::kSchedules[sh.sched].twin;
     // slot schedules: one restart, the unsat-masked loss, and a plan with the
     // occurrence map; elsewhere their twin
-    if (hms::kSchedules[sh.sched].slot && (R != 1 || loss_mode != HMS_LOSS_UNSAT || !allow_mask || !P.slot_ok))
+    if (hms::kSchedules[sh.sched].slot &&
+        (R != 1 || loss_mode != HMS_LOSS_UNSAT || !allow_mask || !allow_slot || !P.slot_ok))
         sh.sched = hms::kSchedules[sh.sched].twin;
     const hms::Schedule& c = hms::kSchedules[sh.sched];
     sh.P = c.P;
@@ -1857,7 +1858,9 @@ hms_status eval_relaxed_impl(const hms_cnf* cnf, const float* x, int32_t R, int3
     const hms::HostPlan& P = cnf->plan;
     hipStream_t s = (hipStream_t)stream;
     Shape sh;
-    hms_status rc = make_shape(P, R, 0, loss_mode, sh);
+    // one evaluation gains nothing from the occurrence slots (its forward
+    // pays for them) and they would take workspace
+    hms_status rc = make_shape(P, R, 0, loss_mode, sh, true, false);
     if (rc) return rc;
     const bool want_g = grad != nullptr;
     Layout lay;
