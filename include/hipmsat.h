@@ -393,7 +393,8 @@ typedef struct {
                                         variable's segments are consecutive rows in segment order */
     const int32_t* var_old;          /* [n] new -> original */
     const uint32_t* c_slot;          /* [c_ent_len] v_ent index of the same occurrence | sign << 31, or
-                                        0xffffffff for padding; NULL when v_ent_len >= 2^31 */
+                                        0xffffffff for padding; entry (c, row) of a tile at
+                                        base + row * len + c (row by row); NULL when v_ent_len >= 2^31 */
     void* priv;
 } hms_plan_view;
 

@@ -508,7 +508,8 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
         // every occurrence of a row in the loss, or that was in it one step
         // ago, gets the row's adjoint (signed by its literal) or 0 in its
         // variable-side slot; slots of other rows already hold 0.  The slot
-        // loads of a batch go out together.
+        // loads of a batch go out together.  A tile's slots are stored row by
+        // row, so the few rows that need theirs fetch few lines.
         uint32_t smax = 0;
 #pragma unroll
         for (int u = 0; u < NT; ++u)
@@ -520,7 +521,7 @@ __device__ __forceinline__ void fwd_nt_body(const FwdArgs& A, const int bx) {
 #pragma unroll
                 for (int u = 0; u < NT; ++u)
                     sl[cc][u] = (put[u] && c0 + cc < d[u].len)
-                                    ? A.slot[(size_t)d[u].base + (size_t)(c0 + cc) * kTile + lane]
+                                    ? A.slot[(size_t)d[u].base + (size_t)lane * d[u].len + c0 + cc]
                                     : kNoSlot;
 #pragma unroll
             for (int cc = 0; cc < 8; ++cc)
@@ -1097,7 +1098,7 @@ __global__ __launch_bounds__(256) void k_slots(SlotArgs A) {
         for (uint32_t cc = 0; cc < cd.len; ++cc) {
             const uint32_t cpos = cd.base + cc * kTile + j % kTile;
             if ((A.c_ent[cpos] & kIdx) == (uint32_t)v) {
-                A.c_slot[cpos] = vpos | (e & kSign);
+                A.c_slot[cd.base + (j % kTile) * cd.len + cc] = vpos | (e & kSign);  // row-major in the tile
                 break;
             }
         }

@@ -65,6 +65,7 @@ struct FwdArgs {
     uint32_t* umask;     // written when the schedule keeps the unsat bitset
     const int64_t* w;    // weight of each clause row (weighted MaxSAT), or null: weight 1
     const uint32_t* slot; // slot schedules: variable-side entry of each clause-side entry | sign
+                          // (tile-major like the entries, but row by row within a tile)
     float* contrib;       // slot schedules: occurrence adjoints (written where they change)
     float two_over_m;
     int64_t* cnt_part;   // unsatisfied weight per unit

@@ -673,7 +673,7 @@ void build_slots(HostPlan& P) {
                 for (uint32_t cc = 0; cc < cd.len; ++cc) {
                     const uint32_t cpos = cd.base + cc * kTile + j % kTile;
                     if ((P.c_ent[cpos] & kIdx) == (uint32_t)v) {
-                        P.c_slot[cpos] = vpos | (e & kSign);
+                        P.c_slot[cd.base + (j % kTile) * cd.len + cc] = vpos | (e & kSign);  // row-major in the tile
                         break;
                     }
                 }

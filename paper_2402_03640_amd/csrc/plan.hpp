@@ -72,7 +72,9 @@ struct HostPlan {
     PVec<int32_t> c_row_orig; // [c_tiles * kTile] original clause of a row, -1 = padding
     // [c_ent.size()] where each clause-side entry sits on the variable side:
     // the index into v_ent of the same occurrence | its sign bit, or kNoSlot
-    // for padding.  The library builds this map on the device at load; the
+    // for padding.  Within a tile the map is stored row by row: entry (c, row)
+    // of the tile at base + row * len + c (the entries themselves are column
+    // by column).  The library builds this map on the device at load; the
     // host copy is filled only by build_slots (the host plan view).
     PVec<uint32_t> c_slot;
     bool slot_ok = false;            // the variable side has fewer than 2^31 entries (slot schedules can run)

@@ -155,7 +155,7 @@ def _check_slots(P, n):
         for q in range(64):
             for c in range(ln):
                 p = base + 64 * c + q
-                e, sl = int(P.c_ent[p]), int(P.c_slot[p])
+                e, sl = int(P.c_ent[p]), int(P.c_slot[base + q * ln + c])  # the map is row by row
                 if e == n:
                     assert sl == 0xFFFFFFFF
                     continue
