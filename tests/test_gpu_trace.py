@@ -88,16 +88,19 @@ def test_trace_tiled_equals_resident():
     np.testing.assert_allclose(a.trace["loss"], b.trace["loss"], rtol=1e-12, atol=0)
 
 
-def test_trace_matches_the_oracle_for_short_solves():
+@pytest.mark.parametrize("n,R,sched", [(500, 4, 3), (5000, 1, 42), (5000, 1, 41)],
+                         ids=["tiled", "slot-one-tile", "slot-two-tiles"])
+def test_trace_matches_the_oracle_for_short_solves(n, R, sched):
     """Six Adam steps at lr 1e-4, counted every other step: each count equals
     the oracle's count of its own iterate, each loss is within the parity
     tolerance (the FP32 and FP64 iterates agree to far below a rounding
-    flip at this step size)."""
-    n, m, R, T, K = 500, 2150, 4, 6, 2
+    flip at this step size); also under the occurrence-slot schedules."""
+    m, T, K = int(4.3 * n), 6, 2
     lits = cnfgen.uniform_kcnf(n, m, 3, seed=8)
     cnf = hm.load_cnf(n, lits)
-    out = hm.solve(cnf, steps=T, restarts=R, eval_every=K, seed=2, lr=1e-4, autotune=False, schedule=3,
+    out = hm.solve(cnf, steps=T, restarts=R, eval_every=K, seed=2, lr=1e-4, autotune=False, schedule=sched,
                    trace_cap=8)
+    assert out.schedule & 0xFF == sched
     oc = O.OracleCNF(n, lits)
     st = oc.init_state(restarts=R, seed=2)
     prev = 0
