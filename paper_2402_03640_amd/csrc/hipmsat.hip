@@ -919,16 +919,20 @@ hms_status tune(const hms_cnf* cnf, const hms_solve_params* p, int32_t iters, in
         if (rc) return rc;
         timed.emplace_back(ms, code);
     }
-    // the three fastest are timed twice more and keep their best time, so
-    // that one noisy measurement does not decide between near-equal choices
+    // the three fastest, and the entry the untimed rule would take, are
+    // timed twice more and keep their best time, so that one noisy
+    // measurement does not decide between near-equal choices
     std::sort(timed.begin(), timed.end());
-    for (size_t k = 0; k < std::min<size_t>(3, timed.size()); ++k)
+    const int untimed = auto_schedule(p->restarts, p->loss_mode, cnf->plan.nnz, cnf->plan.n_act);
+    for (size_t k = 0; k < timed.size(); ++k) {
+        if (k >= 3 && (timed[k].second == kResidentId || (timed[k].second & 0xff) != untimed)) continue;
         for (int rep = 0; rep < 2; ++rep) {
             double ms = 0;
             hms_status rc = time_code(timed[k].second, ms);
             if (rc) return rc;
             timed[k].first = std::min(timed[k].first, ms);
         }
+    }
     for (const auto& tc : timed)
         if (tc.first < best_ms) {
             best_ms = tc.first;
