@@ -197,6 +197,9 @@ def _slot_instances(rng):
         cl.append([int(v) if rng.random() < 0.5 else -int(v) for v in vs])
     cl += [[], [7, -7, 9], [4, 4, -5], [-11, 12, 12, -11], [], [300, -300]]
     out.append((n, cnfgen.from_clauses(cl)))
+    # three variables in 3000 clauses: every variable row is split into
+    # segments and there are no light rows
+    out.append((3, cnfgen.uniform_kcnf(3, 3000, 2, seed=6)))
     return out
 
 
