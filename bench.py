@@ -9,7 +9,9 @@ Printed: one JSON line with fwd+bwd literal nonzeros per second (2 L R T per
 solve), the roofline of the dominant kernel (algorithmic bytes per launch /
 average launch time from HIP events), and the FP64 CPU oracle timed on a
 bounded sample of the same workload on this host.  The default line also
-carries the structured workload (n = 500000, m = 2.5M, one restart) and the
+carries the same 64 restarts solved one at a time against the batched solve
+(at equal per-restart cost), the structured workload (n = 500000, m = 2.5M,
+one restart) and the
 serving workload (512 Poisson requests through the continuous-batching
 server: instances/s, p50/p99 latency, against the plain one-at-a-time loop).
 """
@@ -356,6 +358,38 @@ def make_workload(name):
 STRUCTURED_SCHEDULE = 41 | (64 << 8)
 
 
+def plain_vs_batched_record(cnf, wl, code):
+    """Plain against batched restarts on the headline instance: the R
+    restarts one solve each (restart r is the one-restart solve with seed r,
+    under the untimed one-restart schedule) against the batched solve of all
+    R, wall time with the solves' own device time beside it, and whether every
+    restart reaches the same best cost at the same step either way."""
+    import numpy as np
+    import torch
+
+    import paper_2402_03640_amd as hm
+    R, T, K = wl["R"], wl["T"], wl["K"]
+    kw = dict(steps=T, eval_every=K, lr=1e-4)
+    hm.solve(cnf, restarts=1, seed=0, autotune=False, **kw)  # warm the one-restart code objects
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [hm.solve(cnf, restarts=1, seed=r, autotune=False, **kw) for r in range(R)]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batched = hm.solve(cnf, restarts=R, seed=0, schedule=code, **kw)
+    torch.cuda.synchronize()
+    batched_s = time.perf_counter() - t0
+    pb = np.array([p.best_cost for p in plain])
+    ps = np.array([p.best_step for p in plain])
+    equal = bool(np.array_equal(pb, batched.restart_best) and np.array_equal(ps, batched.restart_step))
+    return {"restarts": R, "plain_schedule": plain[0].schedule, "batched_schedule": batched.schedule,
+            "plain_s": round(plain_s, 4), "plain_device_s": round(sum(p.device_ms for p in plain) / 1e3, 4),
+            "batched_s": round(batched_s, 4), "batched_device_s": round(batched.device_ms / 1e3, 4),
+            "restarts_per_s_plain": round(R / plain_s, 2), "restarts_per_s_batched": round(R / batched_s, 2),
+            "speedup": round(plain_s / batched_s, 2), "equal_cost": equal, "best_cost": int(batched.best_cost)}
+
+
 def structured_record(kernel_iters=100, solves=3):
     """The largest workload (structured n=500000, m=2.5M, one restart, 200
     Adam steps, count every 50) timed as the headline is: µs per gradient step
@@ -541,6 +575,8 @@ def main():
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="leave out the plain-restarts record (64 one-restart solves) of the default line")
     ap.add_argument("--no-structured", action="store_true",
                     help="leave out the structured-workload record of the default line")
     ap.add_argument("--no-serving", action="store_true",
@@ -700,6 +736,13 @@ def main():
         "load_s": round(load_s, 4),
     }
     # the sub-records report a failure in the line instead of losing it
+    if args.config == "cfg2" and not args.no_plain:
+        log("[bench] plain restarts: 64 one-restart solves against the batched solve ...")
+        try:
+            out["plain_vs_batched"] = plain_vs_batched_record(cnf, wl, code)
+        except Exception as e:  # noqa: BLE001
+            out["plain_vs_batched"] = {"error": f"{type(e).__name__}: {e}"}
+        log(f"[bench] plain vs batched: {out['plain_vs_batched']}")
     if args.config == "cfg2" and not args.no_structured:
         log("[bench] the structured workload (n=500000, m=2.5M) ...")
         try:
