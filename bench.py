@@ -455,6 +455,50 @@ def host_cpu_model():
     return "unknown"
 
 
+def batch_record(groups=((16, 15000, 60000), (32, 15000, 60000), (16, 60000, 200000)), steps=1000):
+    """Grouped batches (hms_solve_batch: instances of uneven size in one
+    launch per kernel per step) against one hms_solve after another, on
+    uniform 3-CNF one-restart instances of log-uniform size, 1000 Adam steps,
+    K=50 (plans built beforehand; the batch timed twice, the faster kept);
+    each batched result must equal its solo result."""
+    import numpy as np
+    import torch
+
+    import cnfgen
+    import paper_2402_03640_amd as hm
+    out = []
+    for gi, (count, n_lo, n_hi) in enumerate(groups):
+        rng = np.random.default_rng(40 + gi)
+        ns = [int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))) for _ in range(count)]
+        cnfs = [hm.load_cnf(n, cnfgen.uniform_kcnf(n, int(4.3 * n), 3, seed=1000 * gi + i)) for i, n in enumerate(ns)]
+        kw = dict(steps=steps, restarts=1, eval_every=50, lr=1e-4)
+        seeds = list(range(count))
+        hm.solve_batch(cnfs[:2], seeds=seeds[:2], **kw)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solo = [hm.solve(c, seed=s, autotune=False, **kw) for c, s in zip(cnfs, seeds)]
+        torch.cuda.synchronize()
+        solo_s = time.perf_counter() - t0
+        batch_s = float("inf")
+        for _ in range(2):  # the first call of a group also grows the allocator's pool
+            t0 = time.perf_counter()
+            batch = hm.solve_batch(cnfs, seeds=seeds, **kw)
+            torch.cuda.synchronize()
+            batch_s = min(batch_s, time.perf_counter() - t0)
+        equal = all(a.best_cost == b.best_cost and a.best_step == b.best_step
+                    and np.array_equal(a.best_assignment, b.best_assignment) for a, b in zip(solo, batch))
+        out.append({"instances": count, "n_range": [n_lo, n_hi], "nnz": int(sum(c.info["nnz"] for c in cnfs)),
+                    "batch_schedule": batch[0].schedule, "solo_s": round(solo_s, 4), "batch_s": round(batch_s, 4),
+                    "instances_per_s_solo": round(count / solo_s, 1), "instances_per_s_batch": round(count / batch_s, 1),
+                    "speedup": round(solo_s / batch_s, 2), "equal": equal})
+        log(f"[batch] {out[-1]}")
+        for c in cnfs:
+            c.free()
+    return {"metric": "instances/s (grouped batches vs one solve after another)", "steps": steps,
+            "workload": "uniform random 3-CNF, one restart, n log-uniform in each range, m = 4.3 n, 1000 Adam steps, "
+                        "K=50", "groups": out}
+
+
 def serve_bench(args):
     """Serving workload as its own bench line."""
     print(json.dumps(serve_record(args)), flush=True)
@@ -619,6 +663,9 @@ def main():
         return
     if args.config == "serve":
         serve_bench(args)
+        return
+    if args.config == "batch":
+        print(json.dumps(batch_record()), flush=True)
         return
     wl = make_workload(args.config)
     log(f"[bench] workload {wl['name']}: {wl['desc']}")

@@ -1770,6 +1770,16 @@ hms_status hms_solve_batch(const hms_cnf* const* cnfs, const hms_solve_params* p
             // depends on the instance)
             Shape sh0;
             if (!st) st = make_shape(cnfs[g[k0]]->plan, p.restarts, code, p.loss_mode, sh0);
+            if (!st && p.schedule == 0 && sh0.slot) {
+                // the slot schedules carry two more entry-sized streams; once a
+                // group's instances together pass 2^24 nonzeros (their streams
+                // no longer stay in the Infinity Cache) the bitset schedule
+                // runs the group faster (16 instances of 60000-200000
+                // variables: 86.6 against 78.8 instances/s)
+                int64_t nnz = 0;
+                for (int32_t k = 0; k < cnt; ++k) nnz += cnfs[g[k0 + k]]->plan.nnz;
+                if (nnz > (int64_t(1) << 24)) st = make_shape(cnfs[g[k0]]->plan, p.restarts, 37 | (64 << 8), p.loss_mode, sh0);
+            }
             if (!st) st = solve_tiled_group(cnfs, params, g.data() + k0, cnt, sh0.code, s, results, statuses);
             if (st) {
                 if (statuses)
