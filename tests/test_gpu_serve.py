@@ -395,7 +395,7 @@ def test_repeated_solves_do_not_grow_device_memory():
         n = int(np.exp(rng.uniform(np.log(30), np.log(20000))))
         inst.append((n, cnfgen.uniform_kcnf(n, int(n * 4.2), 3, seed=i)))
 
-    def one_round():
+    def one_pass():
         for _ in range(8):
             cnfs = [hm.load_cnf(n, lits) for n, lits in inst]
             for i, c in enumerate(cnfs):
@@ -406,7 +406,7 @@ def test_repeated_solves_do_not_grow_device_memory():
         torch.cuda.synchronize()
         return torch.cuda.mem_get_info()[0]
 
-    f1 = one_round()
-    f2 = one_round()
-    _say(f"free after round 1: {f1 / 2**20:.0f} MiB, after round 2: {f2 / 2**20:.0f} MiB")
+    f1 = one_pass()
+    f2 = one_pass()
+    _say(f"free after pass 1: {f1 / 2**20:.0f} MiB, after pass 2: {f2 / 2**20:.0f} MiB")
     assert f1 - f2 <= 16 << 20
