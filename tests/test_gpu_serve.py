@@ -386,7 +386,7 @@ def test_concurrent_batches_equal_solo():
 
 def test_repeated_solves_do_not_grow_device_memory():
     """Loading, solving (alone and batched) and freeing the same instances
-    twice over: device memory after the second round equals that after the
+    twice over: device memory after the second pass equals that after the
     first (the stream-ordered pool keeps its high-water mark, nothing more)."""
     import torch
     rng = np.random.default_rng(1)
